@@ -1,0 +1,248 @@
+"""Seeded synthetic Monte Carlo sample data shaped like the workloads of the
+blocked linear method (BLM) paper, Zhao & Neuscamman, arXiv:1702.01481.
+
+This module only draws random numbers.  It holds none of the method's
+arithmetic (no overlap or Hamiltonian estimates, no eigensolves), so it can
+feed both the CPU oracle and the HIP path with the same bytes.
+
+Per-sample quantities (the derivative ratios of Eq. 3 of the paper) follow a
+low-rank Gaussian model:
+
+    O_s   = mu + L z_s + 0.1 xi_s                      mu ~ N(0, 0.1^2), L_ij ~ N(0, 0.3^2)
+    E_L,s = -10 + a . (O_s - mu) + sigma_E eps_s       a ~ N(0, 0.2^2)
+    e_s   = E_L,s O_s + G (O_s - mu) + 0.05 eta_s      G symmetric, G_ij ~ N(0, 0.1^2)
+
+with z, xi, eps, eta standard normal.  Model parameters are drawn once per
+seed; the sample draws of chunk c come from a generator seeded by
+(seed, c), so any chunk can be regenerated on its own, in any order, on the
+CPU or on a GPU.  CPU and GPU draws differ (torch's CPU and device
+generators are different streams); a comparison always hands both sides the
+same bytes.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+# stream ids for the independent quantities of one seed
+_S_MU, _S_L, _S_A, _S_G, _S_BLOCKS, _S_OLD, _S_W = 1, 2, 3, 4, 5, 6, 7
+_S_CHUNK0 = 1 << 20
+
+
+def _seed_of(seed: int, stream: int) -> int:
+    # splitmix64 finaliser of (seed, stream): well-separated 63-bit seeds
+    x = (seed * 0x9E3779B97F4A7C15 + stream * 0xBF58476D1CE4E5B9 + 0x94D049BB133111EB) & ((1 << 64) - 1)
+    x ^= x >> 30
+    x = (x * 0xBF58476D1CE4E5B9) & ((1 << 64) - 1)
+    x ^= x >> 27
+    x = (x * 0x94D049BB133111EB) & ((1 << 64) - 1)
+    x ^= x >> 31
+    return x & ((1 << 63) - 1)
+
+
+def _gen(device, seed: int, stream: int) -> torch.Generator:
+    g = torch.Generator(device=device)
+    g.manual_seed(_seed_of(seed, stream))
+    return g
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Workload:
+    """One synthetic optimization problem: sizes, partition and BLM knobs."""
+    name: str
+    n_params: int
+    block_offsets: np.ndarray          # int64 [N_B + 1], contiguous, ascending
+    n_samples: int
+    chunk: int                          # samples per chunk (last chunk may be shorter)
+    rank: int                           # rank of L
+    n_keep: int                         # N_K
+    n_old: int                          # N_O
+    shifts: Tuple[float, ...]
+    sigma_E: float = 0.5
+    seed: int = 0
+
+    @property
+    def n_blocks(self) -> int:
+        return len(self.block_offsets) - 1
+
+    def chunk_sizes(self) -> List[int]:
+        full, tail = divmod(self.n_samples, self.chunk)
+        return [self.chunk] * full + ([tail] if tail else [])
+
+
+def uniform_offsets(n_params: int, n_blocks: int) -> np.ndarray:
+    """Contiguous blocks of (nearly) equal size."""
+    base, rem = divmod(n_params, n_blocks)
+    sizes = [base + (1 if b < rem else 0) for b in range(n_blocks)]
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def loguniform_offsets(n_params: int, n_blocks: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """Block sizes drawn log-uniform in [lo, hi], rescaled to sum to n_params,
+    floored, with the remainder given to the largest fractional parts; kept in
+    draw order."""
+    g = _gen("cpu", seed, _S_BLOCKS)
+    u = torch.rand(n_blocks, generator=g, dtype=torch.float64).numpy()
+    raw = np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))
+    scaled = raw * (n_params / raw.sum())
+    sizes = np.floor(scaled).astype(np.int64)
+    rem = n_params - int(sizes.sum())
+    order = np.argsort(-(scaled - sizes), kind="stable")
+    sizes[order[:rem]] += 1
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def uniform_int_offsets(n_params: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """Block sizes drawn as uniform integers in [lo, hi] until n_params is
+    covered; the last block takes what is left, and a remainder below lo is
+    merged into the block before it."""
+    g = _gen("cpu", seed, _S_BLOCKS)
+    sizes: List[int] = []
+    left = n_params
+    while left > 0:
+        s = min(int(torch.randint(lo, hi + 1, (1,), generator=g).item()), left)
+        sizes.append(s)
+        left -= s
+    if len(sizes) > 1 and sizes[-1] < lo:
+        sizes[-2] += sizes.pop()
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def workload(name: str, seed: int = 0) -> Workload:
+    """The five synthetic workloads (sizes of the paper's problems and beyond).
+
+    small     N_V=200 in 4x50, N_s=20,000 (one chunk), rank 8, N_K=3, delta=1e-3
+    fp64      N_V=4,096 in 8x512, N_s=1,000,000 in 65,536-sample chunks, rank 32,
+              N_K=5, N_O=1, delta in {1e-4, 1e-3, 1e-2}
+    bf16      N_V=16,384 in 16x1,024, N_s=4,000,000, rank 64, N_K=5, N_O=1
+    uneven    N_V=30,000 in 40 log-uniform blocks in [100, 2,000], N_s=4,000,000,
+              rank 32, N_K=4, N_O=0, delta=1e-3
+    """
+    if name == "small":
+        return Workload("small_200x20k", 200, uniform_offsets(200, 4), 20_000, 65_536, 8, 3, 0,
+                        (1e-3,), seed=seed)
+    if name == "fp64":
+        return Workload("fp64_4096x1M", 4096, uniform_offsets(4096, 8), 1_000_000, 65_536, 32, 5, 1,
+                        (1e-4, 1e-3, 1e-2), seed=seed)
+    if name == "bf16":
+        return Workload("bf16_16384x4M", 16384, uniform_offsets(16384, 16), 4_000_000, 65_536, 64, 5, 1,
+                        (1e-4, 1e-3, 1e-2), seed=seed)
+    if name == "uneven":
+        return Workload("uneven_30000x4M", 30000, loguniform_offsets(30000, 40, 100.0, 2000.0, seed),
+                        4_000_000, 65_536, 32, 4, 0, (1e-3,), seed=seed)
+    raise KeyError(name)
+
+
+# ----------------------------------------------------------------------------
+# generator
+# ----------------------------------------------------------------------------
+
+class SampleGenerator:
+    """Draws the model parameters (mu, L, a, G) once, then chunks on demand."""
+
+    def __init__(self, n_params: int, rank: int, seed: int = 0, sigma_E: float = 0.5,
+                 device: str | torch.device = "cpu"):
+        self.n_params, self.rank, self.seed, self.sigma_E = n_params, rank, seed, sigma_E
+        self.device = torch.device(device)
+        dev = self.device
+        f64 = torch.float64
+        n = n_params
+        self.mu = 0.1 * torch.randn(n, generator=_gen(dev, seed, _S_MU), dtype=f64, device=dev)
+        self.L = 0.3 * torch.randn(n, rank, generator=_gen(dev, seed, _S_L), dtype=f64, device=dev)
+        self.a = 0.2 * torch.randn(n, generator=_gen(dev, seed, _S_A), dtype=f64, device=dev)
+        g = 0.1 * torch.randn(n, n, generator=_gen(dev, seed, _S_G), dtype=f64, device=dev)
+        # symmetric: upper triangle (with diagonal) mirrored
+        up = torch.triu(g)
+        self.G = up + torch.triu(g, 1).transpose(0, 1)
+        del g, up
+
+    def chunk(self, index: int, n_rows: int, out_O: Optional[torch.Tensor] = None,
+              out_e: Optional[torch.Tensor] = None):
+        """Samples of chunk `index`: O [n_rows][N_V], e [n_rows][N_V], E_L [n_rows]."""
+        dev, f64 = self.device, torch.float64
+        g = _gen(dev, self.seed, _S_CHUNK0 + index)
+        n = self.n_params
+        z = torch.randn(n_rows, self.rank, generator=g, dtype=f64, device=dev)
+        dO = z @ self.L.T
+        del z
+        dO.add_(torch.randn(n_rows, n, generator=g, dtype=f64, device=dev), alpha=0.1)
+        eps = torch.randn(n_rows, generator=g, dtype=f64, device=dev)
+        EL = -10.0 + dO @ self.a + self.sigma_E * eps
+        O = out_O if out_O is not None else torch.empty(n_rows, n, dtype=f64, device=dev)
+        torch.add(dO, self.mu, out=O)
+        e = out_e if out_e is not None else torch.empty(n_rows, n, dtype=f64, device=dev)
+        torch.matmul(dO, self.G, out=e)          # G symmetric: rows of (O-mu) G = G (O-mu)
+        del dO
+        e.addcmul_(EL[:, None], O)
+        e.add_(torch.randn(n_rows, n, generator=g, dtype=f64, device=dev), alpha=0.05)
+        return O, e, EL
+
+
+def weights(n_rows: int, seed: int, index: int = 0, device="cpu") -> torch.Tensor:
+    """Non-uniform positive importance weights in [0.5, 1.5) (tests only)."""
+    g = _gen(device, seed, _S_W * 1000 + index)
+    return 0.5 + torch.rand(n_rows, generator=g, dtype=torch.float64, device=device)
+
+
+def old_directions(n_old: int, n_params: int, seed: int, device="cpu") -> torch.Tensor:
+    """Seeded stand-ins for the previous N_O updates, [N_O][N_V]."""
+    g = _gen(device, seed, _S_OLD)
+    return torch.randn(n_old, n_params, generator=g, dtype=torch.float64, device=device)
+
+
+def dyadic_chunk(n_rows: int, n_params: int, seed: int, index: int = 0):
+    """Small-integer samples in [-7, 7] (CPU): every product and every partial
+    sum of the contractions is exact in FP64, BF16 pieces and FP32, so all
+    summation orders give bit-identical results."""
+    g = _gen("cpu", seed, _S_CHUNK0 + 7919 * (index + 1))
+    O = torch.randint(-7, 8, (n_rows, n_params), generator=g).to(torch.float64)
+    e = torch.randint(-7, 8, (n_rows, n_params), generator=g).to(torch.float64)
+    EL = torch.randint(-7, 8, (n_rows,), generator=g).to(torch.float64)
+    return O, e, EL
+
+
+def planted_zero_variance(dim_hilbert: int, n_params: int, seed: int, n_samples: int = 0):
+    """A finite Hilbert-space model whose tangent space holds the exact
+    ground state (the setting of the strong zero-variance principle).
+
+    A random symmetric Hamiltonian matrix Hf on `dim_hilbert` basis states
+    has ground state phi0 (energy E0).  Psi is positive and bounded away from
+    zero; the derivative vectors Psi^x are random except the last, which is
+    solved for so that Psi + sum_x Delta_x Psi^x = phi0 for a random Delta.
+    Per basis state n: O[n, x] = Psi^x(n)/Psi(n), EL[n] = (Hf Psi)(n)/Psi(n),
+    e[n, x] = (Hf Psi^x)(n)/Psi(n).
+
+    n_samples == 0: exact enumeration, weights Psi(n)^2.
+    n_samples > 0: states drawn uniformly, weights Psi(n)^2 / (1/dim).
+    Returns (O, e, EL, w, Delta, E0) as float64 numpy arrays / floats.
+    """
+    g = _gen("cpu", seed, 0xC0FFEE)
+    f64 = torch.float64
+    A = torch.randn(dim_hilbert, dim_hilbert, generator=g, dtype=f64).numpy()
+    Hf = 0.5 * (A + A.T)
+    evals, evecs = np.linalg.eigh(Hf)
+    E0, phi0 = float(evals[0]), evecs[:, 0]
+    psi = 1.0 + torch.rand(dim_hilbert, generator=g, dtype=f64).numpy()
+    dpsi = 0.5 * torch.randn(n_params, dim_hilbert, generator=g, dtype=f64).numpy()
+    delta = 0.3 * torch.randn(n_params, generator=g, dtype=f64).numpy()
+    delta[-1] = 0.5 + abs(delta[-1])
+    # scale phi0 so that the planted state is a modest step away from psi
+    phi = phi0 * (np.linalg.norm(psi) / np.linalg.norm(phi0)) * np.sign(phi0 @ psi)
+    dpsi[-1] = (phi - psi - delta[:-1] @ dpsi[:-1]) / delta[-1]
+    O_all = (dpsi / psi).T
+    EL_all = (Hf @ psi) / psi
+    e_all = ((Hf @ dpsi.T).T / psi).T
+    if n_samples == 0:
+        w = psi ** 2
+        return O_all, e_all, EL_all, w, delta, E0
+    idx = torch.randint(0, dim_hilbert, (n_samples,), generator=g).numpy()
+    w = psi[idx] ** 2 * dim_hilbert
+    return O_all[idx], e_all[idx], EL_all[idx], w, delta, E0
