@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of one blocked-linear-method step on one MI355X.
+
+Workload (FP64): N_V = 4,096 parameters in 8 blocks of 512, N_s = 1,000,000
+samples in 65,536-sample chunks (15 full + a 16,960 tail), low-rank synthetic
+derivative ratios (rank 32), N_K = 5 kept directions per block, N_O = 1
+previous-update direction, shifts {1e-4, 1e-3, 1e-2} solved together.
+
+A step is: begin_step (previous direction) -> build over all chunks ->
+block solves -> projection over all chunks -> stage two.  The sample chunks
+are generated on the device before timing and stay resident in HBM.  The
+previous direction is the update of one untimed step without history on the
+same data (shift 1e-3).
+
+Prints one JSON line.  Value: build FLOP (the algorithmic count
+2 N_s sum_b [d_b^2 + d_b (d_b + 1)/2], d_b = 1 + M_b + N_O (N_B - 1)) per
+second of whole step time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "block H/S build TFLOP/s + BLM step ms; mixed vs FP64 at ≤1e-6 rel energy err"
+PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 (matrix and vector)
+
+
+def build_flops(offsets, n_old, n_samples) -> float:
+    nb = len(offsets) - 1
+    tot = 0.0
+    for b in range(nb):
+        d = 1 + (offsets[b + 1] - offsets[b]) + n_old * (nb - 1)
+        tot += d * d + d * (d + 1) / 2
+    return 2.0 * n_samples * tot
+
+
+def cpu_baseline(O0, e0, EL0, w, offsets, old, n_keep, shifts):
+    """The oracle as it stands on the host cores: block estimates of one
+    65,536-sample chunk, then the 24 block solves of those estimates."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import blm_oracle as orc
+    O = O0.cpu().numpy()
+    e = e0.cpu().numpy()
+    EL = EL0.cpu().numpy()
+    n = O.shape[0]
+    t0 = time.perf_counter()
+    D = orc.previous_directions(old, np.asarray(offsets))
+    probs, _ = orc.block_problems([(O, e, EL, None)], np.asarray(offsets), D)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for delta in shifts:
+        for p in probs:
+            orc.solve_block(p, delta, n_keep)
+    t_solve = time.perf_counter() - t0
+    fl = build_flops(offsets, 1 if old is not None else 0, n)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {
+        "value": fl / t_build / 1e12,
+        "unit": "TFLOP/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"block estimates of the first {n}-sample chunk at full N_V ({t_build:.2f} s), "
+                   f"plus all {len(shifts) * len(probs)} block solves ({t_solve:.2f} s); "
+                   f"host nproc={os.cpu_count()}"),
+        "build_s": t_build,
+        "solve_s": t_solve,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--samples", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sample "
+                                   "sharding is a design only (see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1702_01481_amd import blm, synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    w = synth.workload("fp64")
+    n_samples = args.samples
+    offsets = w.block_offsets
+    shifts = list(w.shifts)
+    dev = torch.device("cuda")
+    gen = synth.SampleGenerator(w.n_params, w.rank, w.seed, sigma_E=w.sigma_E, device=dev)
+    sizes = []
+    left = n_samples
+    while left > 0:
+        sizes.append(min(w.chunk, left))
+        left -= sizes[-1]
+    chunks = []
+    for i, n in enumerate(sizes):
+        O, e, EL = gen.chunk(i, n)
+        chunks.append((O, e, EL))
+    del gen
+    torch.cuda.synchronize()
+
+    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, n_samples)
+    ctx.set_timing(True)
+
+    def step(old):
+        ctx.begin_step(old)
+        ctx.build(chunks)
+        ctx.solve()
+        ctx.project(chunks)
+        return ctx.stage2()
+
+    # previous direction: one step without history (zero rows are dropped)
+    upd, en0, _, _ = step(torch.zeros(w.n_old, w.n_params, dtype=torch.float64, device=dev))
+    old = upd[1:2].clone().contiguous()
+    for _ in range(args.warmup):
+        step(old)
+    torch.cuda.synchronize()
+
+    phase = {k: [] for k in blm.TIMING_NAMES}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        upd, en, al, fl = step(old)
+        for k, v in ctx.timings().items():
+            phase[k].append(v)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+
+    fl_build = build_flops(offsets, w.n_old, n_samples)
+    gram_ms = float(np.mean(phase["block_gram"]))
+    build_ms = float(np.mean([a + b + c for a, b, c in zip(phase["theta_proj"], phase["block_gram"],
+                                                          phase["block_reduce"])]))
+    achieved = fl_build / (gram_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(fl_build / (ms_step * 1e-3) / 1e12, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_params": w.n_params, "n_blocks": w.n_blocks,
+                   "n_samples": n_samples, "chunk": w.chunk, "rank": w.rank, "n_keep": w.n_keep,
+                   "n_old": w.n_old, "shifts": shifts, "precision": "fp64"},
+        "build_tflops": round(fl_build / (build_ms * 1e-3) / 1e12, 4),
+        "build_ms": round(build_ms, 3),
+        "phase_ms": {k: round(float(np.mean(v)), 3) for k, v in phase.items()},
+        "energy": [float(x) for x in en],
+        "flags": [int(x) for x in fl],
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4), "traffic": None,
+                     "kernel": "gram_kernel (block H/S build, FP64 MFMA 16x16x4)",
+                     "flops_per_launch": fl_build},
+    }
+    if not args.no_cpu_baseline:
+        O0, e0, EL0 = chunks[0]
+        cb = cpu_baseline(O0, e0, EL0, None, offsets, old.cpu().numpy(), w.n_keep, shifts)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

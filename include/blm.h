@@ -1,0 +1,176 @@
+/*
+ * blm.h - C ABI of libblm, the MI355X (gfx950) hot path of the blocked
+ * linear method (BLM) for variational Monte Carlo optimisation:
+ * Zhao & Neuscamman, arXiv:1702.01481, Sec. II.
+ *
+ * One optimisation step is, in this call order:
+ *
+ *   blm_begin_step     previous-update directions Theta (Eq. 9)
+ *   blm_build_blocks*  first pass over the samples: every block's overlap S_b
+ *                      and Hamiltonian H_b estimates (Eq. 3 on the one-block
+ *                      basis of Eq. 4 / Eq. 10)
+ *   blm_solve_blocks   every block's shifted generalised eigenproblem, ranked,
+ *                      kept directions B^(b) (Eq. 5 / Eq. 10, Eq. 6)
+ *   blm_project*       second pass over the same samples: stage-two estimates
+ *                      on the kept directions (Eq. 6, Eq. 7)
+ *   blm_stage2         stage-two eigenproblem, energy and update (Eq. 7, Eq. 8)
+ *
+ * Every function returns a blm_status; nothing throws across the ABI.  On an
+ * error, blm_last_error() describes it.  All device pointers are HIP device
+ * memory on the device that was current at blm_create; all work runs on the
+ * stream given to blm_create.
+ *
+ * Numbers and layouts
+ *   - N_V parameters are split into N_B contiguous blocks by block_offsets
+ *     (block b holds parameters [off[b], off[b+1])).
+ *   - Per-sample arrays are sample-major: O[s * ld + x] is the derivative
+ *     ratio <n|Psi^x>/<n|Psi> of parameter x at sample s, e[s * ld + x] is
+ *     <n|H|Psi^x>/<n|Psi>, E_L[s] = <n|H|Psi>/<n|Psi> and w[s] the importance
+ *     weight |<n|Psi>|^2 / P(n) (Eq. 3).  w == NULL means all weights are 1.
+ *   - Estimates are normalised by the total weight, so S[0][0] = 1.
+ *   - The diagonal shift (Sec. II.A) adds delta times the parameter-space
+ *     Euclidean metric to H; the coordinate of Psi itself is never shifted.
+ *   - Eigenvalues are ranked by real part.  A complex conjugate pair supplies
+ *     two directions (real and imaginary parts of its eigenvector) and is
+ *     never split at the N_K cut, so a block keeps N_K or N_K + 1 directions.
+ */
+#ifndef BLM_H
+#define BLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct blm_ctx blm_ctx;
+
+typedef enum {
+  BLM_OK = 0,
+  BLM_E_ARG = 1,        /* bad argument or unsupported size */
+  BLM_E_STATE = 2,      /* call out of order, or pass 2 saw other samples than pass 1 */
+  BLM_E_HIP = 3,        /* a HIP runtime call failed */
+  BLM_E_NOMEM = 4,      /* device allocation failed */
+  BLM_E_S_NOT_PD = 5,   /* an overlap matrix is not positive definite */
+  BLM_E_NONFINITE = 6,  /* NaN or Inf reached an eigenproblem */
+  BLM_E_NOCONV = 7      /* the QR iteration did not converge */
+} blm_status;
+
+typedef enum {
+  BLM_PREC_F64 = 0      /* sample contractions in FP64 on FP64 matrix cores */
+} blm_precision;
+
+/* Flags returned per shift by blm_stage2 (bit mask). */
+enum {
+  BLM_FLAG_COMPLEX_ENERGY = 1u,   /* the stage-two lowest eigenvalue is complex; energy = real part */
+  BLM_FLAG_PAIR_KEPT = 2u,        /* some block kept a complex pair */
+  BLM_FLAG_SMALL_ALPHA = 4u       /* |alpha| < 1e-8 |eigenvector|: the step is very long */
+};
+
+typedef struct {
+  int64_t n_params;              /* N_V >= 1 */
+  int32_t n_blocks;              /* N_B >= 1 */
+  const int64_t* block_offsets;  /* host [N_B + 1]: 0 = off[0] < off[1] < ... < off[N_B] = N_V */
+  int32_t n_keep;                /* N_K >= 1 directions kept per block (Sec. II.B) */
+  int32_t n_old;                 /* N_O >= 0 previous updates used as Theta (Eq. 9); 1 + N_O N_B <= 16 */
+  int32_t n_shifts;              /* >= 1 shifts solved together from one build */
+  const double* shifts;          /* host [n_shifts], each >= 0 */
+  int32_t precision;             /* blm_precision */
+  int64_t max_samples;           /* most samples in one build / project call (sum over its chunks) */
+} blm_config;
+
+typedef struct {                 /* one chunk of samples; device memory, caller-owned */
+  int64_t n_samples;             /* >= 0 */
+  int64_t ld;                    /* row stride of O and e in elements, >= N_V */
+  const double* O;               /* [n_samples][ld] */
+  const double* e;               /* [n_samples][ld] */
+  const double* E_L;             /* [n_samples] */
+  const double* w;               /* [n_samples] >= 0, or NULL for all-ones */
+} blm_chunk;
+
+/* Bytes of device memory blm_create will allocate for this configuration. */
+blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes);
+
+/* Allocates the context and its device workspace.  stream is a hipStream_t
+ * (NULL = the null stream).  The library owns the workspace until
+ * blm_destroy. */
+blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out);
+blm_status blm_destroy(blm_ctx* ctx);
+
+/* Starts a step: clears the accumulators and sets the previous-update
+ * directions Theta_jk (Eq. 9).  d_old is device [N_O][N_V]: row j-1 is the
+ * whole update of step n-j.  Each block's pieces are orthonormalised; zero or
+ * dependent pieces are dropped.  NULL (or N_O == 0) means no Theta. */
+blm_status blm_begin_step(blm_ctx* ctx, const double* d_old);
+
+/* Pass 1: adds the chunks' contributions to every block's S_b and H_b
+ * (Eq. 3 on the Eq. 10 basis).  Asynchronous on the context's stream; the
+ * chunks must stay valid until the stream has passed the call.  May be
+ * called any number of times per step. */
+blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks);
+
+/* Solves every block's shifted pencil (H_b + delta P_b) c = lambda S_b c for
+ * every shift, ranks the eigenvalues by real part and keeps the parameter
+ * part of the best directions, orthonormalised, as B^(b) (Eq. 6).
+ * Synchronises the stream.  Optional host outputs:
+ *   h_evals [n_shifts][N_B][N_K + 1][2]  lowest eigenvalues (re, im)
+ *   h_kept  [n_shifts][N_B]             directions kept per block */
+blm_status blm_solve_blocks(blm_ctx* ctx, double* h_evals, int32_t* h_kept);
+
+/* Pass 2: projects the same samples onto every shift's kept directions and
+ * accumulates the stage-two estimates (Eq. 7).  Asynchronous. */
+blm_status blm_project(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks);
+
+/* Solves each shift's stage-two pencil, lowest eigenvalue by real part, and
+ * forms the update mu_{i,b} += [A B^(b)]_i / alpha (Eq. 8).  Synchronises.
+ *   d_update  device [n_shifts][N_V] (may be NULL)
+ *   h_energy  host [n_shifts] real part of the eigenvalue (may be NULL)
+ *   h_alpha   host [n_shifts] |alpha| / |eigenvector| (may be NULL)
+ *   h_flags   host [n_shifts] BLM_FLAG_* bits (may be NULL)
+ * Returns BLM_E_STATE if pass 2 saw a different sample count or total
+ * weight than pass 1. */
+blm_status blm_stage2(blm_ctx* ctx, double* d_update, double* h_energy, double* h_alpha,
+                      uint32_t* h_flags);
+
+/* Diagnostics (valid after blm_solve_blocks).  Block b's normalised matrices
+ * on the basis [Psi, Psi^{i,b}, Theta_jk (k != b, kept j, k-major)], with
+ * the shift of index `shift` added to H.  h_H, h_S: host [dim][dim] row-major;
+ * *dim receives the dimension (call with h_H == NULL to query it). */
+blm_status blm_get_block_matrices(blm_ctx* ctx, int32_t block, int32_t shift, double* h_H,
+                                  double* h_S, int32_t* dim);
+
+/* Kept directions of block b for a shift: host [*n_rows][M_b] orthonormal rows. */
+blm_status blm_get_directions(blm_ctx* ctx, int32_t block, int32_t shift, double* h_B,
+                              int32_t* n_rows);
+
+/* Stage-two matrices of a shift (valid after blm_project + blm_stage2),
+ * normalised, unshifted: basis [Psi, B^(0) rows, B^(1) rows, ...]. */
+blm_status blm_get_stage2_matrices(blm_ctx* ctx, int32_t shift, double* h_H2, double* h_S2,
+                                   int32_t* dim);
+
+/* Test hook: all eigenvalues of a dense pencil H c = lambda S c (device
+ * [d][d] row-major inputs, S symmetric positive definite), computed by the
+ * library's eigensolver; h_evals host [d][2] (re, im) in the solver's order. */
+blm_status blm_debug_eigvals(const double* d_H, const double* d_S, int32_t d, double* h_evals,
+                             void* stream);
+
+/* Per-phase timing with HIP events recorded on the context's stream
+ * (off by default).  blm_get_timings synchronises the stream and writes, for
+ * the most recent call of each kind, up to n of these durations in ms:
+ *   [0] previous-direction projection   [1] block Gram kernel
+ *   [2] block Gram reduction             [3] block pencil assembly
+ *   [4] block eigensolves                [5] kept-direction projection
+ *   [6] stage-two Gram kernel            [7] stage-two Gram reduction
+ *   [8] stage-two assembly + eigensolve + update */
+#define BLM_N_TIMINGS 9
+blm_status blm_set_timing(blm_ctx* ctx, int32_t enable);
+blm_status blm_get_timings(blm_ctx* ctx, double* h_ms, int32_t n);
+
+const char* blm_last_error(const blm_ctx* ctx);
+const char* blm_status_string(blm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BLM_H */

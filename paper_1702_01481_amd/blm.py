@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libblm (include/blm.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; torch tensors only carry
+device memory and the stream.  Loading fails loudly when the library has not
+been built (python -m paper_1702_01481_amd.build_lib).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblm.so")
+
+BLM_OK = 0
+STATUS_NAMES = {0: "BLM_OK", 1: "BLM_E_ARG", 2: "BLM_E_STATE", 3: "BLM_E_HIP", 4: "BLM_E_NOMEM",
+                5: "BLM_E_S_NOT_PD", 6: "BLM_E_NONFINITE", 7: "BLM_E_NOCONV"}
+FLAG_COMPLEX_ENERGY, FLAG_PAIR_KEPT, FLAG_SMALL_ALPHA = 1, 2, 4
+
+EXPORTED = ("blm_workspace_bytes", "blm_create", "blm_destroy", "blm_begin_step",
+            "blm_build_blocks", "blm_solve_blocks", "blm_project", "blm_stage2",
+            "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
+            "blm_debug_eigvals", "blm_set_timing", "blm_get_timings", "blm_last_error",
+            "blm_status_string")
+TIMING_NAMES = ("theta_proj", "block_gram", "block_reduce", "block_assemble", "block_eig",
+                "dir_proj", "stage2_gram", "stage2_reduce", "stage2_solve")
+
+
+class BLMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Config(C.Structure):
+    _fields_ = [("n_params", C.c_int64), ("n_blocks", C.c_int32),
+                ("block_offsets", C.POINTER(C.c_int64)), ("n_keep", C.c_int32),
+                ("n_old", C.c_int32), ("n_shifts", C.c_int32), ("shifts", C.POINTER(C.c_double)),
+                ("precision", C.c_int32), ("max_samples", C.c_int64)]
+
+
+class _Chunk(C.Structure):
+    _fields_ = [("n_samples", C.c_int64), ("ld", C.c_int64), ("O", C.c_void_p), ("e", C.c_void_p),
+                ("E_L", C.c_void_p), ("w", C.c_void_p)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Loads libblm.so from the package directory (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libblm.so not built at {LIB_PATH}; run python -m paper_1702_01481_amd.build_lib")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.blm_workspace_bytes.argtypes = [C.POINTER(_Config), C.POINTER(C.c_size_t)]
+    lib.blm_create.argtypes = [C.POINTER(_Config), vp, C.POINTER(vp)]
+    lib.blm_destroy.argtypes = [vp]
+    lib.blm_begin_step.argtypes = [vp, vp]
+    lib.blm_build_blocks.argtypes = [vp, C.POINTER(_Chunk), i32]
+    lib.blm_solve_blocks.argtypes = [vp, dp, C.POINTER(i32)]
+    lib.blm_project.argtypes = [vp, C.POINTER(_Chunk), i32]
+    lib.blm_stage2.argtypes = [vp, vp, dp, dp, C.POINTER(C.c_uint32)]
+    lib.blm_get_block_matrices.argtypes = [vp, i32, i32, dp, dp, C.POINTER(i32)]
+    lib.blm_get_directions.argtypes = [vp, i32, i32, dp, C.POINTER(i32)]
+    lib.blm_get_stage2_matrices.argtypes = [vp, i32, dp, dp, C.POINTER(i32)]
+    lib.blm_debug_eigvals.argtypes = [vp, vp, i32, dp, vp]
+    lib.blm_set_timing.argtypes = [vp, i32]
+    lib.blm_get_timings.argtypes = [vp, dp, i32]
+    lib.blm_last_error.argtypes = [vp]
+    lib.blm_last_error.restype = C.c_char_p
+    lib.blm_status_string.argtypes = [C.c_int]
+    lib.blm_status_string.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("blm_last_error", "blm_status_string"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _check_f64_dev(t: torch.Tensor, name: str):
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 device tensor")
+
+
+def _chunk(O, e, EL, w, n_params) -> _Chunk:
+    _check_f64_dev(O, "O")
+    _check_f64_dev(e, "e")
+    _check_f64_dev(EL, "E_L")
+    if O.dim() != 2 or O.shape != e.shape or O.stride(1) != 1 or e.stride(1) != 1 or O.stride(0) != e.stride(0):
+        raise ValueError("O and e must be [n][>= N_V] with unit column stride and equal row stride")
+    if O.shape[1] < n_params or EL.shape[0] != O.shape[0] or not EL.is_contiguous():
+        raise ValueError("chunk shapes do not match")
+    if w is not None:
+        _check_f64_dev(w, "w")
+        if w.shape[0] != O.shape[0] or not w.is_contiguous():
+            raise ValueError("w must be contiguous [n]")
+    return _Chunk(O.shape[0], O.stride(0) if O.shape[0] > 0 else O.shape[1], O.data_ptr(), e.data_ptr(),
+                  EL.data_ptr(), w.data_ptr() if w is not None else None)
+
+
+class BLM:
+    """One BLM optimisation context (blm_create .. blm_destroy)."""
+
+    def __init__(self, n_params: int, block_offsets: Sequence[int], n_keep: int, n_old: int,
+                 shifts: Sequence[float], max_samples: int, stream=None):
+        self.lib = load()
+        self.n_params = int(n_params)
+        self.offsets = np.ascontiguousarray(block_offsets, dtype=np.int64)
+        self.n_blocks = len(self.offsets) - 1
+        self.n_keep, self.n_old = int(n_keep), int(n_old)
+        self.shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+        self.max_samples = int(max_samples)
+        self._cfg = _Config(self.n_params, self.n_blocks, self.offsets.ctypes.data_as(C.POINTER(C.c_int64)),
+                            self.n_keep, self.n_old, len(self.shifts), _dptr(self.shifts), 0,
+                            self.max_samples)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        self._check(self.lib.blm_create(C.byref(self._cfg), C.c_void_p(_stream_handle(self.stream)), C.byref(h)),
+                    ctx=None)
+        self.h = h
+        self._keep = []   # tensors that must outlive queued work
+
+    # -- helpers ----------------------------------------------------------
+    def _check(self, st: int, ctx="self"):
+        if st != BLM_OK:
+            msg = ""
+            if ctx == "self" and getattr(self, "h", None):
+                msg = self.lib.blm_last_error(self.h).decode()
+            raise BLMError(st, msg or self.lib.blm_status_string(st).decode())
+
+    @staticmethod
+    def workspace_bytes(n_params, block_offsets, n_keep, n_old, shifts, max_samples) -> int:
+        lib = load()
+        off = np.ascontiguousarray(block_offsets, dtype=np.int64)
+        sh = np.ascontiguousarray(shifts, dtype=np.float64)
+        cfg = _Config(n_params, len(off) - 1, off.ctypes.data_as(C.POINTER(C.c_int64)), n_keep, n_old,
+                      len(sh), _dptr(sh), 0, max_samples)
+        out = C.c_size_t()
+        st = lib.blm_workspace_bytes(C.byref(cfg), C.byref(out))
+        if st != BLM_OK:
+            raise BLMError(st, lib.blm_status_string(st).decode())
+        return int(out.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.blm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chunks(self, chunks) -> Tuple[C.Array, int]:
+        cs = []
+        for ch in chunks:
+            O, e, EL = ch[0], ch[1], ch[2]
+            w = ch[3] if len(ch) > 3 else None
+            cs.append(_chunk(O, e, EL, w, self.n_params))
+            self._keep.append(ch)
+        arr = (_Chunk * max(len(cs), 1))(*cs)
+        return arr, len(cs)
+
+    # -- the step ---------------------------------------------------------
+    def begin_step(self, old: Optional[torch.Tensor] = None):
+        self._keep = []
+        if old is not None:
+            _check_f64_dev(old, "old")
+            if old.shape != (self.n_old, self.n_params) or not old.is_contiguous():
+                raise ValueError("old must be contiguous [n_old][n_params]")
+            self._keep.append(old)
+        self._check(self.lib.blm_begin_step(self.h, C.c_void_p(old.data_ptr() if old is not None else None)))
+
+    def build(self, chunks: Iterable):
+        arr, n = self._chunks(chunks)
+        self._check(self.lib.blm_build_blocks(self.h, arr, n))
+
+    def solve(self):
+        """Returns (evals [n_shifts][N_B][N_K+1] complex, kept [n_shifts][N_B])."""
+        ns, nb, nk = len(self.shifts), self.n_blocks, self.n_keep
+        ev = np.zeros((ns, nb, nk + 1, 2))
+        kept = np.zeros((ns, nb), dtype=np.int32)
+        self._check(self.lib.blm_solve_blocks(self.h, _dptr(ev), kept.ctypes.data_as(C.POINTER(C.c_int32))))
+        return ev[..., 0] + 1j * ev[..., 1], kept
+
+    def project(self, chunks: Iterable):
+        arr, n = self._chunks(chunks)
+        self._check(self.lib.blm_project(self.h, arr, n))
+
+    def stage2(self, want_update: bool = True):
+        """Returns (update [n_shifts][N_V] device tensor or None, energy, alpha ratio, flags)."""
+        ns = len(self.shifts)
+        upd = torch.empty(ns, self.n_params, dtype=torch.float64, device="cuda") if want_update else None
+        en = np.zeros(ns)
+        al = np.zeros(ns)
+        fl = np.zeros(ns, dtype=np.uint32)
+        self._check(self.lib.blm_stage2(self.h, C.c_void_p(upd.data_ptr() if upd is not None else None),
+                                        _dptr(en), _dptr(al), fl.ctypes.data_as(C.POINTER(C.c_uint32))))
+        self._keep = []
+        return upd, en, al, fl
+
+    # -- diagnostics ------------------------------------------------------
+    def set_timing(self, enable: bool = True):
+        self._check(self.lib.blm_set_timing(self.h, 1 if enable else 0))
+
+    def timings(self) -> dict:
+        """Durations (ms) of the last call of each phase, from HIP events."""
+        out = np.full(len(TIMING_NAMES), -1.0)
+        self._check(self.lib.blm_get_timings(self.h, _dptr(out), len(out)))
+        return {k: float(v) for k, v in zip(TIMING_NAMES, out)}
+
+    def block_matrices(self, block: int, shift: int = 0):
+        d = C.c_int32()
+        self._check(self.lib.blm_get_block_matrices(self.h, block, shift, None, None, C.byref(d)))
+        H = np.zeros((d.value, d.value))
+        S = np.zeros((d.value, d.value))
+        self._check(self.lib.blm_get_block_matrices(self.h, block, shift, _dptr(H), _dptr(S), C.byref(d)))
+        return H, S
+
+    def directions(self, block: int, shift: int = 0) -> np.ndarray:
+        n = C.c_int32()
+        self._check(self.lib.blm_get_directions(self.h, block, shift, None, C.byref(n)))
+        M = int(self.offsets[block + 1] - self.offsets[block])
+        B = np.zeros((n.value, M))
+        self._check(self.lib.blm_get_directions(self.h, block, shift, _dptr(B), C.byref(n)))
+        return B
+
+    def stage2_matrices(self, shift: int = 0):
+        d = C.c_int32()
+        self._check(self.lib.blm_get_stage2_matrices(self.h, shift, None, None, C.byref(d)))
+        H = np.zeros((d.value, d.value))
+        S = np.zeros((d.value, d.value))
+        self._check(self.lib.blm_get_stage2_matrices(self.h, shift, _dptr(H), _dptr(S), C.byref(d)))
+        return H, S
+
+
+def debug_eigvals(H: torch.Tensor, S: torch.Tensor, stream=None) -> np.ndarray:
+    """All eigenvalues of the pencil (H, S) from the library's eigensolver."""
+    lib = load()
+    _check_f64_dev(H, "H")
+    _check_f64_dev(S, "S")
+    d = H.shape[0]
+    H = H.contiguous()
+    S = S.contiguous()
+    out = np.zeros((d, 2))
+    st = lib.blm_debug_eigvals(C.c_void_p(H.data_ptr()), C.c_void_p(S.data_ptr()), d, _dptr(out),
+                               C.c_void_p(_stream_handle(stream)))
+    if st != BLM_OK:
+        raise BLMError(st, lib.blm_status_string(st).decode())
+    return out[:, 0] + 1j * out[:, 1]

@@ -1,0 +1,1077 @@
+// Host side of libblm: the C ABI declared in include/blm.h, the context and
+// its device workspace, the tile and direction tables, and the small
+// glue kernels (previous-direction orthonormalisation, pencil assembly,
+// update assembly).
+//
+// Workspace layout in HBM (FP64 unless noted):
+//   D        [N_O][N_V]        orthonormalised previous-update pieces (Eq. 9)
+//   Xa, Ya   [max_samples][16] per-sample aux columns [1, t_s] and [E_L, u_s]
+//   accS     per block M_b x M_b  sum_s w O_b O_b^T (upper tiles), then 16x16 aux Gram
+//   accH     per block M_b x M_b  sum_s w O_b e_b^T, then 16x16 aux Gram (X^T W Y)
+//   strips   [3][16][N_V]       aux^T W O, aux^T W e, auxE^T W O   (Fig. 1, coupling strips)
+//   partial  per (tile job, slice group) 3 x 64 x 64 partial tiles
+//   eig      per pencil: S, A, Hq, V (d^2 each), W (2 d^2), vectors, outputs
+//   Yp, Zp   [max_samples][n2] stage-two projections [1, B O_b ...], [E_L, B e_b ...]
+//   G2S, G2H [n2][n2]          stage-two accumulators
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/blm.h"
+#include "blm_internal.h"
+
+using namespace blm;
+
+namespace {
+
+constexpr int ST_CREATED = 0, ST_BEGUN = 1, ST_BUILT = 2, ST_SOLVED = 3, ST_PROJECTED = 4,
+              ST_DONE = 5;
+
+struct AsmJob {
+  int32_t d, M, kind, n_aux;  // kind 0: block, 1: stage two
+  int32_t b, pad;
+  double delta;
+  int64_t off_b;              // first parameter of the block
+  int64_t acc_off;            // block accumulators in accS / accH
+  const int32_t* aux_idx;     // block: aux column of each non-parameter basis entry
+  const int32_t* idx2;        // stage two: joint column of each basis entry
+  double* S;
+  double* A;
+};
+
+struct UpdJob {
+  const double* rows;   // kept directions of (shift, block): [n][M_b]
+  int32_t n;
+  int32_t pad;
+};
+
+}  // namespace
+
+struct blm_ctx {
+  // configuration
+  int64_t NV = 0;
+  int NB = 0, NK = 0, NO = 0, NS = 0, prec = 0;
+  std::vector<int64_t> off;
+  std::vector<double> shifts;
+  int64_t max_samples = 0;
+  hipStream_t st = nullptr;
+  int device = 0;
+  std::string err;
+  int state = ST_CREATED;
+
+  // derived sizes
+  int64_t acc_elems = 0, aux_off = 0;
+  std::vector<int64_t> acc_off;
+  std::vector<int> dmax;           // per block: largest pencil dimension
+  int d2max = 0, n2max = 0;        // stage two
+  int Pcap1 = 1, Pcap2 = 1;
+  int max_slices = 0;
+  int64_t* d_off = nullptr;
+
+  // device buffers
+  std::vector<void*> allocs;
+  double *D = nullptr, *Xa = nullptr, *Ya = nullptr, *accS = nullptr, *accH = nullptr;
+  double *strips = nullptr, *partial = nullptr;
+  int32_t* d_dkeep = nullptr;
+  GramJob *d_jobs1 = nullptr, *d_jobs2 = nullptr;
+  int n_jobs1 = 0, n_jobs2 = 0;
+  Slice* d_slices = nullptr;
+  DirBlock *d_theta_blk = nullptr, *d_dir2_blk = nullptr;
+  const double **d_theta_ptr = nullptr, **d_dir2_ptr = nullptr;
+  int32_t* d_auxlist = nullptr;    // per block: [1 + N_O (N_B - 1)]
+  int auxlist_stride = 0;
+  // eigen workspace: block problems [NS][NB], stage two [NS]
+  std::vector<EigJob> eig1, eig2;
+  EigJob *d_eig1 = nullptr, *d_eig2 = nullptr;
+  AsmJob *d_asm1 = nullptr, *d_asm2 = nullptr, *d_asm_x = nullptr;
+  int32_t *d_info1 = nullptr, *d_info2 = nullptr;
+  double *d_ev1 = nullptr, *d_ev2 = nullptr;
+  double *Yp = nullptr, *Zp = nullptr, *G2S = nullptr, *G2H = nullptr;
+  int32_t* d_idx2 = nullptr;       // [NS][n2max]
+  double *exS = nullptr, *exA = nullptr;  // export scratch
+  UpdJob* d_upd = nullptr;
+  double* d_coef = nullptr;        // [NS][NB][EIG_MAXSEL]
+  int32_t* d_blk_of = nullptr;     // [NV]
+  double* d_wsum = nullptr;        // [2] pass-1 and pass-2 total weight
+
+  // step state
+  std::vector<int> dkeep;          // [NB][NO]
+  std::vector<std::vector<int>> auxlist;   // per block
+  std::vector<int> nkept;          // [NS][NB]
+  std::vector<int> pairkept;       // [NS][NB]
+  int n2 = 0;
+  std::vector<std::vector<int>> idx2;   // per shift
+  int64_t n_pass1 = 0, n_pass2 = 0;
+  std::vector<Slice> h_slices;
+
+  // optional phase timing: event pairs (start, end) per phase
+  bool timing = false;
+  hipEvent_t ev[2 * BLM_N_TIMINGS] = {};
+  bool ev_used[BLM_N_TIMINGS] = {};
+};
+
+namespace {
+
+blm_status fail(blm_ctx* c, blm_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+// Records the start (end == false) or end of phase i on the context's stream.
+void mark(blm_ctx* c, int i, bool end) {
+  if (!c->timing) return;
+  (void)hipEventRecord(c->ev[2 * i + (end ? 1 : 0)], c->st);
+  if (end) c->ev_used[i] = true;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(ctx, BLM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+// ------------------------------------------------------------- kernels ----
+
+// Orthonormalises each block's pieces of the previous updates (Eq. 9):
+// modified Gram-Schmidt over j = 1..N_O; zero or dependent pieces dropped.
+__global__ __launch_bounds__(256) void theta_mgs_kernel(double* D, int64_t NV, int NO,
+                                                        const int64_t* off, int32_t* keep) {
+  __shared__ double red[4];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int64_t o = off[k], m = off[k + 1] - off[k];
+  auto bsum = [&](double v) {
+    for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+  };
+  for (int j = 0; j < NO; ++j) {
+    double* r = D + (size_t)j * NV + o;
+    double p = 0.0;
+    for (int64_t i = tid; i < m; i += 256) p += r[i] * r[i];
+    const double n0 = sqrt(bsum(p));
+    for (int q = 0; q < j; ++q) {
+      if (!keep[k * NO + q]) continue;
+      const double* qv = D + (size_t)q * NV + o;
+      double pd = 0.0;
+      for (int64_t i = tid; i < m; i += 256) pd += qv[i] * r[i];
+      const double dot = bsum(pd);
+      for (int64_t i = tid; i < m; i += 256) r[i] -= dot * qv[i];
+    }
+    p = 0.0;
+    for (int64_t i = tid; i < m; i += 256) p += r[i] * r[i];
+    const double nr = sqrt(bsum(p));
+    const bool ok = n0 > 0.0 && nr >= 1e-12 * n0;
+    const double sc = ok ? 1.0 / nr : 0.0;
+    for (int64_t i = tid; i < m; i += 256) r[i] *= sc;
+    if (tid == 0) keep[k * NO + j] = ok ? 1 : 0;
+    __syncthreads();
+  }
+}
+
+// Pencil assembly from the accumulators, normalised by the total weight,
+// with the diagonal shift on every coordinate but Psi's.
+__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs,
+                                                       const double* __restrict__ accS,
+                                                       const double* __restrict__ accH,
+                                                       const double* __restrict__ strips,
+                                                       int64_t NV, int64_t aux_off,
+                                                       const double* __restrict__ G2S,
+                                                       const double* __restrict__ G2H,
+                                                       int64_t ld2) {
+  const AsmJob J = jobs[blockIdx.x];
+  const int d = J.d;
+  const size_t n = (size_t)d * d;
+  const double W = (J.kind == 0) ? accS[aux_off] : G2S[0];
+  const double inv = 1.0 / W;
+  for (size_t t = (size_t)blockIdx.y * blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.y * blockDim.x) {
+    const int x = (int)(t / d), y = (int)(t % d);
+    double s, h;
+    if (J.kind == 1) {
+      const int a = J.idx2[x], b = J.idx2[y];
+      s = G2S[(size_t)std::min(a, b) * ld2 + std::max(a, b)];
+      h = G2H[(size_t)a * ld2 + b];
+    } else {
+      const int M = J.M;
+      const bool px = (x >= 1 && x <= M), py = (y >= 1 && y <= M);
+      const int ax = (x == 0) ? J.aux_idx[0] : J.aux_idx[x > M ? x - M : 0];
+      const int ay = (y == 0) ? J.aux_idx[0] : J.aux_idx[y > M ? y - M : 0];
+      const int64_t p = x - 1, q = y - 1;
+      const size_t S0 = 0, S1 = (size_t)NAUX * NV, S2 = 2 * (size_t)NAUX * NV;
+      if (px && py) {
+        s = accS[J.acc_off + std::min(p, q) * M + std::max(p, q)];
+        h = accH[J.acc_off + p * M + q];
+      } else if (!px && py) {
+        s = strips[S0 + (size_t)ax * NV + J.off_b + q];
+        h = strips[S1 + (size_t)ax * NV + J.off_b + q];
+      } else if (px && !py) {
+        s = strips[S0 + (size_t)ay * NV + J.off_b + p];
+        h = strips[S2 + (size_t)ay * NV + J.off_b + p];
+      } else {
+        s = accS[aux_off + std::min(ax, ay) * NAUX + std::max(ax, ay)];
+        h = accH[aux_off + ax * NAUX + ay];
+      }
+    }
+    s *= inv;
+    h *= inv;
+    if (x == y && x >= 1) h += J.delta;
+    J.S[t] = s;
+    J.A[t] = h;
+  }
+}
+
+// update[s][x] = sum_r coef[s][b][r] B^(s,b)_r[x - off_b]  (Eq. 8)
+__global__ __launch_bounds__(256) void update_kernel(double* __restrict__ upd, int64_t NV, int NB,
+                                                     int NS, const int64_t* __restrict__ off,
+                                                     const int32_t* __restrict__ blk_of,
+                                                     const UpdJob* __restrict__ uj,
+                                                     const double* __restrict__ coef) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (x >= NV) return;
+  const int b = blk_of[x];
+  const UpdJob U = uj[s * NB + b];
+  const int64_t M = off[b + 1] - off[b], i = x - off[b];
+  double acc = 0.0;
+  for (int r = 0; r < U.n; ++r) acc += coef[((size_t)s * NB + b) * EIG_MAXSEL + r] * U.rows[r * M + i];
+  upd[(size_t)s * NV + x] = acc;
+}
+
+// ------------------------------------------------------------- planning ---
+
+struct Plan {
+  std::vector<std::pair<void**, size_t>> items;
+};
+
+size_t eig_bytes(int d, int nbeta, int nk) {
+  const size_t dd = (size_t)d * d;
+  return 8 * (4 * dd + 2 * dd + 2 * (size_t)EIG_MAXSEL * d + 3 * (size_t)d +
+              (size_t)(nk + 2) * std::max(nbeta, 2 * d));
+}
+
+blm_status validate(const blm_config* cfg, blm_ctx* c) {
+  if (!cfg) return fail(c, BLM_E_ARG, "config is NULL");
+  if (cfg->n_params < 1 || cfg->n_blocks < 1 || !cfg->block_offsets)
+    return fail(c, BLM_E_ARG, "n_params and n_blocks must be >= 1 and block_offsets set");
+  if (cfg->n_keep < 1 || cfg->n_keep + 1 > EIG_MAXSEL)
+    return fail(c, BLM_E_ARG, "n_keep must be in [1, 15]");
+  if (cfg->n_old < 0 || 1 + (int64_t)cfg->n_old * cfg->n_blocks > NAUX)
+    return fail(c, BLM_E_ARG, "1 + n_old * n_blocks must be <= 16");
+  if (cfg->n_shifts < 1 || !cfg->shifts) return fail(c, BLM_E_ARG, "need at least one shift");
+  for (int i = 0; i < cfg->n_shifts; ++i)
+    if (!(cfg->shifts[i] >= 0.0) || !std::isfinite(cfg->shifts[i]))
+      return fail(c, BLM_E_ARG, "shifts must be finite and >= 0");
+  if (cfg->precision != BLM_PREC_F64) return fail(c, BLM_E_ARG, "unsupported precision");
+  if (cfg->max_samples < 1) return fail(c, BLM_E_ARG, "max_samples must be >= 1");
+  if (cfg->block_offsets[0] != 0 || cfg->block_offsets[cfg->n_blocks] != cfg->n_params)
+    return fail(c, BLM_E_ARG, "block_offsets must run from 0 to n_params");
+  for (int b = 0; b < cfg->n_blocks; ++b) {
+    if (cfg->block_offsets[b + 1] <= cfg->block_offsets[b])
+      return fail(c, BLM_E_ARG, "block_offsets must be strictly ascending");
+    const int64_t d = 1 + (cfg->block_offsets[b + 1] - cfg->block_offsets[b]) +
+                      (int64_t)cfg->n_old * (cfg->n_blocks - 1);
+    if (d > EIG_MAXD) return fail(c, BLM_E_ARG, "a block pencil exceeds 4096 dimensions");
+  }
+  const int64_t d2 = 1 + (int64_t)cfg->n_blocks * (cfg->n_keep + 1);
+  if (d2 > EIG_MAXD) return fail(c, BLM_E_ARG, "the stage-two pencil exceeds 4096 dimensions");
+  return BLM_OK;
+}
+
+// Fills the derived sizes and the list of allocations (pointer slot, bytes).
+void plan(blm_ctx* c, Plan& P) {
+  const int NB = c->NB, NO = c->NO, NK = c->NK, NS = c->NS;
+  const int64_t NV = c->NV;
+  c->acc_off.assign(NB, 0);
+  int64_t run = 0;
+  c->dmax.assign(NB, 0);
+  int n_jobs1 = 0;
+  for (int b = 0; b < NB; ++b) {
+    const int64_t M = c->off[b + 1] - c->off[b];
+    c->acc_off[b] = run;
+    run += M * M;
+    c->dmax[b] = (int)(1 + M + (int64_t)NO * (NB - 1));
+    const int T = (int)((M + GT - 1) / GT);
+    n_jobs1 += T * (T + 1) / 2;
+  }
+  c->aux_off = run;
+  run += NAUX * NAUX;
+  c->acc_elems = run;
+  c->n_jobs1 = n_jobs1 + 1;
+  c->n2max = 1 + NS * NB * (NK + 1);
+  c->d2max = 1 + NB * (NK + 1);
+  const int T2 = (c->n2max + GT - 1) / GT;
+  const int n_jobs2max = T2 * (T2 + 1) / 2;
+  c->Pcap1 = std::max(1, std::min(64, (4096 + c->n_jobs1 - 1) / c->n_jobs1));
+  c->Pcap2 = std::max(1, std::min(64, (4096 + n_jobs2max - 1) / n_jobs2max));
+  const size_t slots = std::max((size_t)c->n_jobs1 * c->Pcap1, (size_t)n_jobs2max * c->Pcap2);
+  c->max_slices = (int)(c->max_samples / SLICE) + 1024;
+  c->auxlist_stride = 1 + NO * (NB - 1);
+
+  auto add = [&](void** slot, size_t bytes) { P.items.push_back({slot, std::max<size_t>(bytes, 8)}); };
+  add((void**)&c->D, 8 * (size_t)std::max(NO, 1) * NV);
+  add((void**)&c->d_dkeep, 4 * (size_t)std::max(NO * NB, 1));
+  add((void**)&c->Xa, 8 * (size_t)c->max_samples * NAUX);
+  add((void**)&c->Ya, 8 * (size_t)c->max_samples * NAUX);
+  add((void**)&c->accS, 8 * (size_t)c->acc_elems);
+  add((void**)&c->accH, 8 * (size_t)c->acc_elems);
+  add((void**)&c->strips, 8 * (size_t)3 * NAUX * NV);
+  add((void**)&c->partial, 8 * slots * 3 * GT * GT);
+  add((void**)&c->d_off, 8 * (size_t)(NB + 1));
+  add((void**)&c->d_jobs1, sizeof(GramJob) * (size_t)c->n_jobs1);
+  add((void**)&c->d_jobs2, sizeof(GramJob) * (size_t)n_jobs2max);
+  add((void**)&c->d_slices, sizeof(Slice) * (size_t)c->max_slices);
+  add((void**)&c->d_theta_blk, sizeof(DirBlock) * (size_t)NB);
+  add((void**)&c->d_theta_ptr, sizeof(double*) * (size_t)std::max(NO * NB, 1));
+  add((void**)&c->d_dir2_blk, sizeof(DirBlock) * (size_t)NB);
+  add((void**)&c->d_dir2_ptr, sizeof(double*) * (size_t)c->n2max);
+  add((void**)&c->d_auxlist, 4 * (size_t)NB * c->auxlist_stride);
+  add((void**)&c->d_eig1, sizeof(EigJob) * (size_t)NS * NB);
+  add((void**)&c->d_eig2, sizeof(EigJob) * (size_t)NS);
+  add((void**)&c->d_asm1, sizeof(AsmJob) * (size_t)NS * NB);
+  add((void**)&c->d_asm2, sizeof(AsmJob) * (size_t)NS);
+  add((void**)&c->d_asm_x, sizeof(AsmJob));
+  add((void**)&c->d_info1, 16 * (size_t)NS * NB);
+  add((void**)&c->d_info2, 16 * (size_t)NS);
+  add((void**)&c->d_ev1, 16 * (size_t)NS * NB * (NK + 1));
+  add((void**)&c->d_ev2, 16 * (size_t)NS * 2);
+  add((void**)&c->Yp, 8 * (size_t)c->max_samples * c->n2max);
+  add((void**)&c->Zp, 8 * (size_t)c->max_samples * c->n2max);
+  add((void**)&c->G2S, 8 * (size_t)c->n2max * c->n2max);
+  add((void**)&c->G2H, 8 * (size_t)c->n2max * c->n2max);
+  add((void**)&c->d_idx2, 4 * (size_t)NS * c->n2max);
+  int dx = c->d2max;
+  for (int b = 0; b < NB; ++b) dx = std::max(dx, c->dmax[b]);
+  add((void**)&c->exS, 8 * (size_t)dx * dx);
+  add((void**)&c->exA, 8 * (size_t)dx * dx);
+  add((void**)&c->d_upd, sizeof(UpdJob) * (size_t)NS * NB);
+  add((void**)&c->d_coef, 8 * (size_t)NS * NB * EIG_MAXSEL);
+  add((void**)&c->d_blk_of, 4 * (size_t)NV);
+  add((void**)&c->d_wsum, 16);
+}
+
+size_t eig_total_bytes(const blm_ctx* c) {
+  size_t t = 0;
+  for (int s = 0; s < c->NS; ++s) {
+    for (int b = 0; b < c->NB; ++b)
+      t += eig_bytes(c->dmax[b], (int)(c->off[b + 1] - c->off[b]), c->NK);
+    t += eig_bytes(c->d2max, c->d2max, 1);
+  }
+  return t;
+}
+
+// Carves one pencil's workspace from a contiguous allocation.
+EigJob carve(double*& p, int d, int nbeta, int nk, int mode, int want, int beta0,
+             int32_t* info, double* ev) {
+  EigJob J{};
+  const size_t dd = (size_t)d * d;
+  J.d = d;
+  J.mode = mode;
+  J.n_want = want;
+  J.beta0 = beta0;
+  J.nbeta = nbeta;
+  J.S = p; p += dd;
+  J.A = p; p += dd;
+  J.Hq = p; p += dd;
+  J.V = p; p += dd;
+  J.W = p; p += 2 * dd;
+  J.vec = p; p += 2 * (size_t)EIG_MAXSEL * d;
+  J.wr = p; p += d;
+  J.wi = p; p += d;
+  J.tau = p; p += d;
+  J.out = p; p += (size_t)(nk + 2) * std::max(nbeta, 2 * d);
+  J.out_evals = ev;
+  J.info = info;
+  return J;
+}
+
+blm_status upload_gram_jobs1(blm_ctx* c) {
+  std::vector<GramJob> jobs;
+  for (int b = 0; b < c->NB; ++b) {
+    const int64_t M = c->off[b + 1] - c->off[b];
+    const int T = (int)((M + GT - 1) / GT);
+    for (int ti = 0; ti < T; ++ti)
+      for (int tj = ti; tj < T; ++tj) {
+        GramJob J{};
+        J.kind = (ti == tj) ? JOB_DIAG : JOB_OFF;
+        J.mi = (int)std::min<int64_t>(GT, M - (int64_t)GT * ti);
+        J.nj = (int)std::min<int64_t>(GT, M - (int64_t)GT * tj);
+        J.ci = c->off[b] + (int64_t)GT * ti;
+        J.cj = c->off[b] + (int64_t)GT * tj;
+        J.s_off = c->acc_off[b] + (int64_t)GT * ti * M + (int64_t)GT * tj;
+        J.h_off = J.s_off;
+        J.ht_off = c->acc_off[b] + (int64_t)GT * tj * M + (int64_t)GT * ti;
+        J.ld_out = M;
+        J.strip_col = J.ci;
+        jobs.push_back(J);
+      }
+  }
+  GramJob A{};
+  A.kind = JOB_AUX;
+  A.mi = A.nj = NAUX;
+  A.s_off = A.h_off = c->aux_off;
+  A.ld_out = NAUX;
+  jobs.push_back(A);
+  c->n_jobs1 = (int)jobs.size();
+  HIPCHK(c, hipMemcpy(c->d_jobs1, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice));
+  return BLM_OK;
+}
+
+int choose_P(int cap, int n_jobs, int n_slices) {
+  int P = (4096 + n_jobs - 1) / n_jobs;
+  P = std::min(P, cap);
+  P = std::min(P, std::max(1, n_slices));
+  return std::max(P, 1);
+}
+
+blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) {
+  if (n < 0 || (n > 0 && !ch)) return fail(c, BLM_E_ARG, "bad chunk list");
+  int64_t t = 0;
+  for (int i = 0; i < n; ++i) {
+    if (ch[i].n_samples < 0) return fail(c, BLM_E_ARG, "negative n_samples");
+    if (ch[i].n_samples == 0) continue;
+    if (ch[i].ld < c->NV) return fail(c, BLM_E_ARG, "chunk ld < n_params");
+    if (!ch[i].O || !ch[i].e || !ch[i].E_L) return fail(c, BLM_E_ARG, "chunk pointer is NULL");
+    t += ch[i].n_samples;
+  }
+  if (t > c->max_samples) return fail(c, BLM_E_ARG, "more samples in one call than max_samples");
+  *total = t;
+  return BLM_OK;
+}
+
+blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_base,
+                    double* h_base, double* strip_base, int phase) {
+  const int n_slices = (int)c->h_slices.size();
+  if (n_slices == 0) return BLM_OK;
+  if (n_slices > c->max_slices) return fail(c, BLM_E_ARG, "too many slices in one call");
+  HIPCHK(c, hipMemcpyAsync(c->d_slices, c->h_slices.data(), sizeof(Slice) * n_slices,
+                           hipMemcpyHostToDevice, c->st));
+  const int P = choose_P(cap, n_jobs, n_slices);
+  mark(c, phase, false);
+  launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, c->partial, c->st);
+  HIPCHK(c, hipGetLastError());
+  mark(c, phase, true);
+  mark(c, phase + 1, false);
+  launch_gram_reduce(d_jobs, n_jobs, P, c->partial, s_base, h_base, strip_base, c->NV, c->st);
+  HIPCHK(c, hipGetLastError());
+  mark(c, phase + 1, true);
+  return BLM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* blm_status_string(blm_status s) {
+  switch (s) {
+    case BLM_OK: return "ok";
+    case BLM_E_ARG: return "invalid argument";
+    case BLM_E_STATE: return "call out of order or inconsistent passes";
+    case BLM_E_HIP: return "HIP runtime error";
+    case BLM_E_NOMEM: return "out of device memory";
+    case BLM_E_S_NOT_PD: return "overlap matrix not positive definite";
+    case BLM_E_NONFINITE: return "non-finite value in an eigenproblem";
+    case BLM_E_NOCONV: return "QR iteration did not converge";
+  }
+  return "unknown status";
+}
+
+const char* blm_last_error(const blm_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes) {
+  blm_ctx tmp;
+  blm_status s = validate(cfg, &tmp);
+  if (s != BLM_OK) return s;
+  if (!bytes) return BLM_E_ARG;
+  tmp.NV = cfg->n_params;
+  tmp.NB = cfg->n_blocks;
+  tmp.NK = cfg->n_keep;
+  tmp.NO = cfg->n_old;
+  tmp.NS = cfg->n_shifts;
+  tmp.off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
+  tmp.max_samples = cfg->max_samples;
+  Plan P;
+  plan(&tmp, P);
+  size_t t = 0;
+  for (auto& it : P.items) t += (it.second + 255) / 256 * 256;
+  *bytes = t + eig_total_bytes(&tmp);
+  return BLM_OK;
+}
+
+blm_status blm_set_timing(blm_ctx* c, int32_t enable) {
+  if (!c) return BLM_E_ARG;
+  if (enable && !c->timing) {
+    for (auto& e : c->ev)
+      if (!e) HIPCHK(c, hipEventCreate(&e));
+  }
+  c->timing = enable != 0;
+  return BLM_OK;
+}
+
+blm_status blm_get_timings(blm_ctx* c, double* h_ms, int32_t n) {
+  if (!c || !h_ms || n < 0) return BLM_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int i = 0; i < n && i < BLM_N_TIMINGS; ++i) {
+    h_ms[i] = -1.0;
+    if (!c->ev_used[i]) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess) h_ms[i] = ms;
+  }
+  return BLM_OK;
+}
+
+blm_status blm_destroy(blm_ctx* c) {
+  if (!c) return BLM_OK;
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (void* p : c->allocs) (void)hipFree(p);
+  delete c;
+  return BLM_OK;
+}
+
+blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
+  if (!out) return BLM_E_ARG;
+  *out = nullptr;
+  blm_ctx* c = new blm_ctx();
+  blm_status s = validate(cfg, c);
+  if (s != BLM_OK) {
+    delete c;
+    return s;
+  }
+  c->NV = cfg->n_params;
+  c->NB = cfg->n_blocks;
+  c->NK = cfg->n_keep;
+  c->NO = cfg->n_old;
+  c->NS = cfg->n_shifts;
+  c->prec = cfg->precision;
+  c->off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
+  c->shifts.assign(cfg->shifts, cfg->shifts + cfg->n_shifts);
+  c->max_samples = cfg->max_samples;
+  c->st = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return BLM_E_HIP;
+  }
+  Plan P;
+  plan(c, P);
+  for (auto& it : P.items) {
+    void* p = nullptr;
+    if (hipMalloc(&p, it.second) != hipSuccess) {
+      blm_destroy(c);
+      return BLM_E_NOMEM;
+    }
+    c->allocs.push_back(p);
+    *it.first = p;
+  }
+  // eigen workspaces
+  {
+    void* p = nullptr;
+    if (hipMalloc(&p, eig_total_bytes(c)) != hipSuccess) {
+      blm_destroy(c);
+      return BLM_E_NOMEM;
+    }
+    c->allocs.push_back(p);
+    double* q = (double*)p;
+    for (int sh = 0; sh < c->NS; ++sh)
+      for (int b = 0; b < c->NB; ++b) {
+        const int M = (int)(c->off[b + 1] - c->off[b]);
+        const int i = sh * c->NB + b;
+        double* start = q;
+        c->eig1.push_back(carve(q, c->dmax[b], M, c->NK, EIG_BLOCK, c->NK, 1, c->d_info1 + 4 * i,
+                                c->d_ev1 + 2 * (size_t)i * (c->NK + 1)));
+        q = start + eig_bytes(c->dmax[b], M, c->NK) / 8;
+      }
+    for (int sh = 0; sh < c->NS; ++sh) {
+      double* start = q;
+      c->eig2.push_back(carve(q, c->d2max, c->d2max, 1, EIG_STAGE2, 1, 0, c->d_info2 + 4 * sh,
+                              c->d_ev2 + 4 * (size_t)sh));
+      q = start + eig_bytes(c->d2max, c->d2max, 1) / 8;
+    }
+  }
+  blm_status r = upload_gram_jobs1(c);
+  if (r != BLM_OK) {
+    blm_destroy(c);
+    return r;
+  }
+  // static tables: block of each parameter, offsets
+  {
+    std::vector<int32_t> blk(c->NV);
+    for (int b = 0; b < c->NB; ++b)
+      for (int64_t x = c->off[b]; x < c->off[b + 1]; ++x) blk[x] = b;
+    if (hipMemcpy(c->d_blk_of, blk.data(), 4 * (size_t)c->NV, hipMemcpyHostToDevice) != hipSuccess) {
+      blm_destroy(c);
+      return BLM_E_HIP;
+    }
+    (void)hipMemcpy(c->d_off, c->off.data(), 8 * (c->NB + 1), hipMemcpyHostToDevice);
+    // theta direction table (fixed): block k, rows j of D
+    std::vector<DirBlock> tb(c->NB);
+    std::vector<const double*> tp((size_t)std::max(c->NO * c->NB, 1), nullptr);
+    for (int k = 0; k < c->NB; ++k) {
+      tb[k].col0 = c->off[k];
+      tb[k].m = (int)(c->off[k + 1] - c->off[k]);
+      tb[k].d0 = k * c->NO;
+      tb[k].nd = c->NO;
+      for (int j = 0; j < c->NO; ++j) tp[k * c->NO + j] = c->D + (size_t)j * c->NV + c->off[k];
+    }
+    (void)hipMemcpy(c->d_theta_blk, tb.data(), sizeof(DirBlock) * c->NB, hipMemcpyHostToDevice);
+    (void)hipMemcpy(c->d_theta_ptr, tp.data(), sizeof(double*) * tp.size(), hipMemcpyHostToDevice);
+  }
+  *out = c;
+  return BLM_OK;
+}
+
+static const int64_t* dev_offsets(const blm_ctx* c) { return c->d_off; }
+
+blm_status blm_begin_step(blm_ctx* c, const double* d_old) {
+  if (!c) return BLM_E_ARG;
+  HIPCHK(c, hipMemsetAsync(c->accS, 0, 8 * (size_t)c->acc_elems, c->st));
+  HIPCHK(c, hipMemsetAsync(c->accH, 0, 8 * (size_t)c->acc_elems, c->st));
+  HIPCHK(c, hipMemsetAsync(c->strips, 0, 8 * (size_t)3 * NAUX * c->NV, c->st));
+  c->dkeep.assign((size_t)c->NB * c->NO, 0);
+  if (c->NO > 0) {
+    if (d_old) {
+      HIPCHK(c, hipMemcpyAsync(c->D, d_old, 8 * (size_t)c->NO * c->NV, hipMemcpyDeviceToDevice, c->st));
+      hipLaunchKernelGGL(theta_mgs_kernel, dim3(c->NB), dim3(256), 0, c->st, c->D, c->NV, c->NO,
+                         dev_offsets(c), c->d_dkeep);
+      HIPCHK(c, hipGetLastError());
+      std::vector<int32_t> k((size_t)c->NB * c->NO);
+      HIPCHK(c, hipMemcpyAsync(k.data(), c->d_dkeep, 4 * k.size(), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+      for (size_t i = 0; i < k.size(); ++i) c->dkeep[i] = k[i];
+    } else {
+      HIPCHK(c, hipMemsetAsync(c->D, 0, 8 * (size_t)c->NO * c->NV, c->st));
+    }
+  }
+  // per-block aux lists: [0] then Theta_(k,j) for k != b, k-major
+  c->auxlist.assign(c->NB, {});
+  std::vector<int32_t> flat((size_t)c->NB * c->auxlist_stride, 0);
+  for (int b = 0; b < c->NB; ++b) {
+    auto& L = c->auxlist[b];
+    L.push_back(0);
+    for (int k = 0; k < c->NB; ++k) {
+      if (k == b) continue;
+      for (int j = 0; j < c->NO; ++j)
+        if (c->dkeep[k * c->NO + j]) L.push_back(1 + k * c->NO + j);
+    }
+    std::copy(L.begin(), L.end(), flat.begin() + (size_t)b * c->auxlist_stride);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_auxlist, flat.data(), 4 * flat.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->n_pass1 = c->n_pass2 = 0;
+  c->state = ST_BEGUN;
+  return BLM_OK;
+}
+
+blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
+  if (!c) return BLM_E_ARG;
+  if (c->state != ST_BEGUN && c->state != ST_BUILT)
+    return fail(c, BLM_E_STATE, "blm_build_blocks needs blm_begin_step first");
+  int64_t total = 0;
+  blm_status s = check_chunks(c, ch, n, &total);
+  if (s != BLM_OK) return s;
+  c->h_slices.clear();
+  int64_t rb = 0;
+  mark(c, 0, false);
+  for (int i = 0; i < n; ++i) {
+    const int64_t ns = ch[i].n_samples;
+    if (ns == 0) continue;
+    launch_dirproj(ch[i].O, ch[i].e, ch[i].E_L, ch[i].ld, ns, c->d_theta_blk, c->NO > 0 ? c->NB : 0,
+                   c->d_theta_ptr, c->NO * c->NB, c->Xa + (size_t)rb * NAUX,
+                   c->Ya + (size_t)rb * NAUX, NAUX, c->st);
+    HIPCHK(c, hipGetLastError());
+    for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
+      Slice S{};
+      S.O = ch[i].O + (size_t)s0 * ch[i].ld;
+      S.e = ch[i].e + (size_t)s0 * ch[i].ld;
+      S.Xa = c->Xa + (size_t)(rb + s0) * NAUX;
+      S.Ya = c->Ya + (size_t)(rb + s0) * NAUX;
+      S.w = ch[i].w ? ch[i].w + s0 : nullptr;
+      S.ld = ch[i].ld;
+      S.n = std::min<int64_t>(SLICE, ns - s0);
+      c->h_slices.push_back(S);
+    }
+    rb += ns;
+  }
+  mark(c, 0, true);
+  s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1);
+  if (s != BLM_OK) return s;
+  c->n_pass1 += total;
+  c->state = ST_BUILT;
+  return BLM_OK;
+}
+
+static blm_status eig_status(blm_ctx* c, int st, const char* what) {
+  if (st == EIG_OK) return BLM_OK;
+  char buf[160];
+  const char* m = st == EIG_NOT_PD ? "overlap not positive definite"
+                  : st == EIG_NONFINITE ? "non-finite values" : "QR did not converge";
+  snprintf(buf, sizeof buf, "%s: %s", what, m);
+  c->err = buf;
+  return st == EIG_NOT_PD ? BLM_E_S_NOT_PD : st == EIG_NONFINITE ? BLM_E_NONFINITE : BLM_E_NOCONV;
+}
+
+blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
+  if (!c) return BLM_E_ARG;
+  if (c->state != ST_BUILT) return fail(c, BLM_E_STATE, "blm_solve_blocks needs blm_build_blocks first");
+  const int NB = c->NB, NS = c->NS, NK = c->NK;
+  std::vector<AsmJob> asmj;
+  std::vector<EigJob> ej = c->eig1;
+  int dm = 1;
+  for (int sh = 0; sh < NS; ++sh)
+    for (int b = 0; b < NB; ++b) {
+      const int M = (int)(c->off[b + 1] - c->off[b]);
+      const int d = 1 + M + (int)c->auxlist[b].size() - 1;
+      AsmJob A{};
+      A.d = d;
+      A.M = M;
+      A.kind = 0;
+      A.b = b;
+      A.n_aux = (int)c->auxlist[b].size();
+      A.delta = c->shifts[sh];
+      A.off_b = c->off[b];
+      A.acc_off = c->acc_off[b];
+      A.aux_idx = c->d_auxlist + (size_t)b * c->auxlist_stride;
+      EigJob& J = ej[sh * NB + b];
+      J.d = d;
+      A.S = J.S;
+      A.A = J.A;
+      asmj.push_back(A);
+      dm = std::max(dm, d);
+    }
+  HIPCHK(c, hipMemcpyAsync(c->d_asm1, asmj.data(), sizeof(AsmJob) * asmj.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->d_eig1, ej.data(), sizeof(EigJob) * ej.size(), hipMemcpyHostToDevice, c->st));
+  const int gy = std::min(256, std::max(1, (int)(((size_t)dm * dm + 255) / 256 / 8)));
+  mark(c, 3, false);
+  hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)asmj.size(), gy), dim3(256), 0, c->st, c->d_asm1,
+                     c->accS, c->accH, c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2max);
+  HIPCHK(c, hipGetLastError());
+  mark(c, 3, true);
+  mark(c, 4, false);
+  launch_eig(c->d_eig1, (int)ej.size(), c->st);
+  HIPCHK(c, hipGetLastError());
+  mark(c, 4, true);
+  std::vector<int32_t> info((size_t)4 * NS * NB);
+  std::vector<double> ev((size_t)2 * NS * NB * (NK + 1));
+  HIPCHK(c, hipMemcpyAsync(info.data(), c->d_info1, 4 * info.size(), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(ev.data(), c->d_ev1, 8 * ev.size(), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->nkept.assign((size_t)NS * NB, 0);
+  c->pairkept.assign((size_t)NS * NB, 0);
+  for (int i = 0; i < NS * NB; ++i) {
+    char what[64];
+    snprintf(what, sizeof what, "block %d, shift %d", i % NB, i / NB);
+    blm_status s = eig_status(c, info[4 * i], what);
+    if (s != BLM_OK) return s;
+    c->nkept[i] = info[4 * i + 1];
+    c->pairkept[i] = info[4 * i + 2];
+  }
+  if (h_evals) std::copy(ev.begin(), ev.end(), h_evals);
+  if (h_kept) std::copy(c->nkept.begin(), c->nkept.end(), h_kept);
+
+  // stage-two tables: joint directions ordered block, shift, row
+  std::vector<DirBlock> db(NB);
+  std::vector<const double*> dp;
+  std::vector<std::vector<int>> pos((size_t)NS * NB);
+  for (int k = 0; k < NB; ++k) {
+    const int M = (int)(c->off[k + 1] - c->off[k]);
+    db[k].col0 = c->off[k];
+    db[k].m = M;
+    db[k].d0 = (int)dp.size();
+    for (int sh = 0; sh < NS; ++sh) {
+      const EigJob& J = c->eig1[sh * NB + k];
+      for (int r = 0; r < c->nkept[sh * NB + k]; ++r) {
+        pos[sh * NB + k].push_back(1 + (int)dp.size());
+        dp.push_back(J.out + (size_t)r * M);
+      }
+    }
+    db[k].nd = (int)dp.size() - db[k].d0;
+  }
+  c->n2 = 1 + (int)dp.size();
+  c->idx2.assign(NS, {});
+  std::vector<int32_t> flat((size_t)NS * c->n2max, 0);
+  for (int sh = 0; sh < NS; ++sh) {
+    auto& I = c->idx2[sh];
+    I.push_back(0);
+    for (int k = 0; k < NB; ++k)
+      for (int p : pos[sh * NB + k]) I.push_back(p);
+    std::copy(I.begin(), I.end(), flat.begin() + (size_t)sh * c->n2max);
+  }
+  std::vector<GramJob> jobs;
+  const int n2 = c->n2, T = (n2 + GT - 1) / GT;
+  for (int ti = 0; ti < T; ++ti)
+    for (int tj = ti; tj < T; ++tj) {
+      GramJob J{};
+      J.kind = (ti == tj) ? JOB_DIAG_NOSTRIP : JOB_OFF;
+      J.mi = std::min(GT, n2 - GT * ti);
+      J.nj = std::min(GT, n2 - GT * tj);
+      J.ci = (int64_t)GT * ti;
+      J.cj = (int64_t)GT * tj;
+      J.s_off = (int64_t)GT * ti * n2 + (int64_t)GT * tj;
+      J.h_off = J.s_off;
+      J.ht_off = (int64_t)GT * tj * n2 + (int64_t)GT * ti;
+      J.ld_out = n2;
+      jobs.push_back(J);
+    }
+  c->n_jobs2 = (int)jobs.size();
+  HIPCHK(c, hipMemcpyAsync(c->d_dir2_blk, db.data(), sizeof(DirBlock) * NB, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->d_dir2_ptr, dp.data(), sizeof(double*) * std::max<size_t>(dp.size(), 1),
+                           hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->d_idx2, flat.data(), 4 * flat.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->d_jobs2, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemsetAsync(c->G2S, 0, 8 * (size_t)n2 * n2, c->st));
+  HIPCHK(c, hipMemsetAsync(c->G2H, 0, 8 * (size_t)n2 * n2, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->n_pass2 = 0;
+  c->state = ST_SOLVED;
+  return BLM_OK;
+}
+
+blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
+  if (!c) return BLM_E_ARG;
+  if (c->state != ST_SOLVED && c->state != ST_PROJECTED)
+    return fail(c, BLM_E_STATE, "blm_project needs blm_solve_blocks first");
+  int64_t total = 0;
+  blm_status s = check_chunks(c, ch, n, &total);
+  if (s != BLM_OK) return s;
+  const int64_t ldo = c->n2;
+  c->h_slices.clear();
+  int64_t rb = 0;
+  mark(c, 5, false);
+  for (int i = 0; i < n; ++i) {
+    const int64_t ns = ch[i].n_samples;
+    if (ns == 0) continue;
+    launch_dirproj(ch[i].O, ch[i].e, ch[i].E_L, ch[i].ld, ns, c->d_dir2_blk, c->NB, c->d_dir2_ptr,
+                   c->n2 - 1, c->Yp + (size_t)rb * ldo, c->Zp + (size_t)rb * ldo, ldo, c->st);
+    HIPCHK(c, hipGetLastError());
+    for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
+      Slice S{};
+      S.O = c->Yp + (size_t)(rb + s0) * ldo;
+      S.e = c->Zp + (size_t)(rb + s0) * ldo;
+      S.w = ch[i].w ? ch[i].w + s0 : nullptr;
+      S.ld = ldo;
+      S.n = std::min<int64_t>(SLICE, ns - s0);
+      c->h_slices.push_back(S);
+    }
+    rb += ns;
+  }
+  mark(c, 5, true);
+  s = run_gram(c, c->d_jobs2, c->n_jobs2, c->Pcap2, c->G2S, c->G2H, nullptr, 6);
+  if (s != BLM_OK) return s;
+  c->n_pass2 += total;
+  c->state = ST_PROJECTED;
+  return BLM_OK;
+}
+
+blm_status blm_stage2(blm_ctx* c, double* d_update, double* h_energy, double* h_alpha,
+                      uint32_t* h_flags) {
+  if (!c) return BLM_E_ARG;
+  if (c->state != ST_PROJECTED) return fail(c, BLM_E_STATE, "blm_stage2 needs blm_project first");
+  if (c->n_pass2 != c->n_pass1)
+    return fail(c, BLM_E_STATE, "pass 2 saw a different number of samples than pass 1");
+  const int NS = c->NS, NB = c->NB;
+  double w1 = 0.0, w2 = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&w1, c->accS + c->aux_off, 8, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(&w2, c->G2S, 8, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (!(std::fabs(w1 - w2) <= 1e-12 * std::fabs(w1)) || !(w1 > 0.0))
+    return fail(c, BLM_E_STATE, "pass 2 total weight differs from pass 1 (or is not positive)");
+  std::vector<AsmJob> asmj;
+  std::vector<EigJob> ej = c->eig2;
+  int dm = 1;
+  for (int sh = 0; sh < NS; ++sh) {
+    const int d = (int)c->idx2[sh].size();
+    AsmJob A{};
+    A.d = d;
+    A.kind = 1;
+    A.delta = c->shifts[sh];
+    A.idx2 = c->d_idx2 + (size_t)sh * c->n2max;
+    ej[sh].d = d;
+    A.S = ej[sh].S;
+    A.A = ej[sh].A;
+    asmj.push_back(A);
+    dm = std::max(dm, d);
+  }
+  mark(c, 8, false);
+  HIPCHK(c, hipMemcpyAsync(c->d_asm2, asmj.data(), sizeof(AsmJob) * NS, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->d_eig2, ej.data(), sizeof(EigJob) * NS, hipMemcpyHostToDevice, c->st));
+  const int gy = std::min(64, std::max(1, (int)(((size_t)dm * dm + 255) / 256 / 8)));
+  hipLaunchKernelGGL(assemble_kernel, dim3(NS, gy), dim3(256), 0, c->st, c->d_asm2, c->accS, c->accH,
+                     c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2);
+  HIPCHK(c, hipGetLastError());
+  launch_eig(c->d_eig2, NS, c->st);
+  HIPCHK(c, hipGetLastError());
+  std::vector<int32_t> info((size_t)4 * NS);
+  std::vector<double> ev((size_t)4 * NS);
+  HIPCHK(c, hipMemcpyAsync(info.data(), c->d_info2, 4 * info.size(), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(ev.data(), c->d_ev2, 8 * ev.size(), hipMemcpyDeviceToHost, c->st));
+  std::vector<std::vector<double>> vecs(NS);
+  for (int sh = 0; sh < NS; ++sh) {
+    vecs[sh].resize(2 * (size_t)ej[sh].d);
+    HIPCHK(c, hipMemcpyAsync(vecs[sh].data(), ej[sh].out, 8 * vecs[sh].size(), hipMemcpyDeviceToHost, c->st));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  std::vector<double> coef((size_t)NS * NB * EIG_MAXSEL, 0.0);
+  std::vector<UpdJob> uj((size_t)NS * NB);
+  for (int sh = 0; sh < NS; ++sh) {
+    char what[64];
+    snprintf(what, sizeof what, "stage two, shift %d", sh);
+    blm_status s = eig_status(c, info[4 * sh], what);
+    if (s != BLM_OK) return s;
+    const int d = ej[sh].d;
+    const double* vr = vecs[sh].data();
+    const double* vi = vr + d;
+    // alpha = c_0; coefficient of kept row = Re(c_i / alpha)
+    const double ar = vr[0], ai = vi[0];
+    const double den = ar * ar + ai * ai;
+    double nrm = 0.0;
+    for (int i = 0; i < d; ++i) nrm += vr[i] * vr[i] + vi[i] * vi[i];
+    nrm = std::sqrt(nrm);
+    int at = 1;
+    for (int b = 0; b < NB; ++b) {
+      const int nk = c->nkept[sh * NB + b];
+      uj[sh * NB + b].rows = c->eig1[sh * NB + b].out;
+      uj[sh * NB + b].n = nk;
+      for (int r = 0; r < nk; ++r, ++at)
+        coef[((size_t)sh * NB + b) * EIG_MAXSEL + r] = (vr[at] * ar + vi[at] * ai) / den;
+    }
+    uint32_t fl = 0;
+    if (ev[4 * sh + 1] != 0.0) fl |= BLM_FLAG_COMPLEX_ENERGY;
+    for (int b = 0; b < NB; ++b)
+      if (c->pairkept[sh * NB + b]) fl |= BLM_FLAG_PAIR_KEPT;
+    const double ra = std::sqrt(den) / (nrm > 0 ? nrm : 1.0);
+    if (ra < 1e-8) fl |= BLM_FLAG_SMALL_ALPHA;
+    if (h_energy) h_energy[sh] = ev[4 * sh];
+    if (h_alpha) h_alpha[sh] = ra;
+    if (h_flags) h_flags[sh] = fl;
+  }
+  if (d_update) {
+    HIPCHK(c, hipMemcpyAsync(c->d_coef, coef.data(), 8 * coef.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->d_upd, uj.data(), sizeof(UpdJob) * uj.size(), hipMemcpyHostToDevice, c->st));
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)((c->NV + 255) / 256), NS), dim3(256), 0, c->st,
+                       d_update, c->NV, NB, NS, dev_offsets(c), c->d_blk_of, c->d_upd, c->d_coef);
+    HIPCHK(c, hipGetLastError());
+  }
+  mark(c, 8, true);
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->state = ST_DONE;
+  return BLM_OK;
+}
+
+blm_status blm_get_block_matrices(blm_ctx* c, int32_t block, int32_t shift, double* h_H, double* h_S,
+                                  int32_t* dim) {
+  if (!c || !dim) return BLM_E_ARG;
+  if (block < 0 || block >= c->NB || shift < 0 || shift >= c->NS) return fail(c, BLM_E_ARG, "bad index");
+  if (c->state < ST_BUILT) return fail(c, BLM_E_STATE, "no block estimates yet");
+  const int M = (int)(c->off[block + 1] - c->off[block]);
+  const int d = M + (int)c->auxlist[block].size();
+  *dim = d;
+  if (!h_H && !h_S) return BLM_OK;
+  AsmJob A{};
+  A.d = d;
+  A.M = M;
+  A.kind = 0;
+  A.b = block;
+  A.n_aux = (int)c->auxlist[block].size();
+  A.delta = c->shifts[shift];
+  A.off_b = c->off[block];
+  A.acc_off = c->acc_off[block];
+  A.aux_idx = c->d_auxlist + (size_t)block * c->auxlist_stride;
+  A.S = c->exS;
+  A.A = c->exA;
+  HIPCHK(c, hipMemcpyAsync(c->d_asm_x, &A, sizeof A, hipMemcpyHostToDevice, c->st));
+  hipLaunchKernelGGL(assemble_kernel, dim3(1, 64), dim3(256), 0, c->st, c->d_asm_x, c->accS, c->accH,
+                     c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2max);
+  HIPCHK(c, hipGetLastError());
+  if (h_H) HIPCHK(c, hipMemcpyAsync(h_H, c->exA, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
+  if (h_S) HIPCHK(c, hipMemcpyAsync(h_S, c->exS, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return BLM_OK;
+}
+
+blm_status blm_get_directions(blm_ctx* c, int32_t block, int32_t shift, double* h_B, int32_t* n_rows) {
+  if (!c || !n_rows) return BLM_E_ARG;
+  if (block < 0 || block >= c->NB || shift < 0 || shift >= c->NS) return fail(c, BLM_E_ARG, "bad index");
+  if (c->state < ST_SOLVED) return fail(c, BLM_E_STATE, "no directions yet");
+  const int i = shift * c->NB + block;
+  *n_rows = c->nkept[i];
+  if (!h_B) return BLM_OK;
+  const int M = (int)(c->off[block + 1] - c->off[block]);
+  HIPCHK(c, hipMemcpyAsync(h_B, c->eig1[i].out, 8 * (size_t)c->nkept[i] * M, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return BLM_OK;
+}
+
+blm_status blm_get_stage2_matrices(blm_ctx* c, int32_t shift, double* h_H2, double* h_S2, int32_t* dim) {
+  if (!c || !dim) return BLM_E_ARG;
+  if (shift < 0 || shift >= c->NS) return fail(c, BLM_E_ARG, "bad index");
+  if (c->state < ST_PROJECTED) return fail(c, BLM_E_STATE, "no stage-two estimates yet");
+  const int d = (int)c->idx2[shift].size();
+  *dim = d;
+  if (!h_H2 && !h_S2) return BLM_OK;
+  AsmJob A{};
+  A.d = d;
+  A.kind = 1;
+  A.delta = 0.0;
+  A.idx2 = c->d_idx2 + (size_t)shift * c->n2max;
+  A.S = c->exS;
+  A.A = c->exA;
+  HIPCHK(c, hipMemcpyAsync(c->d_asm_x, &A, sizeof A, hipMemcpyHostToDevice, c->st));
+  hipLaunchKernelGGL(assemble_kernel, dim3(1, 16), dim3(256), 0, c->st, c->d_asm_x, c->accS, c->accH,
+                     c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2);
+  HIPCHK(c, hipGetLastError());
+  if (h_H2) HIPCHK(c, hipMemcpyAsync(h_H2, c->exA, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
+  if (h_S2) HIPCHK(c, hipMemcpyAsync(h_S2, c->exS, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return BLM_OK;
+}
+
+blm_status blm_debug_eigvals(const double* d_H, const double* d_S, int32_t d, double* h_evals, void* stream) {
+  if (!d_H || !d_S || !h_evals || d < 1 || d > EIG_MAXD) return BLM_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = eig_bytes(d, d, 1);
+  void *ws = nullptr, *aux = nullptr;
+  if (hipMalloc(&ws, bytes) != hipSuccess) return BLM_E_NOMEM;
+  if (hipMalloc(&aux, 256 + sizeof(EigJob)) != hipSuccess) {
+    (void)hipFree(ws);
+    return BLM_E_NOMEM;
+  }
+  double* q = (double*)ws;
+  int32_t* info = (int32_t*)aux;
+  double* ev = (double*)((char*)aux + 64);
+  EigJob J = carve(q, d, d, 1, EIG_VALUES, 1, 0, info, ev);
+  EigJob* dJ = (EigJob*)((char*)aux + 256);
+  blm_status r = BLM_OK;
+  std::vector<double> wr(d), wi(d);
+  int32_t hinfo[4] = {0, 0, 0, 0};
+  if (hipMemcpyAsync(J.A, d_H, 8 * (size_t)d * d, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(J.S, d_S, 8 * (size_t)d * d, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(dJ, &J, sizeof J, hipMemcpyHostToDevice, st) != hipSuccess) {
+    r = BLM_E_HIP;
+  } else {
+    launch_eig(dJ, 1, st);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(wr.data(), J.wr, 8 * (size_t)d, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(wi.data(), J.wi, 8 * (size_t)d, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hinfo, info, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      r = BLM_E_HIP;
+  }
+  (void)hipFree(ws);
+  (void)hipFree(aux);
+  if (r != BLM_OK) return r;
+  if (hinfo[0] == EIG_NOT_PD) return BLM_E_S_NOT_PD;
+  if (hinfo[0] == EIG_NONFINITE) return BLM_E_NONFINITE;
+  if (hinfo[0] == EIG_NOCONV) return BLM_E_NOCONV;
+  for (int i = 0; i < d; ++i) {
+    h_evals[2 * i] = wr[i];
+    h_evals[2 * i + 1] = wi[i];
+  }
+  return BLM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,732 @@
+// Dense shifted generalised eigensolver for the BLM pencils, FP64, one
+// 1024-thread workgroup per pencil (H' c = lambda S c, S symmetric positive
+// definite, H' not symmetric):
+//
+//   1. S = L L^T (Cholesky)                      -> BLM_E_S_NOT_PD if it fails
+//   2. A = L^-1 H' L^-T (two triangular solves)
+//   3. A = Q Hs Q^T, Hs upper Hessenberg (Householder reflectors kept)
+//   4. eigenvalues of Hs: Francis implicit double-shift QR sweeps on the
+//      active window with deflation (Golub & Van Loan, Sec. 7.5)
+//   5. rank by real part (ties: larger imaginary part first), take the
+//      lowest ones: a complex conjugate pair is taken whole
+//   6. eigenvectors of the chosen eigenvalues by inverse iteration on Hs
+//      (complex shift for a pair), then back to the pencil: c = L^-T Q y
+//   7. block problems: the parameter part of Re c (and Im c for a pair),
+//      orthonormalised by modified Gram-Schmidt -> kept directions (Eq. 6);
+//      stage two: the chosen eigenvector itself (Eq. 7, Eq. 8).
+//
+// The ranking of eigenvalues as update directions follows Sec. II.B of the
+// paper (lowest eigenvalue = best direction).
+#include <float.h>
+
+#include "blm_internal.h"
+
+namespace blm {
+
+namespace {
+
+constexpr int NT = EIG_THREADS;
+constexpr int NW = NT / 64;
+constexpr double EPS = DBL_EPSILON;
+constexpr double DROP_TOL = 1e-12;
+
+struct Shared {
+  double v1[EIG_MAXD];
+  double v2[EIG_MAXD];
+  double red[NW];
+  double sc[16];
+  int isc[16];
+  unsigned char mark[EIG_MAXD];
+  double sel_r[EIG_MAXSEL], sel_i[EIG_MAXSEL];
+  int sel_n;
+  int widx[NW];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Sum over the workgroup, same value returned to every thread, fixed order.
+__device__ double block_sum(Shared& sh, double v) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t += sh.red[i];
+  __syncthreads();
+  return t;
+}
+
+__device__ double block_max(Shared& sh, double v) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = sh.red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) t = fmax(t, sh.red[i]);
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------- step 1 --
+__device__ int cholesky(Shared& sh, double* S, int d) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int k = 0; k < d; ++k) {
+    if (tid == 0) {
+      const double v = S[(size_t)k * d + k];
+      int st = EIG_OK;
+      if (!isfinite(v)) st = EIG_NONFINITE;
+      else if (!(v > 0.0)) st = EIG_NOT_PD;
+      sh.isc[0] = st;
+      sh.sc[0] = st == EIG_OK ? sqrt(v) : 1.0;
+      if (st == EIG_OK) S[(size_t)k * d + k] = sh.sc[0];
+    }
+    __syncthreads();
+    const int st = sh.isc[0];
+    const double piv = sh.sc[0];
+    if (st != EIG_OK) return st;
+    for (int i = k + 1 + tid; i < d; i += NT) {
+      const double x = S[(size_t)i * d + k] / piv;
+      S[(size_t)i * d + k] = x;
+      sh.v1[i] = x;
+    }
+    __syncthreads();
+    for (int i = k + 1 + wv; i < d; i += NW) {
+      const double li = sh.v1[i];
+      double* Si = S + (size_t)i * d;
+      for (int j = k + 1 + lane; j <= i; j += 64) Si[j] -= li * sh.v1[j];
+    }
+    __syncthreads();
+  }
+  return EIG_OK;
+}
+
+// ---------------------------------------------------------------- step 2 --
+// A <- L^-1 A L^-T with L in the lower triangle of S.
+__device__ void congruence(Shared& sh, const double* L, double* A, int d) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // X = L^-1 A, row by row
+  for (int k = 0; k < d; ++k) {
+    const double lkk = L[(size_t)k * d + k];
+    for (int j = tid; j < d; j += NT) {
+      const double x = A[(size_t)k * d + j] / lkk;
+      A[(size_t)k * d + j] = x;
+      sh.v1[j] = x;
+    }
+    __syncthreads();
+    for (int i = k + 1 + wv; i < d; i += NW) {
+      const double lik = L[(size_t)i * d + k];
+      double* Ai = A + (size_t)i * d;
+      for (int j = lane; j < d; j += 64) Ai[j] -= lik * sh.v1[j];
+    }
+    __syncthreads();
+  }
+  // A = X L^-T, column by column: solves Z L^T = X
+  for (int k = 0; k < d; ++k) {
+    const double lkk = L[(size_t)k * d + k];
+    for (int i = tid; i < d; i += NT) {
+      const double x = A[(size_t)i * d + k] / lkk;
+      A[(size_t)i * d + k] = x;
+      sh.v1[i] = x;
+    }
+    for (int j = k + 1 + tid; j < d; j += NT) sh.v2[j] = L[(size_t)j * d + k];
+    __syncthreads();
+    for (int i = wv; i < d; i += NW) {
+      const double xi = sh.v1[i];
+      double* Ai = A + (size_t)i * d;
+      for (int j = k + 1 + lane; j < d; j += 64) Ai[j] -= xi * sh.v2[j];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- step 3 --
+// Householder reduction to upper Hessenberg form.  Reflector k acts on
+// indices k+1..d-1 with vector v (v[k+1] = 1) stored in row k of V and
+// scalar tau[k]: P_k = I - tau v v^T.  A = Q Hs Q^T with Q = P_0 P_1 ... .
+__device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, int d) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int k = 0; k + 2 < d; ++k) {
+    double part = 0.0;
+    for (int i = k + 2 + tid; i < d; i += NT) {
+      const double x = A[(size_t)i * d + k];
+      part += x * x;
+    }
+    const double sigma = block_sum(sh, part);
+    const double alpha = A[(size_t)(k + 1) * d + k];
+    if (sigma == 0.0) {
+      if (tid == 0) tau[k] = 0.0;
+      for (int i = k + 1 + tid; i < d; i += NT) V[(size_t)k * d + i] = (i == k + 1) ? 1.0 : 0.0;
+      __syncthreads();
+      continue;
+    }
+    const double nrm = sqrt(alpha * alpha + sigma);
+    const double beta = alpha <= 0.0 ? nrm : -nrm;
+    const double v0 = alpha - beta;
+    const double tk = (beta - alpha) / beta;
+    for (int i = k + 1 + tid; i < d; i += NT) {
+      const double vi = (i == k + 1) ? 1.0 : A[(size_t)i * d + k] / v0;
+      sh.v1[i] = vi;
+      V[(size_t)k * d + i] = vi;
+    }
+    if (tid == 0) tau[k] = tk;
+    __syncthreads();
+    // left: rows k+1.., columns k+1..d-1 (column k becomes beta e_1)
+    for (int j = k + 1 + tid; j < d; j += NT) {
+      double s = 0.0;
+      for (int i = k + 1; i < d; ++i) s += sh.v1[i] * A[(size_t)i * d + j];
+      s *= tk;
+      for (int i = k + 1; i < d; ++i) A[(size_t)i * d + j] -= s * sh.v1[i];
+    }
+    for (int i = k + 1 + tid; i < d; i += NT) A[(size_t)i * d + k] = (i == k + 1) ? beta : 0.0;
+    __syncthreads();
+    // right: all rows, columns k+1..d-1
+    for (int i = wv; i < d; i += NW) {
+      double* Ai = A + (size_t)i * d;
+      double t = 0.0;
+      for (int j = k + 1 + lane; j < d; j += 64) t += Ai[j] * sh.v1[j];
+      t = wave_sum(t) * tk;
+      for (int j = k + 1 + lane; j < d; j += 64) Ai[j] -= t * sh.v1[j];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- step 4 --
+// Eigenvalues of the upper Hessenberg matrix A (destroyed) into wr, wi.
+// Pairs are stored as (re, +im), (re, -im) at consecutive indices.
+__device__ int hessenberg_eigvals(Shared& sh, double* A, double* wr, double* wi, int d, int* iters) {
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int i = tid; i < d; i += NT)
+    for (int j = (i > 0 ? i - 1 : 0); j < d; ++j) part += fabs(A[(size_t)i * d + j]);
+  const double anorm = block_sum(sh, part);
+  int h = d - 1, its = 0, total = 0;
+  const int max_total = 40 * (d + 1);
+  while (h >= 0) {
+    if (tid == 0) sh.isc[1] = 0;
+    __syncthreads();
+    for (int i = 1 + tid; i <= h; i += NT) {
+      double s = fabs(A[(size_t)(i - 1) * d + i - 1]) + fabs(A[(size_t)i * d + i]);
+      if (s == 0.0) s = anorm;
+      if (fabs(A[(size_t)i * d + i - 1]) <= EPS * s) atomicMax(&sh.isc[1], i);
+    }
+    __syncthreads();
+    const int l = sh.isc[1];
+    if (l == h) {
+      if (tid == 0) {
+        if (l > 0) A[(size_t)l * d + l - 1] = 0.0;
+        wr[h] = A[(size_t)h * d + h];
+        wi[h] = 0.0;
+      }
+      h -= 1;
+      its = 0;
+      __syncthreads();
+      continue;
+    }
+    if (l == h - 1) {
+      if (tid == 0) {
+        if (l > 0) A[(size_t)l * d + l - 1] = 0.0;
+        const double a = A[(size_t)(h - 1) * d + h - 1], b = A[(size_t)(h - 1) * d + h];
+        const double c = A[(size_t)h * d + h - 1], dd = A[(size_t)h * d + h];
+        const double p = 0.5 * (a - dd);
+        const double disc = p * p + b * c;
+        if (disc >= 0.0) {
+          const double z = p + copysign(sqrt(disc), p);
+          wr[h - 1] = dd + z;
+          wr[h] = (z != 0.0) ? dd - b * c / z : dd + z;
+          wi[h - 1] = 0.0;
+          wi[h] = 0.0;
+        } else {
+          wr[h - 1] = wr[h] = dd + p;
+          const double im = sqrt(-disc);
+          wi[h - 1] = im;
+          wi[h] = -im;
+        }
+      }
+      h -= 2;
+      its = 0;
+      __syncthreads();
+      continue;
+    }
+    if (total >= max_total) {
+      *iters = total;
+      return EIG_NOCONV;
+    }
+    ++its;
+    ++total;
+    // shifts: sum and product of the two eigenvalues of the trailing 2x2
+    // block, or an ad hoc pair after 10 and 20 stalled sweeps
+    double ssum, sprod;
+    {
+      const double a = A[(size_t)(h - 1) * d + h - 1], b = A[(size_t)(h - 1) * d + h];
+      const double c = A[(size_t)h * d + h - 1], dd = A[(size_t)h * d + h];
+      if (its % 10 == 0) {
+        const double ex = fabs(c) + fabs(A[(size_t)(h - 1) * d + h - 2]);
+        const double x = dd + 0.75 * ex;
+        ssum = 2.0 * x;
+        sprod = x * x + 0.4375 * ex * ex;
+      } else {
+        ssum = a + dd;
+        sprod = a * dd - b * c;
+      }
+    }
+    // first column of (A - s1)(A - s2) restricted to the window
+    double x, y, z;
+    {
+      const double h00 = A[(size_t)l * d + l], h01 = A[(size_t)l * d + l + 1];
+      const double h10 = A[(size_t)(l + 1) * d + l], h11 = A[(size_t)(l + 1) * d + l + 1];
+      const double h21 = A[(size_t)(l + 2) * d + l + 1];
+      x = h00 * h00 + h01 * h10 - ssum * h00 + sprod;
+      y = h10 * (h00 + h11 - ssum);
+      z = h10 * h21;
+    }
+    if (tid == 0 && l > 0) A[(size_t)l * d + l - 1] = 0.0;
+    __syncthreads();
+    for (int K = l - 1; K <= h - 2; ++K) {
+      const int nr = (K <= h - 3) ? 3 : 2;
+      if (nr == 2) z = 0.0;
+      const double sc = fabs(x) + fabs(y) + fabs(z);
+      double v0 = 0.0, v1 = 0.0, v2 = 0.0, bt = 0.0, newsub = 0.0;
+      bool act = sc != 0.0;
+      if (act) {
+        const double xs = x / sc, ys = y / sc, zs = z / sc;
+        const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
+        v0 = xs + al;
+        v1 = ys;
+        v2 = zs;
+        bt = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+        newsub = -al * sc;
+      }
+      if (act) {
+        // rows K+1..K+nr, columns from max(l, K+1) to h; column K (bulge) set directly
+        const int c0 = (K >= l) ? K + 1 : l;
+        for (int c = c0 + tid; c <= h; c += NT) {
+          double* p1 = A + (size_t)(K + 1) * d + c;
+          double* p2 = p1 + d;
+          double t = v0 * p1[0] + v1 * p2[0];
+          if (nr == 3) t += v2 * p2[d];
+          t *= bt;
+          p1[0] -= t * v0;
+          p2[0] -= t * v1;
+          if (nr == 3) p2[d] -= t * v2;
+        }
+        if (K >= l && tid == 0) {
+          A[(size_t)(K + 1) * d + K] = newsub;
+          A[(size_t)(K + 2) * d + K] = 0.0;
+          if (nr == 3) A[(size_t)(K + 3) * d + K] = 0.0;
+        }
+      }
+      __syncthreads();
+      if (act) {
+        // columns K+1..K+nr, rows l..min(K+4, h)
+        const int r1 = (K + 4 < h) ? K + 4 : h;
+        for (int rr = l + tid; rr <= r1; rr += NT) {
+          double* q = A + (size_t)rr * d + K + 1;
+          double t = q[0] * v0 + q[1] * v1;
+          if (nr == 3) t += q[2] * v2;
+          t *= bt;
+          q[0] -= t * v0;
+          q[1] -= t * v1;
+          if (nr == 3) q[2] -= t * v2;
+          if (rr >= K + 2 && rr <= K + 4) sh.sc[rr - K - 2] = q[0];
+        }
+      }
+      if (tid == 0) {
+        if (K + 4 > h) sh.sc[2] = 0.0;
+        if (!act) {
+          // no reflection: the next bulge column is read as it stands
+          sh.sc[0] = (K + 2 <= h) ? A[(size_t)(K + 2) * d + K + 1] : 0.0;
+          sh.sc[1] = (K + 3 <= h) ? A[(size_t)(K + 3) * d + K + 1] : 0.0;
+          sh.sc[2] = (K + 4 <= h) ? A[(size_t)(K + 4) * d + K + 1] : 0.0;
+        }
+      }
+      __syncthreads();
+      x = sh.sc[0];
+      y = sh.sc[1];
+      z = sh.sc[2];
+      __syncthreads();
+    }
+  }
+  *iters = total;
+  for (int i = tid; i < d; i += NT)
+    if (!isfinite(wr[i]) || !isfinite(wi[i])) sh.isc[2] = 1;
+  return EIG_OK;
+}
+
+// ---------------------------------------------------------------- step 5 --
+// Picks eigenvalues in rank order until `want` directions are held (a pair
+// gives two).  Returns the number of picked eigenvalue entries in sh.sel_*
+// (a pair is one entry with positive imaginary part).
+__device__ int select_lowest(Shared& sh, const double* wr, const double* wi, int d, int want,
+                             double* out_evals, int max_entries) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < d; i += NT) sh.mark[i] = 0;
+  if (tid == 0) sh.sel_n = 0;
+  __syncthreads();
+  int held = 0, n_sel = 0, n_ev = 0;
+  while (held < want && n_sel < EIG_MAXSEL && n_ev < max_entries) {
+    // argmin over unmarked of (wr asc, wi desc, index asc)
+    double br = INFINITY, bi = -INFINITY;
+    int bidx = d;
+    for (int i = tid; i < d; i += NT) {
+      if (sh.mark[i]) continue;
+      const double r = wr[i], im = wi[i];
+      if (r < br || (r == br && (im > bi || (im == bi && i < bidx)))) {
+        br = r;
+        bi = im;
+        bidx = i;
+      }
+    }
+    // wave then block reduction of (br, bi, bidx)
+    for (int off = 32; off > 0; off >>= 1) {
+      const double orr = __shfl_xor(br, off, 64), oi = __shfl_xor(bi, off, 64);
+      const int ox = __shfl_xor(bidx, off, 64);
+      if (orr < br || (orr == br && (oi > bi || (oi == bi && ox < bidx)))) {
+        br = orr;
+        bi = oi;
+        bidx = ox;
+      }
+    }
+    if ((tid & 63) == 0) {
+      sh.v1[tid >> 6] = br;
+      sh.v2[tid >> 6] = bi;
+      sh.widx[tid >> 6] = bidx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double r = sh.v1[0], im = sh.v2[0];
+      int ix = sh.widx[0];
+      for (int w = 1; w < NW; ++w) {
+        const double orr = sh.v1[w], oi = sh.v2[w];
+        const int ox = sh.widx[w];
+        if (orr < r || (orr == r && (oi > im || (oi == im && ox < ix)))) {
+          r = orr;
+          im = oi;
+          ix = ox;
+        }
+      }
+      sh.isc[3] = ix;
+    }
+    __syncthreads();
+    const int ix = sh.isc[3];
+    if (ix >= d) break;
+    const double r = wr[ix], im = wi[ix];
+    if (tid == 0) {
+      sh.mark[ix] = 1;
+      sh.sel_r[n_sel] = r;
+      sh.sel_i[n_sel] = im;
+      out_evals[2 * n_ev] = r;
+      out_evals[2 * n_ev + 1] = im;
+      if (im != 0.0) {
+        // partner: the conjugate, stored right after it
+        for (int j = 0; j < d; ++j)
+          if (!sh.mark[j] && wr[j] == r && wi[j] == -im) {
+            sh.mark[j] = 1;
+            break;
+          }
+        if (n_ev + 1 < max_entries) {
+          out_evals[2 * n_ev + 2] = r;
+          out_evals[2 * n_ev + 3] = -im;
+        }
+      }
+    }
+    __syncthreads();
+    n_sel += 1;
+    if (im != 0.0) {
+      held += 2;
+      n_ev += 2;
+    } else {
+      held += 1;
+      n_ev += 1;
+    }
+  }
+  if (tid == 0) sh.sel_n = n_sel;
+  __syncthreads();
+  return n_sel;
+}
+
+// ---------------------------------------------------------------- step 6 --
+// Inverse iteration on the Hessenberg matrix Hq for eigenvalue (sr, si):
+// LU of Hq - sigma I with adjacent-row pivoting, tiny pivots replaced by
+// eps3, three solves from a vector of ones.  Result (complex) in yr, yi.
+__device__ void inverse_iteration(Shared& sh, const double* Hq, double* Wr, double* Wi, int d,
+                                  double sr, double si, double eps3, double* yr, double* yi) {
+  const int tid = threadIdx.x;
+  for (size_t t = tid; t < (size_t)d * d; t += NT) {
+    const int i = (int)(t / d), j = (int)(t % d);
+    const double v = (j + 1 >= i) ? Hq[t] : 0.0;
+    Wr[t] = (j == i) ? v - sr : v;
+    Wi[t] = (j == i) ? -si : 0.0;
+  }
+  __syncthreads();
+  // multipliers and swaps kept in LDS: v1 = mult re, v2 = mult im, mark = swap
+  for (int k = 0; k + 1 < d; ++k) {
+    const double ar = Wr[(size_t)k * d + k], ai = Wi[(size_t)k * d + k];
+    const double br = Wr[(size_t)(k + 1) * d + k], bi = Wi[(size_t)(k + 1) * d + k];
+    const bool swp = hypot(br, bi) > hypot(ar, ai);
+    double pr = swp ? br : ar, pi = swp ? bi : ai;
+    const double orr = swp ? ar : br, oi = swp ? ai : bi;
+    if (hypot(pr, pi) < eps3) {
+      pr = eps3;
+      pi = 0.0;
+    }
+    const double den = pr * pr + pi * pi;
+    const double mr = (orr * pr + oi * pi) / den, mi = (oi * pr - orr * pi) / den;
+    __syncthreads();
+    if (tid == 0) {
+      sh.v1[k] = mr;
+      sh.v2[k] = mi;
+      sh.mark[k] = swp ? 1 : 0;
+    }
+    for (int j = k + tid; j < d; j += NT) {
+      double tr, ti, ur, ui;
+      if (swp) {
+        tr = Wr[(size_t)(k + 1) * d + j];
+        ti = Wi[(size_t)(k + 1) * d + j];
+        ur = Wr[(size_t)k * d + j];
+        ui = Wi[(size_t)k * d + j];
+      } else {
+        tr = Wr[(size_t)k * d + j];
+        ti = Wi[(size_t)k * d + j];
+        ur = Wr[(size_t)(k + 1) * d + j];
+        ui = Wi[(size_t)(k + 1) * d + j];
+      }
+      if (j == k) {
+        tr = pr;
+        ti = pi;
+      }
+      Wr[(size_t)k * d + j] = tr;
+      Wi[(size_t)k * d + j] = ti;
+      Wr[(size_t)(k + 1) * d + j] = (j == k) ? 0.0 : ur - (mr * tr - mi * ti);
+      Wi[(size_t)(k + 1) * d + j] = (j == k) ? 0.0 : ui - (mr * ti + mi * tr);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const size_t dd = (size_t)(d - 1) * d + d - 1;
+    if (hypot(Wr[dd], Wi[dd]) < eps3) {
+      Wr[dd] = eps3;
+      Wi[dd] = 0.0;
+    }
+  }
+  __syncthreads();
+  // right-hand side in yr/yi (global, owned per index by thread i % NT)
+  for (int i = tid; i < d; i += NT) {
+    yr[i] = 1.0;
+    yi[i] = 0.0;
+  }
+  __syncthreads();
+  for (int it = 0; it < 3; ++it) {
+    if (it > 0) {
+      // apply L^-1: sequential, by one thread
+      if (tid == 0) {
+        for (int k = 0; k + 1 < d; ++k) {
+          double r0 = yr[k], i0 = yi[k], r1 = yr[k + 1], i1 = yi[k + 1];
+          if (sh.mark[k]) {
+            const double tr = r0, ti = i0;
+            r0 = r1;
+            i0 = i1;
+            r1 = tr;
+            i1 = ti;
+          }
+          const double mr = sh.v1[k], mi = sh.v2[k];
+          r1 -= mr * r0 - mi * i0;
+          i1 -= mr * i0 + mi * r0;
+          yr[k] = r0;
+          yi[k] = i0;
+          yr[k + 1] = r1;
+          yi[k + 1] = i1;
+        }
+      }
+      __syncthreads();
+    }
+    // back substitution U y = b; entry i owned by thread i % NT
+    for (int k = d - 1; k >= 0; --k) {
+      if ((k % NT) == tid) {
+        const double ur = Wr[(size_t)k * d + k], ui = Wi[(size_t)k * d + k];
+        const double den = ur * ur + ui * ui;
+        const double br = yr[k], bi = yi[k];
+        const double xr = (br * ur + bi * ui) / den, xi = (bi * ur - br * ui) / den;
+        yr[k] = xr;
+        yi[k] = xi;
+        sh.sc[8] = xr;
+        sh.sc[9] = xi;
+      }
+      __syncthreads();
+      const double xr = sh.sc[8], xi = sh.sc[9];
+      for (int i = tid; i < k; i += NT) {
+        const double ur = Wr[(size_t)i * d + k], ui = Wi[(size_t)i * d + k];
+        yr[i] -= ur * xr - ui * xi;
+        yi[i] -= ur * xi + ui * xr;
+      }
+      __syncthreads();
+    }
+    // normalise (largest modulus -> 1)
+    double m = 0.0;
+    for (int i = tid; i < d; i += NT) m = fmax(m, hypot(yr[i], yi[i]));
+    m = block_max(sh, m);
+    const double inv = (m > 0.0 && isfinite(m)) ? 1.0 / m : 1.0;
+    for (int i = tid; i < d; i += NT) {
+      yr[i] *= inv;
+      yi[i] *= inv;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- step 6b --
+// One wave per real vector z (length d, global): z <- L^-T Q z.
+__device__ void back_transform_wave(const double* V, const double* tau, const double* L, double* z,
+                                    int d) {
+  const int lane = threadIdx.x & 63;
+  for (int k = d - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    const double* v = V + (size_t)k * d;
+    double s = 0.0;
+    for (int i = k + 1 + lane; i < d; i += 64) s += v[i] * z[i];
+    s = wave_sum(s) * tk;
+    for (int i = k + 1 + lane; i < d; i += 64) z[i] -= s * v[i];
+  }
+  // solve L^T c = z from the bottom; lane (k % 64) owns entry k
+  for (int k = d - 1; k >= 0; --k) {
+    double ck = 0.0;
+    if ((k & 63) == lane) {
+      ck = z[k] / L[(size_t)k * d + k];
+      z[k] = ck;
+    }
+    ck = __shfl(ck, k & 63, 64);
+    const double* Lk = L + (size_t)k * d;
+    for (int i = lane; i < k; i += 64) z[i] -= Lk[i] * ck;
+  }
+}
+
+__global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs) {
+  __shared__ Shared sh;
+  const EigJob J = jobs[blockIdx.x];
+  const int d = J.d, tid = threadIdx.x, wv = tid >> 6;
+  if (tid == 0) {
+    sh.isc[2] = 0;
+    J.info[0] = EIG_OK;
+    J.info[1] = 0;
+    J.info[2] = 0;
+    J.info[3] = 0;
+  }
+  __syncthreads();
+  if (d <= 0 || d > EIG_MAXD) return;
+
+  int st = cholesky(sh, J.S, d);
+  if (st != EIG_OK) {
+    if (tid == 0) J.info[0] = st;
+    return;
+  }
+  congruence(sh, J.S, J.A, d);
+  hessenberg(sh, J.A, J.V, J.tau, d);
+  for (size_t i = tid; i < (size_t)d * d; i += NT) J.Hq[i] = J.A[i];
+  __syncthreads();
+  // norm of the Hessenberg matrix for the inverse-iteration pivot floor
+  double part = 0.0;
+  for (size_t i = tid; i < (size_t)d * d; i += NT) part += fabs(J.Hq[i]);
+  const double hnorm = block_sum(sh, part);
+  int iters = 0;
+  st = hessenberg_eigvals(sh, J.A, J.wr, J.wi, d, &iters);
+  __syncthreads();
+  if (tid == 0) J.info[3] = iters;
+  if (st == EIG_OK && sh.isc[2]) st = EIG_NONFINITE;
+  if (st != EIG_OK) {
+    if (tid == 0) J.info[0] = st;
+    return;
+  }
+  if (J.mode == EIG_VALUES) return;
+
+  const int want = (J.mode == EIG_STAGE2) ? 1 : J.n_want;
+  const int max_entries = (J.mode == EIG_STAGE2) ? 2 : J.n_want + 1;
+  const int n_sel = select_lowest(sh, J.wr, J.wi, d, want, J.out_evals, max_entries);
+  const double eps3 = EPS * fmax(hnorm, 1e-300);
+
+  // eigenvectors of the chosen eigenvalues, complex, into vec[s][0|1][d]
+  for (int s = 0; s < n_sel; ++s) {
+    double* yr = J.vec + (size_t)(2 * s) * d;
+    double* yi = yr + d;
+    inverse_iteration(sh, J.Hq, J.W, J.W + (size_t)d * d, d, sh.sel_r[s], sh.sel_i[s], eps3, yr, yi);
+  }
+  // back to the pencil's coordinates: one wave per real vector
+  const int n_real = 2 * n_sel;
+  for (int v = wv; v < n_real; v += NW) {
+    const int s = v >> 1;
+    if ((v & 1) && sh.sel_i[s] == 0.0) continue;
+    back_transform_wave(J.V, J.tau, J.S, J.vec + (size_t)v * d, d);
+  }
+  __syncthreads();
+
+  if (J.mode == EIG_STAGE2) {
+    for (int i = tid; i < d; i += NT) {
+      J.out[i] = J.vec[i];
+      J.out[d + i] = (sh.sel_i[0] == 0.0) ? 0.0 : J.vec[(size_t)d + i];
+    }
+    if (tid == 0) {
+      J.info[1] = n_sel;
+      J.info[2] = (sh.sel_i[0] != 0.0) ? 1 : 0;
+    }
+    return;
+  }
+
+  // block: parameter parts of Re c (and Im c for a pair), MGS, kept rows
+  const int nb = J.nbeta;
+  int kept = 0, pair = 0;
+  for (int s = 0; s < n_sel; ++s) {
+    const int parts = (sh.sel_i[s] != 0.0) ? 2 : 1;
+    if (parts == 2) pair = 1;
+    for (int pc = 0; pc < parts; ++pc) {
+      const double* src = J.vec + (size_t)(2 * s + pc) * d + J.beta0;
+      double* dst = J.out + (size_t)kept * nb;
+      double part0 = 0.0;
+      for (int i = tid; i < nb; i += NT) {
+        const double x = src[i];
+        dst[i] = x;
+        part0 += x * x;
+      }
+      const double n0 = sqrt(block_sum(sh, part0));
+      for (int q = 0; q < kept; ++q) {
+        const double* qv = J.out + (size_t)q * nb;
+        double pd = 0.0;
+        for (int i = tid; i < nb; i += NT) pd += qv[i] * dst[i];
+        const double dot = block_sum(sh, pd);
+        for (int i = tid; i < nb; i += NT) dst[i] -= dot * qv[i];
+        __syncthreads();
+      }
+      double pn = 0.0;
+      for (int i = tid; i < nb; i += NT) pn += dst[i] * dst[i];
+      const double nr = sqrt(block_sum(sh, pn));
+      if (n0 > 0.0 && nr >= DROP_TOL * n0 && kept < nb) {
+        const double inv = 1.0 / nr;
+        for (int i = tid; i < nb; i += NT) dst[i] *= inv;
+        __syncthreads();
+        ++kept;
+      }
+    }
+  }
+  if (tid == 0) {
+    J.info[1] = kept;
+    J.info[2] = pair;
+  }
+}
+
+}  // namespace
+
+void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st) {
+  if (n_jobs <= 0) return;
+  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs);
+}
+
+}  // namespace blm

@@ -1,0 +1,105 @@
+// Internal declarations shared by the libblm translation units (kernels and
+// host API).  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace blm {
+
+// ---------------------------------------------------------------- Gram ----
+// Weighted Gram tiles  C = X^T diag(w) Y  over sample slices, FP64 MFMA.
+constexpr int GT = 64;        // output tile edge
+constexpr int GKS = 16;       // samples per LDS stage
+constexpr int GTHREADS = 256; // 4 waves, 2x2 of 32x32 sub-tiles
+constexpr int NAUX = 16;      // aux columns: [1 | Theta] and [E_L | Theta-energy], padded
+constexpr int SLICE = 4096;   // samples per slice (unit of split-K work)
+
+enum JobKind : int32_t {
+  JOB_OFF = 0,          // i < j: S_ij = O_i^T W O_j, H_ij = O_i^T W e_j, H_ji^T = e_i^T W O_j
+  JOB_DIAG = 1,         // i == j: S_ii, H_ii, plus strips aux^T W O_i, aux^T W e_i, auxE^T W O_i
+  JOB_DIAG_NOSTRIP = 2, // i == j without strips
+  JOB_AUX = 3           // aux x aux: Xa^T W Xa, Xa^T W Ya (panels taken from the aux arrays)
+};
+
+struct GramJob {
+  int32_t kind;
+  int32_t mi, nj;       // valid rows / cols of the tile (<= GT)
+  int32_t pad;
+  int64_t ci, cj;       // first source column of tile i / tile j
+  int64_t s_off;        // destination of S tile (i,j): s_base[s_off + r*ld_out + c]
+  int64_t h_off;        // destination of H tile (i,j)
+  int64_t ht_off;       // destination of H tile (j,i) (JOB_OFF): h_base[ht_off + c*ld_out + r]
+  int64_t ld_out;
+  int64_t strip_col;    // JOB_DIAG: global parameter column of the strip's first column
+};
+
+struct Slice {
+  const double* O;      // main panels (sample-major, row stride ld)
+  const double* e;
+  const double* Xa;     // aux panels (row stride NAUX), already offset to the slice's first row
+  const double* Ya;
+  const double* w;      // weights of the slice's first row, or nullptr
+  int64_t ld;
+  int64_t n;            // samples in the slice
+};
+
+// ------------------------------------------------- direction projection ---
+// out[s][1 + d0 + t] = dir_t . O[s, col0 : col0 + m] for every direction t of a block
+struct DirBlock {
+  int64_t col0;
+  int32_t m;
+  int32_t d0, nd;
+  int32_t pad;
+};
+
+// ------------------------------------------------------------ eigensolve --
+enum EigMode : int32_t {
+  EIG_BLOCK = 0,        // kept directions: beta parts, orthonormalised
+  EIG_STAGE2 = 1,       // lowest eigenvector, full
+  EIG_VALUES = 2        // all eigenvalues only
+};
+
+struct EigJob {
+  int32_t d;            // pencil dimension
+  int32_t mode;
+  int32_t n_want;       // directions wanted (EIG_BLOCK); 1 for EIG_STAGE2
+  int32_t beta0, nbeta; // beta part of each eigenvector: entries [beta0, beta0 + nbeta)
+  int32_t pad;
+  double* S;            // [d][d] overlap in, Cholesky factor out
+  double* A;            // [d][d] shifted Hamiltonian in, destroyed
+  double* Hq;           // [d][d] Hessenberg copy
+  double* V;            // [d][d] Householder vectors (row k: reflector k)
+  double* W;            // [2 d][d] complex LU workspace
+  double* vec;          // [n_sel][2][d] complex eigenvectors
+  double* wr;           // [d]
+  double* wi;           // [d]
+  double* tau;          // [d]
+  double* out;          // EIG_BLOCK: [n_want + 1][nbeta] rows; EIG_STAGE2: [2][d] (re, im)
+  double* out_evals;    // [n_want + 1][2] the used eigenvalues in rank order
+  int32_t* info;        // [0] status, [1] rows/vectors produced, [2] flags, [3] iterations
+};
+
+enum EigStatus : int32_t {
+  EIG_OK = 0,
+  EIG_NOT_PD = 1,
+  EIG_NONFINITE = 2,
+  EIG_NOCONV = 3
+};
+
+constexpr int EIG_THREADS = 1024;
+constexpr int EIG_MAXD = 4096;
+constexpr int EIG_MAXSEL = 16;   // eigenvalues selected per problem (N_K + 1 <= this)
+
+// launchers (blm_kernels.hip / blm_eig.hip)
+void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
+                 double* d_partial, hipStream_t st);
+void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
+                        double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
+                        hipStream_t st);
+void launch_dirproj(const double* O, const double* e, const double* EL, int64_t ld, int64_t n,
+                    const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
+                    int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st);
+void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);
+
+}  // namespace blm

@@ -1,0 +1,361 @@
+// Sample-streaming kernels of the blocked linear method on gfx950:
+//
+//  * gram_kernel: weighted Gram tiles C = X^T diag(w) Y over sample slices
+//    on the FP64 matrix cores (v_mfma_f64_16x16x4).  This is the Monte Carlo
+//    estimate of Eq. 3 restricted to each parameter block (the green
+//    elements of Fig. 1: S_b and H_b of the one-block basis, Eq. 4 / Eq. 10)
+//    and, in the second pass, the stage-two estimates of Eq. 7.
+//  * gram_reduce_kernel: fixed-order sum of the per-slice partial tiles into
+//    the FP64 accumulators (no floating-point atomics: bitwise
+//    reproducible).
+//  * dirproj_kernel: projection of every sample onto per-block directions,
+//    t_s = D . O_{s,k} (previous-update directions, Eq. 9) or y_s = B^(b) O_{s,b}
+//    (kept directions, Eq. 6).
+#include "blm_internal.h"
+
+namespace blm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  // D[i][j] += sum_k A[i][k] B[k][j], 16x16x4; lane l supplies A[l%16][l/16]
+  // and B[l/16][l%16]; D register r of lane l is D[4*r + l/16][l%16].
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Gram tiles
+// ---------------------------------------------------------------------------
+
+struct StageRegs {
+  double a[4], e[4], b[4], f[4];
+  double x, y;
+};
+
+__device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int64_t ro, int tid,
+                                          StageRegs& R) {
+  const int lr = tid >> 4;            // sample row within the stage (0..15)
+  const int lc = (tid & 15) * 4;      // first of 4 tile columns
+  const int64_t row = ro + lr;
+  const bool valid = row < S.n;
+  const bool aux = (J.kind == JOB_AUX);
+  const double* pO = aux ? S.Xa : S.O;
+  const double* pe = aux ? S.Ya : S.e;
+  const int64_t ld = aux ? (int64_t)NAUX : S.ld;
+  const double wgt = (valid && S.w) ? S.w[row] : 1.0;
+  const double* rO = pO + row * ld;
+  const double* re = pe + row * ld;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int col = lc + c;
+    const bool vi = valid && col < J.mi;
+    const bool vj = valid && col < J.nj;
+    R.a[c] = vi ? rO[J.ci + col] * wgt : 0.0;
+    R.e[c] = (vi && J.kind == JOB_OFF) ? re[J.ci + col] * wgt : 0.0;
+    R.b[c] = vj ? rO[J.cj + col] : 0.0;
+    R.f[c] = vj ? re[J.cj + col] : 0.0;
+  }
+  if (J.kind == JOB_DIAG) {
+    const int acol = tid & 15;
+    R.x = valid ? S.Xa[row * NAUX + acol] * wgt : 0.0;
+    R.y = valid ? S.Ya[row * NAUX + acol] * wgt : 0.0;
+  } else {
+    R.x = 0.0;
+    R.y = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __restrict__ jobs,
+                                                           int n_jobs,
+                                                           const Slice* __restrict__ slices,
+                                                           int n_slices, int P,
+                                                           double* __restrict__ partial) {
+  __shared__ double sA[2][GKS][GT];   // O_i * w
+  __shared__ double sE[2][GKS][GT];   // e_i * w
+  __shared__ double sB[2][GKS][GT];   // O_j
+  __shared__ double sF[2][GKS][GT];   // e_j
+  __shared__ double sX[2][GKS][NAUX]; // aux (1, Theta) * w
+  __shared__ double sY[2][GKS][NAUX]; // aux (E_L, Theta energy) * w
+
+  // XCD-aware order: the hardware deals workgroups round-robin over the 8
+  // XCDs; give each XCD a contiguous range of work items so that the tiles of
+  // one block and one slice set (which share their sample panels) run on the
+  // same L2.
+  const int G = gridDim.x, g = blockIdx.x;
+  const int q = G >> 3, r = G & 7, xcd = g & 7, idx = g >> 3;
+  const int wid = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+  const int p = wid / n_jobs, jid = wid % n_jobs;
+  const GramJob J = jobs[jid];
+  const int kind = J.kind;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = wv >> 1, wc = wv & 1;
+  const int i16 = lane & 15, k4 = lane >> 4;
+
+  d4 P0[2][2], P1[2][2], P2[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      P0[x][y] = d4{0, 0, 0, 0};
+      P1[x][y] = d4{0, 0, 0, 0};
+      P2[x][y] = d4{0, 0, 0, 0};
+    }
+
+  int si = p;
+  while (si < n_slices && slices[si].n <= 0) si += P;
+  int64_t ro = 0;
+  StageRegs R;
+  int buf = 0;
+  if (si < n_slices) {
+    Slice S = slices[si];
+    gram_load(J, S, ro, tid, R);
+    const int lr = tid >> 4, lc = (tid & 15) * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sA[0][lr][lc + c] = R.a[c];
+      sE[0][lr][lc + c] = R.e[c];
+      sB[0][lr][lc + c] = R.b[c];
+      sF[0][lr][lc + c] = R.f[c];
+    }
+    sX[0][lr][tid & 15] = R.x;
+    sY[0][lr][tid & 15] = R.y;
+  }
+  __syncthreads();
+
+  while (si < n_slices) {
+    // next stage
+    int si2 = si;
+    int64_t ro2 = ro + GKS;
+    if (ro2 >= slices[si2].n) {
+      si2 += P;
+      ro2 = 0;
+      while (si2 < n_slices && slices[si2].n <= 0) si2 += P;
+    }
+    const bool has_next = si2 < n_slices;
+    if (has_next) {
+      Slice S2 = slices[si2];
+      gram_load(J, S2, ro2, tid, R);
+    }
+
+#pragma unroll
+    for (int kk = 0; kk < GKS; kk += 4) {
+      const int kr = kk + k4;
+      const double a0 = sA[buf][kr][32 * wr + i16], a1 = sA[buf][kr][32 * wr + 16 + i16];
+      const double b0 = sB[buf][kr][32 * wc + i16], b1 = sB[buf][kr][32 * wc + 16 + i16];
+      const double f0 = sF[buf][kr][32 * wc + i16], f1 = sF[buf][kr][32 * wc + 16 + i16];
+      P0[0][0] = mfma_f64(a0, b0, P0[0][0]);
+      P0[0][1] = mfma_f64(a0, b1, P0[0][1]);
+      P0[1][0] = mfma_f64(a1, b0, P0[1][0]);
+      P0[1][1] = mfma_f64(a1, b1, P0[1][1]);
+      P1[0][0] = mfma_f64(a0, f0, P1[0][0]);
+      P1[0][1] = mfma_f64(a0, f1, P1[0][1]);
+      P1[1][0] = mfma_f64(a1, f0, P1[1][0]);
+      P1[1][1] = mfma_f64(a1, f1, P1[1][1]);
+      if (kind == JOB_OFF) {
+        const double e0 = sE[buf][kr][32 * wr + i16], e1 = sE[buf][kr][32 * wr + 16 + i16];
+        P2[0][0] = mfma_f64(e0, b0, P2[0][0]);
+        P2[0][1] = mfma_f64(e0, b1, P2[0][1]);
+        P2[1][0] = mfma_f64(e1, b0, P2[1][0]);
+        P2[1][1] = mfma_f64(e1, b1, P2[1][1]);
+      } else if (kind == JOB_DIAG) {
+        const double xs = sX[buf][kr][i16], ys = sY[buf][kr][i16];
+        const double bs = sB[buf][kr][16 * wv + i16], fs = sF[buf][kr][16 * wv + i16];
+        P2[0][0] = mfma_f64(xs, bs, P2[0][0]);   // aux^T W O_i
+        P2[0][1] = mfma_f64(xs, fs, P2[0][1]);   // aux^T W e_i
+        P2[1][0] = mfma_f64(ys, bs, P2[1][0]);   // auxE^T W O_i
+      }
+    }
+
+    if (has_next) {
+      const int lr = tid >> 4, lc = (tid & 15) * 4;
+      const int nb = buf ^ 1;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sA[nb][lr][lc + c] = R.a[c];
+        sE[nb][lr][lc + c] = R.e[c];
+        sB[nb][lr][lc + c] = R.b[c];
+        sF[nb][lr][lc + c] = R.f[c];
+      }
+      sX[nb][lr][tid & 15] = R.x;
+      sY[nb][lr][tid & 15] = R.y;
+    }
+    __syncthreads();
+    buf ^= 1;
+    si = si2;
+    ro = ro2;
+  }
+
+  double* base = partial + ((size_t)jid * P + p) * (size_t)(3 * GT * GT);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = 32 * wr + 16 * x + 4 * rr + k4;
+        const int col = 32 * wc + 16 * y + i16;
+        base[row * GT + col] = P0[x][y][rr];
+        base[GT * GT + row * GT + col] = P1[x][y][rr];
+        if (kind == JOB_OFF) base[2 * GT * GT + row * GT + col] = P2[x][y][rr];
+      }
+  if (kind == JOB_DIAG) {
+    // strips: [3][NAUX][GT] in the third slot
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int a = 4 * rr + k4;
+      const int c = 16 * wv + i16;
+      base[2 * GT * GT + 0 * NAUX * GT + a * GT + c] = P2[0][0][rr];
+      base[2 * GT * GT + 1 * NAUX * GT + a * GT + c] = P2[0][1][rr];
+      base[2 * GT * GT + 2 * NAUX * GT + a * GT + c] = P2[1][0][rr];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restrict__ jobs, int P,
+                                                          const double* __restrict__ partial,
+                                                          double* __restrict__ s_base,
+                                                          double* __restrict__ h_base,
+                                                          double* __restrict__ strip_base,
+                                                          int64_t strip_ld) {
+  const int jid = blockIdx.x, qd = blockIdx.y;
+  const GramJob J = jobs[jid];
+  const bool strips = (J.kind == JOB_DIAG);
+  if (qd == 2 && J.kind != JOB_OFF && !strips) return;
+  const int n_el = (qd == 2 && strips) ? 3 * NAUX * GT : GT * GT;
+  for (int el = threadIdx.x; el < n_el; el += blockDim.x) {
+    double sum = 0.0;
+    for (int pp = 0; pp < P; ++pp)
+      sum += partial[((size_t)jid * P + pp) * (size_t)(3 * GT * GT) + (size_t)qd * GT * GT + el];
+    if (qd == 2 && strips) {
+      const int sq = el / (NAUX * GT), a = (el / GT) % NAUX, c = el % GT;
+      if (c < J.mi) strip_base[(size_t)sq * NAUX * strip_ld + (size_t)a * strip_ld + J.strip_col + c] += sum;
+      continue;
+    }
+    const int row = el / GT, col = el % GT;
+    if (row >= J.mi || col >= J.nj) continue;
+    if (qd == 0) s_base[J.s_off + row * J.ld_out + col] += sum;
+    else if (qd == 1) h_base[J.h_off + row * J.ld_out + col] += sum;
+    else h_base[J.ht_off + col * J.ld_out + row] += sum;
+  }
+}
+
+void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
+                 double* d_partial, hipStream_t st) {
+  if (n_jobs <= 0) return;
+  hipLaunchKernelGGL(gram_kernel, dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs, n_jobs, d_slices,
+                     n_slices, P, d_partial);
+}
+
+void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
+                        double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
+                        hipStream_t st) {
+  if (n_jobs <= 0) return;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(n_jobs, 3), dim3(256), 0, st, d_jobs, P, d_partial,
+                     s_base, h_base, strip_base, strip_ld);
+}
+
+// ---------------------------------------------------------------------------
+// projection onto per-block directions
+// ---------------------------------------------------------------------------
+
+constexpr int PJ_ROWS = 64;   // samples per workgroup (16 per wave)
+constexpr int PJ_P = 32;      // parameters per LDS stage
+constexpr int PJ_D = 32;      // directions per pass (2 MFMA column groups)
+
+__global__ __launch_bounds__(256) void dirproj_kernel(const double* __restrict__ O,
+                                                      const double* __restrict__ e,
+                                                      const double* __restrict__ EL, int64_t ld,
+                                                      int64_t n, const DirBlock* __restrict__ blocks,
+                                                      int n_blocks,
+                                                      const double* const* __restrict__ dir_ptr,
+                                                      int n_dirs, double* __restrict__ Xo,
+                                                      double* __restrict__ Yo, int64_t ldo) {
+  __shared__ double sO[PJ_ROWS][PJ_P + 1];
+  __shared__ double sE[PJ_ROWS][PJ_P + 1];
+  __shared__ double sD[PJ_D][PJ_P + 1];
+  const int64_t s0 = (int64_t)blockIdx.x * PJ_ROWS;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+
+  // column 0 (the wave function itself: 1 and E_L) and the padding columns
+  for (int t = tid; t < PJ_ROWS * (int)ldo; t += blockDim.x) {
+    const int rr = t / (int)ldo, c = t % (int)ldo;
+    const int64_t s = s0 + rr;
+    if (s >= n) continue;
+    if (c == 0) {
+      Xo[s * ldo] = 1.0;
+      Yo[s * ldo] = EL[s];
+    } else if (c >= 1 + n_dirs) {
+      Xo[s * ldo + c] = 0.0;
+      Yo[s * ldo + c] = 0.0;
+    }
+  }
+
+  for (int bi = 0; bi < n_blocks; ++bi) {
+    const DirBlock B = blocks[bi];
+    for (int dg = 0; dg < B.nd; dg += PJ_D) {
+      d4 aO0 = {0, 0, 0, 0}, aO1 = {0, 0, 0, 0}, aE0 = {0, 0, 0, 0}, aE1 = {0, 0, 0, 0};
+      for (int p0 = 0; p0 < B.m; p0 += PJ_P) {
+        __syncthreads();
+        {
+          const int row = tid >> 2, c8 = (tid & 3) * 8;
+          const int64_t s = s0 + row;
+          const double* rO = O + s * ld + B.col0 + p0;
+          const double* rE = e + s * ld + B.col0 + p0;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int col = c8 + c;
+            const bool v = (s < n) && (p0 + col < B.m);
+            sO[row][col] = v ? rO[col] : 0.0;
+            sE[row][col] = v ? rE[col] : 0.0;
+          }
+          const int dr = tid >> 3, c4 = (tid & 7) * 4;
+          const int dd = dg + dr;
+          const double* rD = (dd < B.nd) ? dir_ptr[B.d0 + dd] : nullptr;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int col = c4 + c;
+            sD[dr][col] = (rD && p0 + col < B.m) ? rD[p0 + col] : 0.0;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < PJ_P; kk += 4) {
+          const int kc = kk + k4;
+          const double ao = sO[16 * wv + i16][kc], ae = sE[16 * wv + i16][kc];
+          const double b0 = sD[i16][kc], b1 = sD[16 + i16][kc];
+          aO0 = mfma_f64(ao, b0, aO0);
+          aO1 = mfma_f64(ao, b1, aO1);
+          aE0 = mfma_f64(ae, b0, aE0);
+          aE1 = mfma_f64(ae, b1, aE1);
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int64_t s = s0 + 16 * wv + 4 * rr + k4;
+        if (s >= n) continue;
+        const int t0 = dg + i16, t1 = dg + 16 + i16;
+        if (t0 < B.nd) {
+          Xo[s * ldo + 1 + B.d0 + t0] = aO0[rr];
+          Yo[s * ldo + 1 + B.d0 + t0] = aE0[rr];
+        }
+        if (t1 < B.nd) {
+          Xo[s * ldo + 1 + B.d0 + t1] = aO1[rr];
+          Yo[s * ldo + 1 + B.d0 + t1] = aE1[rr];
+        }
+      }
+    }
+  }
+}
+
+void launch_dirproj(const double* O, const double* e, const double* EL, int64_t ld, int64_t n,
+                    const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
+                    int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st) {
+  if (n <= 0) return;
+  const int grid = (int)((n + PJ_ROWS - 1) / PJ_ROWS);
+  hipLaunchKernelGGL(dirproj_kernel, dim3(grid), dim3(256), 0, st, O, e, EL, ld, n, d_blocks,
+                     n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+}
+
+}  // namespace blm

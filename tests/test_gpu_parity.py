@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Same seeded input bytes go to both sides.  Tolerances: FP64 path, matrices
+within 1e-12 relative Frobenius, energies within 1e-10 relative; kept
+direction spans and the update are compared through quantities that do not
+depend on the choice of basis inside a span (projectors, the update itself).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import blm_oracle as orc
+from paper_1702_01481_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _blm():
+    from paper_1702_01481_amd import blm
+    return blm
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _make(n_params, n_samples, rank, seed, chunk, weighted=False, sigma_E=0.5):
+    g = synth.SampleGenerator(n_params, rank, seed, sigma_E=sigma_E)
+    O, e, EL = g.chunk(0, n_samples)
+    w = synth.weights(n_samples, seed) if weighted else None
+    host, dev = [], []
+    for a in range(0, n_samples, chunk):
+        b = min(n_samples, a + chunk)
+        wc = None if w is None else w[a:b]
+        host.append((O[a:b].numpy(), e[a:b].numpy(), EL[a:b].numpy(), None if wc is None else wc.numpy()))
+        dev.append((O[a:b].cuda().contiguous(), e[a:b].cuda().contiguous(), EL[a:b].cuda().contiguous(),
+                    None if wc is None else wc.cuda().contiguous()))
+    return host, dev
+
+
+def _run_gpu(offsets, n_keep, n_old, shifts, dev_chunks, old=None, max_samples=None):
+    blm = _blm()
+    n_params = int(offsets[-1])
+    tot = sum(c[0].shape[0] for c in dev_chunks)
+    ctx = blm.BLM(n_params, offsets, n_keep, n_old, shifts, max_samples or tot)
+    ctx.begin_step(None if old is None else torch.from_numpy(old).cuda().contiguous())
+    ctx.build(dev_chunks)
+    ev, kept = ctx.solve()
+    ctx.project(dev_chunks)
+    upd, en, al, fl = ctx.stage2()
+    torch.cuda.synchronize()
+    return ctx, ev, kept, upd.cpu().numpy(), en, al, fl
+
+
+def _compare_step(offsets, n_keep, shifts, host, dev, old=None, n_old=0, mat_tol=1e-12, en_tol=1e-10):
+    offsets = np.asarray(offsets)
+    res, probs = orc.blm_step(lambda: host, offsets, n_keep, shifts, old=old)
+    ctx, ev, kept, upd, en, al, fl = _run_gpu(offsets, n_keep, n_old, shifts, dev, old=old)
+    nb = len(offsets) - 1
+    for si, delta in enumerate(shifts):
+        r = res[si]
+        for b in range(nb):
+            H, S = ctx.block_matrices(b, si)
+            p = probs[b]
+            assert H.shape == p.H.shape
+            assert _rel(S, p.S) <= mat_tol, (b, si, _rel(S, p.S))
+            assert _rel(H, p.H + delta * p.P) <= mat_tol, (b, si, _rel(H, p.H + delta * p.P))
+            # kept span: same count, same projector
+            B = ctx.directions(b, si)
+            Bo = r.blocks[b].B
+            assert B.shape == Bo.shape, (b, si, B.shape, Bo.shape)
+            np.testing.assert_allclose(B @ B.T, np.eye(B.shape[0]), atol=1e-12)
+            assert np.abs(B.T @ B - Bo.T @ Bo).max() < 1e-8, (b, si)
+        # stage-two estimates on the GPU's own directions
+        Bs = [ctx.directions(b, si) for b in range(nb)]
+        H2o, S2o, _ = orc.stage2_matrices(host, offsets, Bs)
+        H2, S2 = ctx.stage2_matrices(si)
+        assert _rel(S2, S2o) <= mat_tol and _rel(H2, H2o) <= mat_tol, (si, _rel(S2, S2o), _rel(H2, H2o))
+        # energy and update against the oracle's whole step
+        assert abs(en[si] - r.step.energy) <= en_tol * abs(r.step.energy), (si, en[si], r.step.energy)
+        cos = upd[si] @ r.step.dmu / (np.linalg.norm(upd[si]) * np.linalg.norm(r.step.dmu))
+        assert cos > 1 - 1e-10, (si, cos)
+        assert _rel(upd[si], r.step.dmu) < 1e-7, (si, _rel(upd[si], r.step.dmu))
+    ctx.close()
+
+
+def test_eigvals_match_lapack():
+    blm = _blm()
+    rng = np.random.default_rng(7)
+    for d in (1, 2, 3, 5, 17, 51, 64, 65, 130, 257):
+        A = rng.standard_normal((d, d))
+        S = A @ A.T / d + np.eye(d)
+        H = rng.standard_normal((d, d)) - 10.0 * np.eye(d)
+        got = blm.debug_eigvals(torch.from_numpy(H).cuda(), torch.from_numpy(S).cuda())
+        ref, _ = orc.generalized_eig(H, S)
+        dist = np.abs(got[:, None] - ref[None, :])
+        scale = np.abs(ref).max()
+        assert dist.min(axis=1).max() < 1e-10 * scale, (d, dist.min(axis=1).max())
+        assert dist.min(axis=0).max() < 1e-10 * scale, (d, dist.min(axis=0).max())
+
+
+def test_small_workload_step():
+    """The 200-parameter, 20,000-sample workload (4 blocks of 50, N_K = 3)."""
+    w = synth.workload("small")
+    host, dev = _make(w.n_params, w.n_samples, w.rank, 0, w.chunk)
+    _compare_step(w.block_offsets, w.n_keep, list(w.shifts), host, dev)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_previous_directions_ragged_chunks(weighted):
+    """N_O = 1 and 2, uneven blocks, several shifts, chunks with a ragged tail."""
+    offsets = [0, 37, 70, 130, 131, 200]
+    host, dev = _make(200, 9000, 6, 4, 4000, weighted=weighted)
+    old = synth.old_directions(2, 200, 9).numpy()
+    old[1, 37:70] = 0.0                       # one dropped piece
+    _compare_step(offsets, 2, [1e-4, 1e-3, 1e-2], host, dev, old=old, n_old=2)
+
+
+def test_multi_tile_blocks():
+    """Blocks spanning several 64-wide tiles with ragged edges."""
+    offsets = [0, 150, 341]
+    host, dev = _make(341, 20000, 8, 5, 7777)
+    old = synth.old_directions(1, 341, 2).numpy()
+    _compare_step(offsets, 4, [1e-3], host, dev, old=old, n_old=1)
+
+
+def test_dyadic_inputs_are_bit_exact():
+    """Small-integer samples: every partial sum is exact, so the block
+    matrices must equal the oracle's bit for bit (N_s a power of two)."""
+    n, nv = 4096, 96
+    O, e, EL = synth.dyadic_chunk(n, nv, 3)
+    offsets = [0, 40, 96]
+    host = [(O.numpy(), e.numpy(), EL.numpy(), None)]
+    dev = [(O.cuda(), e.cuda(), EL.cuda(), None)]
+    blm = _blm()
+    ctx = blm.BLM(nv, offsets, 2, 0, [0.0], n)
+    ctx.begin_step()
+    ctx.build(dev)
+    D = orc.previous_directions(None, np.array(offsets))
+    probs, _ = orc.block_problems(host, np.array(offsets), D)
+    for b in range(2):
+        H, S = ctx.block_matrices(b, 0)
+        Sx = np.triu(probs[b].S) + np.triu(probs[b].S, 1).T
+        assert np.array_equal(S, Sx)
+        assert np.array_equal(H, probs[b].H)
+    ctx.close()
+
+
+def test_planted_exact_eigenstate():
+    """Zero-variance model, exact enumeration, previous direction = planted
+    step: the GPU path must return the planted update."""
+    O, e, EL, w, delta, E0 = synth.planted_zero_variance(40, 12, 0)
+    dev = [(torch.from_numpy(O).cuda().contiguous(), torch.from_numpy(e).cuda().contiguous(),
+            torch.from_numpy(EL).cuda().contiguous(), torch.from_numpy(w).cuda().contiguous())]
+    ctx, ev, kept, upd, en, al, fl = _run_gpu([0, 4, 8, 12], 1, 1, [0.0], dev, old=delta[None, :].copy())
+    assert abs(en[0] - E0) < 1e-10 * abs(E0)
+    np.testing.assert_allclose(upd[0], delta, rtol=1e-8, atol=1e-9)
+    ctx.close()
+
+
+def test_error_paths():
+    blm = _blm()
+    host, dev = _make(30, 500, 3, 1, 500)
+    ctx = blm.BLM(30, [0, 15, 30], 2, 0, [1e-3], 1000)
+    with pytest.raises(blm.BLMError) as ei:
+        ctx.solve()
+    assert ei.value.status == 2
+    ctx.begin_step()
+    ctx.build(dev)
+    ctx.solve()
+    O, e, EL, _ = dev[0]
+    ctx.project([(O[:400], e[:400], EL[:400])])
+    with pytest.raises(blm.BLMError) as ei:
+        ctx.stage2()
+    assert ei.value.status == 2
+    # duplicated parameter columns: S not positive definite
+    O2 = O.clone()
+    O2[:, 1] = O2[:, 0]
+    ctx.begin_step()
+    ctx.build([(O2, e, EL)])
+    with pytest.raises(blm.BLMError) as ei:
+        ctx.solve()
+    assert ei.value.status == 5
+    # NaN in the samples
+    e2 = e.clone()
+    e2[3, 4] = float("nan")
+    ctx.begin_step()
+    ctx.build([(O, e2, EL)])
+    with pytest.raises(blm.BLMError) as ei:
+        ctx.solve()
+    assert ei.value.status in (6, 7)
+    # too many samples for the workspace
+    with pytest.raises(blm.BLMError) as ei:
+        ctx.begin_step()
+        ctx.build([(O, e, EL), (O, e, EL), (O, e, EL)])
+    assert ei.value.status == 1
+    ctx.close()

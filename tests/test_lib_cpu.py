@@ -1,0 +1,46 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every function include/blm.h declares, and sizes its workspace."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1702_01481_amd import blm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "blm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(blm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(blm.LIB_PATH):
+        pytest.skip("libblm.so not built")
+    lib = ctypes.CDLL(blm.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(blm.EXPORTED)
+
+
+def test_workspace_bytes_and_argument_checks():
+    if not os.path.exists(blm.LIB_PATH):
+        pytest.skip("libblm.so not built")
+    off = np.array([0, 512 * 1, 512 * 2, 512 * 3, 512 * 4, 512 * 5, 512 * 6, 512 * 7, 4096])
+    b = blm.BLM.workspace_bytes(4096, off, 5, 1, [1e-4, 1e-3, 1e-2], 1_000_000)
+    # dominated by the per-sample aux and stage-two projection buffers
+    assert 1e9 < b < 2e10
+    small = blm.BLM.workspace_bytes(4096, off, 5, 1, [1e-3], 65536)
+    assert small < b
+    with pytest.raises(blm.BLMError):
+        blm.BLM.workspace_bytes(4096, off, 5, 2, [1e-3], 65536)      # 1 + N_O N_B > 16
+    with pytest.raises(blm.BLMError):
+        blm.BLM.workspace_bytes(4096, off[::-1].copy(), 5, 1, [1e-3], 65536)
+    with pytest.raises(blm.BLMError):
+        blm.BLM.workspace_bytes(4096, off, 5, 1, [-1.0], 65536)
