@@ -30,6 +30,10 @@ METRIC = "block H/S build TFLOP/s + BLM step ms; mixed vs FP64 at ≤1e-6 rel en
 PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 (matrix and vector)
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def build_flops(offsets, n_old, n_samples) -> float:
     nb = len(offsets) - 1
     tot = 0.0
@@ -110,6 +114,7 @@ def main():
         chunks.append((O, e, EL))
     del gen
     torch.cuda.synchronize()
+    log(f"generated {len(chunks)} chunks, {n_samples} samples x {w.n_params} params in HBM")
 
     ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, n_samples)
     ctx.set_timing(True)
@@ -122,11 +127,14 @@ def main():
         return ctx.stage2()
 
     # previous direction: one step without history (zero rows are dropped)
+    t1 = time.perf_counter()
     upd, en0, _, _ = step(torch.zeros(w.n_old, w.n_params, dtype=torch.float64, device=dev))
     old = upd[1:2].clone().contiguous()
+    log(f"history step done in {time.perf_counter() - t1:.3f} s: {ctx.timings()}")
     for _ in range(args.warmup):
         step(old)
     torch.cuda.synchronize()
+    log("warmup done")
 
     phase = {k: [] for k in blm.TIMING_NAMES}
     t0 = time.perf_counter()
@@ -134,10 +142,16 @@ def main():
         upd, en, al, fl = step(old)
         for k, v in ctx.timings().items():
             phase[k].append(v)
+        log(f"step {len(phase['block_gram'])} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
 
+    st = ctx.solver_stats()
+    eig_phase_names = ("cholesky", "congruence", "hessenberg", "qr", "select", "inverse_iter",
+                       "back_transform", "orthonormalise")
+    eig_phases = {k: round(float(st[:, 4 + i].max()) / 1e5, 3) for i, k in enumerate(eig_phase_names)}
+    eig_phases["qr_sweeps_max"] = int(st[:, 3].max())
     fl_build = build_flops(offsets, w.n_old, n_samples)
     gram_ms = float(np.mean(phase["block_gram"]))
     build_ms = float(np.mean([a + b + c for a, b, c in zip(phase["theta_proj"], phase["block_gram"],
@@ -162,6 +176,7 @@ def main():
         "build_tflops": round(fl_build / (build_ms * 1e-3) / 1e12, 4),
         "build_ms": round(build_ms, 3),
         "phase_ms": {k: round(float(np.mean(v)), 3) for k, v in phase.items()},
+        "block_eig_phase_ms_max": eig_phases,
         "energy": [float(x) for x in en],
         "flags": [int(x) for x in fl],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64,
@@ -170,6 +185,7 @@ def main():
                      "flops_per_launch": fl_build},
     }
     if not args.no_cpu_baseline:
+        log("timing the CPU oracle on one chunk")
         O0, e0, EL0 = chunks[0]
         cb = cpu_baseline(O0, e0, EL0, None, offsets, old.cpu().numpy(), w.n_keep, shifts)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

@@ -24,7 +24,8 @@ FLAG_COMPLEX_ENERGY, FLAG_PAIR_KEPT, FLAG_SMALL_ALPHA = 1, 2, 4
 EXPORTED = ("blm_workspace_bytes", "blm_create", "blm_destroy", "blm_begin_step",
             "blm_build_blocks", "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
-            "blm_debug_eigvals", "blm_set_timing", "blm_get_timings", "blm_last_error",
+            "blm_debug_eigvals", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
+            "blm_last_error",
             "blm_status_string")
 TIMING_NAMES = ("theta_proj", "block_gram", "block_reduce", "block_assemble", "block_eig",
                 "dir_proj", "stage2_gram", "stage2_reduce", "stage2_solve")
@@ -72,6 +73,7 @@ def load() -> C.CDLL:
     lib.blm_get_directions.argtypes = [vp, i32, i32, dp, C.POINTER(i32)]
     lib.blm_get_stage2_matrices.argtypes = [vp, i32, dp, dp, C.POINTER(i32)]
     lib.blm_debug_eigvals.argtypes = [vp, vp, i32, dp, vp]
+    lib.blm_get_solver_stats.argtypes = [vp, C.POINTER(i32), i32]
     lib.blm_set_timing.argtypes = [vp, i32]
     lib.blm_get_timings.argtypes = [vp, dp, i32]
     lib.blm_last_error.argtypes = [vp]
@@ -221,6 +223,13 @@ class BLM:
     # -- diagnostics ------------------------------------------------------
     def set_timing(self, enable: bool = True):
         self._check(self.lib.blm_set_timing(self.h, 1 if enable else 0))
+
+    def solver_stats(self) -> np.ndarray:
+        """[n_shifts * N_B][16] int32 statistics of the last block solve."""
+        n = len(self.shifts) * self.n_blocks * 16
+        out = np.zeros(n, dtype=np.int32)
+        self._check(self.lib.blm_get_solver_stats(self.h, out.ctypes.data_as(C.POINTER(C.c_int32)), n))
+        return out.reshape(-1, 16)
 
     def timings(self) -> dict:
         """Durations (ms) of the last call of each phase, from HIP events."""

@@ -27,6 +27,7 @@ using namespace blm;
 
 namespace {
 
+constexpr int MAX_CHUNKS = 4096;   // chunks in one build / project call
 constexpr int ST_CREATED = 0, ST_BEGUN = 1, ST_BUILT = 2, ST_SOLVED = 3, ST_PROJECTED = 4,
               ST_DONE = 5;
 
@@ -79,6 +80,9 @@ struct blm_ctx {
   GramJob *d_jobs1 = nullptr, *d_jobs2 = nullptr;
   int n_jobs1 = 0, n_jobs2 = 0;
   Slice* d_slices = nullptr;
+  ProjChunk* d_pchunks = nullptr;
+  std::vector<ProjChunk> h_pchunks;
+  bool offsets_even = false;
   DirBlock *d_theta_blk = nullptr, *d_dir2_blk = nullptr;
   const double **d_theta_ptr = nullptr, **d_dir2_ptr = nullptr;
   int32_t* d_auxlist = nullptr;    // per block: [1 + N_O (N_B - 1)]
@@ -102,7 +106,8 @@ struct blm_ctx {
   std::vector<std::vector<int>> auxlist;   // per block
   std::vector<int> nkept;          // [NS][NB]
   std::vector<int> pairkept;       // [NS][NB]
-  int n2 = 0;
+  std::vector<int32_t> last_info1; // solver statistics of the last block solve
+  int n2 = 0, ld2 = 0;               // stage-two columns; row stride of Yp / Zp (even)
   std::vector<std::vector<int>> idx2;   // per shift
   int64_t n_pass1 = 0, n_pass2 = 0;
   std::vector<Slice> h_slices;
@@ -326,6 +331,7 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_jobs1, sizeof(GramJob) * (size_t)c->n_jobs1);
   add((void**)&c->d_jobs2, sizeof(GramJob) * (size_t)n_jobs2max);
   add((void**)&c->d_slices, sizeof(Slice) * (size_t)c->max_slices);
+  add((void**)&c->d_pchunks, sizeof(ProjChunk) * (size_t)MAX_CHUNKS);
   add((void**)&c->d_theta_blk, sizeof(DirBlock) * (size_t)NB);
   add((void**)&c->d_theta_ptr, sizeof(double*) * (size_t)std::max(NO * NB, 1));
   add((void**)&c->d_dir2_blk, sizeof(DirBlock) * (size_t)NB);
@@ -336,12 +342,12 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_asm1, sizeof(AsmJob) * (size_t)NS * NB);
   add((void**)&c->d_asm2, sizeof(AsmJob) * (size_t)NS);
   add((void**)&c->d_asm_x, sizeof(AsmJob));
-  add((void**)&c->d_info1, 16 * (size_t)NS * NB);
-  add((void**)&c->d_info2, 16 * (size_t)NS);
+  add((void**)&c->d_info1, 4 * EIG_INFO * (size_t)NS * NB);
+  add((void**)&c->d_info2, 4 * EIG_INFO * (size_t)NS);
   add((void**)&c->d_ev1, 16 * (size_t)NS * NB * (NK + 1));
   add((void**)&c->d_ev2, 16 * (size_t)NS * 2);
-  add((void**)&c->Yp, 8 * (size_t)c->max_samples * c->n2max);
-  add((void**)&c->Zp, 8 * (size_t)c->max_samples * c->n2max);
+  add((void**)&c->Yp, 8 * (size_t)c->max_samples * (c->n2max + 1));
+  add((void**)&c->Zp, 8 * (size_t)c->max_samples * (c->n2max + 1));
   add((void**)&c->G2S, 8 * (size_t)c->n2max * c->n2max);
   add((void**)&c->G2H, 8 * (size_t)c->n2max * c->n2max);
   add((void**)&c->d_idx2, 4 * (size_t)NS * c->n2max);
@@ -431,6 +437,7 @@ int choose_P(int cap, int n_jobs, int n_slices) {
 
 blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) {
   if (n < 0 || (n > 0 && !ch)) return fail(c, BLM_E_ARG, "bad chunk list");
+  if (n > MAX_CHUNKS) return fail(c, BLM_E_ARG, "more than 4096 chunks in one call");
   int64_t t = 0;
   for (int i = 0; i < n; ++i) {
     if (ch[i].n_samples < 0) return fail(c, BLM_E_ARG, "negative n_samples");
@@ -444,16 +451,51 @@ blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) 
   return BLM_OK;
 }
 
+// One projection launch over all chunks of a call; returns via c->h_pchunks.
+blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d_blocks,
+                       int n_blocks, const double* const* d_ptr, int n_dirs, double* Xo,
+                       double* Yo, int64_t ldo) {
+  c->h_pchunks.clear();
+  int tiles = 0;
+  int64_t rb = 0;
+  bool vec = c->offsets_even;
+  for (int i = 0; i < n; ++i) {
+    const int64_t ns = ch[i].n_samples;
+    if (ns == 0) continue;
+    ProjChunk P{};
+    P.O = ch[i].O;
+    P.e = ch[i].e;
+    P.EL = ch[i].E_L;
+    P.ld = ch[i].ld;
+    P.n = ns;
+    P.row_base = rb;
+    P.tile0 = tiles;
+    c->h_pchunks.push_back(P);
+    tiles += (int)((ns + PROJ_ROWS - 1) / PROJ_ROWS);
+    rb += ns;
+    if ((ch[i].ld & 1) || ((uintptr_t)ch[i].O & 15) || ((uintptr_t)ch[i].e & 15)) vec = false;
+  }
+  if (c->h_pchunks.empty()) return BLM_OK;
+  HIPCHK(c, hipMemcpyAsync(c->d_pchunks, c->h_pchunks.data(), sizeof(ProjChunk) * c->h_pchunks.size(),
+                           hipMemcpyHostToDevice, c->st));
+  launch_dirproj(c->d_pchunks, (int)c->h_pchunks.size(), tiles, vec, d_blocks, n_blocks, d_ptr, n_dirs,
+                 Xo, Yo, ldo, c->st);
+  HIPCHK(c, hipGetLastError());
+  return BLM_OK;
+}
+
 blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_base,
-                    double* h_base, double* strip_base, int phase) {
+                    double* h_base, double* strip_base, int phase, bool vec) {
   const int n_slices = (int)c->h_slices.size();
   if (n_slices == 0) return BLM_OK;
+  for (const Slice& S : c->h_slices)
+    if ((S.ld & 1) || ((uintptr_t)S.O & 15) || ((uintptr_t)S.e & 15)) vec = false;
   if (n_slices > c->max_slices) return fail(c, BLM_E_ARG, "too many slices in one call");
   HIPCHK(c, hipMemcpyAsync(c->d_slices, c->h_slices.data(), sizeof(Slice) * n_slices,
                            hipMemcpyHostToDevice, c->st));
   const int P = choose_P(cap, n_jobs, n_slices);
   mark(c, phase, false);
-  launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, c->partial, c->st);
+  launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec, c->partial, c->st);
   HIPCHK(c, hipGetLastError());
   mark(c, phase, true);
   mark(c, phase + 1, false);
@@ -500,6 +542,13 @@ blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes) {
   size_t t = 0;
   for (auto& it : P.items) t += (it.second + 255) / 256 * 256;
   *bytes = t + eig_total_bytes(&tmp);
+  return BLM_OK;
+}
+
+blm_status blm_get_solver_stats(blm_ctx* c, int32_t* h_stats, int32_t n) {
+  if (!c || !h_stats || n < 0) return BLM_E_ARG;
+  const int m = std::min<int>(n, (int)c->last_info1.size());
+  std::copy(c->last_info1.begin(), c->last_info1.begin() + m, h_stats);
   return BLM_OK;
 }
 
@@ -553,6 +602,9 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
   c->shifts.assign(cfg->shifts, cfg->shifts + cfg->n_shifts);
   c->max_samples = cfg->max_samples;
   c->st = (hipStream_t)stream;
+  c->offsets_even = true;
+  for (int64_t o : c->off)
+    if (o & 1) c->offsets_even = false;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return BLM_E_HIP;
@@ -582,13 +634,13 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
         const int M = (int)(c->off[b + 1] - c->off[b]);
         const int i = sh * c->NB + b;
         double* start = q;
-        c->eig1.push_back(carve(q, c->dmax[b], M, c->NK, EIG_BLOCK, c->NK, 1, c->d_info1 + 4 * i,
+        c->eig1.push_back(carve(q, c->dmax[b], M, c->NK, EIG_BLOCK, c->NK, 1, c->d_info1 + EIG_INFO * i,
                                 c->d_ev1 + 2 * (size_t)i * (c->NK + 1)));
         q = start + eig_bytes(c->dmax[b], M, c->NK) / 8;
       }
     for (int sh = 0; sh < c->NS; ++sh) {
       double* start = q;
-      c->eig2.push_back(carve(q, c->d2max, c->d2max, 1, EIG_STAGE2, 1, 0, c->d_info2 + 4 * sh,
+      c->eig2.push_back(carve(q, c->d2max, c->d2max, 1, EIG_STAGE2, 1, 0, c->d_info2 + EIG_INFO * sh,
                               c->d_ev2 + 4 * (size_t)sh));
       q = start + eig_bytes(c->d2max, c->d2max, 1) / 8;
     }
@@ -674,16 +726,15 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   int64_t total = 0;
   blm_status s = check_chunks(c, ch, n, &total);
   if (s != BLM_OK) return s;
+  mark(c, 0, false);
+  s = run_dirproj(c, ch, n, c->d_theta_blk, c->NO > 0 ? c->NB : 0, c->d_theta_ptr, c->NO * c->NB,
+                  c->Xa, c->Ya, NAUX);
+  if (s != BLM_OK) return s;
   c->h_slices.clear();
   int64_t rb = 0;
-  mark(c, 0, false);
   for (int i = 0; i < n; ++i) {
     const int64_t ns = ch[i].n_samples;
     if (ns == 0) continue;
-    launch_dirproj(ch[i].O, ch[i].e, ch[i].E_L, ch[i].ld, ns, c->d_theta_blk, c->NO > 0 ? c->NB : 0,
-                   c->d_theta_ptr, c->NO * c->NB, c->Xa + (size_t)rb * NAUX,
-                   c->Ya + (size_t)rb * NAUX, NAUX, c->st);
-    HIPCHK(c, hipGetLastError());
     for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
       Slice S{};
       S.O = ch[i].O + (size_t)s0 * ch[i].ld;
@@ -698,7 +749,7 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     rb += ns;
   }
   mark(c, 0, true);
-  s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1);
+  s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even);
   if (s != BLM_OK) return s;
   c->n_pass1 += total;
   c->state = ST_BUILT;
@@ -755,7 +806,7 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   launch_eig(c->d_eig1, (int)ej.size(), c->st);
   HIPCHK(c, hipGetLastError());
   mark(c, 4, true);
-  std::vector<int32_t> info((size_t)4 * NS * NB);
+  std::vector<int32_t> info((size_t)EIG_INFO * NS * NB);
   std::vector<double> ev((size_t)2 * NS * NB * (NK + 1));
   HIPCHK(c, hipMemcpyAsync(info.data(), c->d_info1, 4 * info.size(), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipMemcpyAsync(ev.data(), c->d_ev1, 8 * ev.size(), hipMemcpyDeviceToHost, c->st));
@@ -765,11 +816,12 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   for (int i = 0; i < NS * NB; ++i) {
     char what[64];
     snprintf(what, sizeof what, "block %d, shift %d", i % NB, i / NB);
-    blm_status s = eig_status(c, info[4 * i], what);
+    blm_status s = eig_status(c, info[EIG_INFO * i], what);
     if (s != BLM_OK) return s;
-    c->nkept[i] = info[4 * i + 1];
-    c->pairkept[i] = info[4 * i + 2];
+    c->nkept[i] = info[EIG_INFO * i + 1];
+    c->pairkept[i] = info[EIG_INFO * i + 2];
   }
+  c->last_info1 = info;
   if (h_evals) std::copy(ev.begin(), ev.end(), h_evals);
   if (h_kept) std::copy(c->nkept.begin(), c->nkept.end(), h_kept);
 
@@ -792,6 +844,7 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
     db[k].nd = (int)dp.size() - db[k].d0;
   }
   c->n2 = 1 + (int)dp.size();
+  c->ld2 = (c->n2 + 1) & ~1;
   c->idx2.assign(NS, {});
   std::vector<int32_t> flat((size_t)NS * c->n2max, 0);
   for (int sh = 0; sh < NS; ++sh) {
@@ -838,16 +891,15 @@ blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   int64_t total = 0;
   blm_status s = check_chunks(c, ch, n, &total);
   if (s != BLM_OK) return s;
-  const int64_t ldo = c->n2;
+  const int64_t ldo = c->ld2;
+  mark(c, 5, false);
+  s = run_dirproj(c, ch, n, c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->n2 - 1, c->Yp, c->Zp, ldo);
+  if (s != BLM_OK) return s;
   c->h_slices.clear();
   int64_t rb = 0;
-  mark(c, 5, false);
   for (int i = 0; i < n; ++i) {
     const int64_t ns = ch[i].n_samples;
     if (ns == 0) continue;
-    launch_dirproj(ch[i].O, ch[i].e, ch[i].E_L, ch[i].ld, ns, c->d_dir2_blk, c->NB, c->d_dir2_ptr,
-                   c->n2 - 1, c->Yp + (size_t)rb * ldo, c->Zp + (size_t)rb * ldo, ldo, c->st);
-    HIPCHK(c, hipGetLastError());
     for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
       Slice S{};
       S.O = c->Yp + (size_t)(rb + s0) * ldo;
@@ -860,7 +912,7 @@ blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     rb += ns;
   }
   mark(c, 5, true);
-  s = run_gram(c, c->d_jobs2, c->n_jobs2, c->Pcap2, c->G2S, c->G2H, nullptr, 6);
+  s = run_gram(c, c->d_jobs2, c->n_jobs2, c->Pcap2, c->G2S, c->G2H, nullptr, 6, true);
   if (s != BLM_OK) return s;
   c->n_pass2 += total;
   c->state = ST_PROJECTED;
@@ -905,7 +957,7 @@ blm_status blm_stage2(blm_ctx* c, double* d_update, double* h_energy, double* h_
   HIPCHK(c, hipGetLastError());
   launch_eig(c->d_eig2, NS, c->st);
   HIPCHK(c, hipGetLastError());
-  std::vector<int32_t> info((size_t)4 * NS);
+  std::vector<int32_t> info((size_t)EIG_INFO * NS);
   std::vector<double> ev((size_t)4 * NS);
   HIPCHK(c, hipMemcpyAsync(info.data(), c->d_info2, 4 * info.size(), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipMemcpyAsync(ev.data(), c->d_ev2, 8 * ev.size(), hipMemcpyDeviceToHost, c->st));
@@ -920,7 +972,7 @@ blm_status blm_stage2(blm_ctx* c, double* d_update, double* h_energy, double* h_
   for (int sh = 0; sh < NS; ++sh) {
     char what[64];
     snprintf(what, sizeof what, "stage two, shift %d", sh);
-    blm_status s = eig_status(c, info[4 * sh], what);
+    blm_status s = eig_status(c, info[EIG_INFO * sh], what);
     if (s != BLM_OK) return s;
     const int d = ej[sh].d;
     const double* vr = vecs[sh].data();

@@ -611,16 +611,21 @@ __device__ void back_transform_wave(const double* V, const double* tau, const do
   }
 }
 
+// Phase clock (100 MHz constant counter): info[4 + i] = ticks spent in phase i.
+__device__ __forceinline__ void phase_mark(const EigJob& J, uint64_t& t, int i) {
+  const uint64_t now = wall_clock64();
+  if (threadIdx.x == 0) J.info[4 + i] = (int32_t)(now - t);
+  t = now;
+}
+
 __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs) {
   __shared__ Shared sh;
   const EigJob J = jobs[blockIdx.x];
   const int d = J.d, tid = threadIdx.x, wv = tid >> 6;
+  uint64_t clk = wall_clock64();
   if (tid == 0) {
     sh.isc[2] = 0;
-    J.info[0] = EIG_OK;
-    J.info[1] = 0;
-    J.info[2] = 0;
-    J.info[3] = 0;
+    for (int i = 0; i < EIG_INFO; ++i) J.info[i] = 0;
   }
   __syncthreads();
   if (d <= 0 || d > EIG_MAXD) return;
@@ -630,8 +635,11 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
     if (tid == 0) J.info[0] = st;
     return;
   }
+  phase_mark(J, clk, 0);
   congruence(sh, J.S, J.A, d);
+  phase_mark(J, clk, 1);
   hessenberg(sh, J.A, J.V, J.tau, d);
+  phase_mark(J, clk, 2);
   for (size_t i = tid; i < (size_t)d * d; i += NT) J.Hq[i] = J.A[i];
   __syncthreads();
   // norm of the Hessenberg matrix for the inverse-iteration pivot floor
@@ -641,6 +649,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
   int iters = 0;
   st = hessenberg_eigvals(sh, J.A, J.wr, J.wi, d, &iters);
   __syncthreads();
+  phase_mark(J, clk, 3);
   if (tid == 0) J.info[3] = iters;
   if (st == EIG_OK && sh.isc[2]) st = EIG_NONFINITE;
   if (st != EIG_OK) {
@@ -655,11 +664,13 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
   const double eps3 = EPS * fmax(hnorm, 1e-300);
 
   // eigenvectors of the chosen eigenvalues, complex, into vec[s][0|1][d]
+  phase_mark(J, clk, 4);
   for (int s = 0; s < n_sel; ++s) {
     double* yr = J.vec + (size_t)(2 * s) * d;
     double* yi = yr + d;
     inverse_iteration(sh, J.Hq, J.W, J.W + (size_t)d * d, d, sh.sel_r[s], sh.sel_i[s], eps3, yr, yi);
   }
+  phase_mark(J, clk, 5);
   // back to the pencil's coordinates: one wave per real vector
   const int n_real = 2 * n_sel;
   for (int v = wv; v < n_real; v += NW) {
@@ -668,6 +679,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
     back_transform_wave(J.V, J.tau, J.S, J.vec + (size_t)v * d, d);
   }
   __syncthreads();
+  phase_mark(J, clk, 6);
 
   if (J.mode == EIG_STAGE2) {
     for (int i = tid; i < d; i += NT) {
@@ -720,6 +732,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
     J.info[1] = kept;
     J.info[2] = pair;
   }
+  phase_mark(J, clk, 7);
 }
 
 }  // namespace

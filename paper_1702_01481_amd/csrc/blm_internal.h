@@ -53,6 +53,20 @@ struct DirBlock {
   int32_t pad;
 };
 
+// one chunk of a projection launch: its samples go to output rows
+// [row_base, row_base + n); workgroups [tile0, tile0 + ceil(n / 64)) cover it
+struct ProjChunk {
+  const double* O;
+  const double* e;
+  const double* EL;
+  int64_t ld;
+  int64_t n;
+  int64_t row_base;
+  int32_t tile0;
+  int32_t pad;
+};
+constexpr int PROJ_ROWS = 64;
+
 // ------------------------------------------------------------ eigensolve --
 enum EigMode : int32_t {
   EIG_BLOCK = 0,        // kept directions: beta parts, orthonormalised
@@ -77,8 +91,13 @@ struct EigJob {
   double* tau;          // [d]
   double* out;          // EIG_BLOCK: [n_want + 1][nbeta] rows; EIG_STAGE2: [2][d] (re, im)
   double* out_evals;    // [n_want + 1][2] the used eigenvalues in rank order
-  int32_t* info;        // [0] status, [1] rows/vectors produced, [2] flags, [3] iterations
+  int32_t* info;        // [EIG_INFO]: [0] status, [1] rows/vectors produced, [2] flags,
+                        // [3] QR sweeps, [4..11] 100 MHz ticks per phase (Cholesky,
+                        // congruence, Hessenberg, QR, selection, inverse iteration,
+                        // back-transform, orthonormalisation)
 };
+
+constexpr int EIG_INFO = 16;
 
 enum EigStatus : int32_t {
   EIG_OK = 0,
@@ -93,11 +112,11 @@ constexpr int EIG_MAXSEL = 16;   // eigenvalues selected per problem (N_K + 1 <=
 
 // launchers (blm_kernels.hip / blm_eig.hip)
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                 double* d_partial, hipStream_t st);
+                 bool vec, double* d_partial, hipStream_t st);
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
                         hipStream_t st);
-void launch_dirproj(const double* O, const double* e, const double* EL, int64_t ld, int64_t n,
+void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st);
 void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);

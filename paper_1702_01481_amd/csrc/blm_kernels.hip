@@ -32,6 +32,22 @@ struct StageRegs {
   double x, y;
 };
 
+// Loads a pair of adjacent doubles of one panel row: 16 bytes when both are
+// in the tile (VEC: the caller has checked 16-byte alignment), else guarded
+// 8-byte loads.
+template <bool VEC>
+__device__ __forceinline__ void load_pair(const double* p, int col, int lim, double& x, double& y) {
+  if (VEC && col + 1 < lim) {
+    const double2 v = *reinterpret_cast<const double2*>(p + col);
+    x = v.x;
+    y = v.y;
+  } else {
+    x = col < lim ? p[col] : 0.0;
+    y = col + 1 < lim ? p[col + 1] : 0.0;
+  }
+}
+
+template <bool VEC>
 __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int64_t ro, int tid,
                                           StageRegs& R) {
   const int lr = tid >> 4;            // sample row within the stage (0..15)
@@ -43,17 +59,22 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
   const double* pe = aux ? S.Ya : S.e;
   const int64_t ld = aux ? (int64_t)NAUX : S.ld;
   const double wgt = (valid && S.w) ? S.w[row] : 1.0;
+  const int mi = valid ? J.mi : 0, nj = valid ? J.nj : 0;
   const double* rO = pO + row * ld;
   const double* re = pe + row * ld;
 #pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int col = lc + 2 * h;
+    load_pair<VEC>(rO + J.ci, col, mi, R.a[2 * h], R.a[2 * h + 1]);
+    if (J.kind == JOB_OFF) load_pair<VEC>(re + J.ci, col, mi, R.e[2 * h], R.e[2 * h + 1]);
+    else R.e[2 * h] = R.e[2 * h + 1] = 0.0;
+    load_pair<VEC>(rO + J.cj, col, nj, R.b[2 * h], R.b[2 * h + 1]);
+    load_pair<VEC>(re + J.cj, col, nj, R.f[2 * h], R.f[2 * h + 1]);
+  }
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int col = lc + c;
-    const bool vi = valid && col < J.mi;
-    const bool vj = valid && col < J.nj;
-    R.a[c] = vi ? rO[J.ci + col] * wgt : 0.0;
-    R.e[c] = (vi && J.kind == JOB_OFF) ? re[J.ci + col] * wgt : 0.0;
-    R.b[c] = vj ? rO[J.cj + col] : 0.0;
-    R.f[c] = vj ? re[J.cj + col] : 0.0;
+    R.a[c] *= wgt;
+    R.e[c] *= wgt;
   }
   if (J.kind == JOB_DIAG) {
     const int acol = tid & 15;
@@ -65,6 +86,7 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
   }
 }
 
+template <bool VEC>
 __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __restrict__ jobs,
                                                            int n_jobs,
                                                            const Slice* __restrict__ slices,
@@ -109,7 +131,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
   int buf = 0;
   if (si < n_slices) {
     Slice S = slices[si];
-    gram_load(J, S, ro, tid, R);
+    gram_load<VEC>(J, S, ro, tid, R);
     const int lr = tid >> 4, lc = (tid & 15) * 4;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -135,7 +157,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
     const bool has_next = si2 < n_slices;
     if (has_next) {
       Slice S2 = slices[si2];
-      gram_load(J, S2, ro2, tid, R);
+      gram_load<VEC>(J, S2, ro2, tid, R);
     }
 
 #pragma unroll
@@ -241,10 +263,14 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
 }
 
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                 double* d_partial, hipStream_t st) {
+                 bool vec, double* d_partial, hipStream_t st) {
   if (n_jobs <= 0) return;
-  hipLaunchKernelGGL(gram_kernel, dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs, n_jobs, d_slices,
-                     n_slices, P, d_partial);
+  if (vec)
+    hipLaunchKernelGGL(gram_kernel<true>, dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs, n_jobs,
+                       d_slices, n_slices, P, d_partial);
+  else
+    hipLaunchKernelGGL(gram_kernel<false>, dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs, n_jobs,
+                       d_slices, n_slices, P, d_partial);
 }
 
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
@@ -263,10 +289,86 @@ constexpr int PJ_ROWS = 64;   // samples per workgroup (16 per wave)
 constexpr int PJ_P = 32;      // parameters per LDS stage
 constexpr int PJ_D = 32;      // directions per pass (2 MFMA column groups)
 
-__global__ __launch_bounds__(256) void dirproj_kernel(const double* __restrict__ O,
-                                                      const double* __restrict__ e,
-                                                      const double* __restrict__ EL, int64_t ld,
-                                                      int64_t n, const DirBlock* __restrict__ blocks,
+struct PjRegs {
+  double o[8], e[8], d[4];
+};
+
+// Stage loader: 64 samples x 32 parameters of O and e, and 32 directions x
+// 32 parameters of the direction rows.  VEC: 16-byte loads (the caller has
+// checked alignment); otherwise 8-byte loads.
+template <bool VEC>
+__device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const DirBlock& B, int dg,
+                                        int p0, const double* const* __restrict__ dir_ptr, int tid,
+                                        PjRegs& R) {
+  if (VEC) {
+    const int c2 = (tid & 15) * 2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = (tid >> 4) + 16 * i;
+      const int64_t s = s0 + row;
+      const bool v = (s < C.n) && (p0 + c2 < B.m);
+      if (v) {
+        const double2 a = *reinterpret_cast<const double2*>(C.O + s * C.ld + B.col0 + p0 + c2);
+        const double2 b = *reinterpret_cast<const double2*>(C.e + s * C.ld + B.col0 + p0 + c2);
+        R.o[2 * i] = a.x;
+        R.o[2 * i + 1] = a.y;
+        R.e[2 * i] = b.x;
+        R.e[2 * i + 1] = b.y;
+      } else {
+        R.o[2 * i] = R.o[2 * i + 1] = R.e[2 * i] = R.e[2 * i + 1] = 0.0;
+      }
+    }
+  } else {
+    const int col = tid & 31;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int row = (tid >> 5) + 8 * i;
+      const int64_t s = s0 + row;
+      const bool v = (s < C.n) && (p0 + col < B.m);
+      R.o[i] = v ? C.O[s * C.ld + B.col0 + p0 + col] : 0.0;
+      R.e[i] = v ? C.e[s * C.ld + B.col0 + p0 + col] : 0.0;
+    }
+  }
+  const int col = tid & 31;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int dr = (tid >> 5) + 8 * i;
+    const int dd = dg + dr;
+    R.d[i] = (dd < B.nd && p0 + col < B.m) ? dir_ptr[B.d0 + dd][p0 + col] : 0.0;
+  }
+}
+
+template <bool VEC>
+__device__ __forceinline__ void pj_store(double (*sO)[PJ_P + 1], double (*sE)[PJ_P + 1],
+                                         double (*sD)[PJ_P + 1], int tid, const PjRegs& R) {
+  if (VEC) {
+    const int c2 = (tid & 15) * 2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = (tid >> 4) + 16 * i;
+      sO[row][c2] = R.o[2 * i];
+      sO[row][c2 + 1] = R.o[2 * i + 1];
+      sE[row][c2] = R.e[2 * i];
+      sE[row][c2 + 1] = R.e[2 * i + 1];
+    }
+  } else {
+    const int col = tid & 31;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int row = (tid >> 5) + 8 * i;
+      sO[row][col] = R.o[i];
+      sE[row][col] = R.e[i];
+    }
+  }
+  const int col = tid & 31;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) sD[(tid >> 5) + 8 * i][col] = R.d[i];
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restrict__ chunks,
+                                                      int n_chunks,
+                                                      const DirBlock* __restrict__ blocks,
                                                       int n_blocks,
                                                       const double* const* __restrict__ dir_ptr,
                                                       int n_dirs, double* __restrict__ Xo,
@@ -274,7 +376,13 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const double* __restrict__
   __shared__ double sO[PJ_ROWS][PJ_P + 1];
   __shared__ double sE[PJ_ROWS][PJ_P + 1];
   __shared__ double sD[PJ_D][PJ_P + 1];
-  const int64_t s0 = (int64_t)blockIdx.x * PJ_ROWS;
+  // which chunk and which 64-sample tile of it
+  int ci = 0;
+  while (ci + 1 < n_chunks && chunks[ci + 1].tile0 <= (int)blockIdx.x) ++ci;
+  const ProjChunk C = chunks[ci];
+  const int64_t s0 = (int64_t)(blockIdx.x - C.tile0) * PJ_ROWS;
+  double* X = Xo + C.row_base * ldo;
+  double* Y = Yo + C.row_base * ldo;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i16 = lane & 15, k4 = lane >> 4;
 
@@ -282,80 +390,71 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const double* __restrict__
   for (int t = tid; t < PJ_ROWS * (int)ldo; t += blockDim.x) {
     const int rr = t / (int)ldo, c = t % (int)ldo;
     const int64_t s = s0 + rr;
-    if (s >= n) continue;
+    if (s >= C.n) continue;
     if (c == 0) {
-      Xo[s * ldo] = 1.0;
-      Yo[s * ldo] = EL[s];
+      X[s * ldo] = 1.0;
+      Y[s * ldo] = C.EL[s];
     } else if (c >= 1 + n_dirs) {
-      Xo[s * ldo + c] = 0.0;
-      Yo[s * ldo + c] = 0.0;
+      X[s * ldo + c] = 0.0;
+      Y[s * ldo + c] = 0.0;
     }
   }
 
   for (int bi = 0; bi < n_blocks; ++bi) {
     const DirBlock B = blocks[bi];
     for (int dg = 0; dg < B.nd; dg += PJ_D) {
+      const bool two = (B.nd - dg) > 16;
       d4 aO0 = {0, 0, 0, 0}, aO1 = {0, 0, 0, 0}, aE0 = {0, 0, 0, 0}, aE1 = {0, 0, 0, 0};
+      PjRegs R;
+      pj_load<VEC>(C, s0, B, dg, 0, dir_ptr, tid, R);
       for (int p0 = 0; p0 < B.m; p0 += PJ_P) {
+        __syncthreads();   // everyone is done reading the previous stage
+        pj_store<VEC>(sO, sE, sD, tid, R);
         __syncthreads();
-        {
-          const int row = tid >> 2, c8 = (tid & 3) * 8;
-          const int64_t s = s0 + row;
-          const double* rO = O + s * ld + B.col0 + p0;
-          const double* rE = e + s * ld + B.col0 + p0;
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            const int col = c8 + c;
-            const bool v = (s < n) && (p0 + col < B.m);
-            sO[row][col] = v ? rO[col] : 0.0;
-            sE[row][col] = v ? rE[col] : 0.0;
-          }
-          const int dr = tid >> 3, c4 = (tid & 7) * 4;
-          const int dd = dg + dr;
-          const double* rD = (dd < B.nd) ? dir_ptr[B.d0 + dd] : nullptr;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int col = c4 + c;
-            sD[dr][col] = (rD && p0 + col < B.m) ? rD[p0 + col] : 0.0;
-          }
-        }
-        __syncthreads();
+        // the next stage's global loads overlap this stage's matrix-core work
+        if (p0 + PJ_P < B.m) pj_load<VEC>(C, s0, B, dg, p0 + PJ_P, dir_ptr, tid, R);
 #pragma unroll
         for (int kk = 0; kk < PJ_P; kk += 4) {
           const int kc = kk + k4;
           const double ao = sO[16 * wv + i16][kc], ae = sE[16 * wv + i16][kc];
-          const double b0 = sD[i16][kc], b1 = sD[16 + i16][kc];
+          const double b0 = sD[i16][kc];
           aO0 = mfma_f64(ao, b0, aO0);
-          aO1 = mfma_f64(ao, b1, aO1);
           aE0 = mfma_f64(ae, b0, aE0);
-          aE1 = mfma_f64(ae, b1, aE1);
+          if (two) {
+            const double b1 = sD[16 + i16][kc];
+            aO1 = mfma_f64(ao, b1, aO1);
+            aE1 = mfma_f64(ae, b1, aE1);
+          }
         }
       }
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
         const int64_t s = s0 + 16 * wv + 4 * rr + k4;
-        if (s >= n) continue;
+        if (s >= C.n) continue;
         const int t0 = dg + i16, t1 = dg + 16 + i16;
         if (t0 < B.nd) {
-          Xo[s * ldo + 1 + B.d0 + t0] = aO0[rr];
-          Yo[s * ldo + 1 + B.d0 + t0] = aE0[rr];
+          X[s * ldo + 1 + B.d0 + t0] = aO0[rr];
+          Y[s * ldo + 1 + B.d0 + t0] = aE0[rr];
         }
-        if (t1 < B.nd) {
-          Xo[s * ldo + 1 + B.d0 + t1] = aO1[rr];
-          Yo[s * ldo + 1 + B.d0 + t1] = aE1[rr];
+        if (two && t1 < B.nd) {
+          X[s * ldo + 1 + B.d0 + t1] = aO1[rr];
+          Y[s * ldo + 1 + B.d0 + t1] = aE1[rr];
         }
       }
     }
   }
 }
 
-void launch_dirproj(const double* O, const double* e, const double* EL, int64_t ld, int64_t n,
+void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st) {
-  if (n <= 0) return;
-  const int grid = (int)((n + PJ_ROWS - 1) / PJ_ROWS);
-  hipLaunchKernelGGL(dirproj_kernel, dim3(grid), dim3(256), 0, st, O, e, EL, ld, n, d_blocks,
-                     n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+  if (n_tiles <= 0) return;
+  if (vec)
+    hipLaunchKernelGGL(dirproj_kernel<true>, dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks,
+                       d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+  else
+    hipLaunchKernelGGL(dirproj_kernel<false>, dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks,
+                       d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
 }
 
 }  // namespace blm
