@@ -40,6 +40,11 @@ struct Shared {
   double sel_r[EIG_MAXSEL], sel_i[EIG_MAXSEL];
   int sel_n;
   int widx[NW];
+  // multishift QR: shifts of the trailing block and per-bulge state
+  double T[32 * 32];
+  double swr[32], swi[32], sre[32];
+  double bsum[16], bprod[16];
+  double bx[16][3];
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -202,13 +207,29 @@ __device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, int d)
 }
 
 // ---------------------------------------------------------------- step 4 --
-// Eigenvalues of the upper Hessenberg matrix A (destroyed) into wr, wi.
-// Pairs are stored as (re, +im), (re, -im) at consecutive indices.
-__device__ int hessenberg_eigvals(Shared& sh, double* A, double* wr, double* wi, int d, int* iters) {
+// Eigenvalues of the upper Hessenberg matrix A (row stride ld, destroyed)
+// into wr, wi.  A conjugate pair is stored as (re, +im), (re, -im) at
+// consecutive indices.
+//
+// Each sweep chases m double-shift bulges down the active window [l, h]
+// (small-bulge multishift QR).  With MULTI, m pairs of shifts are the
+// eigenvalues of the trailing 2m x 2m block of the window (found by this
+// routine with MULTI off on an LDS copy); bulge b enters four rows after
+// bulge b-1, so the bulges touch disjoint rows and columns in every tick.
+// Left (row) and right (column) reflections commute, so all row updates
+// of a tick run first, then all column updates.  Without MULTI (or after
+// 10 sweeps without deflation) one bulge uses the trailing 2x2 block's
+// eigenvalues, or an ad hoc pair.  Deflation: a subdiagonal entry below
+// eps (|a_{i-1,i-1}| + |a_ii|) is set to zero.
+constexpr int MAX_BULGES = 16;
+
+template <bool MULTI>
+__device__ int hqr(Shared& sh, double* A, int ld, int d, double* wr, double* wi, int* iters) {
   const int tid = threadIdx.x;
+  auto at = [&](int i, int j) -> double& { return A[(size_t)i * ld + j]; };
   double part = 0.0;
   for (int i = tid; i < d; i += NT)
-    for (int j = (i > 0 ? i - 1 : 0); j < d; ++j) part += fabs(A[(size_t)i * d + j]);
+    for (int j = (i > 0 ? i - 1 : 0); j < d; ++j) part += fabs(at(i, j));
   const double anorm = block_sum(sh, part);
   int h = d - 1, its = 0, total = 0;
   const int max_total = 40 * (d + 1);
@@ -216,16 +237,16 @@ __device__ int hessenberg_eigvals(Shared& sh, double* A, double* wr, double* wi,
     if (tid == 0) sh.isc[1] = 0;
     __syncthreads();
     for (int i = 1 + tid; i <= h; i += NT) {
-      double s = fabs(A[(size_t)(i - 1) * d + i - 1]) + fabs(A[(size_t)i * d + i]);
+      double s = fabs(at(i - 1, i - 1)) + fabs(at(i, i));
       if (s == 0.0) s = anorm;
-      if (fabs(A[(size_t)i * d + i - 1]) <= EPS * s) atomicMax(&sh.isc[1], i);
+      if (fabs(at(i, i - 1)) <= EPS * s) atomicMax(&sh.isc[1], i);
     }
     __syncthreads();
     const int l = sh.isc[1];
     if (l == h) {
       if (tid == 0) {
-        if (l > 0) A[(size_t)l * d + l - 1] = 0.0;
-        wr[h] = A[(size_t)h * d + h];
+        if (l > 0) at(l, l - 1) = 0.0;
+        wr[h] = at(h, h);
         wi[h] = 0.0;
       }
       h -= 1;
@@ -235,9 +256,9 @@ __device__ int hessenberg_eigvals(Shared& sh, double* A, double* wr, double* wi,
     }
     if (l == h - 1) {
       if (tid == 0) {
-        if (l > 0) A[(size_t)l * d + l - 1] = 0.0;
-        const double a = A[(size_t)(h - 1) * d + h - 1], b = A[(size_t)(h - 1) * d + h];
-        const double c = A[(size_t)h * d + h - 1], dd = A[(size_t)h * d + h];
+        if (l > 0) at(l, l - 1) = 0.0;
+        const double a = at(h - 1, h - 1), b = at(h - 1, h);
+        const double c = at(h, h - 1), dd = at(h, h);
         const double p = 0.5 * (a - dd);
         const double disc = p * p + b * c;
         if (disc >= 0.0) {
@@ -264,96 +285,142 @@ __device__ int hessenberg_eigvals(Shared& sh, double* A, double* wr, double* wi,
     }
     ++its;
     ++total;
-    // shifts: sum and product of the two eigenvalues of the trailing 2x2
-    // block, or an ad hoc pair after 10 and 20 stalled sweeps
-    double ssum, sprod;
-    {
-      const double a = A[(size_t)(h - 1) * d + h - 1], b = A[(size_t)(h - 1) * d + h];
-      const double c = A[(size_t)h * d + h - 1], dd = A[(size_t)h * d + h];
+    const int w = h - l + 1;
+    int m = 1;
+    if (MULTI && its % 10 != 0) {
+      const int ns = w < 30 ? 2 : w < 60 ? 4 : w < 150 ? 10 : w < 590 ? 16 : 2 * MAX_BULGES;
+      if (ns > 2) {
+        const int o = h - ns + 1;
+        for (int t = tid; t < ns * ns; t += NT) {
+          const int i = t / ns, j = t % ns;
+          sh.T[t] = (j + 1 >= i) ? at(o + i, o + j) : 0.0;
+        }
+        __syncthreads();
+        int it2 = 0;
+        const int st2 = hqr<false>(sh, sh.T, ns, ns, sh.swr, sh.swi, &it2);
+        __syncthreads();
+        if (st2 == EIG_OK) {
+          if (tid == 0) {
+            int mm = 0, nre = 0;
+            double* re = sh.sre;
+            for (int i = 0; i < ns; ++i) {
+              if (!isfinite(sh.swr[i]) || !isfinite(sh.swi[i])) continue;
+              if (sh.swi[i] > 0.0 && mm < MAX_BULGES) {
+                sh.bsum[mm] = 2.0 * sh.swr[i];
+                sh.bprod[mm] = sh.swr[i] * sh.swr[i] + sh.swi[i] * sh.swi[i];
+                ++mm;
+              } else if (sh.swi[i] == 0.0) {
+                re[nre++] = sh.swr[i];
+              }
+            }
+            for (int i = 0; i + 1 < nre && mm < MAX_BULGES; i += 2) {
+              sh.bsum[mm] = re[i] + re[i + 1];
+              sh.bprod[mm] = re[i] * re[i + 1];
+              ++mm;
+            }
+            sh.isc[5] = mm;
+          }
+          __syncthreads();
+          m = sh.isc[5];
+        }
+      }
+    }
+    if (m < 1) m = 1;
+    if (m == 1 && tid == 0) {
+      // one bulge: trailing 2x2 block's eigenvalues, or an ad hoc pair
+      const double a = at(h - 1, h - 1), b = at(h - 1, h);
+      const double c = at(h, h - 1), dd = at(h, h);
       if (its % 10 == 0) {
-        const double ex = fabs(c) + fabs(A[(size_t)(h - 1) * d + h - 2]);
+        const double ex = fabs(c) + fabs(at(h - 1, h - 2));
         const double x = dd + 0.75 * ex;
-        ssum = 2.0 * x;
-        sprod = x * x + 0.4375 * ex * ex;
+        sh.bsum[0] = 2.0 * x;
+        sh.bprod[0] = x * x + 0.4375 * ex * ex;
       } else {
-        ssum = a + dd;
-        sprod = a * dd - b * c;
+        sh.bsum[0] = a + dd;
+        sh.bprod[0] = a * dd - b * c;
       }
     }
-    // first column of (A - s1)(A - s2) restricted to the window
-    double x, y, z;
-    {
-      const double h00 = A[(size_t)l * d + l], h01 = A[(size_t)l * d + l + 1];
-      const double h10 = A[(size_t)(l + 1) * d + l], h11 = A[(size_t)(l + 1) * d + l + 1];
-      const double h21 = A[(size_t)(l + 2) * d + l + 1];
-      x = h00 * h00 + h01 * h10 - ssum * h00 + sprod;
-      y = h10 * (h00 + h11 - ssum);
-      z = h10 * h21;
-    }
-    if (tid == 0 && l > 0) A[(size_t)l * d + l - 1] = 0.0;
     __syncthreads();
-    for (int K = l - 1; K <= h - 2; ++K) {
+
+    // chase: group g of G threads carries bulge g
+    const int mp = m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16;
+    const int G = NT / mp, grp = tid / G, lt = tid % G;
+    const int ticks = (h - l) + 4 * (m - 1);
+    for (int t = 0; t < ticks; ++t) {
+      const int K = l - 1 + t - 4 * grp;
+      const bool act = grp < m && K >= l - 1 && K <= h - 2;
       const int nr = (K <= h - 3) ? 3 : 2;
-      if (nr == 2) z = 0.0;
-      const double sc = fabs(x) + fabs(y) + fabs(z);
       double v0 = 0.0, v1 = 0.0, v2 = 0.0, bt = 0.0, newsub = 0.0;
-      bool act = sc != 0.0;
+      bool refl = false;
       if (act) {
-        const double xs = x / sc, ys = y / sc, zs = z / sc;
-        const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
-        v0 = xs + al;
-        v1 = ys;
-        v2 = zs;
-        bt = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
-        newsub = -al * sc;
+        double x, y, z;
+        if (K == l - 1) {
+          const double ssum = sh.bsum[grp], sprod = sh.bprod[grp];
+          const double h00 = at(l, l), h01 = at(l, l + 1), h10 = at(l + 1, l);
+          const double h11 = at(l + 1, l + 1), h21 = at(l + 2, l + 1);
+          x = h00 * h00 + h01 * h10 - ssum * h00 + sprod;
+          y = h10 * (h00 + h11 - ssum);
+          z = h10 * h21;
+        } else {
+          x = sh.bx[grp][0];
+          y = sh.bx[grp][1];
+          z = sh.bx[grp][2];
+        }
+        if (nr == 2) z = 0.0;
+        const double sc = fabs(x) + fabs(y) + fabs(z);
+        if (sc != 0.0) {
+          refl = true;
+          const double xs = x / sc, ys = y / sc, zs = z / sc;
+          const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
+          v0 = xs + al;
+          v1 = ys;
+          v2 = zs;
+          bt = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+          newsub = -al * sc;
+        }
       }
-      if (act) {
-        // rows K+1..K+nr, columns from max(l, K+1) to h; column K (bulge) set directly
+      // a bulge entering at the top read the window's first rows, which its
+      // own group rewrites below: let every wave finish reading first
+      if ((t & 3) == 0 && (t >> 2) < m) __syncthreads();
+      if (act && refl) {
+        // rows K+1..K+nr, columns max(l, K+1)..h; the bulge column K is set directly
         const int c0 = (K >= l) ? K + 1 : l;
-        for (int c = c0 + tid; c <= h; c += NT) {
-          double* p1 = A + (size_t)(K + 1) * d + c;
-          double* p2 = p1 + d;
-          double t = v0 * p1[0] + v1 * p2[0];
-          if (nr == 3) t += v2 * p2[d];
-          t *= bt;
-          p1[0] -= t * v0;
-          p2[0] -= t * v1;
-          if (nr == 3) p2[d] -= t * v2;
+        for (int c = c0 + lt; c <= h; c += G) {
+          double* p1 = A + (size_t)(K + 1) * ld + c;
+          double* p2 = p1 + ld;
+          double tt = v0 * p1[0] + v1 * p2[0];
+          if (nr == 3) tt += v2 * p2[ld];
+          tt *= bt;
+          p1[0] -= tt * v0;
+          p2[0] -= tt * v1;
+          if (nr == 3) p2[ld] -= tt * v2;
         }
-        if (K >= l && tid == 0) {
-          A[(size_t)(K + 1) * d + K] = newsub;
-          A[(size_t)(K + 2) * d + K] = 0.0;
-          if (nr == 3) A[(size_t)(K + 3) * d + K] = 0.0;
+        if (K >= l && lt == 0) {
+          at(K + 1, K) = newsub;
+          at(K + 2, K) = 0.0;
+          if (nr == 3) at(K + 3, K) = 0.0;
         }
       }
       __syncthreads();
       if (act) {
-        // columns K+1..K+nr, rows l..min(K+4, h)
+        // columns K+1..K+nr, rows l..min(K+4, h); keep column K+1's entries
+        // below the diagonal (the next bulge) for the next tick
         const int r1 = (K + 4 < h) ? K + 4 : h;
-        for (int rr = l + tid; rr <= r1; rr += NT) {
-          double* q = A + (size_t)rr * d + K + 1;
-          double t = q[0] * v0 + q[1] * v1;
-          if (nr == 3) t += q[2] * v2;
-          t *= bt;
-          q[0] -= t * v0;
-          q[1] -= t * v1;
-          if (nr == 3) q[2] -= t * v2;
-          if (rr >= K + 2 && rr <= K + 4) sh.sc[rr - K - 2] = q[0];
+        for (int rr = l + lt; rr <= r1; rr += G) {
+          double* q = A + (size_t)rr * ld + K + 1;
+          if (refl) {
+            double tt = q[0] * v0 + q[1] * v1;
+            if (nr == 3) tt += q[2] * v2;
+            tt *= bt;
+            q[0] -= tt * v0;
+            q[1] -= tt * v1;
+            if (nr == 3) q[2] -= tt * v2;
+          }
+          if (rr >= K + 2) sh.bx[grp][rr - K - 2] = q[0];
         }
+        if (K + 4 > h && lt == 0) sh.bx[grp][2] = 0.0;
+        if (K + 3 > h && lt == 0) sh.bx[grp][1] = 0.0;
       }
-      if (tid == 0) {
-        if (K + 4 > h) sh.sc[2] = 0.0;
-        if (!act) {
-          // no reflection: the next bulge column is read as it stands
-          sh.sc[0] = (K + 2 <= h) ? A[(size_t)(K + 2) * d + K + 1] : 0.0;
-          sh.sc[1] = (K + 3 <= h) ? A[(size_t)(K + 3) * d + K + 1] : 0.0;
-          sh.sc[2] = (K + 4 <= h) ? A[(size_t)(K + 4) * d + K + 1] : 0.0;
-        }
-      }
-      __syncthreads();
-      x = sh.sc[0];
-      y = sh.sc[1];
-      z = sh.sc[2];
       __syncthreads();
     }
   }
@@ -647,7 +714,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
   for (size_t i = tid; i < (size_t)d * d; i += NT) part += fabs(J.Hq[i]);
   const double hnorm = block_sum(sh, part);
   int iters = 0;
-  st = hessenberg_eigvals(sh, J.A, J.wr, J.wi, d, &iters);
+  st = hqr<true>(sh, J.A, d, d, J.wr, J.wi, &iters);
   __syncthreads();
   phase_mark(J, clk, 3);
   if (tid == 0) J.info[3] = iters;

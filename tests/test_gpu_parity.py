@@ -88,16 +88,26 @@ def _compare_step(offsets, n_keep, shifts, host, dev, old=None, n_old=0, mat_tol
 def test_eigvals_match_lapack():
     blm = _blm()
     rng = np.random.default_rng(7)
-    for d in (1, 2, 3, 5, 17, 51, 64, 65, 130, 257):
+    cases = [(d, "gauss") for d in (1, 2, 3, 5, 17, 51, 64, 65, 130, 257, 600)] + [(300, "rot")]
+    for d, kind in cases:
         A = rng.standard_normal((d, d))
         S = A @ A.T / d + np.eye(d)
-        H = rng.standard_normal((d, d)) - 10.0 * np.eye(d)
+        if kind == "gauss":
+            H = rng.standard_normal((d, d)) - 10.0 * np.eye(d)
+        else:
+            # mostly complex pairs: block rotations, similarity-transformed
+            R = np.zeros((d, d))
+            for i in range(0, d - 1, 2):
+                a, b = rng.standard_normal(2)
+                R[i:i + 2, i:i + 2] = [[a, b], [-b, a]]
+            Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+            H = Q @ R @ Q.T
         got = blm.debug_eigvals(torch.from_numpy(H).cuda(), torch.from_numpy(S).cuda())
         ref, _ = orc.generalized_eig(H, S)
         dist = np.abs(got[:, None] - ref[None, :])
         scale = np.abs(ref).max()
-        assert dist.min(axis=1).max() < 1e-10 * scale, (d, dist.min(axis=1).max())
-        assert dist.min(axis=0).max() < 1e-10 * scale, (d, dist.min(axis=0).max())
+        assert dist.min(axis=1).max() < 1e-10 * scale, (d, kind, dist.min(axis=1).max())
+        assert dist.min(axis=0).max() < 1e-10 * scale, (d, kind, dist.min(axis=0).max())
 
 
 def test_small_workload_step():
