@@ -77,6 +77,61 @@ def cpu_baseline(O0, e0, EL0, w, offsets, old, n_keep, shifts):
     }
 
 
+def mixed_step(args, w, chunks, old, offsets, shifts, n_samples, en64, upd64, ms64, build64, fl_build):
+    """The same step with the sample contractions on BF16 split pieces; the
+    pieces are made from the resident FP64 samples before timing."""
+    import torch
+
+    from paper_1702_01481_amd import blm
+    pieces = 3 if args.mixed == "bf16x3" else 2
+    split = [(blm.SplitSamples(O, pieces), blm.SplitSamples(e, pieces), EL) for O, e, EL in chunks]
+    torch.cuda.synchronize()
+    log(f"packed {args.mixed} pieces")
+    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, n_samples, precision=args.mixed)
+    ctx.set_timing(True)
+
+    def step():
+        ctx.begin_step(old)
+        ctx.build(split)
+        ctx.solve()
+        ctx.project(split)
+        return ctx.stage2()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    phase = {k: [] for k in blm.TIMING_NAMES}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        upd, en, _, _ = step()
+        for k, v in ctx.timings().items():
+            phase[k].append(v)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    ctx.close()
+    pm = {k: float(np.mean(v)) for k, v in phase.items()}
+    build_ms = pm["theta_proj"] + pm["block_gram"] + pm["block_reduce"] + max(pm["block_strips"], 0.0)
+    u64 = upd64.double().cpu().numpy()
+    um = upd.double().cpu().numpy()
+    cos = [float(u64[i] @ um[i] / (np.linalg.norm(u64[i]) * np.linalg.norm(um[i]))) for i in range(len(shifts))]
+    rel = [float(abs(en[i] - en64[i]) / abs(en64[i])) for i in range(len(shifts))]
+    log(f"mixed step {ms:.1f} ms, energy rel err {rel}")
+    return {
+        "precision": args.mixed,
+        "ms_per_step": round(ms, 3),
+        "build_ms": round(build_ms, 3),
+        "build_tflops": round(fl_build / (build_ms * 1e-3) / 1e12, 4),
+        "gram_bf16_ms": round(pm["block_gram"], 3),
+        "gram_bf16_algorithmic_tflops": round(fl_build / (pm["block_gram"] * 1e-3) / 1e12, 4),
+        "phase_ms": {k: round(v, 3) for k, v in pm.items()},
+        "energy_rel_err_vs_fp64": rel,
+        "update_cosine_vs_fp64": cos,
+        "step_speedup_vs_fp64": round(ms64 / ms, 3),
+        "build_speedup_vs_fp64": round(build64 / build_ms, 3),
+        "meets_1e-6": bool(max(rel) <= 1e-6),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +139,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed", default="bf16x3", choices=["bf16x3", "bf16x2", "none"],
+                    help="also run the mixed-precision step on the same samples")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sample "
@@ -184,6 +241,9 @@ def main():
                      "kernel": "gram_kernel (block H/S build, FP64 MFMA 16x16x4)",
                      "flops_per_launch": fl_build},
     }
+    if args.mixed != "none":
+        out["mixed"] = mixed_step(args, w, chunks, old, offsets, shifts, n_samples, en, upd, ms_step,
+                                  build_ms, fl_build)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one chunk")
         O0, e0, EL0 = chunks[0]

@@ -58,8 +58,15 @@ typedef enum {
 } blm_status;
 
 typedef enum {
-  BLM_PREC_F64 = 0      /* sample contractions in FP64 on FP64 matrix cores */
+  BLM_PREC_F64 = 0,     /* sample contractions in FP64 on FP64 matrix cores */
+  BLM_PREC_BF16X2 = 1,  /* BF16 hi/lo pieces, 3 piece products, FP32 sums flushed to FP64 */
+  BLM_PREC_BF16X3 = 2   /* BF16 hi/mid/lo pieces, 6 piece products, FP32 sums flushed to FP64 */
 } blm_precision;
+
+typedef enum {
+  BLM_LAYOUT_F64 = 0,        /* O, e: double [n][ld], sample-major */
+  BLM_LAYOUT_BF16_SPLIT = 1  /* O, e: BF16 pieces, k-packed (see blm_pack_bf16) */
+} blm_layout;
 
 /* Flags returned per shift by blm_stage2 (bit mask). */
 enum {
@@ -83,11 +90,25 @@ typedef struct {
 typedef struct {                 /* one chunk of samples; device memory, caller-owned */
   int64_t n_samples;             /* >= 0 */
   int64_t ld;                    /* row stride of O and e in elements, >= N_V */
-  const double* O;               /* [n_samples][ld] */
-  const double* e;               /* [n_samples][ld] */
+  const void* O;                 /* BLM_LAYOUT_F64: double [n_samples][ld]; split: piece 0 */
+  const void* e;                 /* same layout as O */
   const double* E_L;             /* [n_samples] */
-  const double* w;               /* [n_samples] >= 0, or NULL for all-ones */
+  const double* w;               /* [n_samples] >= 0, or NULL for all-ones (required for BF16) */
+  int32_t layout;                /* blm_layout; must be BLM_LAYOUT_F64 for BLM_PREC_F64 and
+                                    BLM_LAYOUT_BF16_SPLIT for the BF16 precisions */
+  int32_t pieces;                /* split layout: pieces stored (2 or 3; >= 3 for BF16X3) */
+  int64_t piece_stride;          /* split layout: elements between pieces, multiple of 8 */
 } blm_chunk;
+
+/* Producer-side utility: splits FP64 samples src [n][ld_src] (columns
+ * 0..ncols-1) into `pieces` (2 or 3) BF16 pieces, hi = bf16(x), mid =
+ * bf16(x - hi), lo = bf16(x - hi - mid), stored k-packed: element (s, x) of
+ * piece p at dst[p * piece_stride + ((s / 8) * ld_dst + x) * 8 + s % 8]
+ * (uint16 bit patterns).  Rows n .. 8*ceil(n/8)-1 are written as zeros.
+ * dst needs pieces * piece_stride elements, piece_stride >= 8*ceil(n/8)*ld_dst,
+ * a multiple of 8, and 16-byte alignment.  Asynchronous on `stream`. */
+blm_status blm_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncols, int32_t pieces,
+                         uint16_t* dst, int64_t ld_dst, int64_t piece_stride, void* stream);
 
 /* Bytes of device memory blm_create will allocate for this configuration. */
 blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes);
@@ -162,8 +183,9 @@ blm_status blm_debug_eigvals(const double* d_H, const double* d_S, int32_t d, do
  *   [2] block Gram reduction             [3] block pencil assembly
  *   [4] block eigensolves                [5] kept-direction projection
  *   [6] stage-two Gram kernel            [7] stage-two Gram reduction
- *   [8] stage-two assembly + eigensolve + update */
-#define BLM_N_TIMINGS 9
+ *   [8] stage-two assembly + eigensolve + update
+ *   [9] FP64 strips of the mixed-precision build (with their reduction) */
+#define BLM_N_TIMINGS 10
 blm_status blm_set_timing(blm_ctx* ctx, int32_t enable);
 blm_status blm_get_timings(blm_ctx* ctx, double* h_ms, int32_t n);
 

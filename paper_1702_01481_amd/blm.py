@@ -21,14 +21,16 @@ STATUS_NAMES = {0: "BLM_OK", 1: "BLM_E_ARG", 2: "BLM_E_STATE", 3: "BLM_E_HIP", 4
                 5: "BLM_E_S_NOT_PD", 6: "BLM_E_NONFINITE", 7: "BLM_E_NOCONV"}
 FLAG_COMPLEX_ENERGY, FLAG_PAIR_KEPT, FLAG_SMALL_ALPHA = 1, 2, 4
 
-EXPORTED = ("blm_workspace_bytes", "blm_create", "blm_destroy", "blm_begin_step",
+PRECISIONS = {"fp64": 0, "bf16x2": 1, "bf16x3": 2}
+
+EXPORTED = ("blm_pack_bf16", "blm_workspace_bytes", "blm_create", "blm_destroy", "blm_begin_step",
             "blm_build_blocks", "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
             "blm_debug_eigvals", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
             "blm_last_error",
             "blm_status_string")
 TIMING_NAMES = ("theta_proj", "block_gram", "block_reduce", "block_assemble", "block_eig",
-                "dir_proj", "stage2_gram", "stage2_reduce", "stage2_solve")
+                "dir_proj", "stage2_gram", "stage2_reduce", "stage2_solve", "block_strips")
 
 
 class BLMError(RuntimeError):
@@ -46,7 +48,8 @@ class _Config(C.Structure):
 
 class _Chunk(C.Structure):
     _fields_ = [("n_samples", C.c_int64), ("ld", C.c_int64), ("O", C.c_void_p), ("e", C.c_void_p),
-                ("E_L", C.c_void_p), ("w", C.c_void_p)]
+                ("E_L", C.c_void_p), ("w", C.c_void_p), ("layout", C.c_int32), ("pieces", C.c_int32),
+                ("piece_stride", C.c_int64)]
 
 
 _lib = None
@@ -61,6 +64,7 @@ def load() -> C.CDLL:
         raise ImportError(f"libblm.so not built at {LIB_PATH}; run python -m paper_1702_01481_amd.build_lib")
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.blm_pack_bf16.argtypes = [vp, i64, i64, i64, i32, vp, i64, i64, vp]
     lib.blm_workspace_bytes.argtypes = [C.POINTER(_Config), C.POINTER(C.c_size_t)]
     lib.blm_create.argtypes = [C.POINTER(_Config), vp, C.POINTER(vp)]
     lib.blm_destroy.argtypes = [vp]
@@ -102,7 +106,48 @@ def _check_f64_dev(t: torch.Tensor, name: str):
         raise TypeError(f"{name} must be a float64 device tensor")
 
 
+class SplitSamples:
+    """BF16 split storage (hi/lo or hi/mid/lo pieces, k-packed) of an FP64
+    [n][>= ncols] device array, made by the library's blm_pack_bf16."""
+
+    def __init__(self, src: torch.Tensor, pieces: int = 3, ncols: Optional[int] = None, stream=None):
+        _check_f64_dev(src, "src")
+        if src.dim() != 2 or src.stride(1) != 1:
+            raise ValueError("src must be [n][ld] with unit column stride")
+        self.n = int(src.shape[0])
+        self.ncols = int(ncols if ncols is not None else src.shape[1])
+        self.ld = self.ncols + (self.ncols & 1)
+        self.pieces = int(pieces)
+        n8 = (self.n + 7) // 8
+        self.piece_stride = n8 * 8 * self.ld
+        self.data = torch.empty(self.pieces * self.piece_stride, dtype=torch.int16, device=src.device)
+        st = load().blm_pack_bf16(C.c_void_p(src.data_ptr()), self.n, src.stride(0) if self.n else self.ncols,
+                                  self.ncols, self.pieces, C.c_void_p(self.data.data_ptr()), self.ld,
+                                  self.piece_stride, C.c_void_p(_stream_handle(stream)))
+        if st != BLM_OK:
+            raise BLMError(st, "blm_pack_bf16 failed")
+
+    def to_numpy(self) -> np.ndarray:
+        """Host copy of the pieces' sum (for checks): [n][ncols] float64."""
+        raw = self.data.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+        pcs = raw.view(np.float32).astype(np.float64).reshape(self.pieces, -1)
+        tot = pcs.sum(axis=0)
+        n8 = (self.n + 7) // 8
+        arr = tot.reshape(n8, self.ld, 8).transpose(0, 2, 1).reshape(n8 * 8, self.ld)
+        return arr[: self.n, : self.ncols]
+
+
 def _chunk(O, e, EL, w, n_params) -> _Chunk:
+    if isinstance(O, SplitSamples):
+        if not isinstance(e, SplitSamples) or e.n != O.n or e.ld != O.ld or e.pieces != O.pieces:
+            raise ValueError("O and e must be SplitSamples of the same shape")
+        if O.ncols < n_params:
+            raise ValueError("split chunk has too few columns")
+        _check_f64_dev(EL, "E_L")
+        if w is not None:
+            raise ValueError("the BF16 path needs uniform weights")
+        return _Chunk(O.n, O.ld, O.data.data_ptr(), e.data.data_ptr(), EL.data_ptr(), None, 1, O.pieces,
+                      O.piece_stride)
     _check_f64_dev(O, "O")
     _check_f64_dev(e, "e")
     _check_f64_dev(EL, "E_L")
@@ -115,14 +160,14 @@ def _chunk(O, e, EL, w, n_params) -> _Chunk:
         if w.shape[0] != O.shape[0] or not w.is_contiguous():
             raise ValueError("w must be contiguous [n]")
     return _Chunk(O.shape[0], O.stride(0) if O.shape[0] > 0 else O.shape[1], O.data_ptr(), e.data_ptr(),
-                  EL.data_ptr(), w.data_ptr() if w is not None else None)
+                  EL.data_ptr(), w.data_ptr() if w is not None else None, 0, 0, 0)
 
 
 class BLM:
     """One BLM optimisation context (blm_create .. blm_destroy)."""
 
     def __init__(self, n_params: int, block_offsets: Sequence[int], n_keep: int, n_old: int,
-                 shifts: Sequence[float], max_samples: int, stream=None):
+                 shifts: Sequence[float], max_samples: int, stream=None, precision: str = "fp64"):
         self.lib = load()
         self.n_params = int(n_params)
         self.offsets = np.ascontiguousarray(block_offsets, dtype=np.int64)
@@ -130,9 +175,10 @@ class BLM:
         self.n_keep, self.n_old = int(n_keep), int(n_old)
         self.shifts = np.ascontiguousarray(shifts, dtype=np.float64)
         self.max_samples = int(max_samples)
+        self.precision = precision
         self._cfg = _Config(self.n_params, self.n_blocks, self.offsets.ctypes.data_as(C.POINTER(C.c_int64)),
-                            self.n_keep, self.n_old, len(self.shifts), _dptr(self.shifts), 0,
-                            self.max_samples)
+                            self.n_keep, self.n_old, len(self.shifts), _dptr(self.shifts),
+                            PRECISIONS[precision], self.max_samples)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         self._check(self.lib.blm_create(C.byref(self._cfg), C.c_void_p(_stream_handle(self.stream)), C.byref(h)),
@@ -149,12 +195,13 @@ class BLM:
             raise BLMError(st, msg or self.lib.blm_status_string(st).decode())
 
     @staticmethod
-    def workspace_bytes(n_params, block_offsets, n_keep, n_old, shifts, max_samples) -> int:
+    def workspace_bytes(n_params, block_offsets, n_keep, n_old, shifts, max_samples,
+                        precision: str = "fp64") -> int:
         lib = load()
         off = np.ascontiguousarray(block_offsets, dtype=np.int64)
         sh = np.ascontiguousarray(shifts, dtype=np.float64)
         cfg = _Config(n_params, len(off) - 1, off.ctypes.data_as(C.POINTER(C.c_int64)), n_keep, n_old,
-                      len(sh), _dptr(sh), 0, max_samples)
+                      len(sh), _dptr(sh), PRECISIONS[precision], max_samples)
         out = C.c_size_t()
         st = lib.blm_workspace_bytes(C.byref(cfg), C.byref(out))
         if st != BLM_OK:

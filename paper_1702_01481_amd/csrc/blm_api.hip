@@ -68,7 +68,7 @@ struct blm_ctx {
   std::vector<int64_t> acc_off;
   std::vector<int> dmax;           // per block: largest pencil dimension
   int d2max = 0, n2max = 0;        // stage two
-  int Pcap1 = 1, Pcap2 = 1;
+  int Pcap1 = 1, Pcap2 = 1, PcapM = 1;
   int max_slices = 0;
   int64_t* d_off = nullptr;
 
@@ -79,6 +79,10 @@ struct blm_ctx {
   int32_t* d_dkeep = nullptr;
   GramJob *d_jobs1 = nullptr, *d_jobs2 = nullptr;
   int n_jobs1 = 0, n_jobs2 = 0;
+  // mixed precision: jobs1 = FP64 strip + aux jobs, jobsM = BF16 main-product jobs
+  GramJob* d_jobsM = nullptr;
+  int n_jobsM = 0;
+  int pieces = 0;                  // 0: FP64 path; 2 or 3: BF16 split pieces used
   Slice* d_slices = nullptr;
   ProjChunk* d_pchunks = nullptr;
   std::vector<ProjChunk> h_pchunks;
@@ -272,7 +276,9 @@ blm_status validate(const blm_config* cfg, blm_ctx* c) {
   for (int i = 0; i < cfg->n_shifts; ++i)
     if (!(cfg->shifts[i] >= 0.0) || !std::isfinite(cfg->shifts[i]))
       return fail(c, BLM_E_ARG, "shifts must be finite and >= 0");
-  if (cfg->precision != BLM_PREC_F64) return fail(c, BLM_E_ARG, "unsupported precision");
+  if (cfg->precision != BLM_PREC_F64 && cfg->precision != BLM_PREC_BF16X2 &&
+      cfg->precision != BLM_PREC_BF16X3)
+    return fail(c, BLM_E_ARG, "unsupported precision");
   if (cfg->max_samples < 1) return fail(c, BLM_E_ARG, "max_samples must be >= 1");
   if (cfg->block_offsets[0] != 0 || cfg->block_offsets[cfg->n_blocks] != cfg->n_params)
     return fail(c, BLM_E_ARG, "block_offsets must run from 0 to n_params");
@@ -308,13 +314,19 @@ void plan(blm_ctx* c, Plan& P) {
   run += NAUX * NAUX;
   c->acc_elems = run;
   c->n_jobs1 = n_jobs1 + 1;
+  int n_diag = 0;
+  for (int b = 0; b < NB; ++b) n_diag += (int)((c->off[b + 1] - c->off[b] + GT - 1) / GT);
+  c->n_jobsM = c->pieces ? n_jobs1 : 0;
+  if (c->pieces) c->n_jobs1 = n_diag + 1;
   c->n2max = 1 + NS * NB * (NK + 1);
   c->d2max = 1 + NB * (NK + 1);
   const int T2 = (c->n2max + GT - 1) / GT;
   const int n_jobs2max = T2 * (T2 + 1) / 2;
   c->Pcap1 = std::max(1, std::min(64, (4096 + c->n_jobs1 - 1) / c->n_jobs1));
   c->Pcap2 = std::max(1, std::min(64, (4096 + n_jobs2max - 1) / n_jobs2max));
-  const size_t slots = std::max((size_t)c->n_jobs1 * c->Pcap1, (size_t)n_jobs2max * c->Pcap2);
+  c->PcapM = c->n_jobsM ? std::max(1, std::min(64, (4096 + c->n_jobsM - 1) / c->n_jobsM)) : 1;
+  const size_t slots = std::max({(size_t)c->n_jobs1 * c->Pcap1, (size_t)n_jobs2max * c->Pcap2,
+                                 (size_t)c->n_jobsM * c->PcapM});
   c->max_slices = (int)(c->max_samples / SLICE) + 1024;
   c->auxlist_stride = 1 + NO * (NB - 1);
 
@@ -330,6 +342,7 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_off, 8 * (size_t)(NB + 1));
   add((void**)&c->d_jobs1, sizeof(GramJob) * (size_t)c->n_jobs1);
   add((void**)&c->d_jobs2, sizeof(GramJob) * (size_t)n_jobs2max);
+  add((void**)&c->d_jobsM, sizeof(GramJob) * (size_t)std::max(c->n_jobsM, 1));
   add((void**)&c->d_slices, sizeof(Slice) * (size_t)c->max_slices);
   add((void**)&c->d_pchunks, sizeof(ProjChunk) * (size_t)MAX_CHUNKS);
   add((void**)&c->d_theta_blk, sizeof(DirBlock) * (size_t)NB);
@@ -397,7 +410,7 @@ EigJob carve(double*& p, int d, int nbeta, int nk, int mode, int want, int beta0
 }
 
 blm_status upload_gram_jobs1(blm_ctx* c) {
-  std::vector<GramJob> jobs;
+  std::vector<GramJob> jobs, main;
   for (int b = 0; b < c->NB; ++b) {
     const int64_t M = c->off[b + 1] - c->off[b];
     const int T = (int)((M + GT - 1) / GT);
@@ -414,7 +427,19 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
         J.ht_off = c->acc_off[b] + (int64_t)GT * tj * M + (int64_t)GT * ti;
         J.ld_out = M;
         J.strip_col = J.ci;
-        jobs.push_back(J);
+        if (!c->pieces) {
+          jobs.push_back(J);
+        } else {
+          // main products on the BF16 matrix cores, strips in FP64
+          GramJob Mj = J;
+          if (ti == tj) Mj.kind = JOB_DIAG_NOSTRIP;
+          main.push_back(Mj);
+          if (ti == tj) {
+            GramJob Sj = J;
+            Sj.kind = JOB_STRIP;
+            jobs.push_back(Sj);
+          }
+        }
       }
   }
   GramJob A{};
@@ -424,7 +449,10 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
   A.ld_out = NAUX;
   jobs.push_back(A);
   c->n_jobs1 = (int)jobs.size();
+  c->n_jobsM = (int)main.size();
   HIPCHK(c, hipMemcpy(c->d_jobs1, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice));
+  if (!main.empty())
+    HIPCHK(c, hipMemcpy(c->d_jobsM, main.data(), sizeof(GramJob) * main.size(), hipMemcpyHostToDevice));
   return BLM_OK;
 }
 
@@ -444,6 +472,16 @@ blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) 
     if (ch[i].n_samples == 0) continue;
     if (ch[i].ld < c->NV) return fail(c, BLM_E_ARG, "chunk ld < n_params");
     if (!ch[i].O || !ch[i].e || !ch[i].E_L) return fail(c, BLM_E_ARG, "chunk pointer is NULL");
+    if (c->pieces == 0 && ch[i].layout != BLM_LAYOUT_F64)
+      return fail(c, BLM_E_ARG, "the FP64 precision needs BLM_LAYOUT_F64 chunks");
+    if (c->pieces) {
+      if (ch[i].layout != BLM_LAYOUT_BF16_SPLIT || ch[i].pieces < c->pieces || ch[i].pieces > 3)
+        return fail(c, BLM_E_ARG, "the BF16 precisions need split chunks with enough pieces");
+      if (ch[i].w) return fail(c, BLM_E_ARG, "the BF16 precisions need uniform weights (w == NULL)");
+      if ((ch[i].piece_stride & 7) || ch[i].piece_stride < 8 * ((ch[i].n_samples + 7) / 8) * ch[i].ld ||
+          ((uintptr_t)ch[i].O & 15) || ((uintptr_t)ch[i].e & 15))
+        return fail(c, BLM_E_ARG, "split chunk: piece_stride or alignment invalid");
+    }
     t += ch[i].n_samples;
   }
   if (t > c->max_samples) return fail(c, BLM_E_ARG, "more samples in one call than max_samples");
@@ -470,6 +508,8 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
     P.n = ns;
     P.row_base = rb;
     P.tile0 = tiles;
+    P.pieces = c->pieces;
+    P.pstride = ch[i].piece_stride;
     c->h_pchunks.push_back(P);
     tiles += (int)((ns + PROJ_ROWS - 1) / PROJ_ROWS);
     rb += ns;
@@ -478,30 +518,38 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
   if (c->h_pchunks.empty()) return BLM_OK;
   HIPCHK(c, hipMemcpyAsync(c->d_pchunks, c->h_pchunks.data(), sizeof(ProjChunk) * c->h_pchunks.size(),
                            hipMemcpyHostToDevice, c->st));
-  launch_dirproj(c->d_pchunks, (int)c->h_pchunks.size(), tiles, vec, d_blocks, n_blocks, d_ptr, n_dirs,
-                 Xo, Yo, ldo, c->st);
+  launch_dirproj(c->d_pchunks, (int)c->h_pchunks.size(), tiles, vec && !c->pieces, c->pieces != 0,
+                 d_blocks, n_blocks, d_ptr, n_dirs, Xo, Yo, ldo, c->st);
   HIPCHK(c, hipGetLastError());
   return BLM_OK;
 }
 
+// kind: 0 FP64 kernel on FP64 storage, 1 FP64 kernel on split storage
+// (strips), 2 BF16 matrix-core kernel on split storage (main products)
 blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_base,
-                    double* h_base, double* strip_base, int phase, bool vec) {
+                    double* h_base, double* strip_base, int phase, bool vec, int kind = 0) {
   const int n_slices = (int)c->h_slices.size();
-  if (n_slices == 0) return BLM_OK;
+  if (n_slices == 0 || n_jobs == 0) return BLM_OK;
   for (const Slice& S : c->h_slices)
     if ((S.ld & 1) || ((uintptr_t)S.O & 15) || ((uintptr_t)S.e & 15)) vec = false;
   if (n_slices > c->max_slices) return fail(c, BLM_E_ARG, "too many slices in one call");
   HIPCHK(c, hipMemcpyAsync(c->d_slices, c->h_slices.data(), sizeof(Slice) * n_slices,
                            hipMemcpyHostToDevice, c->st));
   const int P = choose_P(cap, n_jobs, n_slices);
-  mark(c, phase, false);
-  launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec, c->partial, c->st);
+  if (phase >= 0) mark(c, phase, false);
+  if (kind == 2)
+    launch_gram_bf16(d_jobs, n_jobs, c->d_slices, n_slices, P, c->pieces, c->partial, c->st);
+  else
+    launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec && kind == 0, kind == 1, c->partial,
+                c->st);
   HIPCHK(c, hipGetLastError());
-  mark(c, phase, true);
-  mark(c, phase + 1, false);
+  if (phase >= 0) {
+    mark(c, phase, true);
+    mark(c, phase + 1, false);
+  }
   launch_gram_reduce(d_jobs, n_jobs, P, c->partial, s_base, h_base, strip_base, c->NV, c->st);
   HIPCHK(c, hipGetLastError());
-  mark(c, phase + 1, true);
+  if (phase >= 0) mark(c, phase + 1, true);
   return BLM_OK;
 }
 
@@ -537,12 +585,23 @@ blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes) {
   tmp.NS = cfg->n_shifts;
   tmp.off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
   tmp.max_samples = cfg->max_samples;
+  tmp.pieces = cfg->precision == BLM_PREC_BF16X3 ? 3 : cfg->precision == BLM_PREC_BF16X2 ? 2 : 0;
   Plan P;
   plan(&tmp, P);
   size_t t = 0;
   for (auto& it : P.items) t += (it.second + 255) / 256 * 256;
   *bytes = t + eig_total_bytes(&tmp);
   return BLM_OK;
+}
+
+blm_status blm_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncols, int32_t pieces,
+                         uint16_t* dst, int64_t ld_dst, int64_t piece_stride, void* stream) {
+  if (!src || !dst || n < 0 || ncols < 1 || ld_src < ncols || ld_dst < ncols) return BLM_E_ARG;
+  if (pieces < 2 || pieces > 3 || (piece_stride & 7) || piece_stride < 8 * ((n + 7) / 8) * ld_dst ||
+      ((uintptr_t)dst & 15))
+    return BLM_E_ARG;
+  launch_pack_bf16(src, n, ld_src, ncols, pieces, dst, ld_dst, piece_stride, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? BLM_OK : BLM_E_HIP;
 }
 
 blm_status blm_get_solver_stats(blm_ctx* c, int32_t* h_stats, int32_t n) {
@@ -598,6 +657,7 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
   c->NO = cfg->n_old;
   c->NS = cfg->n_shifts;
   c->prec = cfg->precision;
+  c->pieces = cfg->precision == BLM_PREC_BF16X3 ? 3 : cfg->precision == BLM_PREC_BF16X2 ? 2 : 0;
   c->off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
   c->shifts.assign(cfg->shifts, cfg->shifts + cfg->n_shifts);
   c->max_samples = cfg->max_samples;
@@ -737,8 +797,16 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     if (ns == 0) continue;
     for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
       Slice S{};
-      S.O = ch[i].O + (size_t)s0 * ch[i].ld;
-      S.e = ch[i].e + (size_t)s0 * ch[i].ld;
+      if (c->pieces) {
+        // k-packed pieces: slice starts are multiples of 8 samples
+        S.O = (const uint16_t*)ch[i].O + (size_t)(s0 / 8) * ch[i].ld * 8;
+        S.e = (const uint16_t*)ch[i].e + (size_t)(s0 / 8) * ch[i].ld * 8;
+        S.pstride = ch[i].piece_stride;
+        S.pieces = c->pieces;
+      } else {
+        S.O = (const double*)ch[i].O + (size_t)s0 * ch[i].ld;
+        S.e = (const double*)ch[i].e + (size_t)s0 * ch[i].ld;
+      }
       S.Xa = c->Xa + (size_t)(rb + s0) * NAUX;
       S.Ya = c->Ya + (size_t)(rb + s0) * NAUX;
       S.w = ch[i].w ? ch[i].w + s0 : nullptr;
@@ -749,7 +817,16 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     rb += ns;
   }
   mark(c, 0, true);
-  s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even);
+  if (c->pieces) {
+    // FP64 strips and aux Gram (timed as the reduction phase), then the BF16 main products
+    mark(c, 9, false);
+    s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, -1, false, 1);
+    if (s != BLM_OK) return s;
+    mark(c, 9, true);
+    s = run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, c->accS, c->accH, c->strips, 1, false, 2);
+  } else {
+    s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even);
+  }
   if (s != BLM_OK) return s;
   c->n_pass1 += total;
   c->state = ST_BUILT;

@@ -19,7 +19,8 @@ enum JobKind : int32_t {
   JOB_OFF = 0,          // i < j: S_ij = O_i^T W O_j, H_ij = O_i^T W e_j, H_ji^T = e_i^T W O_j
   JOB_DIAG = 1,         // i == j: S_ii, H_ii, plus strips aux^T W O_i, aux^T W e_i, auxE^T W O_i
   JOB_DIAG_NOSTRIP = 2, // i == j without strips
-  JOB_AUX = 3           // aux x aux: Xa^T W Xa, Xa^T W Ya (panels taken from the aux arrays)
+  JOB_AUX = 3,          // aux x aux: Xa^T W Xa, Xa^T W Ya (panels taken from the aux arrays)
+  JOB_STRIP = 4         // strips of a diagonal tile only (mixed precision: main products elsewhere)
 };
 
 struct GramJob {
@@ -34,14 +35,21 @@ struct GramJob {
   int64_t strip_col;    // JOB_DIAG: global parameter column of the strip's first column
 };
 
+// Sample storage: FP64 sample-major ([n][ld]), or BF16 split pieces in the
+// k-packed layout: element (s, x) of piece p at base + p * pstride +
+// ((s / 8) * ld + x) * 8 + s % 8, so that 8 consecutive samples of one
+// parameter are 16 contiguous bytes (one matrix-core operand).
 struct Slice {
-  const double* O;      // main panels (sample-major, row stride ld)
-  const double* e;
+  const void* O;        // main panels: FP64 (row stride ld) or BF16 pieces (k-packed)
+  const void* e;
   const double* Xa;     // aux panels (row stride NAUX), already offset to the slice's first row
   const double* Ya;
   const double* w;      // weights of the slice's first row, or nullptr
   int64_t ld;
   int64_t n;            // samples in the slice
+  int64_t pstride;      // BF16 pieces: elements between pieces
+  int32_t pieces;       // 0: FP64 storage; 2 or 3: BF16 split pieces
+  int32_t pad;
 };
 
 // ------------------------------------------------- direction projection ---
@@ -56,14 +64,15 @@ struct DirBlock {
 // one chunk of a projection launch: its samples go to output rows
 // [row_base, row_base + n); workgroups [tile0, tile0 + ceil(n / 64)) cover it
 struct ProjChunk {
-  const double* O;
-  const double* e;
+  const void* O;
+  const void* e;
   const double* EL;
   int64_t ld;
   int64_t n;
   int64_t row_base;
+  int64_t pstride;
   int32_t tile0;
-  int32_t pad;
+  int32_t pieces;       // 0: FP64 storage; 2 or 3: BF16 split pieces (k-packed)
 };
 constexpr int PROJ_ROWS = 64;
 
@@ -112,11 +121,15 @@ constexpr int EIG_MAXSEL = 16;   // eigenvalues selected per problem (N_K + 1 <=
 
 // launchers (blm_kernels.hip / blm_eig.hip)
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                 bool vec, double* d_partial, hipStream_t st);
+                 bool vec, bool split, double* d_partial, hipStream_t st);
+void launch_gram_bf16(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
+                      int pieces, double* d_partial, hipStream_t st);
+void launch_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncols, int pieces,
+                      uint16_t* dst, int64_t ld_dst, int64_t pstride, hipStream_t st);
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
                         hipStream_t st);
-void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec,
+void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, bool split,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st);
 void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);

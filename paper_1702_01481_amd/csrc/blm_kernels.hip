@@ -23,6 +23,40 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+__device__ __forceinline__ double bf16_to_f64(uint16_t h) {
+  return (double)__uint_as_float((uint32_t)h << 16);
+}
+
+// Element (row, col) of BF16 split storage (k-packed), as the exact FP64 sum
+// of its pieces.
+__device__ __forceinline__ double split_load(const void* base, int64_t ld, int64_t pstride,
+                                             int pieces, int64_t row, int64_t col) {
+  const uint16_t* b = (const uint16_t*)base;
+  const int64_t i = ((row >> 3) * ld + col) * 8 + (row & 7);
+  double v = bf16_to_f64(b[i]);
+  if (pieces > 1) v += bf16_to_f64(b[i + pstride]);
+  if (pieces > 2) v += bf16_to_f64(b[i + 2 * pstride]);
+  return v;
+}
+
+// The 8 samples of one 8-sample group of one column in BF16 split storage,
+// each as the exact FP64 sum of its pieces: one 16-byte load per piece.
+__device__ __forceinline__ void split_load8(const void* base, int64_t ld, int64_t pstride,
+                                            int pieces, int64_t group, int64_t col, double* v) {
+  const uint16_t* b = (const uint16_t*)base + (group * ld + col) * 8;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = 0.0;
+  for (int pc = 0; pc < pieces; ++pc) {
+    const uint4 w = *reinterpret_cast<const uint4*>(b + (size_t)pc * pstride);
+    const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] += (double)__uint_as_float(u[k] << 16);
+      v[2 * k + 1] += (double)__uint_as_float(u[k] & 0xFFFF0000u);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Gram tiles
 // ---------------------------------------------------------------------------
@@ -47,7 +81,7 @@ __device__ __forceinline__ void load_pair(const double* p, int col, int lim, dou
   }
 }
 
-template <bool VEC>
+template <bool VEC, bool SPLIT>
 __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int64_t ro, int tid,
                                           StageRegs& R) {
   const int lr = tid >> 4;            // sample row within the stage (0..15)
@@ -55,28 +89,49 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
   const int64_t row = ro + lr;
   const bool valid = row < S.n;
   const bool aux = (J.kind == JOB_AUX);
-  const double* pO = aux ? S.Xa : S.O;
-  const double* pe = aux ? S.Ya : S.e;
-  const int64_t ld = aux ? (int64_t)NAUX : S.ld;
   const double wgt = (valid && S.w) ? S.w[row] : 1.0;
   const int mi = valid ? J.mi : 0, nj = valid ? J.nj : 0;
-  const double* rO = pO + row * ld;
-  const double* re = pe + row * ld;
+  if (SPLIT && !aux) {
+    // strip jobs on split storage (uniform weights): thread -> (panel, 8-sample
+    // group, column); 8 samples of one column of O (panel 0) or e (panel 1)
+    // land in a[0..3], e[0..3]
+    const int pnl = tid >> 7, g = (tid >> 6) & 1, c = tid & 63;
+    double v[8];
+    const int64_t r0 = ro + 8 * g;
+    if (r0 < S.n && c < J.nj) {
+      split_load8(pnl ? S.e : S.O, S.ld, S.pstride, S.pieces, r0 >> 3, J.cj + c, v);
+    } else {
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int col = lc + 2 * h;
-    load_pair<VEC>(rO + J.ci, col, mi, R.a[2 * h], R.a[2 * h + 1]);
-    if (J.kind == JOB_OFF) load_pair<VEC>(re + J.ci, col, mi, R.e[2 * h], R.e[2 * h + 1]);
-    else R.e[2 * h] = R.e[2 * h + 1] = 0.0;
-    load_pair<VEC>(rO + J.cj, col, nj, R.b[2 * h], R.b[2 * h + 1]);
-    load_pair<VEC>(re + J.cj, col, nj, R.f[2 * h], R.f[2 * h + 1]);
-  }
+      for (int k = 0; k < 8; ++k) v[k] = 0.0;
+    }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    R.a[c] *= wgt;
-    R.e[c] *= wgt;
+    for (int k = 0; k < 4; ++k) {
+      R.a[k] = v[k];
+      R.e[k] = v[4 + k];
+    }
+  } else {
+    const double* pO = aux ? S.Xa : (const double*)S.O;
+    const double* pe = aux ? S.Ya : (const double*)S.e;
+    const int64_t ld = aux ? (int64_t)NAUX : S.ld;
+    const double* rO = pO + row * ld;
+    const double* re = pe + row * ld;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = lc + 2 * h;
+      if (J.kind != JOB_STRIP) load_pair<VEC>(rO + J.ci, col, mi, R.a[2 * h], R.a[2 * h + 1]);
+      else R.a[2 * h] = R.a[2 * h + 1] = 0.0;
+      if (J.kind == JOB_OFF) load_pair<VEC>(re + J.ci, col, mi, R.e[2 * h], R.e[2 * h + 1]);
+      else R.e[2 * h] = R.e[2 * h + 1] = 0.0;
+      load_pair<VEC>(rO + J.cj, col, nj, R.b[2 * h], R.b[2 * h + 1]);
+      load_pair<VEC>(re + J.cj, col, nj, R.f[2 * h], R.f[2 * h + 1]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      R.a[c] *= wgt;
+      R.e[c] *= wgt;
+    }
   }
-  if (J.kind == JOB_DIAG) {
+  if (J.kind == JOB_DIAG || J.kind == JOB_STRIP) {
     const int acol = tid & 15;
     R.x = valid ? S.Xa[row * NAUX + acol] * wgt : 0.0;
     R.y = valid ? S.Ya[row * NAUX + acol] * wgt : 0.0;
@@ -86,7 +141,7 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
   }
 }
 
-template <bool VEC>
+template <bool VEC, bool SPLIT>
 __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __restrict__ jobs,
                                                            int n_jobs,
                                                            const Slice* __restrict__ slices,
@@ -129,19 +184,33 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
   int64_t ro = 0;
   StageRegs R;
   int buf = 0;
+  // register stage -> LDS buffer nb
+  auto store = [&](int nb) {
+    const int lr = tid >> 4, lc = (tid & 15) * 4;
+    if (SPLIT && kind == JOB_STRIP) {
+      const int pnl = tid >> 7, g = (tid >> 6) & 1, c = tid & 63;
+      double(*dst)[GT] = pnl ? sF[nb] : sB[nb];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        dst[8 * g + k][c] = R.a[k];
+        dst[8 * g + 4 + k][c] = R.e[k];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sA[nb][lr][lc + c] = R.a[c];
+        sE[nb][lr][lc + c] = R.e[c];
+        sB[nb][lr][lc + c] = R.b[c];
+        sF[nb][lr][lc + c] = R.f[c];
+      }
+    }
+    sX[nb][lr][tid & 15] = R.x;
+    sY[nb][lr][tid & 15] = R.y;
+  };
   if (si < n_slices) {
     Slice S = slices[si];
-    gram_load<VEC>(J, S, ro, tid, R);
-    const int lr = tid >> 4, lc = (tid & 15) * 4;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      sA[0][lr][lc + c] = R.a[c];
-      sE[0][lr][lc + c] = R.e[c];
-      sB[0][lr][lc + c] = R.b[c];
-      sF[0][lr][lc + c] = R.f[c];
-    }
-    sX[0][lr][tid & 15] = R.x;
-    sY[0][lr][tid & 15] = R.y;
+    gram_load<VEC, SPLIT>(J, S, ro, tid, R);
+    store(0);
   }
   __syncthreads();
 
@@ -157,7 +226,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
     const bool has_next = si2 < n_slices;
     if (has_next) {
       Slice S2 = slices[si2];
-      gram_load<VEC>(J, S2, ro2, tid, R);
+      gram_load<VEC, SPLIT>(J, S2, ro2, tid, R);
     }
 
 #pragma unroll
@@ -166,21 +235,23 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
       const double a0 = sA[buf][kr][32 * wr + i16], a1 = sA[buf][kr][32 * wr + 16 + i16];
       const double b0 = sB[buf][kr][32 * wc + i16], b1 = sB[buf][kr][32 * wc + 16 + i16];
       const double f0 = sF[buf][kr][32 * wc + i16], f1 = sF[buf][kr][32 * wc + 16 + i16];
-      P0[0][0] = mfma_f64(a0, b0, P0[0][0]);
-      P0[0][1] = mfma_f64(a0, b1, P0[0][1]);
-      P0[1][0] = mfma_f64(a1, b0, P0[1][0]);
-      P0[1][1] = mfma_f64(a1, b1, P0[1][1]);
-      P1[0][0] = mfma_f64(a0, f0, P1[0][0]);
-      P1[0][1] = mfma_f64(a0, f1, P1[0][1]);
-      P1[1][0] = mfma_f64(a1, f0, P1[1][0]);
-      P1[1][1] = mfma_f64(a1, f1, P1[1][1]);
+      if (kind != JOB_STRIP) {
+        P0[0][0] = mfma_f64(a0, b0, P0[0][0]);
+        P0[0][1] = mfma_f64(a0, b1, P0[0][1]);
+        P0[1][0] = mfma_f64(a1, b0, P0[1][0]);
+        P0[1][1] = mfma_f64(a1, b1, P0[1][1]);
+        P1[0][0] = mfma_f64(a0, f0, P1[0][0]);
+        P1[0][1] = mfma_f64(a0, f1, P1[0][1]);
+        P1[1][0] = mfma_f64(a1, f0, P1[1][0]);
+        P1[1][1] = mfma_f64(a1, f1, P1[1][1]);
+      }
       if (kind == JOB_OFF) {
         const double e0 = sE[buf][kr][32 * wr + i16], e1 = sE[buf][kr][32 * wr + 16 + i16];
         P2[0][0] = mfma_f64(e0, b0, P2[0][0]);
         P2[0][1] = mfma_f64(e0, b1, P2[0][1]);
         P2[1][0] = mfma_f64(e1, b0, P2[1][0]);
         P2[1][1] = mfma_f64(e1, b1, P2[1][1]);
-      } else if (kind == JOB_DIAG) {
+      } else if (kind == JOB_DIAG || kind == JOB_STRIP) {
         const double xs = sX[buf][kr][i16], ys = sY[buf][kr][i16];
         const double bs = sB[buf][kr][16 * wv + i16], fs = sF[buf][kr][16 * wv + i16];
         P2[0][0] = mfma_f64(xs, bs, P2[0][0]);   // aux^T W O_i
@@ -189,19 +260,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
       }
     }
 
-    if (has_next) {
-      const int lr = tid >> 4, lc = (tid & 15) * 4;
-      const int nb = buf ^ 1;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        sA[nb][lr][lc + c] = R.a[c];
-        sE[nb][lr][lc + c] = R.e[c];
-        sB[nb][lr][lc + c] = R.b[c];
-        sF[nb][lr][lc + c] = R.f[c];
-      }
-      sX[nb][lr][tid & 15] = R.x;
-      sY[nb][lr][tid & 15] = R.y;
-    }
+    if (has_next) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
     si = si2;
@@ -221,7 +280,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
         base[GT * GT + row * GT + col] = P1[x][y][rr];
         if (kind == JOB_OFF) base[2 * GT * GT + row * GT + col] = P2[x][y][rr];
       }
-  if (kind == JOB_DIAG) {
+  if (kind == JOB_DIAG || kind == JOB_STRIP) {
     // strips: [3][NAUX][GT] in the third slot
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
@@ -242,8 +301,9 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
                                                           int64_t strip_ld) {
   const int jid = blockIdx.x, qd = blockIdx.y;
   const GramJob J = jobs[jid];
-  const bool strips = (J.kind == JOB_DIAG);
+  const bool strips = (J.kind == JOB_DIAG || J.kind == JOB_STRIP);
   if (qd == 2 && J.kind != JOB_OFF && !strips) return;
+  if (qd < 2 && J.kind == JOB_STRIP) return;
   const int n_el = (qd == 2 && strips) ? 3 * NAUX * GT : GT * GT;
   for (int el = threadIdx.x; el < n_el; el += blockDim.x) {
     double sum = 0.0;
@@ -263,14 +323,17 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
 }
 
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                 bool vec, double* d_partial, hipStream_t st) {
+                 bool vec, bool split, double* d_partial, hipStream_t st) {
   if (n_jobs <= 0) return;
-  if (vec)
-    hipLaunchKernelGGL(gram_kernel<true>, dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs, n_jobs,
-                       d_slices, n_slices, P, d_partial);
+  if (split)
+    hipLaunchKernelGGL((gram_kernel<false, true>), dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs,
+                       n_jobs, d_slices, n_slices, P, d_partial);
+  else if (vec)
+    hipLaunchKernelGGL((gram_kernel<true, false>), dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs,
+                       n_jobs, d_slices, n_slices, P, d_partial);
   else
-    hipLaunchKernelGGL(gram_kernel<false>, dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs, n_jobs,
-                       d_slices, n_slices, P, d_partial);
+    hipLaunchKernelGGL((gram_kernel<false, false>), dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs,
+                       n_jobs, d_slices, n_slices, P, d_partial);
 }
 
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
@@ -296,11 +359,22 @@ struct PjRegs {
 // Stage loader: 64 samples x 32 parameters of O and e, and 32 directions x
 // 32 parameters of the direction rows.  VEC: 16-byte loads (the caller has
 // checked alignment); otherwise 8-byte loads.
-template <bool VEC>
+template <bool VEC, bool SPLIT>
 __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const DirBlock& B, int dg,
                                         int p0, const double* const* __restrict__ dir_ptr, int tid,
                                         PjRegs& R) {
-  if (VEC) {
+  if (SPLIT) {
+    // thread -> (8-sample group g, parameter col): 8 samples of O and of e
+    const int col = tid & 31, g = tid >> 5;
+    const int64_t r0 = s0 + 8 * g;
+    if (r0 < C.n && p0 + col < B.m) {
+      split_load8(C.O, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.o);
+      split_load8(C.e, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.e);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) R.o[k] = R.e[k] = 0.0;
+    }
+  } else if (VEC) {
     const int c2 = (tid & 15) * 2;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -308,8 +382,10 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
       const int64_t s = s0 + row;
       const bool v = (s < C.n) && (p0 + c2 < B.m);
       if (v) {
-        const double2 a = *reinterpret_cast<const double2*>(C.O + s * C.ld + B.col0 + p0 + c2);
-        const double2 b = *reinterpret_cast<const double2*>(C.e + s * C.ld + B.col0 + p0 + c2);
+        const double2 a =
+            *reinterpret_cast<const double2*>((const double*)C.O + s * C.ld + B.col0 + p0 + c2);
+        const double2 b =
+            *reinterpret_cast<const double2*>((const double*)C.e + s * C.ld + B.col0 + p0 + c2);
         R.o[2 * i] = a.x;
         R.o[2 * i + 1] = a.y;
         R.e[2 * i] = b.x;
@@ -325,8 +401,8 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
       const int row = (tid >> 5) + 8 * i;
       const int64_t s = s0 + row;
       const bool v = (s < C.n) && (p0 + col < B.m);
-      R.o[i] = v ? C.O[s * C.ld + B.col0 + p0 + col] : 0.0;
-      R.e[i] = v ? C.e[s * C.ld + B.col0 + p0 + col] : 0.0;
+      R.o[i] = v ? ((const double*)C.O)[s * C.ld + B.col0 + p0 + col] : 0.0;
+      R.e[i] = v ? ((const double*)C.e)[s * C.ld + B.col0 + p0 + col] : 0.0;
     }
   }
   const int col = tid & 31;
@@ -338,10 +414,17 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
   }
 }
 
-template <bool VEC>
+template <bool VEC, bool SPLIT>
 __device__ __forceinline__ void pj_store(double (*sO)[PJ_P + 1], double (*sE)[PJ_P + 1],
                                          double (*sD)[PJ_P + 1], int tid, const PjRegs& R) {
-  if (VEC) {
+  if (SPLIT) {
+    const int col = tid & 31, g = tid >> 5;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      sO[8 * g + k][col] = R.o[k];
+      sE[8 * g + k][col] = R.e[k];
+    }
+  } else if (VEC) {
     const int c2 = (tid & 15) * 2;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -365,7 +448,7 @@ __device__ __forceinline__ void pj_store(double (*sO)[PJ_P + 1], double (*sE)[PJ
   for (int i = 0; i < 4; ++i) sD[(tid >> 5) + 8 * i][col] = R.d[i];
 }
 
-template <bool VEC>
+template <bool VEC, bool SPLIT>
 __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restrict__ chunks,
                                                       int n_chunks,
                                                       const DirBlock* __restrict__ blocks,
@@ -406,13 +489,13 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
       const bool two = (B.nd - dg) > 16;
       d4 aO0 = {0, 0, 0, 0}, aO1 = {0, 0, 0, 0}, aE0 = {0, 0, 0, 0}, aE1 = {0, 0, 0, 0};
       PjRegs R;
-      pj_load<VEC>(C, s0, B, dg, 0, dir_ptr, tid, R);
+      pj_load<VEC, SPLIT>(C, s0, B, dg, 0, dir_ptr, tid, R);
       for (int p0 = 0; p0 < B.m; p0 += PJ_P) {
         __syncthreads();   // everyone is done reading the previous stage
-        pj_store<VEC>(sO, sE, sD, tid, R);
+        pj_store<VEC, SPLIT>(sO, sE, sD, tid, R);
         __syncthreads();
         // the next stage's global loads overlap this stage's matrix-core work
-        if (p0 + PJ_P < B.m) pj_load<VEC>(C, s0, B, dg, p0 + PJ_P, dir_ptr, tid, R);
+        if (p0 + PJ_P < B.m) pj_load<VEC, SPLIT>(C, s0, B, dg, p0 + PJ_P, dir_ptr, tid, R);
 #pragma unroll
         for (int kk = 0; kk < PJ_P; kk += 4) {
           const int kc = kk + k4;
@@ -445,16 +528,19 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
   }
 }
 
-void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec,
+void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, bool split,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st) {
   if (n_tiles <= 0) return;
-  if (vec)
-    hipLaunchKernelGGL(dirproj_kernel<true>, dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks,
-                       d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+  if (split)
+    hipLaunchKernelGGL((dirproj_kernel<false, true>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
+                       n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+  else if (vec)
+    hipLaunchKernelGGL((dirproj_kernel<true, false>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
+                       n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
   else
-    hipLaunchKernelGGL(dirproj_kernel<false>, dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks,
-                       d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+    hipLaunchKernelGGL((dirproj_kernel<false, false>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
+                       n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
 }
 
 }  // namespace blm

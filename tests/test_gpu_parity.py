@@ -206,3 +206,78 @@ def test_error_paths():
         ctx.build([(O, e, EL), (O, e, EL), (O, e, EL)])
     assert ei.value.status == 1
     ctx.close()
+
+
+# --------------------------------------------------------- mixed precision --
+
+def test_pack_bf16_split_is_accurate():
+    blm = _blm()
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((37, 21)) * np.exp(rng.uniform(-8, 8, size=(37, 21)))
+    for pieces, tol in ((3, 2.0 ** -22), (2, 2.0 ** -14)):
+        sp = blm.SplitSamples(torch.from_numpy(x).cuda(), pieces)
+        torch.cuda.synchronize()
+        y = sp.to_numpy()
+        assert np.all(np.abs(y - x) <= tol * np.abs(x)), (pieces, np.max(np.abs(y - x) / np.abs(x)))
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x2"])
+def test_mixed_build_is_exact_on_small_integers(precision):
+    """Integers in [-7, 7] are exact in one BF16 piece and every partial sum
+    is exact in FP32: the mixed build must equal the oracle bit for bit."""
+    blm = _blm()
+    n, nv = 4096, 160
+    O, e, EL = synth.dyadic_chunk(n, nv, 8)
+    offsets = [0, 70, 160]
+    host = [(O.numpy(), e.numpy(), EL.numpy(), None)]
+    pieces = 3 if precision == "bf16x3" else 2
+    dev = [(blm.SplitSamples(O.cuda(), pieces), blm.SplitSamples(e.cuda(), pieces), EL.cuda())]
+    old = synth.dyadic_chunk(1, nv, 9)[0].numpy()
+    ctx = blm.BLM(nv, offsets, 2, 1, [0.0], n, precision=precision)
+    ctx.begin_step(torch.from_numpy(old).cuda())
+    ctx.build(dev)
+    D = orc.previous_directions(old, np.array(offsets))
+    probs, _ = orc.block_problems(host, np.array(offsets), D)
+    for b in range(2):
+        H, S = ctx.block_matrices(b, 0)
+        M = offsets[b + 1] - offsets[b]
+        Sx = np.triu(probs[b].S) + np.triu(probs[b].S, 1).T
+        # parameter block: BF16 matrix cores, exact
+        assert np.array_equal(S[1:1 + M, 1:1 + M], Sx[1:1 + M, 1:1 + M])
+        assert np.array_equal(H[1:1 + M, 1:1 + M], probs[b].H[1:1 + M, 1:1 + M])
+        # rows and columns of Psi and Theta: FP64 (Theta columns are not integers)
+        assert _rel(S, Sx) < 1e-13 and _rel(H, probs[b].H) < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,en_tol,cos_tol", [("bf16x3", 1e-6, 1e-6), ("bf16x2", 1e-4, 1e-4)])
+def test_mixed_step_against_fp64_oracle(precision, en_tol, cos_tol):
+    """Mixed precision on the 200-parameter workload: energy within en_tol
+    relative of the FP64 oracle, update cosine above 1 - cos_tol."""
+    blm = _blm()
+    w = synth.workload("small")
+    host, dev = _make(w.n_params, w.n_samples, w.rank, 0, w.chunk)
+    shifts = [1e-3, 1e-2]
+    res, probs = orc.blm_step(lambda: host, w.block_offsets, w.n_keep, shifts)
+    pieces = 3 if precision == "bf16x3" else 2
+    sdev = [(blm.SplitSamples(O, pieces), blm.SplitSamples(e, pieces), EL) for O, e, EL, _ in dev]
+    ctx = blm.BLM(w.n_params, w.block_offsets, w.n_keep, 0, shifts, w.n_samples, precision=precision)
+    ctx.begin_step()
+    ctx.build(sdev)
+    errs = []
+    for b in range(w.n_blocks):
+        H, S = ctx.block_matrices(b, 0)
+        errs.append((_rel(S, probs[b].S), _rel(H, probs[b].H + shifts[0] * probs[b].P)))
+    ctx.solve()
+    ctx.project(sdev)
+    upd, en, _, _ = ctx.stage2()
+    upd = upd.cpu().numpy()
+    print(precision, "max matrix rel errors (S, H):", np.max(errs, axis=0))
+    for si in range(len(shifts)):
+        ref = res[si].step
+        rel_e = abs(en[si] - ref.energy) / abs(ref.energy)
+        cos = upd[si] @ ref.dmu / (np.linalg.norm(upd[si]) * np.linalg.norm(ref.dmu))
+        print(precision, "shift", shifts[si], "energy rel err", rel_e, "update cosine", cos)
+        assert rel_e <= en_tol, (si, rel_e)
+        assert cos >= 1 - cos_tol, (si, cos)
+    ctx.close()
