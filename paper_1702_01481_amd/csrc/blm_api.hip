@@ -260,7 +260,7 @@ struct Plan {
 
 size_t eig_bytes(int d, int nbeta, int nk) {
   const size_t dd = (size_t)d * d;
-  return 8 * (4 * dd + 2 * dd + 2 * (size_t)EIG_MAXSEL * d + 3 * (size_t)d +
+  return 8 * (4 * dd + std::max(2 * dd, (size_t)16 * d) + 2 * (size_t)EIG_MAXSEL * d + 3 * (size_t)d +
               (size_t)(nk + 2) * std::max(nbeta, 2 * d));
 }
 
@@ -398,7 +398,7 @@ EigJob carve(double*& p, int d, int nbeta, int nk, int mode, int want, int beta0
   J.A = p; p += dd;
   J.Hq = p; p += dd;
   J.V = p; p += dd;
-  J.W = p; p += 2 * dd;
+  J.W = p; p += std::max(2 * dd, (size_t)16 * d);
   J.vec = p; p += 2 * (size_t)EIG_MAXSEL * d;
   J.wr = p; p += d;
   J.wi = p; p += d;

@@ -33,6 +33,8 @@ constexpr double DROP_TOL = 1e-12;
 struct Shared {
   double v1[EIG_MAXD];
   double v2[EIG_MAXD];
+  double v3[EIG_MAXD];
+  double stage[16][256];
   double red[NW];
   double sc[16];
   int isc[16];
@@ -116,50 +118,84 @@ __device__ int cholesky(Shared& sh, double* S, int d) {
 }
 
 // ---------------------------------------------------------------- step 2 --
-// A <- L^-1 A L^-T with L in the lower triangle of S.
-__device__ void congruence(Shared& sh, const double* L, double* A, int d) {
+// In place X <- L^-1 X for an n x n row-major X (L in the lower triangle of
+// Lm), 16 rows at a time: the block's rows are solved in turn, staged in LDS
+// by column chunks, and subtracted from all rows below in one pass (each
+// trailing element is read and written once per 16 rows of L).
+constexpr int CB = 16;       // rows per block
+constexpr int CCH = 256;     // columns per LDS chunk
+
+__device__ void lower_solve_rows(Shared& sh, const double* Lm, double* X, int n) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // X = L^-1 A, row by row
-  for (int k = 0; k < d; ++k) {
-    const double lkk = L[(size_t)k * d + k];
-    for (int j = tid; j < d; j += NT) {
-      const double x = A[(size_t)k * d + j] / lkk;
-      A[(size_t)k * d + j] = x;
-      sh.v1[j] = x;
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    const int kb = min(CB, n - k0);
+    // diagonal block: rows k0 .. k0+kb-1, in order
+    for (int kk = k0; kk < k0 + kb; ++kk) {
+      const double lkk = Lm[(size_t)kk * n + kk];
+      for (int j = tid; j < n; j += NT) {
+        double v = X[(size_t)kk * n + j];
+        for (int m = k0; m < kk; ++m) v -= Lm[(size_t)kk * n + m] * X[(size_t)m * n + j];
+        X[(size_t)kk * n + j] = v / lkk;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int i = k + 1 + wv; i < d; i += NW) {
-      const double lik = L[(size_t)i * d + k];
-      double* Ai = A + (size_t)i * d;
-      for (int j = lane; j < d; j += 64) Ai[j] -= lik * sh.v1[j];
+    // trailing rows, by column chunks staged in LDS
+    for (int c0 = 0; c0 < n; c0 += CCH) {
+      const int cw = min(CCH, n - c0);
+      for (int t = tid; t < kb * CCH; t += NT) {
+        const int m = t / CCH, j = t % CCH;
+        sh.stage[m][j] = (j < cw) ? X[(size_t)(k0 + m) * n + c0 + j] : 0.0;
+      }
+      __syncthreads();
+      for (int i = k0 + kb + wv; i < n; i += NW) {
+        double l[CB];
+#pragma unroll
+        for (int m = 0; m < CB; ++m) l[m] = (m < kb) ? Lm[(size_t)i * n + k0 + m] : 0.0;
+        double* Xi = X + (size_t)i * n + c0;
+        for (int j = lane; j < cw; j += 64) {
+          double acc = Xi[j];
+#pragma unroll
+          for (int m = 0; m < CB; ++m) acc -= l[m] * sh.stage[m][j];
+          Xi[j] = acc;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // A = X L^-T, column by column: solves Z L^T = X
-  for (int k = 0; k < d; ++k) {
-    const double lkk = L[(size_t)k * d + k];
-    for (int i = tid; i < d; i += NT) {
-      const double x = A[(size_t)i * d + k] / lkk;
-      A[(size_t)i * d + k] = x;
-      sh.v1[i] = x;
-    }
-    for (int j = k + 1 + tid; j < d; j += NT) sh.v2[j] = L[(size_t)j * d + k];
-    __syncthreads();
-    for (int i = wv; i < d; i += NW) {
-      const double xi = sh.v1[i];
-      double* Ai = A + (size_t)i * d;
-      for (int j = k + 1 + lane; j < d; j += 64) Ai[j] -= xi * sh.v2[j];
-    }
-    __syncthreads();
+}
+
+// B <- A^T for n x n row-major matrices (distinct buffers).
+__device__ void transpose(const double* A, double* B, int n) {
+  const int tid = threadIdx.x;
+  for (size_t t = tid; t < (size_t)n * n; t += NT) {
+    const int i = (int)(t / n), j = (int)(t % n);
+    B[(size_t)j * n + i] = A[t];
   }
+  __syncthreads();
+}
+
+// A <- L^-1 A L^-T, using W (n x n) as scratch: X = L^-1 A, then
+// A^T = L^-1 X^T.
+__device__ void congruence(Shared& sh, const double* L, double* A, double* W, int d) {
+  lower_solve_rows(sh, L, A, d);
+  transpose(A, W, d);
+  lower_solve_rows(sh, L, W, d);
+  transpose(W, A, d);
 }
 
 // ---------------------------------------------------------------- step 3 --
 // Householder reduction to upper Hessenberg form.  Reflector k acts on
 // indices k+1..d-1 with vector v (v[k+1] = 1) stored in row k of V and
 // scalar tau[k]: P_k = I - tau v v^T.  A = Q Hs Q^T with Q = P_0 P_1 ... .
-__device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, int d) {
+//
+// Both sides of a step in two passes over the trailing columns:
+// P A P = A - tau (p v^T + v q'^T) with p = A v, q = A^T v,
+// beta = v^T A v and q' = q - tau beta v (rows above k+1 only get p v^T).
+// Pass 1: one wave per row reads the row once for p_i and its share of q;
+// the waves' q partials are summed in a fixed order (Qs scratch, 16 x d).
+__device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, double* Qs, int d) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int QCH = 8;                      // q accumulators per lane (512 columns)
   for (int k = 0; k + 2 < d; ++k) {
     double part = 0.0;
     for (int i = k + 2 + tid; i < d; i += NT) {
@@ -175,32 +211,63 @@ __device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, int d)
       continue;
     }
     const double nrm = sqrt(alpha * alpha + sigma);
-    const double beta = alpha <= 0.0 ? nrm : -nrm;
-    const double v0 = alpha - beta;
-    const double tk = (beta - alpha) / beta;
-    for (int i = k + 1 + tid; i < d; i += NT) {
-      const double vi = (i == k + 1) ? 1.0 : A[(size_t)i * d + k] / v0;
+    const double beta_h = alpha <= 0.0 ? nrm : -nrm;
+    const double v0 = alpha - beta_h;
+    const double tk = (beta_h - alpha) / beta_h;
+    for (int i = tid; i < d; i += NT) {
+      const double vi = (i <= k) ? 0.0 : (i == k + 1) ? 1.0 : A[(size_t)i * d + k] / v0;
       sh.v1[i] = vi;
-      V[(size_t)k * d + i] = vi;
+      if (i > k) V[(size_t)k * d + i] = vi;
+      sh.v2[i] = 0.0;   // p
     }
     if (tid == 0) tau[k] = tk;
     __syncthreads();
-    // left: rows k+1.., columns k+1..d-1 (column k becomes beta e_1)
-    for (int j = k + 1 + tid; j < d; j += NT) {
-      double s = 0.0;
-      for (int i = k + 1; i < d; ++i) s += sh.v1[i] * A[(size_t)i * d + j];
-      s *= tk;
-      for (int i = k + 1; i < d; ++i) A[(size_t)i * d + j] -= s * sh.v1[i];
+    // pass 1: p = A v (all rows), partial q = A^T v (rows > k) per wave
+    const int j0 = k + 1, nj = d - j0;
+    for (int c0 = 0; c0 < nj; c0 += 64 * QCH) {
+      double qacc[QCH];
+#pragma unroll
+      for (int m = 0; m < QCH; ++m) qacc[m] = 0.0;
+      for (int i = wv; i < d; i += NW) {
+        const double* Ai = A + (size_t)i * d + j0 + c0;
+        const double vi = sh.v1[i];
+        double pp = 0.0;
+#pragma unroll
+        for (int m = 0; m < QCH; ++m) {
+          const int j = lane + 64 * m;
+          if (c0 + j < nj) {
+            const double a = Ai[j];
+            pp += a * sh.v1[j0 + c0 + j];
+            qacc[m] += vi * a;
+          }
+        }
+        pp = wave_sum(pp);
+        if (lane == 0) sh.v2[i] += pp;
+      }
+#pragma unroll
+      for (int m = 0; m < QCH; ++m) {
+        const int j = lane + 64 * m;
+        if (c0 + j < nj) Qs[(size_t)wv * d + j0 + c0 + j] = qacc[m];
+      }
     }
-    for (int i = k + 1 + tid; i < d; i += NT) A[(size_t)i * d + k] = (i == k + 1) ? beta : 0.0;
     __syncthreads();
-    // right: all rows, columns k+1..d-1
+    // q' = q - tau beta v, beta = v^T p
+    double bp = 0.0;
+    for (int i = k + 1 + tid; i < d; i += NT) bp += sh.v1[i] * sh.v2[i];
+    const double beta = block_sum(sh, bp);
+    for (int j = j0 + tid; j < d; j += NT) {
+      double q = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) q += Qs[(size_t)w * d + j];
+      sh.v3[j] = q - tk * beta * sh.v1[j];
+    }
+    __syncthreads();
+    // pass 2: update the trailing columns; column k becomes beta_h e_(k+1)
     for (int i = wv; i < d; i += NW) {
       double* Ai = A + (size_t)i * d;
-      double t = 0.0;
-      for (int j = k + 1 + lane; j < d; j += 64) t += Ai[j] * sh.v1[j];
-      t = wave_sum(t) * tk;
-      for (int j = k + 1 + lane; j < d; j += 64) Ai[j] -= t * sh.v1[j];
+      const double pi = tk * sh.v2[i], vi = tk * sh.v1[i];
+      for (int j = j0 + lane; j < d; j += 64) Ai[j] -= pi * sh.v1[j] + vi * sh.v3[j];
+      if (i > k && lane == 0) Ai[k] = (i == k + 1) ? beta_h : 0.0;
     }
     __syncthreads();
   }
@@ -703,9 +770,9 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
     return;
   }
   phase_mark(J, clk, 0);
-  congruence(sh, J.S, J.A, d);
+  congruence(sh, J.S, J.A, J.W, d);
   phase_mark(J, clk, 1);
-  hessenberg(sh, J.A, J.V, J.tau, d);
+  hessenberg(sh, J.A, J.V, J.tau, J.W, d);
   phase_mark(J, clk, 2);
   for (size_t i = tid; i < (size_t)d * d; i += NT) J.Hq[i] = J.A[i];
   __syncthreads();

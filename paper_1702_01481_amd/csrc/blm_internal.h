@@ -93,7 +93,7 @@ struct EigJob {
   double* A;            // [d][d] shifted Hamiltonian in, destroyed
   double* Hq;           // [d][d] Hessenberg copy
   double* V;            // [d][d] Householder vectors (row k: reflector k)
-  double* W;            // [2 d][d] complex LU workspace
+  double* W;            // max(2 d^2, 16 d): complex LU, congruence and Hessenberg scratch
   double* vec;          // [n_sel][2][d] complex eigenvectors
   double* wr;           // [d]
   double* wi;           // [d]
