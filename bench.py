@@ -141,7 +141,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed", default="bf16x3", choices=["bf16x3", "bf16x2", "none"],
                     help="also run the mixed-precision step on the same samples")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device-to-device copy three times (the reference "
+                         "for scaling HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 1 << 28                       # 2 GiB of float64
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 8 * n, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sample "
                                    "sharding is a design only (see DESIGN.md)", "n_gpus": args.gpus}))

@@ -37,8 +37,8 @@ __device__ __forceinline__ f4 mfma_bf16(const bf16x8& a, const bf16x8& b, f4 c) 
 // it differs from the FP64 16x16x4 instruction's layout).
 __device__ __forceinline__ int bf16_d_row(int lane, int r) { return 4 * (lane >> 4) + r; }
 
-__device__ __forceinline__ bf16x8 load_frag(const uint16_t* p, bool v) {
-  if (v) return *reinterpret_cast<const bf16x8*>(p);
+__device__ __forceinline__ bf16x8 load_frag(const BLM_GLOBAL uint16_t* p, bool v) {
+  if (v) return *reinterpret_cast<const BLM_GLOBAL bf16x8*>(p);
   bf16x8 z;
 #pragma unroll
   for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
@@ -89,8 +89,8 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_bf16_kernel(const GramJob* _
       }
   for (int si = p; si < n_slices; si += P) {
     const Slice S = slices[si];
-    const uint16_t* O = (const uint16_t*)S.O;
-    const uint16_t* E = (const uint16_t*)S.e;
+    const BLM_GLOBAL uint16_t* O = as_global((const uint16_t*)S.O);
+    const BLM_GLOBAL uint16_t* E = as_global((const uint16_t*)S.e);
     const int64_t n8 = (S.n + 7) >> 3;
     for (int64_t g0 = 0; g0 < n8; g0 += 4) {
       const int64_t gg = g0 + g4;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_bf16_kernel(const GramJob* _
     }
   }
 
-  double* base = partial + ((size_t)jid * P + p) * (size_t)(3 * GT * GT);
+  BLM_GLOBAL double* base = as_global(partial) + ((size_t)jid * P + p) * (size_t)(3 * GT * GT);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll

@@ -85,7 +85,7 @@ __device__ double block_max(Shared& sh, double v) {
 }
 
 // ---------------------------------------------------------------- step 1 --
-__device__ int cholesky(Shared& sh, double* S, int d) {
+__device__ int cholesky(Shared& sh, gdouble* S, int d) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int k = 0; k < d; ++k) {
     if (tid == 0) {
@@ -109,7 +109,7 @@ __device__ int cholesky(Shared& sh, double* S, int d) {
     __syncthreads();
     for (int i = k + 1 + wv; i < d; i += NW) {
       const double li = sh.v1[i];
-      double* Si = S + (size_t)i * d;
+      gdouble* Si = S + (size_t)i * d;
       for (int j = k + 1 + lane; j <= i; j += 64) Si[j] -= li * sh.v1[j];
     }
     __syncthreads();
@@ -125,7 +125,7 @@ __device__ int cholesky(Shared& sh, double* S, int d) {
 constexpr int CB = 16;       // rows per block
 constexpr int CCH = 256;     // columns per LDS chunk
 
-__device__ void lower_solve_rows(Shared& sh, const double* Lm, double* X, int n) {
+__device__ void lower_solve_rows(Shared& sh, const gdouble* Lm, gdouble* X, int n) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int k0 = 0; k0 < n; k0 += CB) {
     const int kb = min(CB, n - k0);
@@ -151,7 +151,7 @@ __device__ void lower_solve_rows(Shared& sh, const double* Lm, double* X, int n)
         double l[CB];
 #pragma unroll
         for (int m = 0; m < CB; ++m) l[m] = (m < kb) ? Lm[(size_t)i * n + k0 + m] : 0.0;
-        double* Xi = X + (size_t)i * n + c0;
+        gdouble* Xi = X + (size_t)i * n + c0;
         for (int j = lane; j < cw; j += 64) {
           double acc = Xi[j];
 #pragma unroll
@@ -165,7 +165,7 @@ __device__ void lower_solve_rows(Shared& sh, const double* Lm, double* X, int n)
 }
 
 // B <- A^T for n x n row-major matrices (distinct buffers).
-__device__ void transpose(const double* A, double* B, int n) {
+__device__ void transpose(const gdouble* A, gdouble* B, int n) {
   const int tid = threadIdx.x;
   for (size_t t = tid; t < (size_t)n * n; t += NT) {
     const int i = (int)(t / n), j = (int)(t % n);
@@ -176,7 +176,7 @@ __device__ void transpose(const double* A, double* B, int n) {
 
 // A <- L^-1 A L^-T, using W (n x n) as scratch: X = L^-1 A, then
 // A^T = L^-1 X^T.
-__device__ void congruence(Shared& sh, const double* L, double* A, double* W, int d) {
+__device__ void congruence(Shared& sh, const gdouble* L, gdouble* A, gdouble* W, int d) {
   lower_solve_rows(sh, L, A, d);
   transpose(A, W, d);
   lower_solve_rows(sh, L, W, d);
@@ -193,7 +193,7 @@ __device__ void congruence(Shared& sh, const double* L, double* A, double* W, in
 // beta = v^T A v and q' = q - tau beta v (rows above k+1 only get p v^T).
 // Pass 1: one wave per row reads the row once for p_i and its share of q;
 // the waves' q partials are summed in a fixed order (Qs scratch, 16 x d).
-__device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, double* Qs, int d) {
+__device__ void hessenberg(Shared& sh, gdouble* A, gdouble* V, gdouble* tau, gdouble* Qs, int d) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int QCH = 8;                      // q accumulators per lane (512 columns)
   for (int k = 0; k + 2 < d; ++k) {
@@ -229,7 +229,7 @@ __device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, double
 #pragma unroll
       for (int m = 0; m < QCH; ++m) qacc[m] = 0.0;
       for (int i = wv; i < d; i += NW) {
-        const double* Ai = A + (size_t)i * d + j0 + c0;
+        const gdouble* Ai = A + (size_t)i * d + j0 + c0;
         const double vi = sh.v1[i];
         double pp = 0.0;
 #pragma unroll
@@ -264,7 +264,7 @@ __device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, double
     __syncthreads();
     // pass 2: update the trailing columns; column k becomes beta_h e_(k+1)
     for (int i = wv; i < d; i += NW) {
-      double* Ai = A + (size_t)i * d;
+      gdouble* Ai = A + (size_t)i * d;
       const double pi = tk * sh.v2[i], vi = tk * sh.v1[i];
       for (int j = j0 + lane; j < d; j += 64) Ai[j] -= pi * sh.v1[j] + vi * sh.v3[j];
       if (i > k && lane == 0) Ai[k] = (i == k + 1) ? beta_h : 0.0;
@@ -290,8 +290,8 @@ __device__ void hessenberg(Shared& sh, double* A, double* V, double* tau, double
 // eps (|a_{i-1,i-1}| + |a_ii|) is set to zero.
 constexpr int MAX_BULGES = 16;
 
-template <bool MULTI>
-__device__ int hqr(Shared& sh, double* A, int ld, int d, double* wr, double* wi, int* iters) {
+template <bool MULTI, class Real>
+__device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* iters) {
   const int tid = threadIdx.x;
   auto at = [&](int i, int j) -> double& { return A[(size_t)i * ld + j]; };
   double part = 0.0;
@@ -453,8 +453,8 @@ __device__ int hqr(Shared& sh, double* A, int ld, int d, double* wr, double* wi,
         // rows K+1..K+nr, columns max(l, K+1)..h; the bulge column K is set directly
         const int c0 = (K >= l) ? K + 1 : l;
         for (int c = c0 + lt; c <= h; c += G) {
-          double* p1 = A + (size_t)(K + 1) * ld + c;
-          double* p2 = p1 + ld;
+          Real* p1 = A + (size_t)(K + 1) * ld + c;
+          Real* p2 = p1 + ld;
           double tt = v0 * p1[0] + v1 * p2[0];
           if (nr == 3) tt += v2 * p2[ld];
           tt *= bt;
@@ -474,7 +474,7 @@ __device__ int hqr(Shared& sh, double* A, int ld, int d, double* wr, double* wi,
         // below the diagonal (the next bulge) for the next tick
         const int r1 = (K + 4 < h) ? K + 4 : h;
         for (int rr = l + lt; rr <= r1; rr += G) {
-          double* q = A + (size_t)rr * ld + K + 1;
+          Real* q = A + (size_t)rr * ld + K + 1;
           if (refl) {
             double tt = q[0] * v0 + q[1] * v1;
             if (nr == 3) tt += q[2] * v2;
@@ -501,8 +501,8 @@ __device__ int hqr(Shared& sh, double* A, int ld, int d, double* wr, double* wi,
 // Picks eigenvalues in rank order until `want` directions are held (a pair
 // gives two).  Returns the number of picked eigenvalue entries in sh.sel_*
 // (a pair is one entry with positive imaginary part).
-__device__ int select_lowest(Shared& sh, const double* wr, const double* wi, int d, int want,
-                             double* out_evals, int max_entries) {
+__device__ int select_lowest(Shared& sh, const gdouble* wr, const gdouble* wi, int d, int want,
+                             gdouble* out_evals, int max_entries) {
   const int tid = threadIdx.x;
   for (int i = tid; i < d; i += NT) sh.mark[i] = 0;
   if (tid == 0) sh.sel_n = 0;
@@ -593,8 +593,8 @@ __device__ int select_lowest(Shared& sh, const double* wr, const double* wi, int
 // Inverse iteration on the Hessenberg matrix Hq for eigenvalue (sr, si):
 // LU of Hq - sigma I with adjacent-row pivoting, tiny pivots replaced by
 // eps3, three solves from a vector of ones.  Result (complex) in yr, yi.
-__device__ void inverse_iteration(Shared& sh, const double* Hq, double* Wr, double* Wi, int d,
-                                  double sr, double si, double eps3, double* yr, double* yi) {
+__device__ void inverse_iteration(Shared& sh, const gdouble* Hq, gdouble* Wr, gdouble* Wi, int d,
+                                  double sr, double si, double eps3, gdouble* yr, gdouble* yi) {
   const int tid = threadIdx.x;
   for (size_t t = tid; t < (size_t)d * d; t += NT) {
     const int i = (int)(t / d), j = (int)(t % d);
@@ -720,13 +720,13 @@ __device__ void inverse_iteration(Shared& sh, const double* Hq, double* Wr, doub
 
 // ---------------------------------------------------------------- step 6b --
 // One wave per real vector z (length d, global): z <- L^-T Q z.
-__device__ void back_transform_wave(const double* V, const double* tau, const double* L, double* z,
+__device__ void back_transform_wave(const gdouble* V, const gdouble* tau, const gdouble* L, gdouble* z,
                                     int d) {
   const int lane = threadIdx.x & 63;
   for (int k = d - 3; k >= 0; --k) {
     const double tk = tau[k];
     if (tk == 0.0) continue;
-    const double* v = V + (size_t)k * d;
+    const gdouble* v = V + (size_t)k * d;
     double s = 0.0;
     for (int i = k + 1 + lane; i < d; i += 64) s += v[i] * z[i];
     s = wave_sum(s) * tk;
@@ -740,13 +740,43 @@ __device__ void back_transform_wave(const double* V, const double* tau, const do
       z[k] = ck;
     }
     ck = __shfl(ck, k & 63, 64);
-    const double* Lk = L + (size_t)k * d;
+    const gdouble* Lk = L + (size_t)k * d;
     for (int i = lane; i < k; i += 64) z[i] -= Lk[i] * ck;
   }
 }
 
+// An eigen-job with its buffers typed as global memory, so that every access
+// is a global (not flat) memory instruction and LDS waits never wait for them.
+struct GJob {
+  int32_t d, mode, n_want, beta0, nbeta;
+  gdouble *S, *A, *Hq, *V, *W, *vec, *wr, *wi, *tau, *out, *out_evals;
+  BLM_GLOBAL int32_t* info;
+};
+
+__device__ __forceinline__ GJob global_view(const EigJob& E) {
+  GJob J;
+  J.d = E.d;
+  J.mode = E.mode;
+  J.n_want = E.n_want;
+  J.beta0 = E.beta0;
+  J.nbeta = E.nbeta;
+  J.S = as_global(E.S);
+  J.A = as_global(E.A);
+  J.Hq = as_global(E.Hq);
+  J.V = as_global(E.V);
+  J.W = as_global(E.W);
+  J.vec = as_global(E.vec);
+  J.wr = as_global(E.wr);
+  J.wi = as_global(E.wi);
+  J.tau = as_global(E.tau);
+  J.out = as_global(E.out);
+  J.out_evals = as_global(E.out_evals);
+  J.info = as_global(E.info);
+  return J;
+}
+
 // Phase clock (100 MHz constant counter): info[4 + i] = ticks spent in phase i.
-__device__ __forceinline__ void phase_mark(const EigJob& J, uint64_t& t, int i) {
+__device__ __forceinline__ void phase_mark(const GJob& J, uint64_t& t, int i) {
   const uint64_t now = wall_clock64();
   if (threadIdx.x == 0) J.info[4 + i] = (int32_t)(now - t);
   t = now;
@@ -754,7 +784,7 @@ __device__ __forceinline__ void phase_mark(const EigJob& J, uint64_t& t, int i) 
 
 __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs) {
   __shared__ Shared sh;
-  const EigJob J = jobs[blockIdx.x];
+  const GJob J = global_view(jobs[blockIdx.x]);
   const int d = J.d, tid = threadIdx.x, wv = tid >> 6;
   uint64_t clk = wall_clock64();
   if (tid == 0) {
@@ -800,8 +830,8 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
   // eigenvectors of the chosen eigenvalues, complex, into vec[s][0|1][d]
   phase_mark(J, clk, 4);
   for (int s = 0; s < n_sel; ++s) {
-    double* yr = J.vec + (size_t)(2 * s) * d;
-    double* yi = yr + d;
+    gdouble* yr = J.vec + (size_t)(2 * s) * d;
+    gdouble* yi = yr + d;
     inverse_iteration(sh, J.Hq, J.W, J.W + (size_t)d * d, d, sh.sel_r[s], sh.sel_i[s], eps3, yr, yi);
   }
   phase_mark(J, clk, 5);
@@ -834,8 +864,8 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
     const int parts = (sh.sel_i[s] != 0.0) ? 2 : 1;
     if (parts == 2) pair = 1;
     for (int pc = 0; pc < parts; ++pc) {
-      const double* src = J.vec + (size_t)(2 * s + pc) * d + J.beta0;
-      double* dst = J.out + (size_t)kept * nb;
+      const gdouble* src = J.vec + (size_t)(2 * s + pc) * d + J.beta0;
+      gdouble* dst = J.out + (size_t)kept * nb;
       double part0 = 0.0;
       for (int i = tid; i < nb; i += NT) {
         const double x = src[i];
@@ -844,7 +874,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
       }
       const double n0 = sqrt(block_sum(sh, part0));
       for (int q = 0; q < kept; ++q) {
-        const double* qv = J.out + (size_t)q * nb;
+        const gdouble* qv = J.out + (size_t)q * nb;
         double pd = 0.0;
         for (int i = tid; i < nb; i += NT) pd += qv[i] * dst[i];
         const double dot = block_sum(sh, pd);

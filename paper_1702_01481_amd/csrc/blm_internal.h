@@ -7,6 +7,21 @@
 
 namespace blm {
 
+// Global-address-space view of a pointer read from a job or slice table.
+// Loads through generic (flat) pointers count against the LDS wait counter
+// too, so waiting for LDS would also wait for in-flight global prefetches.
+// (Device pass only: the host pass of a .hip file sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BLM_GLOBAL __attribute__((address_space(1)))
+#else
+#define BLM_GLOBAL
+#endif
+template <class T>
+__device__ __forceinline__ BLM_GLOBAL T* as_global(T* p) {
+  return (BLM_GLOBAL T*)p;
+}
+typedef BLM_GLOBAL double gdouble;
+
 // ---------------------------------------------------------------- Gram ----
 // Weighted Gram tiles  C = X^T diag(w) Y  over sample slices, FP64 MFMA.
 constexpr int GT = 64;        // output tile edge

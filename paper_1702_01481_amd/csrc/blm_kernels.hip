@@ -31,7 +31,7 @@ __device__ __forceinline__ double bf16_to_f64(uint16_t h) {
 // of its pieces.
 __device__ __forceinline__ double split_load(const void* base, int64_t ld, int64_t pstride,
                                              int pieces, int64_t row, int64_t col) {
-  const uint16_t* b = (const uint16_t*)base;
+  const BLM_GLOBAL uint16_t* b = as_global((const uint16_t*)base);
   const int64_t i = ((row >> 3) * ld + col) * 8 + (row & 7);
   double v = bf16_to_f64(b[i]);
   if (pieces > 1) v += bf16_to_f64(b[i + pstride]);
@@ -43,11 +43,11 @@ __device__ __forceinline__ double split_load(const void* base, int64_t ld, int64
 // each as the exact FP64 sum of its pieces: one 16-byte load per piece.
 __device__ __forceinline__ void split_load8(const void* base, int64_t ld, int64_t pstride,
                                             int pieces, int64_t group, int64_t col, double* v) {
-  const uint16_t* b = (const uint16_t*)base + (group * ld + col) * 8;
+  const BLM_GLOBAL uint16_t* b = as_global((const uint16_t*)base) + (group * ld + col) * 8;
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = 0.0;
   for (int pc = 0; pc < pieces; ++pc) {
-    const uint4 w = *reinterpret_cast<const uint4*>(b + (size_t)pc * pstride);
+    const uint4 w = *reinterpret_cast<const BLM_GLOBAL uint4*>(b + (size_t)pc * pstride);
     const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -61,113 +61,151 @@ __device__ __forceinline__ void split_load8(const void* base, int64_t ld, int64_
 // Gram tiles
 // ---------------------------------------------------------------------------
 
+// One sample row of a stage as held in registers between its global loads
+// and its LDS store.  Values are raw; the sample weight is applied (and
+// columns outside the tile are zeroed) when the stage is stored, so that no
+// instruction uses a loaded value before the next stage's products.
 struct StageRegs {
   double a[4], e[4], b[4], f[4];
   double x, y;
+  double w;             // sample weight (of the clamped row)
+  bool valid;           // the row is inside the slice
 };
 
-// Loads a pair of adjacent doubles of one panel row: 16 bytes when both are
-// in the tile (VEC: the caller has checked 16-byte alignment), else guarded
-// 8-byte loads.
-template <bool VEC>
-__device__ __forceinline__ void load_pair(const double* p, int col, int lim, double& x, double& y) {
-  if (VEC && col + 1 < lim) {
-    const double2 v = *reinterpret_cast<const double2*>(p + col);
-    x = v.x;
-    y = v.y;
-  } else {
-    x = col < lim ? p[col] : 0.0;
-    y = col + 1 < lim ? p[col + 1] : 0.0;
+// Load cursor: the slice whose stages are being loaded and its descriptor,
+// kept in registers (re-read only when the cursor moves to another slice).
+struct Cursor {
+  Slice S;
+  int si;
+  int64_t ro;
+};
+
+__device__ __forceinline__ void cursor_skip_empty(Cursor& c, const Slice* __restrict__ slices,
+                                                  int n_slices, int P) {
+  while (c.si < n_slices) {
+    c.S = slices[c.si];
+    if (c.S.n > 0) return;
+    c.si += P;
   }
 }
 
-template <bool VEC, bool SPLIT>
+__device__ __forceinline__ void cursor_next(Cursor& c, const Slice* __restrict__ slices,
+                                            int n_slices, int P) {
+  c.ro += GKS;
+  if (c.ro >= c.S.n) {
+    c.ro = 0;
+    c.si += P;
+    cursor_skip_empty(c, slices, n_slices, P);
+  }
+}
+
+__device__ __forceinline__ void ld2(const BLM_GLOBAL double* p, double& x, double& y) {
+  const double2 v = *reinterpret_cast<const BLM_GLOBAL double2*>(p);
+  x = v.x;
+  y = v.y;
+}
+
+// Global loads of one 16-sample stage.  Every load is unconditional: rows
+// past the end of the slice read the slice's last row (and get weight 0),
+// columns past a ragged tile edge read the tile's last column (and are
+// zeroed at the store).  FULL: the tile is 64 x 64 and 16-byte aligned.
+template <int KIND, bool FULL, bool SPLIT>
 __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int64_t ro, int tid,
                                           StageRegs& R) {
   const int lr = tid >> 4;            // sample row within the stage (0..15)
   const int lc = (tid & 15) * 4;      // first of 4 tile columns
   const int64_t row = ro + lr;
   const bool valid = row < S.n;
-  const bool aux = (J.kind == JOB_AUX);
-  const double wgt = (valid && S.w) ? S.w[row] : 1.0;
-  const int mi = valid ? J.mi : 0, nj = valid ? J.nj : 0;
-  if (SPLIT && !aux) {
-    // strip jobs on split storage (uniform weights): thread -> (panel, 8-sample
-    // group, column); 8 samples of one column of O (panel 0) or e (panel 1)
-    // land in a[0..3], e[0..3]
-    const int pnl = tid >> 7, g = (tid >> 6) & 1, c = tid & 63;
-    double v[8];
-    const int64_t r0 = ro + 8 * g;
-    if (r0 < S.n && c < J.nj) {
-      split_load8(pnl ? S.e : S.O, S.ld, S.pstride, S.pieces, r0 >> 3, J.cj + c, v);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      R.a[k] = v[k];
-      R.e[k] = v[4 + k];
-    }
-  } else {
-    const double* pO = aux ? S.Xa : (const double*)S.O;
-    const double* pe = aux ? S.Ya : (const double*)S.e;
-    const int64_t ld = aux ? (int64_t)NAUX : S.ld;
-    const double* rO = pO + row * ld;
-    const double* re = pe + row * ld;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int col = lc + 2 * h;
-      if (J.kind != JOB_STRIP) load_pair<VEC>(rO + J.ci, col, mi, R.a[2 * h], R.a[2 * h + 1]);
-      else R.a[2 * h] = R.a[2 * h + 1] = 0.0;
-      if (J.kind == JOB_OFF) load_pair<VEC>(re + J.ci, col, mi, R.e[2 * h], R.e[2 * h + 1]);
-      else R.e[2 * h] = R.e[2 * h + 1] = 0.0;
-      load_pair<VEC>(rO + J.cj, col, nj, R.b[2 * h], R.b[2 * h + 1]);
-      load_pair<VEC>(re + J.cj, col, nj, R.f[2 * h], R.f[2 * h + 1]);
-    }
+  const int64_t rc = valid ? row : S.n - 1;
+  R.w = S.w ? as_global(S.w)[rc] : 1.0;
+  R.valid = valid;
+  if constexpr (KIND == JOB_AUX) {
+    const BLM_GLOBAL double* xa = as_global(S.Xa) + rc * NAUX;
+    const BLM_GLOBAL double* ya = as_global(S.Ya) + rc * NAUX;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      R.a[c] *= wgt;
-      R.e[c] *= wgt;
+      const int cc = min(lc + c, NAUX - 1);
+      R.a[c] = xa[cc];
+      R.b[c] = R.a[c];
+      R.f[c] = ya[cc];
+      R.e[c] = 0.0;
+    }
+  } else if constexpr (SPLIT) {
+    // strip jobs on split storage (uniform weights): thread -> (panel,
+    // 8-sample group, column); 8 samples of one column of O (panel 0) or e
+    // (panel 1) land in a[0..3], e[0..3]
+    const int pnl = tid >> 7, g = (tid >> 6) & 1, c = tid & 63;
+    const int64_t r0 = ro + 8 * g;
+    const bool ok = r0 < S.n && c < J.nj;
+    const int64_t grp = (r0 < S.n ? r0 : S.n - 1) >> 3;
+    double v[8];
+    split_load8(pnl ? S.e : S.O, S.ld, S.pstride, S.pieces, grp, J.cj + min(c, J.nj - 1), v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      R.a[k] = ok ? v[k] : 0.0;
+      R.e[k] = ok ? v[4 + k] : 0.0;
+    }
+  } else {
+    const BLM_GLOBAL double* rO = as_global((const double*)S.O) + rc * S.ld;
+    const BLM_GLOBAL double* re = as_global((const double*)S.e) + rc * S.ld;
+    constexpr bool LOAD_A = KIND != JOB_STRIP;
+    constexpr bool LOAD_E = KIND == JOB_OFF;
+    // diagonal tiles: the column panel is the row panel
+    constexpr bool LOAD_B = KIND == JOB_OFF || KIND == JOB_STRIP;
+    if constexpr (FULL) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int col = lc + 2 * h;
+        if (LOAD_A) ld2(rO + J.ci + col, R.a[2 * h], R.a[2 * h + 1]);
+        if (LOAD_E) ld2(re + J.ci + col, R.e[2 * h], R.e[2 * h + 1]);
+        if (LOAD_B) ld2(rO + J.cj + col, R.b[2 * h], R.b[2 * h + 1]);
+        ld2(re + J.cj + col, R.f[2 * h], R.f[2 * h + 1]);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int ca = min(lc + c, J.mi - 1), cb = min(lc + c, J.nj - 1);
+        if (LOAD_A) R.a[c] = rO[J.ci + ca];
+        if (LOAD_E) R.e[c] = re[J.ci + ca];
+        if (LOAD_B) R.b[c] = rO[J.cj + cb];
+        R.f[c] = re[J.cj + cb];
+      }
     }
   }
-  if (J.kind == JOB_DIAG || J.kind == JOB_STRIP) {
+  if constexpr (KIND == JOB_DIAG || KIND == JOB_STRIP) {
     const int acol = tid & 15;
-    R.x = valid ? S.Xa[row * NAUX + acol] * wgt : 0.0;
-    R.y = valid ? S.Ya[row * NAUX + acol] * wgt : 0.0;
-  } else {
-    R.x = 0.0;
-    R.y = 0.0;
+    R.x = as_global(S.Xa)[rc * NAUX + acol];
+    R.y = as_global(S.Ya)[rc * NAUX + acol];
   }
 }
 
-template <bool VEC, bool SPLIT>
-__global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __restrict__ jobs,
-                                                           int n_jobs,
-                                                           const Slice* __restrict__ slices,
-                                                           int n_slices, int P,
-                                                           double* __restrict__ partial) {
-  __shared__ double sA[2][GKS][GT];   // O_i * w
-  __shared__ double sE[2][GKS][GT];   // e_i * w
-  __shared__ double sB[2][GKS][GT];   // O_j
-  __shared__ double sF[2][GKS][GT];   // e_j
-  __shared__ double sX[2][GKS][NAUX]; // aux (1, Theta) * w
-  __shared__ double sY[2][GKS][NAUX]; // aux (E_L, Theta energy) * w
+// Double-buffered LDS panels of one workgroup (declared once per kernel: the
+// per-kind bodies share it).
+struct GramLds {
+  double A[2][GKS][GT];   // O_i * w
+  double E[2][GKS][GT];   // e_i * w
+  double B[2][GKS][GT];   // O_j
+  double F[2][GKS][GT];   // e_j
+  double X[2][GKS][NAUX]; // aux (1, Theta) * w
+  double Y[2][GKS][NAUX]; // aux (E_L, Theta energy) * w
+};
 
-  // XCD-aware order: the hardware deals workgroups round-robin over the 8
-  // XCDs; give each XCD a contiguous range of work items so that the tiles of
-  // one block and one slice set (which share their sample panels) run on the
-  // same L2.
-  const int G = gridDim.x, g = blockIdx.x;
-  const int q = G >> 3, r = G & 7, xcd = g & 7, idx = g >> 3;
-  const int wid = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-  const int p = wid / n_jobs, jid = wid % n_jobs;
-  const GramJob J = jobs[jid];
-  const int kind = J.kind;
+template <int KIND, bool FULL, bool SPLIT>
+__device__ __forceinline__ void gram_body(GramLds& L, const GramJob& J,
+                                          const Slice* __restrict__ slices, int n_slices, int P,
+                                          int p, double* __restrict__ out) {
+  auto& sA = L.A;
+  auto& sE = L.E;
+  auto& sB = L.B;
+  auto& sF = L.F;
+  auto& sX = L.X;
+  auto& sY = L.Y;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = wv >> 1, wc = wv & 1;
   const int i16 = lane & 15, k4 = lane >> 4;
+  constexpr bool STRIPS = KIND == JOB_DIAG || KIND == JOB_STRIP;
+  constexpr bool MAIN = KIND != JOB_STRIP;
 
   d4 P0[2][2], P1[2][2], P2[2][2];
 #pragma unroll
@@ -179,15 +217,10 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
       P2[x][y] = d4{0, 0, 0, 0};
     }
 
-  int si = p;
-  while (si < n_slices && slices[si].n <= 0) si += P;
-  int64_t ro = 0;
-  StageRegs R;
-  int buf = 0;
-  // register stage -> LDS buffer nb
-  auto store = [&](int nb) {
+  // register stage -> LDS buffer nb (weights applied, ragged columns zeroed)
+  auto store = [&](const StageRegs& R, int nb) {
     const int lr = tid >> 4, lc = (tid & 15) * 4;
-    if (SPLIT && kind == JOB_STRIP) {
+    if constexpr (SPLIT && KIND == JOB_STRIP) {
       const int pnl = tid >> 7, g = (tid >> 6) & 1, c = tid & 63;
       double(*dst)[GT] = pnl ? sF[nb] : sB[nb];
 #pragma unroll
@@ -196,46 +229,39 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
         dst[8 * g + 4 + k][c] = R.e[k];
       }
     } else {
+      const double w = R.valid ? R.w : 0.0;
+      double a[4], e[4], b[4], f[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        sA[nb][lr][lc + c] = R.a[c];
-        sE[nb][lr][lc + c] = R.e[c];
-        sB[nb][lr][lc + c] = R.b[c];
-        sF[nb][lr][lc + c] = R.f[c];
+        const bool oka = FULL || lc + c < J.mi, okb = FULL || lc + c < J.nj;
+        a[c] = oka ? R.a[c] * w : 0.0;
+        e[c] = oka ? R.e[c] * w : 0.0;
+        if constexpr (KIND == JOB_DIAG || KIND == JOB_DIAG_NOSTRIP) b[c] = okb ? R.a[c] : 0.0;
+        else b[c] = okb ? R.b[c] : 0.0;
+        f[c] = okb ? R.f[c] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (MAIN) sA[nb][lr][lc + c] = a[c];
+        if (KIND == JOB_OFF) sE[nb][lr][lc + c] = e[c];
+        sB[nb][lr][lc + c] = b[c];
+        sF[nb][lr][lc + c] = f[c];
       }
     }
-    sX[nb][lr][tid & 15] = R.x;
-    sY[nb][lr][tid & 15] = R.y;
+    if constexpr (STRIPS) {
+      const double w = R.valid ? R.w : 0.0;
+      sX[nb][lr][tid & 15] = R.x * w;
+      sY[nb][lr][tid & 15] = R.y * w;
+    }
   };
-  if (si < n_slices) {
-    Slice S = slices[si];
-    gram_load<VEC, SPLIT>(J, S, ro, tid, R);
-    store(0);
-  }
-  __syncthreads();
-
-  while (si < n_slices) {
-    // next stage
-    int si2 = si;
-    int64_t ro2 = ro + GKS;
-    if (ro2 >= slices[si2].n) {
-      si2 += P;
-      ro2 = 0;
-      while (si2 < n_slices && slices[si2].n <= 0) si2 += P;
-    }
-    const bool has_next = si2 < n_slices;
-    if (has_next) {
-      Slice S2 = slices[si2];
-      gram_load<VEC, SPLIT>(J, S2, ro2, tid, R);
-    }
-
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < GKS; kk += 4) {
       const int kr = kk + k4;
-      const double a0 = sA[buf][kr][32 * wr + i16], a1 = sA[buf][kr][32 * wr + 16 + i16];
-      const double b0 = sB[buf][kr][32 * wc + i16], b1 = sB[buf][kr][32 * wc + 16 + i16];
-      const double f0 = sF[buf][kr][32 * wc + i16], f1 = sF[buf][kr][32 * wc + 16 + i16];
-      if (kind != JOB_STRIP) {
+      if constexpr (MAIN) {
+        const double a0 = sA[buf][kr][32 * wr + i16], a1 = sA[buf][kr][32 * wr + 16 + i16];
+        const double b0 = sB[buf][kr][32 * wc + i16], b1 = sB[buf][kr][32 * wc + 16 + i16];
+        const double f0 = sF[buf][kr][32 * wc + i16], f1 = sF[buf][kr][32 * wc + 16 + i16];
         P0[0][0] = mfma_f64(a0, b0, P0[0][0]);
         P0[0][1] = mfma_f64(a0, b1, P0[0][1]);
         P0[1][0] = mfma_f64(a1, b0, P0[1][0]);
@@ -244,14 +270,15 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
         P1[0][1] = mfma_f64(a0, f1, P1[0][1]);
         P1[1][0] = mfma_f64(a1, f0, P1[1][0]);
         P1[1][1] = mfma_f64(a1, f1, P1[1][1]);
+        if constexpr (KIND == JOB_OFF) {
+          const double e0 = sE[buf][kr][32 * wr + i16], e1 = sE[buf][kr][32 * wr + 16 + i16];
+          P2[0][0] = mfma_f64(e0, b0, P2[0][0]);
+          P2[0][1] = mfma_f64(e0, b1, P2[0][1]);
+          P2[1][0] = mfma_f64(e1, b0, P2[1][0]);
+          P2[1][1] = mfma_f64(e1, b1, P2[1][1]);
+        }
       }
-      if (kind == JOB_OFF) {
-        const double e0 = sE[buf][kr][32 * wr + i16], e1 = sE[buf][kr][32 * wr + 16 + i16];
-        P2[0][0] = mfma_f64(e0, b0, P2[0][0]);
-        P2[0][1] = mfma_f64(e0, b1, P2[0][1]);
-        P2[1][0] = mfma_f64(e1, b0, P2[1][0]);
-        P2[1][1] = mfma_f64(e1, b1, P2[1][1]);
-      } else if (kind == JOB_DIAG || kind == JOB_STRIP) {
+      if constexpr (STRIPS) {
         const double xs = sX[buf][kr][i16], ys = sY[buf][kr][i16];
         const double bs = sB[buf][kr][16 * wv + i16], fs = sF[buf][kr][16 * wv + i16];
         P2[0][0] = mfma_f64(xs, bs, P2[0][0]);   // aux^T W O_i
@@ -259,28 +286,52 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
         P2[1][0] = mfma_f64(ys, bs, P2[1][0]);   // auxE^T W O_i
       }
     }
+  };
 
-    if (has_next) store(buf ^ 1);
+  // Number of 16-sample stages of this workgroup's slices.
+  int n_stages = 0;
+  for (int si = p; si < n_slices; si += P) n_stages += (int)((slices[si].n + GKS - 1) / GKS);
+
+  // One stage is in flight in registers while another is in LDS: the global
+  // loads of stage t+1 are issued before stage t is computed.
+  Cursor cur;
+  cur.si = p;
+  cur.ro = 0;
+  cursor_skip_empty(cur, slices, n_slices, P);
+  StageRegs R;
+  if (n_stages > 0) {
+    gram_load<KIND, FULL, SPLIT>(J, cur.S, cur.ro, tid, R);
+    cursor_next(cur, slices, n_slices, P);
+    store(R, 0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int t = 0; t + 1 < n_stages; ++t) {
+    gram_load<KIND, FULL, SPLIT>(J, cur.S, cur.ro, tid, R);
+    cursor_next(cur, slices, n_slices, P);
+    compute(buf);
+    store(R, buf ^ 1);
     __syncthreads();
     buf ^= 1;
-    si = si2;
-    ro = ro2;
   }
+  if (n_stages > 0) compute(buf);
 
-  double* base = partial + ((size_t)jid * P + p) * (size_t)(3 * GT * GT);
+  BLM_GLOBAL double* base = as_global(out);
+  if constexpr (MAIN) {
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int row = 32 * wr + 16 * x + 4 * rr + k4;
-        const int col = 32 * wc + 16 * y + i16;
-        base[row * GT + col] = P0[x][y][rr];
-        base[GT * GT + row * GT + col] = P1[x][y][rr];
-        if (kind == JOB_OFF) base[2 * GT * GT + row * GT + col] = P2[x][y][rr];
-      }
-  if (kind == JOB_DIAG || kind == JOB_STRIP) {
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = 32 * wr + 16 * x + 4 * rr + k4;
+          const int col = 32 * wc + 16 * y + i16;
+          base[row * GT + col] = P0[x][y][rr];
+          base[GT * GT + row * GT + col] = P1[x][y][rr];
+          if (KIND == JOB_OFF) base[2 * GT * GT + row * GT + col] = P2[x][y][rr];
+        }
+  }
+  if constexpr (STRIPS) {
     // strips: [3][NAUX][GT] in the third slot
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
@@ -289,6 +340,55 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
       base[2 * GT * GT + 0 * NAUX * GT + a * GT + c] = P2[0][0][rr];
       base[2 * GT * GT + 1 * NAUX * GT + a * GT + c] = P2[0][1][rr];
       base[2 * GT * GT + 2 * NAUX * GT + a * GT + c] = P2[1][0][rr];
+    }
+  }
+}
+
+// VEC: every job's columns are 16-byte aligned (even leading dimension and
+// tile origins, aligned panels), so full 64 x 64 tiles use 16-byte loads.
+// SPLIT: the jobs are strip jobs on BF16 split storage, plus the aux job.
+template <bool VEC, bool SPLIT>
+__global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __restrict__ jobs,
+                                                           int n_jobs,
+                                                           const Slice* __restrict__ slices,
+                                                           int n_slices, int P,
+                                                           double* __restrict__ partial) {
+  // XCD-aware order: the hardware deals workgroups round-robin over the 8
+  // XCDs; give each XCD a contiguous range of work items so that the tiles of
+  // one block and one slice set (which share their sample panels) run on the
+  // same L2.
+  const int G = gridDim.x, g = blockIdx.x;
+  const int q = G >> 3, r = G & 7, xcd = g & 7, idx = g >> 3;
+  const int wid = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+  const int p = wid / n_jobs, jid = wid % n_jobs;
+  const GramJob J = jobs[jid];
+  __shared__ GramLds L;
+  double* out = partial + ((size_t)jid * P + p) * (size_t)(3 * GT * GT);
+  const bool full = VEC && J.mi == GT && J.nj == GT;
+  if constexpr (SPLIT) {
+    if (J.kind == JOB_STRIP) gram_body<JOB_STRIP, false, true>(L, J, slices, n_slices, P, p, out);
+    else gram_body<JOB_AUX, false, false>(L, J, slices, n_slices, P, p, out);
+  } else {
+    switch (J.kind) {
+      case JOB_OFF:
+        if (full) gram_body<JOB_OFF, VEC, false>(L, J, slices, n_slices, P, p, out);
+        else gram_body<JOB_OFF, false, false>(L, J, slices, n_slices, P, p, out);
+        break;
+      case JOB_DIAG:
+        if (full) gram_body<JOB_DIAG, VEC, false>(L, J, slices, n_slices, P, p, out);
+        else gram_body<JOB_DIAG, false, false>(L, J, slices, n_slices, P, p, out);
+        break;
+      case JOB_DIAG_NOSTRIP:
+        if (full) gram_body<JOB_DIAG_NOSTRIP, VEC, false>(L, J, slices, n_slices, P, p, out);
+        else gram_body<JOB_DIAG_NOSTRIP, false, false>(L, J, slices, n_slices, P, p, out);
+        break;
+      case JOB_STRIP:
+        if (full) gram_body<JOB_STRIP, VEC, false>(L, J, slices, n_slices, P, p, out);
+        else gram_body<JOB_STRIP, false, false>(L, J, slices, n_slices, P, p, out);
+        break;
+      default:
+        gram_body<JOB_AUX, false, false>(L, J, slices, n_slices, P, p, out);
+        break;
     }
   }
 }
@@ -382,10 +482,10 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
       const int64_t s = s0 + row;
       const bool v = (s < C.n) && (p0 + c2 < B.m);
       if (v) {
-        const double2 a =
-            *reinterpret_cast<const double2*>((const double*)C.O + s * C.ld + B.col0 + p0 + c2);
-        const double2 b =
-            *reinterpret_cast<const double2*>((const double*)C.e + s * C.ld + B.col0 + p0 + c2);
+        const double2 a = *reinterpret_cast<const BLM_GLOBAL double2*>(
+            as_global((const double*)C.O) + s * C.ld + B.col0 + p0 + c2);
+        const double2 b = *reinterpret_cast<const BLM_GLOBAL double2*>(
+            as_global((const double*)C.e) + s * C.ld + B.col0 + p0 + c2);
         R.o[2 * i] = a.x;
         R.o[2 * i + 1] = a.y;
         R.e[2 * i] = b.x;
@@ -401,8 +501,8 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
       const int row = (tid >> 5) + 8 * i;
       const int64_t s = s0 + row;
       const bool v = (s < C.n) && (p0 + col < B.m);
-      R.o[i] = v ? ((const double*)C.O)[s * C.ld + B.col0 + p0 + col] : 0.0;
-      R.e[i] = v ? ((const double*)C.e)[s * C.ld + B.col0 + p0 + col] : 0.0;
+      R.o[i] = v ? as_global((const double*)C.O)[s * C.ld + B.col0 + p0 + col] : 0.0;
+      R.e[i] = v ? as_global((const double*)C.e)[s * C.ld + B.col0 + p0 + col] : 0.0;
     }
   }
   const int col = tid & 31;
@@ -410,7 +510,7 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
   for (int i = 0; i < 4; ++i) {
     const int dr = (tid >> 5) + 8 * i;
     const int dd = dg + dr;
-    R.d[i] = (dd < B.nd && p0 + col < B.m) ? dir_ptr[B.d0 + dd][p0 + col] : 0.0;
+    R.d[i] = (dd < B.nd && p0 + col < B.m) ? as_global(dir_ptr[B.d0 + dd])[p0 + col] : 0.0;
   }
 }
 
@@ -464,8 +564,8 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
   while (ci + 1 < n_chunks && chunks[ci + 1].tile0 <= (int)blockIdx.x) ++ci;
   const ProjChunk C = chunks[ci];
   const int64_t s0 = (int64_t)(blockIdx.x - C.tile0) * PJ_ROWS;
-  double* X = Xo + C.row_base * ldo;
-  double* Y = Yo + C.row_base * ldo;
+  BLM_GLOBAL double* X = as_global(Xo) + C.row_base * ldo;
+  BLM_GLOBAL double* Y = as_global(Yo) + C.row_base * ldo;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i16 = lane & 15, k4 = lane >> 4;
 
@@ -476,7 +576,7 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
     if (s >= C.n) continue;
     if (c == 0) {
       X[s * ldo] = 1.0;
-      Y[s * ldo] = C.EL[s];
+      Y[s * ldo] = as_global(C.EL)[s];
     } else if (c >= 1 + n_dirs) {
       X[s * ldo + c] = 0.0;
       Y[s * ldo + c] = 0.0;
