@@ -195,7 +195,7 @@ __device__ void congruence(Shared& sh, const gdouble* L, gdouble* A, gdouble* W,
 // the waves' q partials are summed in a fixed order (Qs scratch, 16 x d).
 __device__ void hessenberg(Shared& sh, gdouble* A, gdouble* V, gdouble* tau, gdouble* Qs, int d) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  constexpr int QCH = 8;                      // q accumulators per lane (512 columns)
+  constexpr int QCH = 4;                      // q accumulators per lane (256 columns)
   for (int k = 0; k + 2 < d; ++k) {
     double part = 0.0;
     for (int i = k + 2 + tid; i < d; i += NT) {
@@ -222,27 +222,44 @@ __device__ void hessenberg(Shared& sh, gdouble* A, gdouble* V, gdouble* tau, gdo
     }
     if (tid == 0) tau[k] = tk;
     __syncthreads();
-    // pass 1: p = A v (all rows), partial q = A^T v (rows > k) per wave
+    // pass 1: p = A v (all rows), partial q = A^T v (rows > k) per wave.
+    // Two rows per wave at a time, loads unconditional (columns clamped,
+    // values past the end zeroed), so 2 QCH loads per lane are in flight.
     const int j0 = k + 1, nj = d - j0;
     for (int c0 = 0; c0 < nj; c0 += 64 * QCH) {
       double qacc[QCH];
 #pragma unroll
       for (int m = 0; m < QCH; ++m) qacc[m] = 0.0;
-      for (int i = wv; i < d; i += NW) {
-        const gdouble* Ai = A + (size_t)i * d + j0 + c0;
-        const double vi = sh.v1[i];
-        double pp = 0.0;
+      for (int i = wv; i < d; i += 2 * NW) {
+        const int i2 = i + NW;
+        const bool has2 = i2 < d;
+        const gdouble* A1 = A + (size_t)i * d + j0;
+        const gdouble* A2 = A + (size_t)(has2 ? i2 : i) * d + j0;
+        double a1[QCH], a2[QCH];
 #pragma unroll
         for (int m = 0; m < QCH; ++m) {
-          const int j = lane + 64 * m;
-          if (c0 + j < nj) {
-            const double a = Ai[j];
-            pp += a * sh.v1[j0 + c0 + j];
-            qacc[m] += vi * a;
-          }
+          const int jc = min(c0 + lane + 64 * m, nj - 1);
+          a1[m] = A1[jc];
+          a2[m] = A2[jc];
         }
-        pp = wave_sum(pp);
-        if (lane == 0) sh.v2[i] += pp;
+        const double v_1 = sh.v1[i], v_2 = has2 ? sh.v1[i2] : 0.0;
+        double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < QCH; ++m) {
+          const int j = c0 + lane + 64 * m;
+          const bool ok = j < nj;
+          const double vj = ok ? sh.v1[j0 + j] : 0.0;
+          const double x1 = ok ? a1[m] : 0.0, x2 = ok ? a2[m] : 0.0;
+          p1 += x1 * vj;
+          p2 += x2 * vj;
+          qacc[m] += v_1 * x1 + v_2 * x2;
+        }
+        p1 = wave_sum(p1);
+        p2 = wave_sum(p2);
+        if (lane == 0) {
+          sh.v2[i] += p1;
+          if (has2) sh.v2[i2] += p2;
+        }
       }
 #pragma unroll
       for (int m = 0; m < QCH; ++m) {
@@ -262,11 +279,21 @@ __device__ void hessenberg(Shared& sh, gdouble* A, gdouble* V, gdouble* tau, gdo
       sh.v3[j] = q - tk * beta * sh.v1[j];
     }
     __syncthreads();
-    // pass 2: update the trailing columns; column k becomes beta_h e_(k+1)
+    // pass 2: update the trailing columns; column k becomes beta_h e_(k+1).
+    // Loads of a row chunk are issued together (clamped), stores guarded.
     for (int i = wv; i < d; i += NW) {
       gdouble* Ai = A + (size_t)i * d;
       const double pi = tk * sh.v2[i], vi = tk * sh.v1[i];
-      for (int j = j0 + lane; j < d; j += 64) Ai[j] -= pi * sh.v1[j] + vi * sh.v3[j];
+      for (int c0 = j0; c0 < d; c0 += 64 * QCH) {
+        double a[QCH];
+#pragma unroll
+        for (int m = 0; m < QCH; ++m) a[m] = Ai[min(c0 + lane + 64 * m, d - 1)];
+#pragma unroll
+        for (int m = 0; m < QCH; ++m) {
+          const int j = c0 + lane + 64 * m;
+          if (j < d) Ai[j] = a[m] - (pi * sh.v1[j] + vi * sh.v3[j]);
+        }
+      }
       if (i > k && lane == 0) Ai[k] = (i == k + 1) ? beta_h : 0.0;
     }
     __syncthreads();

@@ -628,6 +628,148 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
   }
 }
 
+// FP64 storage: each wave projects its own 16 samples with operands taken
+// straight from global memory (no LDS, no barriers).  In matrix-core product
+// j of a 32-parameter stage, lane group g = lane / 16 supplies parameter
+// p0 + 8 g + j on both operand sides (the contraction runs over the same
+// permutation of the parameters on both sides), so each lane reads 8
+// consecutive parameters of its sample row, 64 contiguous bytes.  Loads are
+// unconditional (rows clamped to the chunk, columns to the block; values
+// past the block edge meet zeroed direction entries) and the next stage is
+// loaded before the current one is multiplied.
+struct Pj64Regs {
+  double o[8], e[8], x0[8], x1[8];
+};
+
+template <bool VEC>
+__device__ __forceinline__ void pj64_row8(const BLM_GLOBAL double* p, int c0, int m, double* v) {
+  if constexpr (VEC) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = min(c0 + 2 * q, m - 2);
+      const double2 t = *reinterpret_cast<const BLM_GLOBAL double2*>(p + c);
+      v[2 * q] = t.x;
+      v[2 * q + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = p[min(c0 + q, m - 1)];
+  }
+}
+
+template <bool VEC>
+__device__ __forceinline__ void pj64_load(const BLM_GLOBAL double* rO, const BLM_GLOBAL double* rE,
+                                          const BLM_GLOBAL double* d0, const BLM_GLOBAL double* d1,
+                                          bool two, int c0, int m, Pj64Regs& R) {
+  pj64_row8<VEC>(rO, c0, m, R.o);
+  pj64_row8<VEC>(rE, c0, m, R.e);
+  pj64_row8<VEC>(d0, c0, m, R.x0);
+  if (two) pj64_row8<VEC>(d1, c0, m, R.x1);
+}
+
+template <bool VEC, bool TWO>
+__device__ __forceinline__ void pj64_mul(const Pj64Regs& R, bool ok0, bool ok1, int p, int m, d4& aO0,
+                                         d4& aE0, d4& aO1, d4& aE1) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const bool inb = p + j < m;
+    const double b0 = (ok0 && inb) ? R.x0[j] : 0.0;
+    aO0 = mfma_f64(R.o[j], b0, aO0);
+    aE0 = mfma_f64(R.e[j], b0, aE0);
+    if constexpr (TWO) {
+      const double b1 = (ok1 && inb) ? R.x1[j] : 0.0;
+      aO1 = mfma_f64(R.o[j], b1, aO1);
+      aE1 = mfma_f64(R.e[j], b1, aE1);
+    }
+  }
+}
+
+// All stages of one block for one direction group; two register stages
+// alternate (stage t+1 is loaded while stage t is multiplied).  A block
+// whose width is not a multiple of 64 multiplies one all-zero stage more.
+template <bool VEC, bool TWO>
+__device__ __forceinline__ void pj64_block(const BLM_GLOBAL double* rO, const BLM_GLOBAL double* rE,
+                                           const BLM_GLOBAL double* d0, const BLM_GLOBAL double* d1,
+                                           bool ok0, bool ok1, int m, int g, d4& aO0, d4& aE0,
+                                           d4& aO1, d4& aE1) {
+  Pj64Regs Ra, Rb;
+  pj64_load<VEC>(rO, rE, d0, d1, TWO, 8 * g, m, Ra);
+  for (int p0 = 0; p0 < m; p0 += 2 * PJ_P) {
+    pj64_load<VEC>(rO, rE, d0, d1, TWO, p0 + PJ_P + 8 * g, m, Rb);
+    pj64_mul<VEC, TWO>(Ra, ok0, ok1, p0 + 8 * g, m, aO0, aE0, aO1, aE1);
+    pj64_load<VEC>(rO, rE, d0, d1, TWO, p0 + 2 * PJ_P + 8 * g, m, Ra);
+    pj64_mul<VEC, TWO>(Rb, ok0, ok1, p0 + PJ_P + 8 * g, m, aO0, aE0, aO1, aE1);
+  }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void dirproj64_kernel(const ProjChunk* __restrict__ chunks,
+                                                        int n_chunks,
+                                                        const DirBlock* __restrict__ blocks,
+                                                        int n_blocks,
+                                                        const double* const* __restrict__ dir_ptr,
+                                                        int n_dirs, double* __restrict__ Xo,
+                                                        double* __restrict__ Yo, int64_t ldo) {
+  int ci = 0;
+  while (ci + 1 < n_chunks && chunks[ci + 1].tile0 <= (int)blockIdx.x) ++ci;
+  const ProjChunk C = chunks[ci];
+  const int64_t s0 = (int64_t)(blockIdx.x - C.tile0) * PJ_ROWS;
+  BLM_GLOBAL double* X = as_global(Xo) + C.row_base * ldo;
+  BLM_GLOBAL double* Y = as_global(Yo) + C.row_base * ldo;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
+
+  // column 0 (the wave function itself: 1 and E_L) and the padding columns
+  for (int t = tid; t < PJ_ROWS * (int)ldo; t += blockDim.x) {
+    const int rr = t / (int)ldo, c = t % (int)ldo;
+    const int64_t s = s0 + rr;
+    if (s >= C.n) continue;
+    if (c == 0) {
+      X[s * ldo] = 1.0;
+      Y[s * ldo] = as_global(C.EL)[s];
+    } else if (c >= 1 + n_dirs) {
+      X[s * ldo + c] = 0.0;
+      Y[s * ldo + c] = 0.0;
+    }
+  }
+
+  const int64_t sw = s0 + 16 * wv;                      // first sample of this wave
+  const int64_t sl = min(sw + i16, C.n - 1);            // this lane's (clamped) sample row
+  const BLM_GLOBAL double* rowO = as_global((const double*)C.O) + sl * C.ld;
+  const BLM_GLOBAL double* rowE = as_global((const double*)C.e) + sl * C.ld;
+  for (int bi = 0; bi < n_blocks; ++bi) {
+    const DirBlock B = blocks[bi];
+    const BLM_GLOBAL double* rO = rowO + B.col0;
+    const BLM_GLOBAL double* rE = rowE + B.col0;
+    for (int dg = 0; dg < B.nd; dg += 32) {
+      const bool two = (B.nd - dg) > 16;
+      const int t0 = dg + i16, t1 = dg + 16 + i16;
+      const bool ok0 = t0 < B.nd, ok1 = two && t1 < B.nd;
+      const BLM_GLOBAL double* d0 = as_global(dir_ptr[B.d0 + min(t0, B.nd - 1)]);
+      const BLM_GLOBAL double* d1 = as_global(dir_ptr[B.d0 + min(t1, B.nd - 1)]);
+      d4 aO0 = {0, 0, 0, 0}, aO1 = {0, 0, 0, 0}, aE0 = {0, 0, 0, 0}, aE1 = {0, 0, 0, 0};
+      if (two)
+        pj64_block<VEC, true>(rO, rE, d0, d1, ok0, ok1, B.m, g, aO0, aE0, aO1, aE1);
+      else
+        pj64_block<VEC, false>(rO, rE, d0, d1, ok0, ok1, B.m, g, aO0, aE0, aO1, aE1);
+      // lane holds D[4 rr + g][i16]: sample sw + 4 rr + g, direction dg + i16 (+16)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int64_t s = sw + 4 * rr + g;
+        if (s >= C.n) continue;
+        if (ok0) {
+          X[s * ldo + 1 + B.d0 + t0] = aO0[rr];
+          Y[s * ldo + 1 + B.d0 + t0] = aE0[rr];
+        }
+        if (ok1) {
+          X[s * ldo + 1 + B.d0 + t1] = aO1[rr];
+          Y[s * ldo + 1 + B.d0 + t1] = aE1[rr];
+        }
+      }
+    }
+  }
+}
+
 void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, bool split,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st) {
@@ -636,10 +778,10 @@ void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool v
     hipLaunchKernelGGL((dirproj_kernel<false, true>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
                        n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
   else if (vec)
-    hipLaunchKernelGGL((dirproj_kernel<true, false>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
+    hipLaunchKernelGGL((dirproj64_kernel<true>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
                        n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
   else
-    hipLaunchKernelGGL((dirproj_kernel<false, false>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
+    hipLaunchKernelGGL((dirproj64_kernel<false>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
                        n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
 }
 
