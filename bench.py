@@ -29,6 +29,31 @@ import numpy as np
 METRIC = "block H/S build TFLOP/s + BLM step ms; mixed vs FP64 at ≤1e-6 rel energy err"
 PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 (matrix and vector)
 
+# HBM bytes of one FP64 block-build launch on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
+# counter reads for a plain 2 GiB copy (FETCH x2, WRITE x1).  Valid only for
+# the kernel source they were taken on: reported as null once the source of
+# the sample-streaming kernels has changed.
+GRAM_TRAFFIC = {
+    "source_sha256": "ed4db9e729e90f2b239606a93a2772c4a57cd8eeacb53740de6efa04aa1d8237",
+    "fetch_kib": 233883072.84, "fetch_scale": 1.99996,
+    "write_kib": 408000.0, "write_scale": 1.0,
+}
+
+
+def gram_traffic_bytes():
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1702_01481_amd", "csrc",
+                       "blm_kernels.hip")
+    try:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if digest != GRAM_TRAFFIC["source_sha256"]:
+        return None
+    t = GRAM_TRAFFIC
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -250,7 +275,8 @@ def main():
         "energy": [float(x) for x in en],
         "flags": [int(x) for x in fl],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
+                     "traffic": gram_traffic_bytes(),
                      "kernel": "gram_kernel (block H/S build, FP64 MFMA 16x16x4)",
                      "flops_per_launch": fl_build},
     }

@@ -30,10 +30,25 @@ constexpr int NW = NT / 64;
 constexpr double EPS = DBL_EPSILON;
 constexpr double DROP_TOL = 1e-12;
 
+constexpr int AEDMAX = 64;            // largest deflation window
+constexpr int AEDLD = AEDMAX + 1;     // LDS row stride of the window arrays
+
 struct Shared {
-  double v1[EIG_MAXD];
-  double v2[EIG_MAXD];
-  double v3[EIG_MAXD];
+  union {
+    struct {
+      double v1[EIG_MAXD];
+      double v2[EIG_MAXD];
+      double v3[EIG_MAXD];
+    };
+    // QR phase only: the deflation window, its Schur vectors, the spike and
+    // the window's eigenvalues
+    struct {
+      double aT[AEDMAX][AEDLD];
+      double aZ[AEDMAX][AEDLD];
+      double au[AEDMAX], av[AEDMAX];
+      double ewr[AEDMAX], ewi[AEDMAX];
+    };
+  };
   double stage[16][256];
   double red[NW];
   double sc[16];
@@ -300,6 +315,219 @@ __device__ void hessenberg(Shared& sh, gdouble* A, gdouble* V, gdouble* tau, gdo
   }
 }
 
+// ------------------------------------------ step 4a: deflation window --
+// Aggressive early deflation (Braman, Byers & Mathias, SIAM J. Matrix Anal.
+// Appl. 23 (2002) 948) for the eigenvalue-only QR iteration below: the
+// trailing nw x nw window W of the active block is brought to real Schur
+// form W = Z S Z^T; the coupling column (the "spike", s times the first row
+// of Z) shows which of S's trailing eigenvalues are already converged; those
+// are deflated, the rest is returned to Hessenberg form and the window's
+// unconverged eigenvalues serve as the next sweep's shifts.
+//
+// The window routines run on one wave with the window in LDS: the wave's LDS
+// accesses complete in program order, so they need no barriers.
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Real Schur form of the n x n upper Hessenberg T (n <= AEDMAX) by Francis
+// double-shift QR with whole-row and whole-column updates, accumulating the
+// transformations into Z (which enters as the identity): T_in = Z T_out Z^T.
+// 2 x 2 diagonal blocks are left as they converge (not standardised).
+// Returns false if the iteration did not converge.
+__device__ bool wave_schur(double (*T)[AEDLD], double (*Z)[AEDLD], int n) {
+  const int lane = threadIdx.x & 63;
+  double part = 0.0;
+  for (int r = lane; r < n; r += 64)
+    for (int c = (r > 0 ? r - 1 : 0); c < n; ++c) part += fabs(T[r][c]);
+  const double tnorm = wave_sum(part);
+  int h = n - 1, its = 0, total = 0;
+  while (h >= 0) {
+    int cand = 0;
+    for (int k = 1 + lane; k <= h; k += 64) {
+      double sc = fabs(T[k - 1][k - 1]) + fabs(T[k][k]);
+      if (sc == 0.0) sc = tnorm;
+      if (fabs(T[k][k - 1]) <= EPS * sc) cand = max(cand, k);
+    }
+    const int l = wave_max_i(cand);
+    if (l >= h - 1) {
+      if (l > 0 && lane == 0) T[l][l - 1] = 0.0;
+      h = l - 1;
+      its = 0;
+      continue;
+    }
+    if (++total > 30 * n) return false;
+    ++its;
+    double ssum, sprod;
+    if (its % 10 == 0) {
+      const double ex = fabs(T[h][h - 1]) + fabs(T[h - 1][h - 2]);
+      const double x = T[h][h] + 0.75 * ex;
+      ssum = 2.0 * x;
+      sprod = x * x + 0.4375 * ex * ex;
+    } else {
+      ssum = T[h - 1][h - 1] + T[h][h];
+      sprod = T[h - 1][h - 1] * T[h][h] - T[h - 1][h] * T[h][h - 1];
+    }
+    for (int K = l - 1; K <= h - 2; ++K) {
+      const int nr = (K <= h - 3) ? 3 : 2;
+      double x, y, z;
+      if (K == l - 1) {
+        const double h00 = T[l][l], h01 = T[l][l + 1], h10 = T[l + 1][l];
+        const double h11 = T[l + 1][l + 1], h21 = T[l + 2][l + 1];
+        x = h00 * h00 + h01 * h10 - ssum * h00 + sprod;
+        y = h10 * (h00 + h11 - ssum);
+        z = h10 * h21;
+      } else {
+        x = T[K + 1][K];
+        y = T[K + 2][K];
+        z = (nr == 3) ? T[K + 3][K] : 0.0;
+      }
+      if (nr == 2) z = 0.0;
+      const double sc = fabs(x) + fabs(y) + fabs(z);
+      if (sc == 0.0) continue;
+      const double xs = x / sc, ys = y / sc, zs = z / sc;
+      const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
+      const double v0 = xs + al, v1 = ys, v2 = zs;
+      const double bt = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+      for (int c = K + 1 + lane; c < n; c += 64) {
+        double tt = v0 * T[K + 1][c] + v1 * T[K + 2][c];
+        if (nr == 3) tt += v2 * T[K + 3][c];
+        tt *= bt;
+        T[K + 1][c] -= tt * v0;
+        T[K + 2][c] -= tt * v1;
+        if (nr == 3) T[K + 3][c] -= tt * v2;
+      }
+      if (K >= l && lane == 0) {
+        T[K + 1][K] = -al * sc;
+        T[K + 2][K] = 0.0;
+        if (nr == 3) T[K + 3][K] = 0.0;
+      }
+      const int r1 = min(K + 4, h);
+      for (int r = lane; r <= r1; r += 64) {
+        double tt = T[r][K + 1] * v0 + T[r][K + 2] * v1;
+        if (nr == 3) tt += T[r][K + 3] * v2;
+        tt *= bt;
+        T[r][K + 1] -= tt * v0;
+        T[r][K + 2] -= tt * v1;
+        if (nr == 3) T[r][K + 3] -= tt * v2;
+      }
+      for (int r = lane; r < n; r += 64) {
+        double tt = Z[r][K + 1] * v0 + Z[r][K + 2] * v1;
+        if (nr == 3) tt += Z[r][K + 3] * v2;
+        tt *= bt;
+        Z[r][K + 1] -= tt * v0;
+        Z[r][K + 2] -= tt * v1;
+        if (nr == 3) Z[r][K + 3] -= tt * v2;
+      }
+    }
+  }
+  return true;
+}
+
+// Deflation test of the window's Schur form (T, Z) against the spike s Z[0][:],
+// from the bottom up: blocks whose spike entries are below ulp times the
+// block's size are converged and deflate, up to the first one that is not.
+// (Moving unconverged blocks up to test the ones above, as LAPACK does, found
+// hardly any more on these pencils, whose spectra are mostly complex pairs,
+// and cost more than it saved.)  Returns the number of deflated eigenvalues.
+__device__ int wave_aed_deflate(double (*T)[AEDLD], double (*Z)[AEDLD], int n, double spike) {
+  int ns = n;
+  while (ns > 0) {
+    const int k = ns - 1;
+    const bool two = (k > 0) && T[k][k - 1] != 0.0;
+    double foo = fabs(T[k][k]);
+    if (two) foo += sqrt(fabs(T[k][k - 1])) * sqrt(fabs(T[k - 1][k]));
+    if (foo == 0.0) foo = fabs(spike);
+    double f = fabs(spike * Z[0][k]);
+    if (two) f = fmax(f, fabs(spike * Z[0][k - 1]));
+    if (!(f <= fmax(DBL_MIN, EPS * foo))) break;
+    ns -= two ? 2 : 1;
+  }
+  return n - ns;
+}
+
+// Eigenvalues of the diagonal blocks of a quasi-triangular S (n x n): a
+// 2 x 2 block sits where S[k][k-1] != 0.
+__device__ void wave_block_eigs(double (*S)[AEDLD], int n, double* er, double* ei) {
+  const int lane = threadIdx.x & 63;
+  for (int k = lane; k < n; k += 64) {
+    const bool top = (k + 1 < n) && S[k + 1][k] != 0.0;
+    const bool bot = (k > 0) && S[k][k - 1] != 0.0;
+    if (!top && !bot) {
+      er[k] = S[k][k];
+      ei[k] = 0.0;
+      continue;
+    }
+    const int i = top ? k : k - 1;
+    const double a = S[i][i], b = S[i][i + 1], c = S[i + 1][i], dd = S[i + 1][i + 1];
+    const double p = 0.5 * (a - dd);
+    const double disc = p * p + b * c;
+    if (disc >= 0.0) {
+      const double zz = p + copysign(sqrt(disc), p);
+      const double e0 = dd + zz, e1 = (zz != 0.0) ? dd - b * c / zz : dd + zz;
+      er[k] = top ? e0 : e1;
+      ei[k] = 0.0;
+    } else {
+      er[k] = dd + p;
+      ei[k] = top ? sqrt(-disc) : -sqrt(-disc);
+    }
+  }
+}
+
+// Returns the leading nu x nu block of T, whose first column carries the
+// spike u (length nu) on the left, to Hessenberg form by Householder
+// reflections H_k (k = -1 reflects the spike onto e_0): T <- H T H on the
+// window (rows k+1..nu-1 from the left over all columns, columns k+1..nu-1
+// from the right), Z <- Z H.  Returns the spike's remaining first entry.
+__device__ double wave_rehess(double (*T)[AEDLD], double (*Z)[AEDLD], double* u, double* v, int nu,
+                              int nw) {
+  const int lane = threadIdx.x & 63;
+  double spike0 = u[0];
+  for (int k = -1; k <= nu - 3; ++k) {
+    const int r0 = k + 1, len = nu - r0;
+    // x = column k below the diagonal (the spike for k = -1)
+    const double xi = (lane < len) ? (k < 0 ? u[r0 + lane] : T[r0 + lane][k]) : 0.0;
+    const double alpha = __shfl(xi, 0, 64);
+    const double xn2 = wave_sum(lane > 0 ? xi * xi : 0.0);
+    if (xn2 == 0.0) continue;
+    const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    const double tau = (beta - alpha) / beta;
+    const double scal = 1.0 / (alpha - beta);
+    if (lane < len) v[lane] = (lane == 0) ? 1.0 : xi * scal;
+    // the reflected column becomes beta e_0
+    if (k < 0) {
+      if (lane < len) u[lane] = (lane == 0) ? beta : 0.0;
+      spike0 = beta;
+    } else if (lane < len) {
+      T[r0 + lane][k] = (lane == 0) ? beta : 0.0;
+    }
+    // left: rows r0..nu-1, columns k+1..nw-1
+    for (int c = k + 1 + lane; c < nw; c += 64) {
+      double wsum = 0.0;
+      for (int i = 0; i < len; ++i) wsum += v[i] * T[r0 + i][c];
+      wsum *= tau;
+      for (int i = 0; i < len; ++i) T[r0 + i][c] -= wsum * v[i];
+    }
+    // right: columns r0..nu-1, rows 0..nu-1 (rows below nu are zero there)
+    for (int r = lane; r < nu; r += 64) {
+      double wsum = 0.0;
+      for (int i = 0; i < len; ++i) wsum += T[r][r0 + i] * v[i];
+      wsum *= tau;
+      for (int i = 0; i < len; ++i) T[r][r0 + i] -= wsum * v[i];
+    }
+    for (int r = lane; r < nw; r += 64) {
+      double wsum = 0.0;
+      for (int i = 0; i < len; ++i) wsum += Z[r][r0 + i] * v[i];
+      wsum *= tau;
+      for (int i = 0; i < len; ++i) Z[r][r0 + i] -= wsum * v[i];
+    }
+  }
+  return spike0;
+}
+
 // ---------------------------------------------------------------- step 4 --
 // Eigenvalues of the upper Hessenberg matrix A (row stride ld, destroyed)
 // into wr, wi.  A conjugate pair is stored as (re, +im), (re, -im) at
@@ -316,6 +544,8 @@ __device__ void hessenberg(Shared& sh, gdouble* A, gdouble* V, gdouble* tau, gdo
 // eigenvalues, or an ad hoc pair.  Deflation: a subdiagonal entry below
 // eps (|a_{i-1,i-1}| + |a_ii|) is set to zero.
 constexpr int MAX_BULGES = 16;
+constexpr int AED_MIN_W = 75;   // active blocks at least this wide use early deflation
+constexpr int AED_NIBBLE = 14;  // percent of the window deflated to skip a sweep
 
 template <bool MULTI, class Real>
 __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* iters) {
@@ -381,7 +611,98 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
     ++total;
     const int w = h - l + 1;
     int m = 1;
-    if (MULTI && its % 10 != 0) {
+    bool shifts_set = false;
+    if (MULTI && w >= AED_MIN_W && its % 10 != 0) {
+      // aggressive early deflation on the trailing window
+      const int ns = w < 150 ? 10 : w < 300 ? 16 : 2 * MAX_BULGES;
+      const int nw = min(AEDMAX, ns);
+      const int kwtop = h - nw + 1;
+      const double spike = at(kwtop, kwtop - 1);
+      for (int t = tid; t < nw * nw; t += NT) {
+        const int i = t / nw, j = t % nw;
+        sh.aT[i][j] = (j + 1 >= i) ? at(kwtop + i, kwtop + j) : 0.0;
+        sh.aZ[i][j] = (i == j) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const bool ok = wave_schur(sh.aT, sh.aZ, nw);
+        const int nd = ok ? wave_aed_deflate(sh.aT, sh.aZ, nw, spike) : 0;
+        wave_block_eigs(sh.aT, nw, sh.ewr, sh.ewi);
+        const int nu = nw - nd;
+        double beta = 0.0;
+        if (ok && nd > 0 && nu > 0) {
+          for (int i = tid; i < nu; i += 64) sh.au[i] = spike * sh.aZ[0][i];
+          beta = wave_rehess(sh.aT, sh.aZ, sh.au, sh.av, nu, nw);
+        }
+        if (tid == 0) {
+          sh.isc[6] = ok ? 1 : 0;
+          sh.isc[7] = nd;
+          sh.sc[8] = beta;
+        }
+      }
+      __syncthreads();
+      if (sh.isc[6]) {
+        const int nd = sh.isc[7], nu = nw - nd;
+        if (nd > 0) {
+          for (int i = nu + tid; i < nw; i += NT) {
+            wr[kwtop + i] = sh.ewr[i];
+            wi[kwtop + i] = sh.ewi[i];
+          }
+          // rows of the active block above the window: A <- A Z
+          const int lane = tid & 63, wv = tid >> 6;
+          for (int r = l + wv; r < kwtop; r += NW) {
+            if (lane < nw) sh.stage[wv][lane] = at(r, kwtop + lane);
+            if (lane < nw) {
+              double acc = 0.0;
+              for (int i = 0; i < nw; ++i) acc += sh.stage[wv][i] * sh.aZ[i][lane];
+              at(r, kwtop + lane) = acc;
+            }
+          }
+          for (int t = tid; t < nw * nw; t += NT) {
+            const int i = t / nw, j = t % nw;
+            if (j + 1 >= i) at(kwtop + i, kwtop + j) = sh.aT[i][j];
+          }
+          if (tid == 0) at(kwtop, kwtop - 1) = (nu > 0) ? sh.sc[8] : 0.0;
+          __syncthreads();
+          h = kwtop + nu - 1;
+          its = 0;
+        }
+        // skip the sweep when the window deflated enough
+        if (nd > 0 && 100 * nd > AED_NIBBLE * nw) continue;
+        if (h - l + 1 < 3) continue;
+        if (tid == 0) {
+          // shifts: the window's bottom-most unconverged eigenvalues
+          int mm = 0, i = nu - 1;
+          double rpend = 0.0;
+          bool have_r = false;
+          while (i >= 0 && mm < MAX_BULGES && mm * 2 < ns) {
+            if (sh.ewi[i] != 0.0 && i > 0) {
+              const double re = sh.ewr[i], im = sh.ewi[i];
+              sh.bsum[mm] = 2.0 * re;
+              sh.bprod[mm] = re * re + im * im;
+              ++mm;
+              i -= 2;
+            } else {
+              if (have_r) {
+                sh.bsum[mm] = rpend + sh.ewr[i];
+                sh.bprod[mm] = rpend * sh.ewr[i];
+                ++mm;
+                have_r = false;
+              } else {
+                rpend = sh.ewr[i];
+                have_r = true;
+              }
+              i -= 1;
+            }
+          }
+          sh.isc[5] = mm;
+        }
+        __syncthreads();
+        m = sh.isc[5];
+        shifts_set = m > 0;
+      }
+    }
+    if (MULTI && !shifts_set && its % 10 != 0) {
       const int ns = w < 30 ? 2 : w < 60 ? 4 : w < 150 ? 10 : w < 590 ? 16 : 2 * MAX_BULGES;
       if (ns > 2) {
         const int o = h - ns + 1;
