@@ -82,6 +82,8 @@ struct blm_ctx {
   // mixed precision: jobs1 = FP64 strip + aux jobs, jobsM = BF16 main-product jobs
   GramJob* d_jobsM = nullptr;
   int n_jobsM = 0;
+  PairJob* d_pairsM = nullptr;   // BF16 build: pairs of main jobs sharing a row tile
+  int n_pairsM = 0;
   int pieces = 0;                  // 0: FP64 path; 2 or 3: BF16 split pieces used
   Slice* d_slices = nullptr;
   ProjChunk* d_pchunks = nullptr;
@@ -343,6 +345,7 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_jobs1, sizeof(GramJob) * (size_t)c->n_jobs1);
   add((void**)&c->d_jobs2, sizeof(GramJob) * (size_t)n_jobs2max);
   add((void**)&c->d_jobsM, sizeof(GramJob) * (size_t)std::max(c->n_jobsM, 1));
+  add((void**)&c->d_pairsM, sizeof(PairJob) * (size_t)std::max(c->n_jobsM, 1));
   add((void**)&c->d_slices, sizeof(Slice) * (size_t)c->max_slices);
   add((void**)&c->d_pchunks, sizeof(ProjChunk) * (size_t)MAX_CHUNKS);
   add((void**)&c->d_theta_blk, sizeof(DirBlock) * (size_t)NB);
@@ -451,8 +454,19 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
   c->n_jobs1 = (int)jobs.size();
   c->n_jobsM = (int)main.size();
   HIPCHK(c, hipMemcpy(c->d_jobs1, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice));
-  if (!main.empty())
+  if (!main.empty()) {
     HIPCHK(c, hipMemcpy(c->d_jobsM, main.data(), sizeof(GramJob) * main.size(), hipMemcpyHostToDevice));
+    // consecutive main jobs of one row tile (same first column) pair up
+    std::vector<PairJob> pairs;
+    for (size_t k = 0; k < main.size();) {
+      PairJob pj{(int32_t)k, -1};
+      if (k + 1 < main.size() && main[k + 1].ci == main[k].ci) pj.jb = (int32_t)(k + 1);
+      pairs.push_back(pj);
+      k += (pj.jb >= 0) ? 2 : 1;
+    }
+    c->n_pairsM = (int)pairs.size();
+    HIPCHK(c, hipMemcpy(c->d_pairsM, pairs.data(), sizeof(PairJob) * pairs.size(), hipMemcpyHostToDevice));
+  }
   return BLM_OK;
 }
 
@@ -538,7 +552,8 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
   const int P = choose_P(cap, n_jobs, n_slices);
   if (phase >= 0) mark(c, phase, false);
   if (kind == 2)
-    launch_gram_bf16(d_jobs, n_jobs, c->d_slices, n_slices, P, c->pieces, c->partial, c->st);
+    launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->pieces,
+                     c->partial, c->st);
   else
     launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec && kind == 0, kind == 1, c->partial,
                 c->st);

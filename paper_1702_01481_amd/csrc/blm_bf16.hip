@@ -21,6 +21,7 @@ namespace blm {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4b __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 // FP32 accumulators are added into FP64 after every 32-sample step: each
 // FP32 partial then holds one step's sum, which keeps the block estimates
@@ -45,36 +46,65 @@ __device__ __forceinline__ bf16x8 load_frag(const BLM_GLOBAL uint16_t* p, bool v
   return z;
 }
 
-// Each wave loads its own operands straight from HBM/L2 (the k-packed
-// layout makes every operand one 16-byte load per lane); wave (wr, wc) owns
-// rows 32 wr .. +31 and columns 32 wc .. +31 of each product.  (A variant
-// that staged the panels in LDS for all 8 waves of a tile ran slower: one
-// workgroup per CU left the loads' latency exposed.)
+// One workgroup computes a pair of 64 x 64 tile jobs that share their row
+// tile i: the A side is {O_i, e_i} (64 parameters), the B side {O_j, e_j,
+// O_j', e_j'} (128 parameters, j' = j + 1).  Per 32-sample step the pieces of
+// both sides are copied once into LDS by direct global->LDS loads (no
+// registers involved; double-buffered, 72 KB per buffer, one workgroup per
+// CU).  Eight waves, two per SIMD: wave (wr, wc) owns rows 32 wr .. + 31 and
+// columns 32 wc .. + 31 of the 64 x 128 output of each product, so while one
+// wave of a SIMD adds its FP32 partial sums into FP64, the other keeps the
+// matrix core busy.  Per step a wave reads 24 fragments from LDS for 72
+// matrix-core products.
+constexpr int BP_COLS = 2 * GT;                  // B-side columns of a pair
+constexpr int BP_STEP = 32;                      // samples per step (one k-depth)
+constexpr int BP_KG = BP_STEP / 8;               // 8-sample groups per step
+constexpr int BP_THREADS = 512;
+
 template <int PIECES>
-__global__ __launch_bounds__(GTHREADS, 2) void gram_bf16_kernel(const GramJob* __restrict__ jobs,
-                                                                int n_jobs,
-                                                                const Slice* __restrict__ slices,
-                                                                int n_slices, int P,
-                                                                double* __restrict__ partial) {
+struct BpLds {
+  u4v A[2][PIECES][BP_KG][GT];        // [O or e][piece][group][column]
+  u4v B[2][PIECES][BP_KG][BP_COLS];
+};
+
+__device__ __forceinline__ void lds_dma16(const BLM_GLOBAL void* src, u4v* lds_base) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
+}
+
+template <int PIECES>
+__global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob* __restrict__ pairs,
+                                                                 int n_pairs,
+                                                                 const GramJob* __restrict__ jobs,
+                                                                 const Slice* __restrict__ slices,
+                                                                 int n_slices, int P,
+                                                                 double* __restrict__ partial) {
+  // wave instructions per step: one per (side, array, piece, group[, half])
+  constexpr int NIA = 2 * PIECES * BP_KG;              // A side, 64 columns each
+  constexpr int NIB = 2 * PIECES * BP_KG * 2;          // B side, two 64-column halves
+  constexpr int NW = BP_THREADS / 64;
+  __shared__ BpLds<PIECES> L[2];
+
   const int G = gridDim.x, g = blockIdx.x;
   const int q = G >> 3, r = G & 7, xcd = g & 7, idx = g >> 3;
   const int wid = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-  const int p = wid / n_jobs, jid = wid % n_jobs;
-  const GramJob J = jobs[jid];
-  const bool off = (J.kind == JOB_OFF);
+  const int p = wid / n_pairs, pid = wid % n_pairs;
+  const PairJob PJ = pairs[pid];
+  const GramJob JA = jobs[PJ.ja];
+  const bool has_b = PJ.jb >= 0;
+  const GramJob JB = jobs[has_b ? PJ.jb : PJ.ja];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wr = wv >> 1, wc = wv & 1;
-  const int i16 = lane & 15, g4 = lane >> 4;
-  int ca[2], cb[2];
-  bool va[2], vb[2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    ca[x] = 32 * wr + 16 * x + i16;
-    cb[x] = 32 * wc + 16 * x + i16;
-    va[x] = ca[x] < J.mi;
-    vb[x] = cb[x] < J.nj;
-  }
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int wr = wv & 1, wc = wv >> 1;           // 2 x 4 waves over 64 x 128
+  const bool wave_b = wc >= 2;
+  const bool wave_on = !wave_b || has_b;
+  const GramJob& JW = wave_b ? JB : JA;
+  const bool third = JW.kind == JOB_OFF;
+
+  // this lane's global column in each 64-column half (clamped into the tile)
+  const int acol = JA.ci + min(lane, JA.mi - 1);
+  const int bcol0 = JA.cj + min(lane, JA.nj - 1);
+  const int bcol1 = JB.cj + min(lane, JB.nj - 1);
 
   f4 acc[3][2][2];
   d4b a64[3][2][2];
@@ -87,58 +117,133 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_bf16_kernel(const GramJob* _
         acc[t][x][y] = f4{0.f, 0.f, 0.f, 0.f};
         a64[t][x][y] = d4b{0.0, 0.0, 0.0, 0.0};
       }
-  for (int si = p; si < n_slices; si += P) {
-    const Slice S = slices[si];
+
+  // copies step (slice sl, first group grp0) into LDS buffer buf: this wave
+  // issues instructions wv, wv + NW, ...; every address is inside the slice
+  // (columns and groups clamped), granules the pair does not use are never
+  // multiplied
+  auto issue = [&](int sl, int64_t grp0, int buf) {
+    const Slice S = slices[sl];
+    const int64_t n8 = (S.n + 7) >> 3;
     const BLM_GLOBAL uint16_t* O = as_global((const uint16_t*)S.O);
     const BLM_GLOBAL uint16_t* E = as_global((const uint16_t*)S.e);
-    const int64_t n8 = (S.n + 7) >> 3;
-    for (int64_t g0 = 0; g0 < n8; g0 += 4) {
-      const int64_t gg = g0 + g4;
-      const bool gv = gg < n8;
-      bf16x8 bO[2][PIECES], bE[2][PIECES];
 #pragma unroll
-      for (int pc = 0; pc < PIECES; ++pc)
+    for (int ii = 0; ii < (NIA + NIB + NW - 1) / NW; ++ii) {
+      const int in = wv + ii * NW;
+      if (in >= NIA + NIB) break;
+      int arr, pc, grp, col;
+      u4v* dst;
+      if (in < NIA) {
+        grp = in % BP_KG;
+        pc = (in / BP_KG) % PIECES;
+        arr = in / (BP_KG * PIECES);
+        col = acol;
+        dst = &L[buf].A[arr][pc][grp][0];
+      } else {
+        const int ib = in - NIA;
+        const int half = ib & 1;
+        grp = (ib >> 1) % BP_KG;
+        pc = ((ib >> 1) / BP_KG) % PIECES;
+        arr = (ib >> 1) / (BP_KG * PIECES);
+        col = half ? bcol1 : bcol0;
+        dst = &L[buf].B[arr][pc][grp][GT * half];
+      }
+      const int64_t gg = min(grp0 + grp, n8 - 1);
+      const BLM_GLOBAL uint16_t* base = arr ? E : O;
+      lds_dma16(base + (int64_t)pc * S.pstride + (gg * S.ld + col) * 8, dst);
+    }
+  };
+  auto compute = [&](int buf, int64_t n8_left) {
+    // groups at or past the slice's end contribute nothing (A side zeroed by
+    // a lane mask, without branches)
+    const unsigned km = (k4 < n8_left) ? 0xFFFFFFFFu : 0u;
+    const unsigned kme = third ? km : 0u;
+    const BpLds<PIECES>& Lb = L[buf];
+    bf16x8 bO[2][PIECES], bE[2][PIECES];
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          const int64_t o = (size_t)pc * S.pstride + (gg * S.ld + J.cj + cb[y]) * 8;
-          bO[y][pc] = load_frag(O + o, gv && vb[y]);
-          bE[y][pc] = load_frag(E + o, gv && vb[y]);
-        }
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int pa = 0; pa < PIECES; ++pa) {
-        bf16x8 aO[2], aE[2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          const int64_t o = (size_t)pa * S.pstride + (gg * S.ld + J.ci + ca[x]) * 8;
-          aO[x] = load_frag(O + o, gv && va[x]);
-          aE[x] = load_frag(E + o, gv && va[x] && off);
-        }
-#pragma unroll
-        for (int pb = 0; pb + pa < PIECES; ++pb)
-#pragma unroll
-          for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y) {
-              acc[0][x][y] = mfma_bf16(aO[x], bO[y][pb], acc[0][x][y]);
-              acc[1][x][y] = mfma_bf16(aO[x], bE[y][pb], acc[1][x][y]);
-              if (off) acc[2][x][y] = mfma_bf16(aE[x], bO[y][pb], acc[2][x][y]);
-            }
+      for (int pc = 0; pc < PIECES; ++pc) {
+        const int col = 32 * wc + 16 * y + i16;
+        bO[y][pc] = __builtin_bit_cast(bf16x8, Lb.B[0][pc][k4][col]);
+        bE[y][pc] = __builtin_bit_cast(bf16x8, Lb.B[1][pc][k4][col]);
       }
 #pragma unroll
-      for (int t = 0; t < 3; ++t)
+    for (int pa = 0; pa < PIECES; ++pa) {
+      bf16x8 aO[2], aE[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int row = 32 * wr + 16 * x + i16;
+        aO[x] = __builtin_bit_cast(bf16x8, Lb.A[0][pa][k4][row] & km);
+        aE[x] = __builtin_bit_cast(bf16x8, Lb.A[1][pa][k4][row] & kme);
+      }
+#pragma unroll
+      for (int pb = 0; pb + pa < PIECES; ++pb)
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-              a64[t][x][y][rr] += (double)acc[t][x][y][rr];
-              acc[t][x][y][rr] = 0.f;
-            }
+          for (int y = 0; y < 2; ++y) {
+            acc[0][x][y] = mfma_bf16(aO[x], bO[y][pb], acc[0][x][y]);
+            acc[1][x][y] = mfma_bf16(aO[x], bE[y][pb], acc[1][x][y]);
+            if (third) acc[2][x][y] = mfma_bf16(aE[x], bO[y][pb], acc[2][x][y]);
+          }
     }
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            a64[t][x][y][rr] += (double)acc[t][x][y][rr];
+            acc[t][x][y][rr] = 0.f;
+          }
+  };
+
+  // number of steps of this workgroup
+  int n_steps = 0;
+  for (int sl = p; sl < n_slices; sl += P) n_steps += (int)((slices[sl].n + BP_STEP - 1) / BP_STEP);
+
+  int si = p;                 // cursor: slice and first group of the next step to copy
+  while (si < n_slices && slices[si].n <= 0) si += P;
+  int64_t g0 = 0;
+  auto advance = [&]() {
+    g0 += BP_KG;
+    if (g0 * 8 >= slices[si].n) {
+      g0 = 0;
+      si += P;
+      while (si < n_slices && slices[si].n <= 0) si += P;
+    }
+  };
+  int csi = si;               // slice and first group of the step in LDS
+  int64_t cg0 = 0;
+  if (n_steps > 0) {
+    issue(si, g0, 0);
+    advance();
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int buf = 0;
+  for (int t = 0; t < n_steps; ++t) {
+    const bool more = t + 1 < n_steps;
+    const int64_t n8_left = ((slices[csi].n + 7) >> 3) - cg0;
+    const int nsi = si;
+    const int64_t ng0 = g0;
+    if (more) issue(si, g0, buf ^ 1);
+    if (wave_on) compute(buf, n8_left);
+    if (more) advance();
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's copies of the next step have landed
+    __syncthreads();                 // ... and everyone's; the current buffer is free
+    buf ^= 1;
+    csi = nsi;
+    cg0 = ng0;
   }
 
-  BLM_GLOBAL double* base = as_global(partial) + ((size_t)jid * P + p) * (size_t)(3 * GT * GT);
+  if (!wave_on) return;
+  const int jw = wave_b ? PJ.jb : PJ.ja;
+  BLM_GLOBAL double* base = as_global(partial) + ((size_t)jw * P + p) * (size_t)(3 * GT * GT);
+  const int c0 = 32 * (wc & 1);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -146,22 +251,23 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_bf16_kernel(const GramJob* _
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
         const int row = 32 * wr + 16 * x + bf16_d_row(lane, rr);
-        const int col = 32 * wc + 16 * y + i16;
+        const int col = c0 + 16 * y + i16;
         base[row * GT + col] = a64[0][x][y][rr];
         base[GT * GT + row * GT + col] = a64[1][x][y][rr];
-        if (off) base[2 * GT * GT + row * GT + col] = a64[2][x][y][rr];
+        if (third) base[2 * GT * GT + row * GT + col] = a64[2][x][y][rr];
       }
 }
 
-void launch_gram_bf16(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                      int pieces, double* d_partial, hipStream_t st) {
-  if (n_jobs <= 0) return;
+void launch_gram_bf16(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
+                      const Slice* d_slices, int n_slices, int P, int pieces, double* d_partial,
+                      hipStream_t st) {
+  if (n_pairs <= 0) return;
   if (pieces == 3)
-    hipLaunchKernelGGL(gram_bf16_kernel<3>, dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs, n_jobs,
-                       d_slices, n_slices, P, d_partial);
+    hipLaunchKernelGGL(gram_bf16_kernel<3>, dim3(n_pairs * P), dim3(BP_THREADS), 0, st, d_pairs,
+                       n_pairs, d_jobs, d_slices, n_slices, P, d_partial);
   else
-    hipLaunchKernelGGL(gram_bf16_kernel<2>, dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs, n_jobs,
-                       d_slices, n_slices, P, d_partial);
+    hipLaunchKernelGGL(gram_bf16_kernel<2>, dim3(n_pairs * P), dim3(BP_THREADS), 0, st, d_pairs,
+                       n_pairs, d_jobs, d_slices, n_slices, P, d_partial);
 }
 
 // ---------------------------------------------------------------------------

@@ -50,6 +50,11 @@ struct GramJob {
   int64_t strip_col;    // JOB_DIAG: global parameter column of the strip's first column
 };
 
+// Two tile jobs of the BF16 build that share their row tile (jb < 0: none).
+struct PairJob {
+  int32_t ja, jb;
+};
+
 // Sample storage: FP64 sample-major ([n][ld]), or BF16 split pieces in the
 // k-packed layout: element (s, x) of piece p at base + p * pstride +
 // ((s / 8) * ld + x) * 8 + s % 8, so that 8 consecutive samples of one
@@ -137,8 +142,9 @@ constexpr int EIG_MAXSEL = 16;   // eigenvalues selected per problem (N_K + 1 <=
 // launchers (blm_kernels.hip / blm_eig.hip)
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
                  bool vec, bool split, double* d_partial, hipStream_t st);
-void launch_gram_bf16(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                      int pieces, double* d_partial, hipStream_t st);
+void launch_gram_bf16(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
+                      const Slice* d_slices, int n_slices, int P, int pieces, double* d_partial,
+                      hipStream_t st);
 void launch_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncols, int pieces,
                       uint16_t* dst, int64_t ld_dst, int64_t pstride, hipStream_t st);
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
