@@ -190,9 +190,11 @@ blm_status blm_set_timing(blm_ctx* ctx, int32_t enable);
 blm_status blm_get_timings(blm_ctx* ctx, double* h_ms, int32_t n);
 
 /* Statistics of the last blm_solve_blocks, 16 int32 per pencil in the order
- * [shift][block]: status, kept rows, pair flag, QR sweeps, then 100 MHz
+ * [shift][block]: status, kept rows, pair flag, QR iterations, then 100 MHz
  * clock ticks of the solver phases (Cholesky, congruence, Hessenberg,
- * QR, selection, inverse iteration, back-transform, orthonormalisation). */
+ * QR, selection, inverse iteration, back-transform, orthonormalisation),
+ * then ticks spent in early deflation and in bulge chases, and the number
+ * of early deflations and of bulge chases. */
 blm_status blm_get_solver_stats(blm_ctx* ctx, int32_t* h_stats, int32_t n);
 
 const char* blm_last_error(const blm_ctx* ctx);

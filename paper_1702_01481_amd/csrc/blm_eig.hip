@@ -62,6 +62,9 @@ struct Shared {
   double swr[32], swi[32], sre[32];
   double bsum[16], bprod[16];
   double bx[16][3];
+  // QR statistics: 100 MHz ticks in early deflation and in bulge chases,
+  // number of early deflations and of chases
+  unsigned long long qst[4];
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -546,10 +549,13 @@ __device__ double wave_rehess(double (*T)[AEDLD], double (*Z)[AEDLD], double* u,
 constexpr int MAX_BULGES = 16;
 constexpr int AED_MIN_W = 75;   // active blocks at least this wide use early deflation
 constexpr int AED_NIBBLE = 14;  // percent of the window deflated to skip a sweep
+constexpr int CU = 4;           // chase: elements per thread whose loads go out together
 
 template <bool MULTI, class Real>
 __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* iters) {
   const int tid = threadIdx.x;
+  if (MULTI && tid == 0)
+    for (int i = 0; i < 4; ++i) sh.qst[i] = 0;
   auto at = [&](int i, int j) -> double& { return A[(size_t)i * ld + j]; };
   double part = 0.0;
   for (int i = tid; i < d; i += NT)
@@ -612,9 +618,11 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
     const int w = h - l + 1;
     int m = 1;
     bool shifts_set = false;
+    const uint64_t t_aed = wall_clock64();
     if (MULTI && w >= AED_MIN_W && its % 10 != 0) {
+      if (tid == 0) sh.qst[2] += 1;
       // aggressive early deflation on the trailing window
-      const int ns = w < 150 ? 10 : w < 300 ? 16 : 2 * MAX_BULGES;
+      const int ns = w < 150 ? 10 : w < 300 ? 16 : 24;
       const int nw = min(AEDMAX, ns);
       const int kwtop = h - nw + 1;
       const double spike = at(kwtop, kwtop - 1);
@@ -668,8 +676,14 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
           its = 0;
         }
         // skip the sweep when the window deflated enough
-        if (nd > 0 && 100 * nd > AED_NIBBLE * nw) continue;
-        if (h - l + 1 < 3) continue;
+        if (nd > 0 && 100 * nd > AED_NIBBLE * nw) {
+          if (MULTI && tid == 0) sh.qst[0] += wall_clock64() - t_aed;
+          continue;
+        }
+        if (h - l + 1 < 3) {
+          if (MULTI && tid == 0) sh.qst[0] += wall_clock64() - t_aed;
+          continue;
+        }
         if (tid == 0) {
           // shifts: the window's bottom-most unconverged eigenvalues
           int mm = 0, i = nu - 1;
@@ -757,6 +771,11 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
     }
     __syncthreads();
 
+    const uint64_t t_chase = wall_clock64();
+    if (MULTI && tid == 0) {
+      sh.qst[0] += t_chase - t_aed;
+      sh.qst[3] += 1;
+    }
     // chase: group g of G threads carries bulge g
     const int mp = m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16;
     const int G = NT / mp, grp = tid / G, lt = tid % G;
@@ -798,17 +817,32 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
       // own group rewrites below: let every wave finish reading first
       if ((t & 3) == 0 && (t >> 2) < m) __syncthreads();
       if (act && refl) {
-        // rows K+1..K+nr, columns max(l, K+1)..h; the bulge column K is set directly
+        // rows K+1..K+nr, columns max(l, K+1)..h; the bulge column K is set
+        // directly.  CU columns per thread per pass: their loads are issued
+        // together (indices clamped into the row), the stores guarded.
         const int c0 = (K >= l) ? K + 1 : l;
-        for (int c = c0 + lt; c <= h; c += G) {
-          Real* p1 = A + (size_t)(K + 1) * ld + c;
-          Real* p2 = p1 + ld;
-          double tt = v0 * p1[0] + v1 * p2[0];
-          if (nr == 3) tt += v2 * p2[ld];
-          tt *= bt;
-          p1[0] -= tt * v0;
-          p2[0] -= tt * v1;
-          if (nr == 3) p2[ld] -= tt * v2;
+        Real* r1p = A + (size_t)(K + 1) * ld;
+        Real* r2p = r1p + ld;
+        Real* r3p = r2p + ld;
+        for (int cb = c0 + lt; cb <= h; cb += G * CU) {
+          double x0[CU], x1[CU], x2[CU];
+#pragma unroll
+          for (int u = 0; u < CU; ++u) {
+            const int c = min(cb + G * u, h);
+            x0[u] = r1p[c];
+            x1[u] = r2p[c];
+            x2[u] = (nr == 3) ? r3p[c] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < CU; ++u) {
+            const int c = cb + G * u;
+            if (c <= h) {
+              const double tt = bt * (v0 * x0[u] + v1 * x1[u] + v2 * x2[u]);
+              r1p[c] = x0[u] - tt * v0;
+              r2p[c] = x1[u] - tt * v1;
+              if (nr == 3) r3p[c] = x2[u] - tt * v2;
+            }
+          }
         }
         if (K >= l && lt == 0) {
           at(K + 1, K) = newsub;
@@ -821,23 +855,37 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
         // columns K+1..K+nr, rows l..min(K+4, h); keep column K+1's entries
         // below the diagonal (the next bulge) for the next tick
         const int r1 = (K + 4 < h) ? K + 4 : h;
-        for (int rr = l + lt; rr <= r1; rr += G) {
-          Real* q = A + (size_t)rr * ld + K + 1;
-          if (refl) {
-            double tt = q[0] * v0 + q[1] * v1;
-            if (nr == 3) tt += q[2] * v2;
-            tt *= bt;
-            q[0] -= tt * v0;
-            q[1] -= tt * v1;
-            if (nr == 3) q[2] -= tt * v2;
+        for (int rb = l + lt; rb <= r1; rb += G * CU) {
+          double y0[CU], y1[CU], y2[CU];
+#pragma unroll
+          for (int u = 0; u < CU; ++u) {
+            const Real* q = A + (size_t)min(rb + G * u, r1) * ld + K + 1;
+            y0[u] = q[0];
+            y1[u] = q[1];
+            y2[u] = (nr == 3) ? q[2] : 0.0;
           }
-          if (rr >= K + 2) sh.bx[grp][rr - K - 2] = q[0];
+#pragma unroll
+          for (int u = 0; u < CU; ++u) {
+            const int rr = rb + G * u;
+            if (rr > r1) continue;
+            Real* q = A + (size_t)rr * ld + K + 1;
+            double n0 = y0[u];
+            if (refl) {
+              const double tt = bt * (y0[u] * v0 + y1[u] * v1 + y2[u] * v2);
+              n0 = y0[u] - tt * v0;
+              q[0] = n0;
+              q[1] = y1[u] - tt * v1;
+              if (nr == 3) q[2] = y2[u] - tt * v2;
+            }
+            if (rr >= K + 2) sh.bx[grp][rr - K - 2] = n0;
+          }
         }
         if (K + 4 > h && lt == 0) sh.bx[grp][2] = 0.0;
         if (K + 3 > h && lt == 0) sh.bx[grp][1] = 0.0;
       }
       __syncthreads();
     }
+    if (MULTI && tid == 0) sh.qst[1] += wall_clock64() - t_chase;
   }
   *iters = total;
   for (int i = tid; i < d; i += NT)
@@ -1162,7 +1210,10 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
   st = hqr<true>(sh, J.A, d, d, J.wr, J.wi, &iters);
   __syncthreads();
   phase_mark(J, clk, 3);
-  if (tid == 0) J.info[3] = iters;
+  if (tid == 0) {
+    J.info[3] = iters;
+    for (int i = 0; i < 4; ++i) J.info[12 + i] = (int32_t)sh.qst[i];
+  }
   if (st == EIG_OK && sh.isc[2]) st = EIG_NONFINITE;
   if (st != EIG_OK) {
     if (tid == 0) J.info[0] = st;

@@ -121,9 +121,11 @@ struct EigJob {
   double* out;          // EIG_BLOCK: [n_want + 1][nbeta] rows; EIG_STAGE2: [2][d] (re, im)
   double* out_evals;    // [n_want + 1][2] the used eigenvalues in rank order
   int32_t* info;        // [EIG_INFO]: [0] status, [1] rows/vectors produced, [2] flags,
-                        // [3] QR sweeps, [4..11] 100 MHz ticks per phase (Cholesky,
+                        // [3] QR iterations, [4..11] 100 MHz ticks per phase (Cholesky,
                         // congruence, Hessenberg, QR, selection, inverse iteration,
-                        // back-transform, orthonormalisation)
+                        // back-transform, orthonormalisation), [12] ticks in early
+                        // deflation, [13] ticks in bulge chases, [14] early
+                        // deflations, [15] chases
 };
 
 constexpr int EIG_INFO = 16;
