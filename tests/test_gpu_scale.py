@@ -1,0 +1,214 @@
+"""Parity at the full size of the 4,096-parameter x 1,000,000-sample workload.
+
+The step is the one the benchmark times (8 blocks of 512, N_K = 5, one
+previous direction, shifts 1e-4, 1e-3, 1e-2), in the same launch
+configuration.  The oracle cannot form every block matrix of this size in a
+test's time, so it checks sampled outputs it can compute one by one, from
+the same sample bytes (streamed chunk by chunk to the host):
+
+* entries of S_b and H_b (Eq. 3 on the Eq. 10 basis) of one block: the
+  wave-function row and column, parameter columns, and the Theta column of
+  one other block, against the whole 1,000,000-sample sums;
+* the kept directions of that block, from the oracle's own shifted solve
+  (Eq. 5, Eq. 6) of those (checked) matrices;
+* the stage-two entries (Eq. 7) that involve the wave function and that
+  block's directions;
+* the energy and the update (Eq. 7, Eq. 8) from the oracle's stage-two solve
+  of the stage-two matrices.
+
+Tolerances are the FP64 ones: entries within 1e-12 of the matrix's
+Frobenius norm, energies within 1e-10 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import blm_oracle as orc
+from paper_1702_01481_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CHECK_BLOCK = 2      # block whose matrices, directions and stage-two rows are checked
+THETA_BLOCK = 5      # other block whose Theta column is checked
+SHIFT = 1            # shift index (1e-3)
+
+
+def _step(ctx, chunks, old):
+    ctx.begin_step(old)
+    ctx.build(chunks)
+    ev, kept = ctx.solve()
+    ctx.project(chunks)
+    upd, en, al, fl = ctx.stage2()
+    torch.cuda.synchronize()
+    return upd, en
+
+
+@pytest.fixture(scope="module")
+def workload():
+    w = synth.workload("fp64")
+    gen = synth.SampleGenerator(w.n_params, w.rank, w.seed, sigma_E=w.sigma_E, device="cuda")
+    chunks, left, i = [], w.n_samples, 0
+    while left > 0:
+        n = min(w.chunk, left)
+        chunks.append(gen.chunk(i, n))
+        left -= n
+        i += 1
+    del gen
+    torch.cuda.synchronize()
+    print(f"[scale] {len(chunks)} chunks of {w.n_params} parameters on the device", flush=True)
+    state = {"w": w, "chunks": chunks}
+    yield state
+    state.clear()
+    torch.cuda.empty_cache()
+
+
+def _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th):
+    """Whole-sample sums for the sampled basis indices [0, pcols, th] of
+    block b and the stage-two rows [Psi, B^(b)], streamed chunk by chunk."""
+    nidx = 2 + len(pcols)
+    nb = Bb.shape[0]
+    sS = np.zeros((nidx, nidx))
+    sH = np.zeros((nidx, nidx))
+    s2S = np.zeros((1 + nb, 1 + nb))
+    s2H = np.zeros((1 + nb, 1 + nb))
+    N = 0
+    cb = slice(int(offsets[b]), int(offsets[b + 1]))
+    ck = slice(int(offsets[k]), int(offsets[k + 1]))
+    for O, e, EL in chunks:
+        Ob = O[:, cb].cpu().numpy()
+        eb = e[:, cb].cpu().numpy()
+        Ok = O[:, ck].cpu().numpy()
+        ek = e[:, ck].cpu().numpy()
+        el = EL.cpu().numpy()
+        n = Ob.shape[0]
+        ones = np.ones(n)
+        t = Ok @ D[k][0]
+        u = ek @ D[k][0]
+        X = np.column_stack([ones] + [Ob[:, c - 1] for c in pcols] + [t])
+        Y = np.column_stack([el] + [eb[:, c - 1] for c in pcols] + [u])
+        sS += X.T @ X
+        sH += X.T @ Y
+        y2 = np.column_stack([ones, Ob @ Bb.T])
+        z2 = np.column_stack([el, eb @ Bb.T])
+        s2S += y2.T @ y2
+        s2H += y2.T @ z2
+        N += n
+    return sS / N, sH / N, s2S / N, s2H / N
+
+
+def test_full_size_sampled_parity(workload):
+    from paper_1702_01481_amd import blm
+    w, chunks = workload["w"], workload["chunks"]
+    offsets = np.asarray(w.block_offsets)
+    shifts = list(w.shifts)
+
+    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.n_samples)
+    upd0, _ = _step(ctx, chunks, torch.zeros(w.n_old, w.n_params, dtype=torch.float64, device="cuda"))
+    old = upd0[1:2].cpu().numpy().copy()
+    upd, en = _step(ctx, chunks, torch.from_numpy(old).cuda().contiguous())
+    workload["old"] = old
+    workload["energy"] = [float(x) for x in en]
+    workload["update"] = upd.cpu().numpy().copy()
+    print("[scale] GPU steps done", flush=True)
+
+    b, k, si = CHECK_BLOCK, THETA_BLOCK, SHIFT
+    delta = shifts[si]
+    M = int(offsets[b + 1] - offsets[b])
+    H_gpu, S_gpu = ctx.block_matrices(b, si)
+    d = H_gpu.shape[0]
+    others = [kk for kk in range(len(offsets) - 1) if kk != b]
+    th = 1 + M + others.index(k)                       # Theta column of block k (N_O = 1)
+    D = orc.previous_directions(old, offsets)
+    assert D[k].shape[0] == 1
+    Bs = [ctx.directions(bb, si) for bb in range(len(offsets) - 1)]
+    Bb = Bs[b]
+    ob = 1 + sum(B.shape[0] for B in Bs[:b])          # first stage-two row of block b
+    nb = Bb.shape[0]
+
+    rng = np.random.default_rng(11)
+    pcols = np.sort(rng.choice(M, 6, replace=False)) + 1
+    idx = np.concatenate([[0], pcols, [th]])          # basis indices checked
+    sS, sH, s2S, s2H = _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th)
+    print("[scale] oracle sums done", flush=True)
+
+    # block matrices: sampled entries against the whole-sample sums
+    P = np.zeros((d, d))
+    P[1:, 1:] = np.eye(d - 1)                          # Theta rows orthonormal, one per block
+    H_un = H_gpu - delta * P
+    nS, nH = np.linalg.norm(S_gpu), np.linalg.norm(H_un)
+    gS = S_gpu[np.ix_(idx, idx)]
+    gH = H_un[np.ix_(idx, idx)]
+    assert np.abs(gS - sS).max() <= 1e-12 * nS, np.abs(gS - sS).max() / nS
+    assert np.abs(gH - sH).max() <= 1e-12 * nH, np.abs(gH - sH).max() / nH
+
+    # kept directions of the block from the oracle's solve of these matrices
+    theta = [(kk, 0) for kk in others]
+    res = orc.solve_block(orc.BlockProblem(H_un, S_gpu, P, M, theta), delta, w.n_keep)
+    assert res.B.shape == Bb.shape, (res.B.shape, Bb.shape)
+    np.testing.assert_allclose(Bb @ Bb.T, np.eye(nb), atol=1e-12)
+    assert np.abs(Bb.T @ Bb - res.B.T @ res.B).max() < 1e-8
+
+    # stage-two rows of the wave function and of block b
+    H2, S2 = ctx.stage2_matrices(si)
+    rows = np.concatenate([[0], np.arange(ob, ob + nb)])
+    g2S = S2[np.ix_(rows, rows)]
+    g2H = H2[np.ix_(rows, rows)]
+    assert np.abs(g2S - s2S).max() <= 1e-12 * np.linalg.norm(S2)
+    assert np.abs(g2H - s2H).max() <= 1e-12 * np.linalg.norm(H2)
+
+    # energy and update from the stage-two pencil
+    st = orc.stage2_solve(H2, S2, Bs, offsets, delta)
+    assert abs(en[si] - st.energy) <= 1e-10 * abs(st.energy), (en[si], st.energy)
+    u_gpu = upd[si].cpu().numpy()
+    cos = u_gpu @ st.dmu / (np.linalg.norm(u_gpu) * np.linalg.norm(st.dmu))
+    assert cos > 1 - 1e-10, cos
+    print(f"[scale] energy {en[si]:.12f} vs oracle {st.energy:.12f}, update cosine {cos:.15f}", flush=True)
+    ctx.close()
+
+
+def test_full_size_mixed_precision(workload):
+    """The same step with the sample contractions on BF16 hi/mid/lo pieces:
+    sampled block-matrix entries against the oracle's FP64 sums (the pieces
+    keep 24 significant bits: within 1e-7 of the Frobenius norm), and the
+    energy and update against the FP64 step checked above (energy within
+    1e-6 relative, update cosine above 1 - 1e-6)."""
+    from paper_1702_01481_amd import blm
+    if "old" not in workload:
+        pytest.skip("needs the FP64 full-size step")
+    w, chunks, old = workload["w"], workload["chunks"], workload["old"]
+    offsets = np.asarray(w.block_offsets)
+    shifts = list(w.shifts)
+    split = [(blm.SplitSamples(O, 3), blm.SplitSamples(e, 3), EL) for O, e, EL in chunks]
+    torch.cuda.synchronize()
+    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.n_samples, precision="bf16x3")
+    upd, en = _step(ctx, split, torch.from_numpy(old).cuda().contiguous())
+    b, k, si = CHECK_BLOCK, THETA_BLOCK, SHIFT
+    delta = shifts[si]
+    M = int(offsets[b + 1] - offsets[b])
+    H_gpu, S_gpu = ctx.block_matrices(b, si)
+    d = H_gpu.shape[0]
+    others = [kk for kk in range(len(offsets) - 1) if kk != b]
+    th = 1 + M + others.index(k)
+    D = orc.previous_directions(old, offsets)
+    Bb = ctx.directions(b, si)
+    rng = np.random.default_rng(12)
+    pcols = np.sort(rng.choice(M, 6, replace=False)) + 1
+    idx = np.concatenate([[0], pcols, [th]])
+    sS, sH, _, _ = _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th)
+    P = np.zeros((d, d))
+    P[1:, 1:] = np.eye(d - 1)
+    H_un = H_gpu - delta * P
+    eS = np.abs(S_gpu[np.ix_(idx, idx)] - sS).max() / np.linalg.norm(S_gpu)
+    eH = np.abs(H_un[np.ix_(idx, idx)] - sH).max() / np.linalg.norm(H_un)
+    print(f"[scale] mixed entries: S {eS:.2e}, H {eH:.2e} of the Frobenius norm", flush=True)
+    assert eS <= 1e-7 and eH <= 1e-7, (eS, eH)
+    for s_i in range(len(shifts)):
+        e64 = workload["energy"][s_i]
+        rel = abs(en[s_i] - e64) / abs(e64)
+        u64 = workload["update"][s_i]
+        um = upd[s_i].cpu().numpy()
+        cos = um @ u64 / (np.linalg.norm(um) * np.linalg.norm(u64))
+        print(f"[scale] shift {shifts[s_i]}: energy rel err {rel:.2e}, update cosine {cos:.12f}", flush=True)
+        assert rel <= 1e-6, (s_i, rel)
+        assert cos >= 1 - 1e-6, (s_i, cos)
+    ctx.close()
