@@ -23,10 +23,11 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4b __attribute__((ext_vector_type(4)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
-// FP32 accumulators are added into FP64 after every 32-sample step: each
-// FP32 partial then holds one step's sum, which keeps the block estimates
-// within about 2e-8 of FP64 (flushing every 256 samples gave 6e-8, and the
-// block eigenvectors amplify that into 2e-6 of the energy).
+// FP32 accumulators are added into FP64 every few 32-sample steps, so that
+// each FP32 partial holds only a few steps' sums: flushing every 256 samples
+// gave block estimates within 6e-8 of FP64, and the block eigenvectors
+// amplified that into 2e-6 of the energy; every 32 samples gave 2e-8 and
+// 5.5e-8.
 
 __device__ __forceinline__ f4 mfma_bf16(const bf16x8& a, const bf16x8& b, f4 c) {
   // D[i][j] += sum_k A[i][k] B[k][j], 16x16x32; lane l supplies
@@ -60,6 +61,10 @@ constexpr int BP_COLS = 2 * GT;                  // B-side columns of a pair
 constexpr int BP_STEP = 32;                      // samples per step (one k-depth)
 constexpr int BP_KG = BP_STEP / 8;               // 8-sample groups per step
 constexpr int BP_THREADS = 512;
+// FP32 accumulators are added into FP64 every BP_FLUSH steps (64 samples):
+// each FP32 partial then holds 12 matrix-core results (6 piece products of
+// 2 steps), within about 1e-7 of its FP64 sum.
+constexpr int BP_FLUSH = 2;
 
 template <int PIECES>
 struct BpLds {
@@ -153,11 +158,11 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
       lds_dma16(base + (int64_t)pc * S.pstride + (gg * S.ld + col) * 8, dst);
     }
   };
-  auto compute = [&](int buf, int64_t n8_left) {
-    // groups at or past the slice's end contribute nothing (A side zeroed by
-    // a lane mask, without branches)
+  auto compute = [&](int buf, int64_t n8_left, bool flush) {
+    // groups at or past the slice's end contribute nothing: on the last step
+    // of a slice the A side is zeroed by a lane mask
+    const bool partial = n8_left < BP_KG;
     const unsigned km = (k4 < n8_left) ? 0xFFFFFFFFu : 0u;
-    const unsigned kme = third ? km : 0u;
     const BpLds<PIECES>& Lb = L[buf];
     bf16x8 bO[2][PIECES], bE[2][PIECES];
 #pragma unroll
@@ -174,8 +179,14 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
         const int row = 32 * wr + 16 * x + i16;
-        aO[x] = __builtin_bit_cast(bf16x8, Lb.A[0][pa][k4][row] & km);
-        aE[x] = __builtin_bit_cast(bf16x8, Lb.A[1][pa][k4][row] & kme);
+        u4v vo = Lb.A[0][pa][k4][row];
+        u4v ve = Lb.A[1][pa][k4][row];
+        if (partial) {
+          vo &= km;
+          ve &= km;
+        }
+        aO[x] = __builtin_bit_cast(bf16x8, vo);
+        aE[x] = __builtin_bit_cast(bf16x8, ve);
       }
 #pragma unroll
       for (int pb = 0; pb + pa < PIECES; ++pb)
@@ -188,6 +199,7 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
             if (third) acc[2][x][y] = mfma_bf16(aE[x], bO[y][pb], acc[2][x][y]);
           }
     }
+    if (!flush) return;
 #pragma unroll
     for (int t = 0; t < 3; ++t)
 #pragma unroll
@@ -231,7 +243,7 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
     const int nsi = si;
     const int64_t ng0 = g0;
     if (more) issue(si, g0, buf ^ 1);
-    if (wave_on) compute(buf, n8_left);
+    if (wave_on) compute(buf, n8_left, ((t + 1) % BP_FLUSH) == 0 || !more);
     if (more) advance();
     __builtin_amdgcn_s_waitcnt(0);   // this wave's copies of the next step have landed
     __syncthreads();                 // ... and everyone's; the current buffer is free

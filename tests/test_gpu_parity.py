@@ -135,6 +135,17 @@ def test_multi_tile_blocks():
     _compare_step(offsets, 4, [1e-3], host, dev, old=old, n_old=1)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_aligned_full_tiles(weighted):
+    """Blocks of whole 64-wide tiles with an even leading dimension (the
+    direct-to-LDS path of the build), weights, one previous direction, and
+    chunks whose tails leave partial 16-sample stages."""
+    offsets = [0, 128, 256, 384]
+    host, dev = _make(384, 20007, 8, 6, 6151, weighted=weighted)
+    old = synth.old_directions(1, 384, 4).numpy()
+    _compare_step(offsets, 4, [1e-4, 1e-2], host, dev, old=old, n_old=1)
+
+
 def test_dyadic_inputs_are_bit_exact():
     """Small-integer samples: every partial sum is exact, so the block
     matrices must equal the oracle's bit for bit (N_s a power of two)."""
