@@ -84,6 +84,8 @@ struct blm_ctx {
   int n_jobsM = 0;
   PairJob* d_pairsM = nullptr;   // BF16 build: pairs of main jobs sharing a row tile
   int n_pairsM = 0;
+  uint16_t* auxP = nullptr;      // BF16 build: aux columns as BF16 pieces (k-packed, ld 16)
+  int64_t aux_pstride = 0;       // elements between pieces of auxP (Xa pieces, then Ya pieces)
   int pieces = 0;                  // 0: FP64 path; 2 or 3: BF16 split pieces used
   Slice* d_slices = nullptr;
   ProjChunk* d_pchunks = nullptr;
@@ -316,10 +318,12 @@ void plan(blm_ctx* c, Plan& P) {
   run += NAUX * NAUX;
   c->acc_elems = run;
   c->n_jobs1 = n_jobs1 + 1;
-  int n_diag = 0;
-  for (int b = 0; b < NB; ++b) n_diag += (int)((c->off[b + 1] - c->off[b] + GT - 1) / GT);
   c->n_jobsM = c->pieces ? n_jobs1 : 0;
-  if (c->pieces) c->n_jobs1 = n_diag + 1;
+  // mixed precision: the strips ride on the BF16 diagonal jobs; only the aux
+  // Gram stays on the FP64 kernel
+  if (c->pieces) c->n_jobs1 = 1;
+  const int64_t aux_groups = c->max_samples / 8 + MAX_CHUNKS;
+  c->aux_pstride = c->pieces ? aux_groups * NAUX * 8 : 0;
   c->n2max = 1 + NS * NB * (NK + 1);
   c->d2max = 1 + NB * (NK + 1);
   const int T2 = (c->n2max + GT - 1) / GT;
@@ -346,6 +350,7 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_jobs2, sizeof(GramJob) * (size_t)n_jobs2max);
   add((void**)&c->d_jobsM, sizeof(GramJob) * (size_t)std::max(c->n_jobsM, 1));
   add((void**)&c->d_pairsM, sizeof(PairJob) * (size_t)std::max(c->n_jobsM, 1));
+  add((void**)&c->auxP, 2 * 2 * (size_t)c->pieces * c->aux_pstride);
   add((void**)&c->d_slices, sizeof(Slice) * (size_t)c->max_slices);
   add((void**)&c->d_pchunks, sizeof(ProjChunk) * (size_t)MAX_CHUNKS);
   add((void**)&c->d_theta_blk, sizeof(DirBlock) * (size_t)NB);
@@ -430,19 +435,8 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
         J.ht_off = c->acc_off[b] + (int64_t)GT * tj * M + (int64_t)GT * ti;
         J.ld_out = M;
         J.strip_col = J.ci;
-        if (!c->pieces) {
-          jobs.push_back(J);
-        } else {
-          // main products on the BF16 matrix cores, strips in FP64
-          GramJob Mj = J;
-          if (ti == tj) Mj.kind = JOB_DIAG_NOSTRIP;
-          main.push_back(Mj);
-          if (ti == tj) {
-            GramJob Sj = J;
-            Sj.kind = JOB_STRIP;
-            jobs.push_back(Sj);
-          }
-        }
+        if (!c->pieces) jobs.push_back(J);
+        else main.push_back(J);   // all products, strips included, on the BF16 matrix cores
       }
   }
   GramJob A{};
@@ -806,10 +800,19 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
                   c->Xa, c->Ya, NAUX);
   if (s != BLM_OK) return s;
   c->h_slices.clear();
-  int64_t rb = 0;
+  int64_t rb = 0, gbase = 0;
   for (int i = 0; i < n; ++i) {
     const int64_t ns = ch[i].n_samples;
     if (ns == 0) continue;
+    if (c->pieces) {
+      // this chunk's aux columns as BF16 pieces, from an 8-sample group boundary
+      uint16_t* xp = c->auxP + gbase * NAUX * 8;
+      launch_pack_bf16(c->Xa + (size_t)rb * NAUX, ns, NAUX, NAUX, c->pieces, xp, NAUX, c->aux_pstride,
+                       c->st);
+      launch_pack_bf16(c->Ya + (size_t)rb * NAUX, ns, NAUX, NAUX, c->pieces,
+                       xp + (size_t)c->pieces * c->aux_pstride, NAUX, c->aux_pstride, c->st);
+      HIPCHK(c, hipGetLastError());
+    }
     for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
       Slice S{};
       if (c->pieces) {
@@ -824,16 +827,22 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
       }
       S.Xa = c->Xa + (size_t)(rb + s0) * NAUX;
       S.Ya = c->Ya + (size_t)(rb + s0) * NAUX;
+      if (c->pieces) {
+        S.Xp = c->auxP + (size_t)(gbase + s0 / 8) * NAUX * 8;
+        S.Yp = S.Xp + (size_t)c->pieces * c->aux_pstride;
+        S.apstride = c->aux_pstride;
+      }
       S.w = ch[i].w ? ch[i].w + s0 : nullptr;
       S.ld = ch[i].ld;
       S.n = std::min<int64_t>(SLICE, ns - s0);
       c->h_slices.push_back(S);
     }
     rb += ns;
+    gbase += (ns + 7) / 8;
   }
   mark(c, 0, true);
   if (c->pieces) {
-    // FP64 strips and aux Gram (timed as the reduction phase), then the BF16 main products
+    // FP64 aux Gram (timed in the strips slot), then the BF16 products and strips
     mark(c, 9, false);
     s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, -1, false, 1);
     if (s != BLM_OK) return s;

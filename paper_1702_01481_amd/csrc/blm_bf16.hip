@@ -70,6 +70,7 @@ template <int PIECES>
 struct BpLds {
   u4v A[2][PIECES][BP_KG][GT];        // [O or e][piece][group][column]
   u4v B[2][PIECES][BP_KG][BP_COLS];
+  u4v X[2][PIECES][BP_KG][NAUX];      // aux columns [Xa or Ya][piece][group][column]
 };
 
 __device__ __forceinline__ void lds_dma16(const BLM_GLOBAL void* src, u4v* lds_base) {
@@ -83,9 +84,11 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
                                                                  const Slice* __restrict__ slices,
                                                                  int n_slices, int P,
                                                                  double* __restrict__ partial) {
-  // wave instructions per step: one per (side, array, piece, group[, half])
+  // wave instructions per step: one per (side, array, piece, group[, half]);
+  // diagonal pairs also copy the aux columns (one per array and piece)
   constexpr int NIA = 2 * PIECES * BP_KG;              // A side, 64 columns each
   constexpr int NIB = 2 * PIECES * BP_KG * 2;          // B side, two 64-column halves
+  constexpr int NIX = 2 * PIECES;                      // aux: 4 groups x 16 columns each
   constexpr int NW = BP_THREADS / 64;
   __shared__ BpLds<PIECES> L[2];
 
@@ -98,13 +101,24 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
   const bool has_b = PJ.jb >= 0;
   const GramJob JB = jobs[has_b ? PJ.jb : PJ.ja];
 
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // The wave index is made provably wave-uniform, so that every per-wave
+  // choice below (which products, which job) is a scalar branch: a
+  // matrix-core instruction is not masked by the lane mask, so it must
+  // never sit under a divergent condition.
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i16 = lane & 15, k4 = lane >> 4;
   const int wr = wv & 1, wc = wv >> 1;           // 2 x 4 waves over 64 x 128
   const bool wave_b = wc >= 2;
   const bool wave_on = !wave_b || has_b;
   const GramJob& JW = wave_b ? JB : JA;
   const bool third = JW.kind == JOB_OFF;
+  // Diagonal job with strips: the waves of its tile (wc < 2) compute the
+  // coupling strips of Fig. 1 in the third product's registers:
+  // aux^T O_i and aux^T e_i (wr = 0), auxE^T O_i (wr = 1), 16 x 32 each.
+  const bool pair_strips = JA.kind == JOB_DIAG;
+  const bool strip = pair_strips && !wave_b;
+  const int n_instr = NIA + NIB + (pair_strips ? NIX : 0);
 
   // this lane's global column in each 64-column half (clamped into the tile)
   const int acol = JA.ci + min(lane, JA.mi - 1);
@@ -133,9 +147,18 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
     const BLM_GLOBAL uint16_t* O = as_global((const uint16_t*)S.O);
     const BLM_GLOBAL uint16_t* E = as_global((const uint16_t*)S.e);
 #pragma unroll
-    for (int ii = 0; ii < (NIA + NIB + NW - 1) / NW; ++ii) {
+    for (int ii = 0; ii < (NIA + NIB + NIX + NW - 1) / NW; ++ii) {
       const int in = wv + ii * NW;
-      if (in >= NIA + NIB) break;
+      if (in >= n_instr) break;
+      if (in >= NIA + NIB) {
+        // aux columns: lane -> (group lane / 16, column lane % 16)
+        const int ix = in - NIA - NIB, xarr = ix / PIECES, xpc = ix % PIECES;
+        const int64_t gg = min(grp0 + (lane >> 4), n8 - 1);
+        const BLM_GLOBAL uint16_t* xb = as_global(xarr ? S.Yp : S.Xp);
+        lds_dma16(xb + (int64_t)xpc * S.apstride + (gg * NAUX + (lane & 15)) * 8,
+                  &L[buf].X[xarr][xpc][0][0]);
+        continue;
+      }
       int arr, pc, grp, col;
       u4v* dst;
       if (in < NIA) {
@@ -158,12 +181,23 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
       lds_dma16(base + (int64_t)pc * S.pstride + (gg * S.ld + col) * 8, dst);
     }
   };
+  // Third product slot, fixed per wave: e_i^T O_j for an off-diagonal tile,
+  // the coupling strips for a diagonal one (x = 0: aux^T O_i, or auxE^T O_i
+  // on the wr = 1 waves; x = 1: aux^T e_i).  Its A operand is chosen by LDS
+  // address and its B operand by a register select, so every wave runs the
+  // same straight-line sequence of matrix-core instructions.
+  const int a3_base = strip ? (int)((const char*)&L[0].X[wr][0][k4][i16] - (const char*)&L[0])
+                            : (int)((const char*)&L[0].A[1][0][k4][32 * wr + i16] - (const char*)&L[0]);
+  const int a3_x = strip ? 0 : 16 * (int)sizeof(u4v);                  // next 16 rows
+  const int a3_p = strip ? BP_KG * NAUX * (int)sizeof(u4v) : BP_KG * GT * (int)sizeof(u4v);
+  const bool b3_e = strip && wr == 0;                                  // x = 1 pairs with e_i
   auto compute = [&](int buf, int64_t n8_left, bool flush) {
     // groups at or past the slice's end contribute nothing: on the last step
     // of a slice the A side is zeroed by a lane mask
     const bool partial = n8_left < BP_KG;
     const unsigned km = (k4 < n8_left) ? 0xFFFFFFFFu : 0u;
     const BpLds<PIECES>& Lb = L[buf];
+    const char* lb = (const char*)&Lb;
     bf16x8 bO[2][PIECES], bE[2][PIECES];
 #pragma unroll
     for (int y = 0; y < 2; ++y)
@@ -175,18 +209,18 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
       }
 #pragma unroll
     for (int pa = 0; pa < PIECES; ++pa) {
-      bf16x8 aO[2], aE[2];
+      bf16x8 aO[2], a3[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
         const int row = 32 * wr + 16 * x + i16;
         u4v vo = Lb.A[0][pa][k4][row];
-        u4v ve = Lb.A[1][pa][k4][row];
+        u4v v3 = *(const u4v*)(lb + a3_base + x * a3_x + pa * a3_p);
         if (partial) {
           vo &= km;
-          ve &= km;
+          v3 &= km;
         }
         aO[x] = __builtin_bit_cast(bf16x8, vo);
-        aE[x] = __builtin_bit_cast(bf16x8, ve);
+        a3[x] = __builtin_bit_cast(bf16x8, v3);
       }
 #pragma unroll
       for (int pb = 0; pb + pa < PIECES; ++pb)
@@ -196,7 +230,8 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
           for (int y = 0; y < 2; ++y) {
             acc[0][x][y] = mfma_bf16(aO[x], bO[y][pb], acc[0][x][y]);
             acc[1][x][y] = mfma_bf16(aO[x], bE[y][pb], acc[1][x][y]);
-            if (third) acc[2][x][y] = mfma_bf16(aE[x], bO[y][pb], acc[2][x][y]);
+            const bf16x8 b3 = (x == 1 && b3_e) ? bE[y][pb] : bO[y][pb];
+            acc[2][x][y] = mfma_bf16(a3[x], b3, acc[2][x][y]);
           }
     }
     if (!flush) return;
@@ -256,6 +291,22 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
   const int jw = wave_b ? PJ.jb : PJ.ja;
   BLM_GLOBAL double* base = as_global(partial) + ((size_t)jw * P + p) * (size_t)(3 * GT * GT);
   const int c0 = 32 * (wc & 1);
+  if (strip) {
+    // strips [3][NAUX][GT] in the third slot: q = 0 aux^T O, 1 aux^T e, 2 auxE^T O
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int a = bf16_d_row(lane, rr);
+        const int col = c0 + 16 * y + i16;
+        if (wr == 0) {
+          base[2 * GT * GT + 0 * NAUX * GT + a * GT + col] = a64[2][0][y][rr];
+          base[2 * GT * GT + 1 * NAUX * GT + a * GT + col] = a64[2][1][y][rr];
+        } else {
+          base[2 * GT * GT + 2 * NAUX * GT + a * GT + col] = a64[2][0][y][rr];
+        }
+      }
+  }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll

@@ -70,6 +70,12 @@ struct Slice {
   int64_t pstride;      // BF16 pieces: elements between pieces
   int32_t pieces;       // 0: FP64 storage; 2 or 3: BF16 split pieces
   int32_t pad;
+  // BF16 split storage only: the aux columns (Xa, Ya) as BF16 pieces in the
+  // k-packed layout with ld = NAUX, from the slice's first 8-sample group;
+  // piece p of Xa at Xp + p * apstride (Ya likewise at Yp)
+  const uint16_t* Xp;
+  const uint16_t* Yp;
+  int64_t apstride;
 };
 
 // ------------------------------------------------- direction projection ---
