@@ -60,12 +60,17 @@ typedef enum {
 typedef enum {
   BLM_PREC_F64 = 0,     /* sample contractions in FP64 on FP64 matrix cores */
   BLM_PREC_BF16X2 = 1,  /* BF16 hi/lo pieces, 3 piece products, FP32 sums flushed to FP64 */
-  BLM_PREC_BF16X3 = 2   /* BF16 hi/mid/lo pieces, 6 piece products, FP32 sums flushed to FP64 */
+  BLM_PREC_BF16X3 = 2,  /* BF16 hi/mid/lo pieces, 6 piece products, FP32 sums flushed to FP64 */
+  BLM_PREC_FP8 = 3      /* e4m3 codes with power-of-two column scales and a BF16 residual:
+                           code x code on FP8 matrix cores, the three residual terms on
+                           BF16 ones, FP32 sums scaled and flushed to FP64 */
 } blm_precision;
 
 typedef enum {
   BLM_LAYOUT_F64 = 0,        /* O, e: double [n][ld], sample-major */
-  BLM_LAYOUT_BF16_SPLIT = 1  /* O, e: BF16 pieces, k-packed (see blm_pack_bf16) */
+  BLM_LAYOUT_BF16_SPLIT = 1, /* O, e: BF16 pieces, k-packed (see blm_pack_bf16) */
+  BLM_LAYOUT_FP8_SCALED = 2  /* O, e: e4m3 codes, plus O_res/e_res and O_scale/e_scale
+                                (see blm_pack_fp8) */
 } blm_layout;
 
 /* Flags returned per shift by blm_stage2 (bit mask). */
@@ -93,11 +98,16 @@ typedef struct {                 /* one chunk of samples; device memory, caller-
   const void* O;                 /* BLM_LAYOUT_F64: double [n_samples][ld]; split: piece 0 */
   const void* e;                 /* same layout as O */
   const double* E_L;             /* [n_samples] */
-  const double* w;               /* [n_samples] >= 0, or NULL for all-ones (required for BF16) */
-  int32_t layout;                /* blm_layout; must be BLM_LAYOUT_F64 for BLM_PREC_F64 and
-                                    BLM_LAYOUT_BF16_SPLIT for the BF16 precisions */
+  const double* w;               /* [n_samples] >= 0, or NULL for all-ones (required for BF16, FP8) */
+  int32_t layout;                /* blm_layout; must be BLM_LAYOUT_F64 for BLM_PREC_F64,
+                                    BLM_LAYOUT_BF16_SPLIT for the BF16 precisions and
+                                    BLM_LAYOUT_FP8_SCALED for BLM_PREC_FP8 */
   int32_t pieces;                /* split layout: pieces stored (2 or 3; >= 3 for BF16X3) */
   int64_t piece_stride;          /* split layout: elements between pieces, multiple of 8 */
+  const void* O_res;             /* FP8 layout: BF16 residuals of O (uint16, see blm_pack_fp8) */
+  const void* e_res;             /* FP8 layout: BF16 residuals of e */
+  const float* O_scale;          /* FP8 layout: [ld] power-of-two column scales of O */
+  const float* e_scale;          /* FP8 layout: [ld] column scales of e */
 } blm_chunk;
 
 /* Producer-side utility: splits FP64 samples src [n][ld_src] (columns
@@ -109,6 +119,25 @@ typedef struct {                 /* one chunk of samples; device memory, caller-
  * a multiple of 8, and 16-byte alignment.  Asynchronous on `stream`. */
 blm_status blm_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncols, int32_t pieces,
                          uint16_t* dst, int64_t ld_dst, int64_t piece_stride, void* stream);
+
+/* Producer-side utility: FP8 storage of FP64 samples src [n][ld_src]
+ * (columns 0..ncols-1), each value x of column c as x = scale[c] (q + r):
+ *   scale[c]  the smallest power of two (2^-126 .. 2^127) with
+ *             max_s |x| / scale[c] <= 448;
+ *   q         x / scale[c] rounded to OCP e4m3 (nearest, ties to even,
+ *             saturating at 448), stored as its code byte;
+ *   r         the exact remainder x / scale[c] - q rounded to FP32 and then
+ *             to BF16 (nearest even), stored as uint16 bits.
+ * The stored value is within 2^-13 |x| of x in q's normal range.  Layouts
+ * (k-packed): code of (s, x) at codes[((s / 16) * ld_dst + x) * 16 + s % 16],
+ * residual at res[((s / 8) * ld_dst + x) * 8 + s % 8]; rows n .. up to the
+ * next multiple of 16 (codes) or 8 (residuals) are zeros.  codes needs
+ * 16 * ceil(n / 16) * ld_dst bytes, res 8 * ceil(n / 8) * ld_dst elements,
+ * both 16-byte aligned; scale ncols floats.  (Reduced-precision storage of
+ * the samples of Eq. 3 is this library's option; the paper works in FP64.)
+ * Asynchronous on `stream`. */
+blm_status blm_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,
+                        uint16_t* res, float* scale, int64_t ld_dst, void* stream);
 
 /* Bytes of device memory blm_create will allocate for this configuration. */
 blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes);

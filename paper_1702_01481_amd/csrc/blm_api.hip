@@ -87,6 +87,12 @@ struct blm_ctx {
   uint16_t* auxP = nullptr;      // BF16 build: aux columns as BF16 pieces (k-packed, ld 16)
   int64_t aux_pstride = 0;       // elements between pieces of auxP (Xa pieces, then Ya pieces)
   int pieces = 0;                  // 0: FP64 path; 2 or 3: BF16 split pieces used
+  bool fp8 = false;                // FP8 storage (e4m3 codes, BF16 residuals, column scales)
+  uint8_t* auxQ = nullptr;         // FP8 build: aux codes (k-packed by 16, ld 16), Xa then Ya
+  uint16_t* auxR = nullptr;        // FP8 build: aux residuals (k-packed by 8, ld 16), Xa then Ya
+  float* auxS = nullptr;           // FP8 build: aux column scales [chunk][Xa, Ya][16]
+  int64_t auxq_stride = 0, auxr_stride = 0;   // bytes / elements from the Xa to the Ya part
+  bool mixed() const { return pieces != 0 || fp8; }
   Slice* d_slices = nullptr;
   ProjChunk* d_pchunks = nullptr;
   std::vector<ProjChunk> h_pchunks;
@@ -281,7 +287,7 @@ blm_status validate(const blm_config* cfg, blm_ctx* c) {
     if (!(cfg->shifts[i] >= 0.0) || !std::isfinite(cfg->shifts[i]))
       return fail(c, BLM_E_ARG, "shifts must be finite and >= 0");
   if (cfg->precision != BLM_PREC_F64 && cfg->precision != BLM_PREC_BF16X2 &&
-      cfg->precision != BLM_PREC_BF16X3)
+      cfg->precision != BLM_PREC_BF16X3 && cfg->precision != BLM_PREC_FP8)
     return fail(c, BLM_E_ARG, "unsupported precision");
   if (cfg->max_samples < 1) return fail(c, BLM_E_ARG, "max_samples must be >= 1");
   if (cfg->block_offsets[0] != 0 || cfg->block_offsets[cfg->n_blocks] != cfg->n_params)
@@ -318,12 +324,14 @@ void plan(blm_ctx* c, Plan& P) {
   run += NAUX * NAUX;
   c->acc_elems = run;
   c->n_jobs1 = n_jobs1 + 1;
-  c->n_jobsM = c->pieces ? n_jobs1 : 0;
+  c->n_jobsM = c->mixed() ? n_jobs1 : 0;
   // mixed precision: the strips ride on the BF16 diagonal jobs; only the aux
   // Gram stays on the FP64 kernel
-  if (c->pieces) c->n_jobs1 = 1;
+  if (c->mixed()) c->n_jobs1 = 1;
   const int64_t aux_groups = c->max_samples / 8 + MAX_CHUNKS;
   c->aux_pstride = c->pieces ? aux_groups * NAUX * 8 : 0;
+  c->auxq_stride = c->fp8 ? (c->max_samples / 16 + MAX_CHUNKS) * NAUX * 16 : 0;
+  c->auxr_stride = c->fp8 ? (c->max_samples / 8 + MAX_CHUNKS) * NAUX * 8 : 0;
   c->n2max = 1 + NS * NB * (NK + 1);
   c->d2max = 1 + NB * (NK + 1);
   const int T2 = (c->n2max + GT - 1) / GT;
@@ -351,6 +359,9 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_jobsM, sizeof(GramJob) * (size_t)std::max(c->n_jobsM, 1));
   add((void**)&c->d_pairsM, sizeof(PairJob) * (size_t)std::max(c->n_jobsM, 1));
   add((void**)&c->auxP, 2 * 2 * (size_t)c->pieces * c->aux_pstride);
+  add((void**)&c->auxQ, 2 * (size_t)c->auxq_stride);
+  add((void**)&c->auxR, 2 * 2 * (size_t)c->auxr_stride);
+  add((void**)&c->auxS, c->fp8 ? 4 * (size_t)MAX_CHUNKS * 2 * NAUX : 0);
   add((void**)&c->d_slices, sizeof(Slice) * (size_t)c->max_slices);
   add((void**)&c->d_pchunks, sizeof(ProjChunk) * (size_t)MAX_CHUNKS);
   add((void**)&c->d_theta_blk, sizeof(DirBlock) * (size_t)NB);
@@ -435,8 +446,8 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
         J.ht_off = c->acc_off[b] + (int64_t)GT * tj * M + (int64_t)GT * ti;
         J.ld_out = M;
         J.strip_col = J.ci;
-        if (!c->pieces) jobs.push_back(J);
-        else main.push_back(J);   // all products, strips included, on the BF16 matrix cores
+        if (!c->mixed()) jobs.push_back(J);
+        else main.push_back(J);   // all products, strips included, on the mixed-precision kernel
       }
   }
   GramJob A{};
@@ -480,8 +491,17 @@ blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) 
     if (ch[i].n_samples == 0) continue;
     if (ch[i].ld < c->NV) return fail(c, BLM_E_ARG, "chunk ld < n_params");
     if (!ch[i].O || !ch[i].e || !ch[i].E_L) return fail(c, BLM_E_ARG, "chunk pointer is NULL");
-    if (c->pieces == 0 && ch[i].layout != BLM_LAYOUT_F64)
+    if (!c->mixed() && ch[i].layout != BLM_LAYOUT_F64)
       return fail(c, BLM_E_ARG, "the FP64 precision needs BLM_LAYOUT_F64 chunks");
+    if (c->fp8) {
+      if (ch[i].layout != BLM_LAYOUT_FP8_SCALED)
+        return fail(c, BLM_E_ARG, "the FP8 precision needs BLM_LAYOUT_FP8_SCALED chunks");
+      if (ch[i].w) return fail(c, BLM_E_ARG, "the FP8 precision needs uniform weights (w == NULL)");
+      if (!ch[i].O_res || !ch[i].e_res || !ch[i].O_scale || !ch[i].e_scale)
+        return fail(c, BLM_E_ARG, "FP8 chunk: residual or scale pointer is NULL");
+      if (((uintptr_t)ch[i].O | (uintptr_t)ch[i].e | (uintptr_t)ch[i].O_res | (uintptr_t)ch[i].e_res) & 15)
+        return fail(c, BLM_E_ARG, "FP8 chunk: codes and residuals need 16-byte alignment");
+    }
     if (c->pieces) {
       if (ch[i].layout != BLM_LAYOUT_BF16_SPLIT || ch[i].pieces < c->pieces || ch[i].pieces > 3)
         return fail(c, BLM_E_ARG, "the BF16 precisions need split chunks with enough pieces");
@@ -518,6 +538,12 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
     P.tile0 = tiles;
     P.pieces = c->pieces;
     P.pstride = ch[i].piece_stride;
+    if (c->fp8) {
+      P.Or = (const uint16_t*)ch[i].O_res;
+      P.er = (const uint16_t*)ch[i].e_res;
+      P.Os = ch[i].O_scale;
+      P.es = ch[i].e_scale;
+    }
     c->h_pchunks.push_back(P);
     tiles += (int)((ns + PROJ_ROWS - 1) / PROJ_ROWS);
     rb += ns;
@@ -526,14 +552,16 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
   if (c->h_pchunks.empty()) return BLM_OK;
   HIPCHK(c, hipMemcpyAsync(c->d_pchunks, c->h_pchunks.data(), sizeof(ProjChunk) * c->h_pchunks.size(),
                            hipMemcpyHostToDevice, c->st));
-  launch_dirproj(c->d_pchunks, (int)c->h_pchunks.size(), tiles, vec && !c->pieces, c->pieces != 0,
+  const int store = c->fp8 ? STORE_FP8 : c->pieces ? STORE_BF16 : STORE_F64;
+  launch_dirproj(c->d_pchunks, (int)c->h_pchunks.size(), tiles, vec && store == STORE_F64, store,
                  d_blocks, n_blocks, d_ptr, n_dirs, Xo, Yo, ldo, c->st);
   HIPCHK(c, hipGetLastError());
   return BLM_OK;
 }
 
 // kind: 0 FP64 kernel on FP64 storage, 1 FP64 kernel on split storage
-// (strips), 2 BF16 matrix-core kernel on split storage (main products)
+// (strips), 2 BF16 matrix-core kernel on split storage (main products),
+// 3 FP8 + BF16 matrix-core kernel on FP8 storage (main products)
 blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_base,
                     double* h_base, double* strip_base, int phase, bool vec, int kind = 0) {
   const int n_slices = (int)c->h_slices.size();
@@ -548,6 +576,8 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
   if (kind == 2)
     launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->pieces,
                      c->partial, c->st);
+  else if (kind == 3)
+    launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->partial, c->st);
   else
     launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec && kind == 0, kind == 1, c->partial,
                 c->st);
@@ -595,6 +625,7 @@ blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes) {
   tmp.off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
   tmp.max_samples = cfg->max_samples;
   tmp.pieces = cfg->precision == BLM_PREC_BF16X3 ? 3 : cfg->precision == BLM_PREC_BF16X2 ? 2 : 0;
+  tmp.fp8 = cfg->precision == BLM_PREC_FP8;
   Plan P;
   plan(&tmp, P);
   size_t t = 0;
@@ -610,6 +641,15 @@ blm_status blm_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t n
       ((uintptr_t)dst & 15))
     return BLM_E_ARG;
   launch_pack_bf16(src, n, ld_src, ncols, pieces, dst, ld_dst, piece_stride, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? BLM_OK : BLM_E_HIP;
+}
+
+blm_status blm_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,
+                        uint16_t* res, float* scale, int64_t ld_dst, void* stream) {
+  if (!src || !codes || !res || !scale || n < 0 || ncols < 1 || ld_src < ncols || ld_dst < ncols)
+    return BLM_E_ARG;
+  if (((uintptr_t)codes & 15) || ((uintptr_t)res & 15)) return BLM_E_ARG;
+  launch_pack_fp8(src, n, ld_src, ncols, codes, res, scale, ld_dst, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? BLM_OK : BLM_E_HIP;
 }
 
@@ -667,6 +707,7 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
   c->NS = cfg->n_shifts;
   c->prec = cfg->precision;
   c->pieces = cfg->precision == BLM_PREC_BF16X3 ? 3 : cfg->precision == BLM_PREC_BF16X2 ? 2 : 0;
+  c->fp8 = cfg->precision == BLM_PREC_FP8;
   c->off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
   c->shifts.assign(cfg->shifts, cfg->shifts + cfg->n_shifts);
   c->max_samples = cfg->max_samples;
@@ -800,10 +841,24 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
                   c->Xa, c->Ya, NAUX);
   if (s != BLM_OK) return s;
   c->h_slices.clear();
-  int64_t rb = 0, gbase = 0;
+  int64_t rb = 0, gbase = 0, g16base = 0;
+  int ci = 0;
   for (int i = 0; i < n; ++i) {
     const int64_t ns = ch[i].n_samples;
     if (ns == 0) continue;
+    uint8_t* xq = nullptr;
+    uint16_t* xr = nullptr;
+    float* xs = nullptr;
+    if (c->fp8) {
+      // this chunk's aux columns in FP8 storage, with their own scales
+      xq = c->auxQ + g16base * NAUX * 16;
+      xr = c->auxR + gbase * NAUX * 8;
+      xs = c->auxS + (size_t)ci * 2 * NAUX;
+      launch_pack_fp8(c->Xa + (size_t)rb * NAUX, ns, NAUX, NAUX, xq, xr, xs, NAUX, c->st);
+      launch_pack_fp8(c->Ya + (size_t)rb * NAUX, ns, NAUX, NAUX, xq + c->auxq_stride, xr + c->auxr_stride,
+                      xs + NAUX, NAUX, c->st);
+      HIPCHK(c, hipGetLastError());
+    }
     if (c->pieces) {
       // this chunk's aux columns as BF16 pieces, from an 8-sample group boundary
       uint16_t* xp = c->auxP + gbase * NAUX * 8;
@@ -815,7 +870,21 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     }
     for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
       Slice S{};
-      if (c->pieces) {
+      if (c->fp8) {
+        // slice starts are multiples of 16 samples
+        S.O = (const uint8_t*)ch[i].O + (size_t)(s0 / 16) * ch[i].ld * 16;
+        S.e = (const uint8_t*)ch[i].e + (size_t)(s0 / 16) * ch[i].ld * 16;
+        S.Or = (const uint16_t*)ch[i].O_res + (size_t)(s0 / 8) * ch[i].ld * 8;
+        S.er = (const uint16_t*)ch[i].e_res + (size_t)(s0 / 8) * ch[i].ld * 8;
+        S.Os = ch[i].O_scale;
+        S.es = ch[i].e_scale;
+        S.Xq = xq + (size_t)(s0 / 16) * NAUX * 16;
+        S.Yq = S.Xq + c->auxq_stride;
+        S.Xr = xr + (size_t)(s0 / 8) * NAUX * 8;
+        S.Yr = S.Xr + c->auxr_stride;
+        S.Xs = xs;
+        S.Ys = xs + NAUX;
+      } else if (c->pieces) {
         // k-packed pieces: slice starts are multiples of 8 samples
         S.O = (const uint16_t*)ch[i].O + (size_t)(s0 / 8) * ch[i].ld * 8;
         S.e = (const uint16_t*)ch[i].e + (size_t)(s0 / 8) * ch[i].ld * 8;
@@ -839,15 +908,19 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     }
     rb += ns;
     gbase += (ns + 7) / 8;
+    g16base += (ns + 15) / 16;
+    ++ci;
   }
   mark(c, 0, true);
-  if (c->pieces) {
-    // FP64 aux Gram (timed in the strips slot), then the BF16 products and strips
+  if (c->mixed()) {
+    // FP64 aux Gram (timed in the strips slot), then the mixed-precision
+    // products and strips
     mark(c, 9, false);
     s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, -1, false, 1);
     if (s != BLM_OK) return s;
     mark(c, 9, true);
-    s = run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, c->accS, c->accH, c->strips, 1, false, 2);
+    s = run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, c->accS, c->accH, c->strips, 1, false,
+                 c->fp8 ? 3 : 2);
   } else {
     s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even);
   }

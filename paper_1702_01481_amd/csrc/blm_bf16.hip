@@ -173,7 +173,8 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
         grp = (ib >> 1) % BP_KG;
         pc = ((ib >> 1) / BP_KG) % PIECES;
         arr = (ib >> 1) / (BP_KG * PIECES);
-        col = half ? bcol1 : bcol0;
+        col = bcol0 + half * (bcol1 - bcol0);   // arithmetic: a conditional over captured
+                                                // values would keep them in memory
         dst = &L[buf].B[arr][pc][grp][GT * half];
       }
       const int64_t gg = min(grp0 + grp, n8 - 1);

@@ -76,6 +76,20 @@ struct Slice {
   const uint16_t* Xp;
   const uint16_t* Yp;
   int64_t apstride;
+  // FP8 storage only (O, e then hold the e4m3 codes, k-packed by 16 samples:
+  // element (s, x) at ((s / 16) * ld + x) * 16 + s % 16 bytes, from the
+  // slice's first sample): BF16 residuals k-packed by 8, and the chunk's
+  // per-column power-of-two scales; the aux columns likewise with ld = NAUX
+  const uint16_t* Or;
+  const uint16_t* er;
+  const float* Os;
+  const float* es;
+  const uint8_t* Xq;
+  const uint8_t* Yq;
+  const uint16_t* Xr;
+  const uint16_t* Yr;
+  const float* Xs;
+  const float* Ys;
 };
 
 // ------------------------------------------------- direction projection ---
@@ -99,7 +113,14 @@ struct ProjChunk {
   int64_t pstride;
   int32_t tile0;
   int32_t pieces;       // 0: FP64 storage; 2 or 3: BF16 split pieces (k-packed)
+  // FP8 storage (O, e are e4m3 codes k-packed by 16): residuals and scales
+  const uint16_t* Or;
+  const uint16_t* er;
+  const float* Os;
+  const float* es;
 };
+// sample storage of a projection launch
+enum StoreKind : int32_t { STORE_F64 = 0, STORE_BF16 = 1, STORE_FP8 = 2 };
 constexpr int PROJ_ROWS = 64;
 
 // ------------------------------------------------------------ eigensolve --
@@ -158,7 +179,13 @@ void launch_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncol
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
                         hipStream_t st);
-void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, bool split,
+void launch_gram_fp8(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
+                     const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st);
+// FP64 [n][ld_src] -> e4m3 codes (k-packed by 16), BF16 residuals (k-packed
+// by 8) and per-column power-of-two scales (blm_fp8.hip)
+void launch_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,
+                     uint16_t* res, float* scale, int64_t ld_dst, hipStream_t st);
+void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st);
 void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);

@@ -57,6 +57,34 @@ __device__ __forceinline__ void split_load8(const void* base, int64_t ld, int64_
   }
 }
 
+// The 8 samples of one 8-sample group of one column in FP8 storage (e4m3
+// codes k-packed by 16 samples, BF16 residuals by 8, power-of-two column
+// scale), each as the exact FP64 value scale (q + r).
+__device__ __forceinline__ void fp8_load8(const void* codes, const uint16_t* res, const float* scale,
+                                          int64_t ld, int64_t group, int64_t col, double* v) {
+  const BLM_GLOBAL uint8_t* qb =
+      as_global((const uint8_t*)codes) + ((group >> 1) * ld + col) * 16 + 8 * (group & 1);
+  const uint2 q = *reinterpret_cast<const BLM_GLOBAL uint2*>(qb);
+  const uint4 r = *reinterpret_cast<const BLM_GLOBAL uint4*>(as_global(res) + (group * ld + col) * 8);
+  const double sc = as_global(scale)[col];
+  const uint32_t qw[2] = {q.x, q.y};
+  const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+  // codes to BF16 (exact), two per conversion, then to FP64
+  const uint32_t pw[4] = {
+      __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(qw[0], 1.0f, false)),
+      __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(qw[0], 1.0f, true)),
+      __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(qw[1], 1.0f, false)),
+      __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(qw[1], 1.0f, true))};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t pb = pw[k];
+    const double q0 = (double)__uint_as_float(pb << 16), q1 = (double)__uint_as_float(pb & 0xFFFF0000u);
+    const double r0 = (double)__uint_as_float(rw[k] << 16), r1 = (double)__uint_as_float(rw[k] & 0xFFFF0000u);
+    v[2 * k] = sc * (q0 + r0);
+    v[2 * k + 1] = sc * (q1 + r1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Gram tiles
 // ---------------------------------------------------------------------------
@@ -459,17 +487,22 @@ struct PjRegs {
 // Stage loader: 64 samples x 32 parameters of O and e, and 32 directions x
 // 32 parameters of the direction rows.  VEC: 16-byte loads (the caller has
 // checked alignment); otherwise 8-byte loads.
-template <bool VEC, bool SPLIT>
+template <bool VEC, int ST>
 __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const DirBlock& B, int dg,
                                         int p0, const double* const* __restrict__ dir_ptr, int tid,
                                         PjRegs& R) {
-  if (SPLIT) {
+  if (ST != STORE_F64) {
     // thread -> (8-sample group g, parameter col): 8 samples of O and of e
     const int col = tid & 31, g = tid >> 5;
     const int64_t r0 = s0 + 8 * g;
     if (r0 < C.n && p0 + col < B.m) {
-      split_load8(C.O, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.o);
-      split_load8(C.e, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.e);
+      if constexpr (ST == STORE_FP8) {
+        fp8_load8(C.O, C.Or, C.Os, C.ld, r0 >> 3, B.col0 + p0 + col, R.o);
+        fp8_load8(C.e, C.er, C.es, C.ld, r0 >> 3, B.col0 + p0 + col, R.e);
+      } else {
+        split_load8(C.O, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.o);
+        split_load8(C.e, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.e);
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < 8; ++k) R.o[k] = R.e[k] = 0.0;
@@ -514,10 +547,10 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
   }
 }
 
-template <bool VEC, bool SPLIT>
+template <bool VEC, int ST>
 __device__ __forceinline__ void pj_store(double (*sO)[PJ_P + 1], double (*sE)[PJ_P + 1],
                                          double (*sD)[PJ_P + 1], int tid, const PjRegs& R) {
-  if (SPLIT) {
+  if (ST != STORE_F64) {
     const int col = tid & 31, g = tid >> 5;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -548,7 +581,7 @@ __device__ __forceinline__ void pj_store(double (*sO)[PJ_P + 1], double (*sE)[PJ
   for (int i = 0; i < 4; ++i) sD[(tid >> 5) + 8 * i][col] = R.d[i];
 }
 
-template <bool VEC, bool SPLIT>
+template <bool VEC, int ST>
 __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restrict__ chunks,
                                                       int n_chunks,
                                                       const DirBlock* __restrict__ blocks,
@@ -589,13 +622,13 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
       const bool two = (B.nd - dg) > 16;
       d4 aO0 = {0, 0, 0, 0}, aO1 = {0, 0, 0, 0}, aE0 = {0, 0, 0, 0}, aE1 = {0, 0, 0, 0};
       PjRegs R;
-      pj_load<VEC, SPLIT>(C, s0, B, dg, 0, dir_ptr, tid, R);
+      pj_load<VEC, ST>(C, s0, B, dg, 0, dir_ptr, tid, R);
       for (int p0 = 0; p0 < B.m; p0 += PJ_P) {
         __syncthreads();   // everyone is done reading the previous stage
-        pj_store<VEC, SPLIT>(sO, sE, sD, tid, R);
+        pj_store<VEC, ST>(sO, sE, sD, tid, R);
         __syncthreads();
         // the next stage's global loads overlap this stage's matrix-core work
-        if (p0 + PJ_P < B.m) pj_load<VEC, SPLIT>(C, s0, B, dg, p0 + PJ_P, dir_ptr, tid, R);
+        if (p0 + PJ_P < B.m) pj_load<VEC, ST>(C, s0, B, dg, p0 + PJ_P, dir_ptr, tid, R);
 #pragma unroll
         for (int kk = 0; kk < PJ_P; kk += 4) {
           const int kc = kk + k4;
@@ -770,12 +803,15 @@ __global__ __launch_bounds__(256) void dirproj64_kernel(const ProjChunk* __restr
   }
 }
 
-void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, bool split,
+void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st) {
   if (n_tiles <= 0) return;
-  if (split)
-    hipLaunchKernelGGL((dirproj_kernel<false, true>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
+  if (store == STORE_BF16)
+    hipLaunchKernelGGL((dirproj_kernel<false, STORE_BF16>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
+                       n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+  else if (store == STORE_FP8)
+    hipLaunchKernelGGL((dirproj_kernel<false, STORE_FP8>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
                        n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
   else if (vec)
     hipLaunchKernelGGL((dirproj64_kernel<true>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
