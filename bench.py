@@ -102,17 +102,21 @@ def cpu_baseline(O0, e0, EL0, w, offsets, old, n_keep, shifts):
     }
 
 
-def mixed_step(args, w, chunks, old, offsets, shifts, n_samples, en64, upd64, ms64, build64, fl_build):
-    """The same step with the sample contractions on BF16 split pieces; the
-    pieces are made from the resident FP64 samples before timing."""
+def mixed_step(args, prec, w, chunks, old, offsets, shifts, n_samples, en64, upd64, ms64, build64, fl_build):
+    """The same step with the sample contractions in mixed precision (BF16
+    split pieces, or FP8 codes with BF16 residuals); the reduced-precision
+    copies are made from the resident FP64 samples before timing."""
     import torch
 
     from paper_1702_01481_amd import blm
-    pieces = 3 if args.mixed == "bf16x3" else 2
-    split = [(blm.SplitSamples(O, pieces), blm.SplitSamples(e, pieces), EL) for O, e, EL in chunks]
+    if prec == "fp8":
+        split = [(blm.Fp8Samples(O), blm.Fp8Samples(e), EL) for O, e, EL in chunks]
+    else:
+        pieces = 3 if prec == "bf16x3" else 2
+        split = [(blm.SplitSamples(O, pieces), blm.SplitSamples(e, pieces), EL) for O, e, EL in chunks]
     torch.cuda.synchronize()
-    log(f"packed {args.mixed} pieces")
-    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, n_samples, precision=args.mixed)
+    log(f"packed {prec} storage")
+    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, n_samples, precision=prec)
     ctx.set_timing(True)
 
     def step():
@@ -134,20 +138,22 @@ def mixed_step(args, w, chunks, old, offsets, shifts, n_samples, en64, upd64, ms
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / args.steps
     ctx.close()
+    del split
+    torch.cuda.empty_cache()
     pm = {k: float(np.mean(v)) for k, v in phase.items()}
     build_ms = pm["theta_proj"] + pm["block_gram"] + pm["block_reduce"] + max(pm["block_strips"], 0.0)
     u64 = upd64.double().cpu().numpy()
     um = upd.double().cpu().numpy()
     cos = [float(u64[i] @ um[i] / (np.linalg.norm(u64[i]) * np.linalg.norm(um[i]))) for i in range(len(shifts))]
     rel = [float(abs(en[i] - en64[i]) / abs(en64[i])) for i in range(len(shifts))]
-    log(f"mixed step {ms:.1f} ms, energy rel err {rel}")
+    log(f"{prec} step {ms:.1f} ms, energy rel err {rel}")
     return {
-        "precision": args.mixed,
+        "precision": prec,
         "ms_per_step": round(ms, 3),
         "build_ms": round(build_ms, 3),
         "build_tflops": round(fl_build / (build_ms * 1e-3) / 1e12, 4),
-        "gram_bf16_ms": round(pm["block_gram"], 3),
-        "gram_bf16_algorithmic_tflops": round(fl_build / (pm["block_gram"] * 1e-3) / 1e12, 4),
+        "gram_ms": round(pm["block_gram"], 3),
+        "gram_algorithmic_tflops": round(fl_build / (pm["block_gram"] * 1e-3) / 1e12, 4),
         "phase_ms": {k: round(v, 3) for k, v in pm.items()},
         "energy_rel_err_vs_fp64": rel,
         "update_cosine_vs_fp64": cos,
@@ -164,8 +170,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mixed", default="bf16x3", choices=["bf16x3", "bf16x2", "none"],
-                    help="also run the mixed-precision step on the same samples")
+    ap.add_argument("--mixed", default="bf16x3,fp8",
+                    help="comma-separated mixed precisions (bf16x3, bf16x2, fp8) also run on the same "
+                         "samples, or none")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy three times (the reference "
                          "for scaling HBM byte counters)")
@@ -281,8 +288,12 @@ def main():
                      "flops_per_launch": fl_build},
     }
     if args.mixed != "none":
-        out["mixed"] = mixed_step(args, w, chunks, old, offsets, shifts, n_samples, en, upd, ms_step,
-                                  build_ms, fl_build)
+        out["mixed"] = []
+        for prec in args.mixed.split(","):
+            if prec not in ("bf16x3", "bf16x2", "fp8"):
+                raise SystemExit(f"unknown mixed precision {prec}")
+            out["mixed"].append(mixed_step(args, prec, w, chunks, old, offsets, shifts, n_samples, en, upd,
+                                           ms_step, build_ms, fl_build))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one chunk")
         O0, e0, EL0 = chunks[0]

@@ -24,6 +24,7 @@ import pytest
 import torch
 
 from oracle import blm_oracle as orc
+from oracle import fp8_storage as f8
 from paper_1702_01481_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +41,7 @@ def _step(ctx, chunks, old):
     ctx.project(chunks)
     upd, en, al, fl = ctx.stage2()
     torch.cuda.synchronize()
-    return upd, en
+    return upd, en, kept
 
 
 @pytest.fixture(scope="module")
@@ -62,9 +63,17 @@ def workload():
     torch.cuda.empty_cache()
 
 
-def _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th):
+def _fp8_stored(x):
+    q, r, s = f8.fp8_store(x)
+    return f8.fp8_values(q, r, s)
+
+
+def _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th, transform=None):
     """Whole-sample sums for the sampled basis indices [0, pcols, th] of
-    block b and the stage-two rows [Psi, B^(b)], streamed chunk by chunk."""
+    block b and the stage-two rows [Psi, B^(b)], streamed chunk by chunk.
+    transform (optional) maps each chunk's sampled parameter columns to the
+    values a reduced-precision storage stands for (column scales are per
+    chunk); the Theta and stage-two sums then stay on the FP64 values."""
     nidx = 2 + len(pcols)
     nb = Bb.shape[0]
     sS = np.zeros((nidx, nidx))
@@ -84,8 +93,11 @@ def _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th):
         ones = np.ones(n)
         t = Ok @ D[k][0]
         u = ek @ D[k][0]
-        X = np.column_stack([ones] + [Ob[:, c - 1] for c in pcols] + [t])
-        Y = np.column_stack([el] + [eb[:, c - 1] for c in pcols] + [u])
+        Xp, Yp = Ob[:, pcols - 1], eb[:, pcols - 1]
+        if transform is not None:
+            Xp, Yp = transform(Xp), transform(Yp)
+        X = np.column_stack([ones, Xp, t])
+        Y = np.column_stack([el, Yp, u])
         sS += X.T @ X
         sH += X.T @ Y
         y2 = np.column_stack([ones, Ob @ Bb.T])
@@ -103,9 +115,10 @@ def test_full_size_sampled_parity(workload):
     shifts = list(w.shifts)
 
     ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.n_samples)
-    upd0, _ = _step(ctx, chunks, torch.zeros(w.n_old, w.n_params, dtype=torch.float64, device="cuda"))
+    upd0, _, _ = _step(ctx, chunks, torch.zeros(w.n_old, w.n_params, dtype=torch.float64, device="cuda"))
     old = upd0[1:2].cpu().numpy().copy()
-    upd, en = _step(ctx, chunks, torch.from_numpy(old).cuda().contiguous())
+    upd, en, kept = _step(ctx, chunks, torch.from_numpy(old).cuda().contiguous())
+    workload["kept"] = kept.copy()
     workload["old"] = old
     workload["energy"] = [float(x) for x in en]
     workload["update"] = upd.cpu().numpy().copy()
@@ -181,7 +194,7 @@ def test_full_size_mixed_precision(workload):
     split = [(blm.SplitSamples(O, 3), blm.SplitSamples(e, 3), EL) for O, e, EL in chunks]
     torch.cuda.synchronize()
     ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.n_samples, precision="bf16x3")
-    upd, en = _step(ctx, split, torch.from_numpy(old).cuda().contiguous())
+    upd, en, _ = _step(ctx, split, torch.from_numpy(old).cuda().contiguous())
     b, k, si = CHECK_BLOCK, THETA_BLOCK, SHIFT
     delta = shifts[si]
     M = int(offsets[b + 1] - offsets[b])
@@ -211,4 +224,69 @@ def test_full_size_mixed_precision(workload):
         print(f"[scale] shift {shifts[s_i]}: energy rel err {rel:.2e}, update cosine {cos:.12f}", flush=True)
         assert rel <= 1e-6, (s_i, rel)
         assert cos >= 1 - 1e-6, (s_i, cos)
+    ctx.close()
+
+
+def test_full_size_fp8(workload):
+    """The same step on FP8 storage (e4m3 codes, column scales, BF16
+    residuals).  Sampled block-matrix entries against the oracle's sums of
+    the values the storage stands for (the oracle's own FP8 storage of the
+    same columns): within 1e-5 of the Frobenius norm, the remaining error
+    being the FP8 matrix core's ~12-bit sums.  (The Theta columns are
+    checked against stored values in the small FP8 build test.)
+    Energy and update against the FP64 step: the storage moves every sample
+    value by up to 2^-13 and the block matrices by about 2.4e-6 relative, so
+    for a shift at which every block keeps as many directions as in FP64,
+    energy within 2e-4 relative and update cosine above 0.999.  At a shift
+    where that perturbation moves the N_K cut (a near-degenerate pair at the
+    cut splitting into a real eigenvalue and a pair; it happens on this
+    workload at 1e-3), the step is a different BLM step: reported, not
+    compared.  That FP8 storage does not meet 1e-6 is the measured cost of
+    its 13-bit values."""
+    from paper_1702_01481_amd import blm
+    if "old" not in workload:
+        pytest.skip("needs the FP64 full-size step")
+    w, chunks, old = workload["w"], workload["chunks"], workload["old"]
+    offsets = np.asarray(w.block_offsets)
+    shifts = list(w.shifts)
+    f8c = [(blm.Fp8Samples(O), blm.Fp8Samples(e), EL) for O, e, EL in chunks]
+    torch.cuda.synchronize()
+    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.n_samples, precision="fp8")
+    upd, en, kept = _step(ctx, f8c, torch.from_numpy(old).cuda().contiguous())
+    b, k, si = CHECK_BLOCK, THETA_BLOCK, SHIFT
+    delta = shifts[si]
+    M = int(offsets[b + 1] - offsets[b])
+    H_gpu, S_gpu = ctx.block_matrices(b, si)
+    d = H_gpu.shape[0]
+    others = [kk for kk in range(len(offsets) - 1) if kk != b]
+    th = 1 + M + others.index(k)
+    D = orc.previous_directions(old, offsets)
+    Bb = ctx.directions(b, si)
+    rng = np.random.default_rng(13)
+    pcols = np.sort(rng.choice(M, 6, replace=False)) + 1
+    sS, sH, _, _ = _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th, transform=_fp8_stored)
+    idx = np.concatenate([[0], pcols])                # without the Theta column
+    sS, sH = sS[:-1, :-1], sH[:-1, :-1]
+    P = np.zeros((d, d))
+    P[1:, 1:] = np.eye(d - 1)
+    H_un = H_gpu - delta * P
+    eS = np.abs(S_gpu[np.ix_(idx, idx)] - sS).max() / np.linalg.norm(S_gpu)
+    eH = np.abs(H_un[np.ix_(idx, idx)] - sH).max() / np.linalg.norm(H_un)
+    print(f"[scale] fp8 entries: S {eS:.2e}, H {eH:.2e} of the Frobenius norm", flush=True)
+    assert eS <= 1e-5 and eH <= 1e-5, (eS, eH)
+    compared = 0
+    for s_i in range(len(shifts)):
+        e64 = workload["energy"][s_i]
+        rel = abs(en[s_i] - e64) / abs(e64)
+        u64 = workload["update"][s_i]
+        um = upd[s_i].cpu().numpy()
+        cos = um @ u64 / (np.linalg.norm(um) * np.linalg.norm(u64))
+        same_cut = np.array_equal(kept[s_i], workload["kept"][s_i])
+        print(f"[scale] fp8 shift {shifts[s_i]}: energy rel err {rel:.2e}, update cosine {cos:.10f}, "
+              f"kept {kept[s_i].tolist()} vs FP64 {workload['kept'][s_i].tolist()}", flush=True)
+        if same_cut:
+            compared += 1
+            assert rel <= 2e-4, (s_i, rel)
+            assert cos >= 0.999, (s_i, cos)
+    assert compared >= 1
     ctx.close()
