@@ -35,21 +35,23 @@ constexpr int AEDLD = AEDMAX + 1;     // LDS row stride of the window arrays
 
 struct Shared {
   union {
+    // Cholesky, Hessenberg reduction, selection, inverse iteration
     struct {
       double v1[EIG_MAXD];
       double v2[EIG_MAXD];
       double v3[EIG_MAXD];
+      double v4[EIG_MAXD];
     };
-    // QR phase only: the deflation window, its Schur vectors, the spike and
-    // the window's eigenvalues
+    // congruence (stage) and the QR phase (stage, and the deflation window,
+    // its Schur vectors, the spike and the window's eigenvalues)
     struct {
+      double stage[16][256];
       double aT[AEDMAX][AEDLD];
       double aZ[AEDMAX][AEDLD];
       double au[AEDMAX], av[AEDMAX];
       double ewr[AEDMAX], ewi[AEDMAX];
     };
   };
-  double stage[16][256];
   double red[NW];
   double sc[16];
   int isc[16];
@@ -206,115 +208,194 @@ __device__ void congruence(Shared& sh, const gdouble* L, gdouble* A, gdouble* W,
 // indices k+1..d-1 with vector v (v[k+1] = 1) stored in row k of V and
 // scalar tau[k]: P_k = I - tau v v^T.  A = Q Hs Q^T with Q = P_0 P_1 ... .
 //
-// Both sides of a step in two passes over the trailing columns:
-// P A P = A - tau (p v^T + v q'^T) with p = A v, q = A^T v,
-// beta = v^T A v and q' = q - tau beta v (rows above k+1 only get p v^T).
-// Pass 1: one wave per row reads the row once for p_i and its share of q;
-// the waves' q partials are summed in a fixed order (Qs scratch, 16 x d).
-__device__ void hessenberg(Shared& sh, gdouble* A, gdouble* V, gdouble* tau, gdouble* Qs, int d) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  constexpr int QCH = 4;                      // q accumulators per lane (256 columns)
-  for (int k = 0; k + 2 < d; ++k) {
-    double part = 0.0;
-    for (int i = k + 2 + tid; i < d; i += NT) {
-      const double x = A[(size_t)i * d + k];
-      part += x * x;
-    }
-    const double sigma = block_sum(sh, part);
-    const double alpha = A[(size_t)(k + 1) * d + k];
-    if (sigma == 0.0) {
-      if (tid == 0) tau[k] = 0.0;
-      for (int i = k + 1 + tid; i < d; i += NT) V[(size_t)k * d + i] = (i == k + 1) ? 1.0 : 0.0;
-      __syncthreads();
-      continue;
-    }
-    const double nrm = sqrt(alpha * alpha + sigma);
-    const double beta_h = alpha <= 0.0 ? nrm : -nrm;
-    const double v0 = alpha - beta_h;
-    const double tk = (beta_h - alpha) / beta_h;
+// Both sides of step k: P A P = A - tau (p v^T + v q'^T) with p = A v,
+// q = A^T v, beta = v^T p and q' = q - tau beta v (rows above k+1 only get
+// p v^T).  One pass over the matrix per step: column k+1 after step k is
+// formed first, which gives reflector k+1; the pass then writes step k's
+// update and, from the values it has just written, accumulates step k+1's
+// products p = A v (per row, one wave per row) and q = A^T v (per wave over
+// its rows, summed in a fixed order through the Qs scratch, 16 x d).
+
+// column value after a step: a - tau (p_i v_j + v_i q'_j)
+__device__ __forceinline__ double hess_upd(double a, double tk, double pi, double vj, double vi,
+                                           double qj) {
+  return a - tk * (pi * vj + vi * qj);
+}
+
+// Reflector of step k from column values c[i] (rows k+1..d-1) held in
+// vec[i]: on return vec holds v (zeros up to k, 1 at k+1), V row k and tau[k]
+// are written; returns tau, and the new subdiagonal entry in *beta_h.
+__device__ double hess_reflector(Shared& sh, double* vec, gdouble* V, gdouble* tau, int k, int d,
+                                 double* beta_h) {
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int i = k + 2 + tid; i < d; i += NT) part += vec[i] * vec[i];
+  const double sigma = block_sum(sh, part);
+  const double alpha = vec[k + 1];
+  if (sigma == 0.0) {
+    *beta_h = alpha;
     for (int i = tid; i < d; i += NT) {
-      const double vi = (i <= k) ? 0.0 : (i == k + 1) ? 1.0 : A[(size_t)i * d + k] / v0;
-      sh.v1[i] = vi;
+      const double vi = (i == k + 1) ? 1.0 : 0.0;
+      vec[i] = vi;
       if (i > k) V[(size_t)k * d + i] = vi;
-      sh.v2[i] = 0.0;   // p
     }
-    if (tid == 0) tau[k] = tk;
+    if (tid == 0) tau[k] = 0.0;
     __syncthreads();
-    // pass 1: p = A v (all rows), partial q = A^T v (rows > k) per wave.
-    // Two rows per wave at a time, loads unconditional (columns clamped,
-    // values past the end zeroed), so 2 QCH loads per lane are in flight.
-    const int j0 = k + 1, nj = d - j0;
-    for (int c0 = 0; c0 < nj; c0 += 64 * QCH) {
-      double qacc[QCH];
+    return 0.0;
+  }
+  const double nrm = sqrt(alpha * alpha + sigma);
+  const double bh = alpha <= 0.0 ? nrm : -nrm;
+  const double v0 = alpha - bh;
+  const double tk = (bh - alpha) / bh;
+  for (int i = tid; i < d; i += NT) {
+    const double vi = (i <= k) ? 0.0 : (i == k + 1) ? 1.0 : vec[i] / v0;
+    vec[i] = vi;
+    if (i > k) V[(size_t)k * d + i] = vi;
+  }
+  if (tid == 0) tau[k] = tk;
+  __syncthreads();
+  *beta_h = bh;
+  return tk;
+}
+
+// One pass over rows 0..d-1, columns k+1..d-1.  UPD: apply step k (v = cv,
+// p from Pg, q' = cq, scalar tk; column k set to beta_h e_(k+1)).  PROD:
+// accumulate p_next = A' nv into pn (LDS, zeroed by the caller) and the
+// per-wave partials of A'^T nv into Qs (columns k+2..d-1 when UPD, k+1..
+// otherwise).  Two rows per wave at a time; loads unconditional (columns
+// clamped), stores guarded.
+template <bool UPD, bool PROD>
+__device__ void hess_pass(Shared& sh, gdouble* A, int d, int k, double tk, double beta_h,
+                          const double* cv, const gdouble* Pg, const double* cq, const double* nv,
+                          double* pn, gdouble* Qs) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int QCH = 4;                      // columns per lane per chunk (256 per chunk)
+  const int j0 = k + 1, nj = d - j0;
+  for (int c0 = 0; c0 < nj; c0 += 64 * QCH) {
+    double qacc[QCH];
 #pragma unroll
-      for (int m = 0; m < QCH; ++m) qacc[m] = 0.0;
-      for (int i = wv; i < d; i += 2 * NW) {
-        const int i2 = i + NW;
-        const bool has2 = i2 < d;
-        const gdouble* A1 = A + (size_t)i * d + j0;
-        const gdouble* A2 = A + (size_t)(has2 ? i2 : i) * d + j0;
-        double a1[QCH], a2[QCH];
+    for (int m = 0; m < QCH; ++m) qacc[m] = 0.0;
+    for (int i = wv; i < d; i += 2 * NW) {
+      const int i2 = i + NW;
+      const bool has2 = i2 < d;
+      gdouble* A1 = A + (size_t)i * d + j0;
+      gdouble* A2 = A + (size_t)(has2 ? i2 : i) * d + j0;
+      double a1[QCH], a2[QCH];
 #pragma unroll
-        for (int m = 0; m < QCH; ++m) {
-          const int jc = min(c0 + lane + 64 * m, nj - 1);
-          a1[m] = A1[jc];
-          a2[m] = A2[jc];
-        }
-        const double v_1 = sh.v1[i], v_2 = has2 ? sh.v1[i2] : 0.0;
-        double p1 = 0.0, p2 = 0.0;
+      for (int m = 0; m < QCH; ++m) {
+        const int jc = min(c0 + lane + 64 * m, nj - 1);
+        a1[m] = A1[jc];
+        a2[m] = A2[jc];
+      }
+      double p1 = 0.0, p2 = 0.0;
+      const double nv1 = PROD ? nv[i] : 0.0, nv2 = (PROD && has2) ? nv[i2] : 0.0;
+      if (UPD) {
+        const double pi1 = Pg[i], pi2 = has2 ? Pg[i2] : 0.0;
+        const double vi1 = cv[i], vi2 = has2 ? cv[i2] : 0.0;
 #pragma unroll
         for (int m = 0; m < QCH; ++m) {
           const int j = c0 + lane + 64 * m;
           const bool ok = j < nj;
-          const double vj = ok ? sh.v1[j0 + j] : 0.0;
+          const double vj = ok ? cv[j0 + j] : 0.0, qj = ok ? cq[j0 + j] : 0.0;
+          a1[m] = hess_upd(a1[m], tk, pi1, vj, vi1, qj);
+          a2[m] = hess_upd(a2[m], tk, pi2, vj, vi2, qj);
+          if (ok) {
+            A1[j] = a1[m];
+            if (has2) A2[j] = a2[m];
+          }
+        }
+      }
+      if (PROD) {
+#pragma unroll
+        for (int m = 0; m < QCH; ++m) {
+          const int j = c0 + lane + 64 * m;
+          const bool ok = j < nj;
+          const double w = ok ? nv[j0 + j] : 0.0;
           const double x1 = ok ? a1[m] : 0.0, x2 = ok ? a2[m] : 0.0;
-          p1 += x1 * vj;
-          p2 += x2 * vj;
-          qacc[m] += v_1 * x1 + v_2 * x2;
+          p1 += x1 * w;
+          p2 += x2 * w;
+          qacc[m] += nv1 * x1 + nv2 * x2;
         }
         p1 = wave_sum(p1);
         p2 = wave_sum(p2);
         if (lane == 0) {
-          sh.v2[i] += p1;
-          if (has2) sh.v2[i2] += p2;
+          pn[i] += p1;
+          if (has2) pn[i2] += p2;
         }
       }
+    }
+    if (PROD) {
 #pragma unroll
       for (int m = 0; m < QCH; ++m) {
         const int j = lane + 64 * m;
         if (c0 + j < nj) Qs[(size_t)wv * d + j0 + c0 + j] = qacc[m];
       }
     }
-    __syncthreads();
-    // q' = q - tau beta v, beta = v^T p
+  }
+  if (UPD) {
+    for (int i = k + 1 + tid; i < d; i += NT) A[(size_t)i * d + k] = (i == k + 1) ? beta_h : 0.0;
+  }
+}
+
+__device__ void hessenberg(Shared& sh, gdouble* A, gdouble* V, gdouble* tau, gdouble* W, int d) {
+  const int tid = threadIdx.x;
+  if (d < 3) return;
+  gdouble* Qs = W;                            // [16][d] per-wave partials of A^T v
+  gdouble* Pg = W + (size_t)NW * d;           // [d] p = A v of the current step
+  // arrays: cv = v of step k, cq = q' of step k, nv = v of step k+1,
+  // pn = p of step k+1 (accumulated by the pass)
+  double* cv = sh.v1;
+  double* pn = sh.v2;
+  double* cq = sh.v3;
+  double* nv = sh.v4;
+  // step 0's reflector from column 0, and its products
+  for (int i = tid; i < d; i += NT) {
+    cv[i] = (i >= 1) ? A[(size_t)i * d] : 0.0;
+    pn[i] = 0.0;
+  }
+  __syncthreads();
+  double beta_h = 0.0;
+  double tk = hess_reflector(sh, cv, V, tau, 0, d, &beta_h);
+  hess_pass<false, true>(sh, A, d, 0, 0.0, 0.0, nullptr, nullptr, nullptr, cv, pn, Qs);
+  __syncthreads();
+  for (int k = 0; k + 2 < d; ++k) {
+    // p of step k to global (the pass reuses pn for step k+1), beta = v^T p
     double bp = 0.0;
-    for (int i = k + 1 + tid; i < d; i += NT) bp += sh.v1[i] * sh.v2[i];
+    for (int i = tid; i < d; i += NT) {
+      const double pi = pn[i];
+      Pg[i] = pi;
+      if (i > k) bp += cv[i] * pi;
+    }
     const double beta = block_sum(sh, bp);
-    for (int j = j0 + tid; j < d; j += NT) {
+    // q' = q - tau beta v (q summed over the waves in a fixed order)
+    for (int j = k + 1 + tid; j < d; j += NT) {
       double q = 0.0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) q += Qs[(size_t)w * d + j];
-      sh.v3[j] = q - tk * beta * sh.v1[j];
+      cq[j] = q - tk * beta * cv[j];
     }
     __syncthreads();
-    // pass 2: update the trailing columns; column k becomes beta_h e_(k+1).
-    // Loads of a row chunk are issued together (clamped), stores guarded.
-    for (int i = wv; i < d; i += NW) {
-      gdouble* Ai = A + (size_t)i * d;
-      const double pi = tk * sh.v2[i], vi = tk * sh.v1[i];
-      for (int c0 = j0; c0 < d; c0 += 64 * QCH) {
-        double a[QCH];
-#pragma unroll
-        for (int m = 0; m < QCH; ++m) a[m] = Ai[min(c0 + lane + 64 * m, d - 1)];
-#pragma unroll
-        for (int m = 0; m < QCH; ++m) {
-          const int j = c0 + lane + 64 * m;
-          if (j < d) Ai[j] = a[m] - (pi * sh.v1[j] + vi * sh.v3[j]);
-        }
+    const bool next = k + 3 < d;
+    double tk_next = 0.0, bh_next = 0.0;
+    if (next) {
+      // column k+1 after step k (v[k+1] = 1), rows k+2..d-1: reflector k+1
+      for (int i = tid; i < d; i += NT) {
+        nv[i] = (i >= k + 2) ? hess_upd(A[(size_t)i * d + k + 1], tk, Pg[i], 1.0, cv[i], cq[k + 1]) : 0.0;
+        pn[i] = 0.0;
       }
-      if (i > k && lane == 0) Ai[k] = (i == k + 1) ? beta_h : 0.0;
+      __syncthreads();
+      tk_next = hess_reflector(sh, nv, V, tau, k + 1, d, &bh_next);
+      hess_pass<true, true>(sh, A, d, k, tk, beta_h, cv, Pg, cq, nv, pn, Qs);
+    } else {
+      hess_pass<true, false>(sh, A, d, k, tk, beta_h, cv, Pg, cq, nullptr, nullptr, Qs);
     }
     __syncthreads();
+    // step k+1's vector becomes the current one
+    double* t = cv;
+    cv = nv;
+    nv = t;
+    tk = tk_next;
+    beta_h = bh_next;
   }
 }
 
