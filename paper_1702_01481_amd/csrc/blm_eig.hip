@@ -32,6 +32,18 @@ constexpr double DROP_TOL = 1e-12;
 
 constexpr int AEDMAX = 64;            // largest deflation window
 constexpr int AEDLD = AEDMAX + 1;     // LDS row stride of the window arrays
+constexpr int MAX_BULGES = 16;
+// bulge chase: ticks per batch (8 measured as fast as 12 and faster than 16,
+// whose register segments spill), largest diagonal window (at most
+// CT + 4 m for m <= MAX_BULGES bulges), its LDS row stride
+constexpr int CT = 8;
+constexpr int CWMAX = CT + 4 * MAX_BULGES + 4;
+constexpr int CWLD = CWMAX + 1;
+static_assert(CWMAX >= CT + 4 * MAX_BULGES + 2, "a batch's window must fit");
+
+struct ChaseRec {
+  double v0, v1, v2, bt;              // reflector I - bt v v^T; bt = 0: none
+};
 
 struct Shared {
   union {
@@ -46,10 +58,16 @@ struct Shared {
     // its Schur vectors, the spike and the window's eigenvalues)
     struct {
       double stage[16][256];
-      double aT[AEDMAX][AEDLD];
-      double aZ[AEDMAX][AEDLD];
+      union {
+        struct {
+          double aT[AEDMAX][AEDLD];
+          double aZ[AEDMAX][AEDLD];
+        };
+        double cw[CWMAX][CWLD];       // bulge chase: the diagonal window of a batch
+      };
       double au[AEDMAX], av[AEDMAX];
       double ewr[AEDMAX], ewi[AEDMAX];
+      ChaseRec rec[CT][MAX_BULGES];   // bulge chase: reflectors of a batch [tick][bulge]
     };
   };
   double red[NW];
@@ -627,7 +645,190 @@ __device__ double wave_rehess(double (*T)[AEDLD], double (*Z)[AEDLD], double* u,
 // 10 sweeps without deflation) one bulge uses the trailing 2x2 block's
 // eigenvalues, or an ad hoc pair.  Deflation: a subdiagonal entry below
 // eps (|a_{i-1,i-1}| + |a_ii|) is set to zero.
-constexpr int MAX_BULGES = 16;
+// ------------------------------------------- step 4b: windowed bulge chase --
+// One multishift sweep (m bulges, shifts in sh.bsum / sh.bprod) over the
+// active block l..h, in batches of CT ticks.  At tick t bulge g sits at
+// K = l - 1 + t - 4 g (active while l - 1 <= K <= h - 2) and applies its
+// 3 x 3 reflector P = I - bt v v^T (2 x 2 at the bottom) to rows and to
+// columns K+1..K+3.  Per batch:
+//   1. the diagonal window that holds every element those reflectors reach
+//      near the diagonal is copied to LDS; the ticks run there (reflector
+//      from the window, its rows and columns updated inside the window) and
+//      each reflector is recorded;
+//   2. the window is written back, and the recorded reflectors are applied
+//      outside it: from the left to the columns right of the window, from
+//      the right to the rows above it.
+// Every element receives the same reflectors in the same order as in a
+// tick-by-tick sweep: where a leading and a trailing bulge touch the same
+// rows (or columns), the leading bulge's reflector always comes first, so
+// the far parts can take one bulge's reflectors after another.  They are
+// read and written once per batch instead of once per tick.
+
+// Bulge g's recorded reflectors (ticks 0..CT-1) applied to a segment of
+// CT + 2 consecutive rows (or columns) that starts at the bulge's first one.
+__device__ __forceinline__ void chase_apply(const Shared& sh, int g, double (&x)[CT + 2]) {
+#pragma unroll
+  for (int tau = 0; tau < CT; ++tau) {
+    const ChaseRec R = sh.rec[tau][g];
+    const double tt = R.bt * (R.v0 * x[tau] + R.v1 * x[tau + 1] + R.v2 * x[tau + 2]);
+    x[tau] -= tt * R.v0;
+    x[tau + 1] -= tt * R.v1;
+    x[tau + 2] -= tt * R.v2;
+  }
+}
+
+// The recorded reflectors of a batch (first tick t0) applied to one item
+// outside the window: a column right of it (right = true: rows change) or
+// a row above it (columns change).  Bulge g's segment starts at position
+// l + t0 - 4 g; consecutive bulges' segments overlap, so the segment rolls
+// through registers: 4 new entries loaded, 4 finished ones stored per bulge.
+// Only positions inside the window [wlo, whi] can change; loads are clamped
+// there and stores limited to it.
+template <class Real>
+__device__ void chase_far(const Shared& sh, Real* A, int ld, int wlo, int whi, int t0, int l, int m,
+                          bool right, int item) {
+  auto ptr = [&](int pos) -> Real* {
+    const int q = min(max(pos, wlo), whi);
+    return right ? A + (size_t)q * ld + item : A + (size_t)item * ld + q;
+  };
+  double x[CT + 2];
+  int B = l + t0;
+#pragma unroll
+  for (int i = 0; i < CT + 2; ++i) x[i] = *ptr(B + i);
+  for (int g = 0; g < m; ++g) {
+    chase_apply(sh, g, x);
+    const int nfin = (g + 1 < m) ? 4 : CT + 2;     // entries final after this bulge
+#pragma unroll
+    for (int i = 0; i < CT + 2; ++i) {
+      const int pos = B + i;
+      if (i >= CT + 2 - nfin && pos >= wlo && pos <= whi) *ptr(pos) = x[i];
+    }
+    if (g + 1 < m) {
+#pragma unroll
+      for (int i = CT + 1; i >= 4; --i) x[i] = x[i - 4];
+      B -= 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = *ptr(B + i);
+    }
+  }
+}
+
+template <class Real>
+__device__ void chase_windowed(Shared& sh, Real* A, int ld, int l, int h, int m) {
+  const int tid = threadIdx.x;
+  // group grp of G threads carries bulge grp
+  const int mp = m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16;
+  const int G = NT / mp, grp = tid / G, lt = tid % G;
+  const int ticks = (h - l) + 4 * (m - 1);
+  for (int t0 = 0; t0 < ticks; t0 += CT) {
+    const int t1 = min(t0 + CT, ticks);
+    // the batch's reflectors sit at K in [Kmin, Kmax]; they reach rows and
+    // columns up to K + 4 near the diagonal
+    const int Kmax = min(l - 1 + t1 - 1, h - 2);
+    const int Kmin = min(max(l - 1, l - 1 + t0 - 4 * (m - 1)), h - 2);
+    const int wlo = max(l, Kmin), whi = min(h, Kmax + 4);
+    const int nw = whi - wlo + 1;                   // <= CT + 4 m <= CWMAX
+    for (int e = tid; e < nw * nw; e += NT) {
+      const int i = e / nw, j = e % nw;
+      sh.cw[i][j] = A[(size_t)(wlo + i) * ld + wlo + j];
+    }
+    for (int e = tid; e < CT * MAX_BULGES; e += NT)
+      sh.rec[e / MAX_BULGES][e % MAX_BULGES] = ChaseRec{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+    auto W = [&](int i, int j) -> double& { return sh.cw[i - wlo][j - wlo]; };
+    for (int t = t0; t < t1; ++t) {
+      const int K = l - 1 + t - 4 * grp;
+      const bool act = grp < m && K >= l - 1 && K <= h - 2;
+      const int nr = (K <= h - 3) ? 3 : 2;
+      double v0 = 0.0, v1 = 0.0, v2 = 0.0, bt = 0.0, newsub = 0.0;
+      bool refl = false;
+      if (act) {
+        double x, y, z;
+        if (K == l - 1) {
+          const double ssum = sh.bsum[grp], sprod = sh.bprod[grp];
+          const double h00 = W(l, l), h01 = W(l, l + 1), h10 = W(l + 1, l);
+          const double h11 = W(l + 1, l + 1), h21 = W(l + 2, l + 1);
+          x = h00 * h00 + h01 * h10 - ssum * h00 + sprod;
+          y = h10 * (h00 + h11 - ssum);
+          z = h10 * h21;
+        } else {
+          x = sh.bx[grp][0];
+          y = sh.bx[grp][1];
+          z = sh.bx[grp][2];
+        }
+        if (nr == 2) z = 0.0;
+        const double sc = fabs(x) + fabs(y) + fabs(z);
+        if (sc != 0.0) {
+          refl = true;
+          const double xs = x / sc, ys = y / sc, zs = z / sc;
+          const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
+          v0 = xs + al;
+          v1 = ys;
+          v2 = zs;
+          bt = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+          newsub = -al * sc;
+        }
+        if (refl && lt == 0) sh.rec[t - t0][grp] = ChaseRec{v0, v1, v2, bt};
+      }
+      // a bulge entering at the top read the window's first rows, which its
+      // own group rewrites below: let every wave finish reading first
+      if ((t & 3) == 0 && (t >> 2) < m) __syncthreads();
+      if (act && refl) {
+        // rows K+1..K+nr, window columns max(l, K+1)..whi; the bulge column
+        // K is set directly
+        const int c0 = (K >= l) ? K + 1 : l;
+        for (int c = c0 + lt; c <= whi; c += G) {
+          const double x0 = W(K + 1, c), x1 = W(K + 2, c), x2 = (nr == 3) ? W(K + 3, c) : 0.0;
+          const double tt = bt * (v0 * x0 + v1 * x1 + v2 * x2);
+          W(K + 1, c) = x0 - tt * v0;
+          W(K + 2, c) = x1 - tt * v1;
+          if (nr == 3) W(K + 3, c) = x2 - tt * v2;
+        }
+        if (K >= l && lt == 0) {
+          W(K + 1, K) = newsub;
+          W(K + 2, K) = 0.0;
+          if (nr == 3) W(K + 3, K) = 0.0;
+        }
+      }
+      __syncthreads();
+      if (act) {
+        // columns K+1..K+nr, window rows wlo..min(K+4, h); keep column K+1's
+        // entries below the diagonal (the next bulge) for the next tick
+        const int r1 = (K + 4 < h) ? K + 4 : h;
+        for (int rr = wlo + lt; rr <= r1; rr += G) {
+          const double y0 = W(rr, K + 1), y1 = W(rr, K + 2), y2 = (nr == 3) ? W(rr, K + 3) : 0.0;
+          double n0 = y0;
+          if (refl) {
+            const double tt = bt * (y0 * v0 + y1 * v1 + y2 * v2);
+            n0 = y0 - tt * v0;
+            W(rr, K + 1) = n0;
+            W(rr, K + 2) = y1 - tt * v1;
+            if (nr == 3) W(rr, K + 3) = y2 - tt * v2;
+          }
+          if (rr >= K + 2) sh.bx[grp][rr - K - 2] = n0;
+        }
+        if (K + 4 > h && lt == 0) sh.bx[grp][2] = 0.0;
+        if (K + 3 > h && lt == 0) sh.bx[grp][1] = 0.0;
+      }
+      __syncthreads();
+    }
+    // the window back; the batch's reflectors to the columns right of it
+    // (from the left) and to the rows above it (from the right)
+    for (int e = tid; e < nw * nw; e += NT) {
+      const int i = e / nw, j = e % nw;
+      A[(size_t)(wlo + i) * ld + wlo + j] = sh.cw[i][j];
+    }
+    const int nright = h - whi, ntop = wlo - l;
+    for (int it = tid; it < nright + ntop; it += NT) {
+      if (it < nright)
+        chase_far(sh, A, ld, wlo, whi, t0, l, m, true, whi + 1 + it);
+      else
+        chase_far(sh, A, ld, wlo, whi, t0, l, m, false, l + (it - nright));
+    }
+    __syncthreads();
+  }
+}
+
 constexpr int AED_MIN_W = 75;   // active blocks at least this wide use early deflation
 constexpr int AED_NIBBLE = 14;  // percent of the window deflated to skip a sweep
 constexpr int CU = 4;           // chase: elements per thread whose loads go out together
@@ -856,6 +1057,11 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
     if (MULTI && tid == 0) {
       sh.qst[0] += t_chase - t_aed;
       sh.qst[3] += 1;
+    }
+    if constexpr (MULTI) {
+      chase_windowed(sh, A, ld, l, h, m);
+      if (tid == 0) sh.qst[1] += wall_clock64() - t_chase;
+      continue;
     }
     // chase: group g of G threads carries bulge g
     const int mp = m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16;
