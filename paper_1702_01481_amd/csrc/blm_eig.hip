@@ -435,6 +435,26 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// Householder reflector P = I - bt v v^T with P (x, y, z)^T = (beta, 0, 0)^T.
+// The inputs are scaled by a power of two (exact) instead of by their sum,
+// and bt = 2 / |v|^2 = 1 / (al v0) since |v|^2 = 2 al (al + x): one division
+// and one square root, which are the latency of a bulge step.  Returns false
+// (no reflector) if x = y = z = 0.
+__device__ __forceinline__ bool house3(double x, double y, double z, double& v0, double& v1,
+                                       double& v2, double& bt, double& beta) {
+  const double m = fmax(fabs(x), fmax(fabs(y), fabs(z)));
+  if (m == 0.0) return false;
+  const int e = ilogb(m);
+  const double xs = ldexp(x, -e), ys = ldexp(y, -e), zs = ldexp(z, -e);
+  const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
+  v0 = xs + al;
+  v1 = ys;
+  v2 = zs;
+  bt = 1.0 / (al * v0);
+  beta = -ldexp(al, e);
+  return true;
+}
+
 // Real Schur form of the n x n upper Hessenberg T (n <= AEDMAX) by Francis
 // double-shift QR with whole-row and whole-column updates, accumulating the
 // transformations into Z (which enters as the identity): T_in = Z T_out Z^T.
@@ -488,22 +508,38 @@ __device__ bool wave_schur(double (*T)[AEDLD], double (*Z)[AEDLD], int n) {
         z = (nr == 3) ? T[K + 3][K] : 0.0;
       }
       if (nr == 2) z = 0.0;
-      const double sc = fabs(x) + fabs(y) + fabs(z);
-      if (sc == 0.0) continue;
-      const double xs = x / sc, ys = y / sc, zs = z / sc;
-      const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
-      const double v0 = xs + al, v1 = ys, v2 = zs;
-      const double bt = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
-      for (int c = K + 1 + lane; c < n; c += 64) {
-        double tt = v0 * T[K + 1][c] + v1 * T[K + 2][c];
-        if (nr == 3) tt += v2 * T[K + 3][c];
-        tt *= bt;
-        T[K + 1][c] -= tt * v0;
-        T[K + 2][c] -= tt * v1;
-        if (nr == 3) T[K + 3][c] -= tt * v2;
+      double v0, v1, v2, bt, beta;
+      if (!house3(x, y, z, v0, v1, v2, bt, beta)) continue;
+      // Z <- Z P does not depend on T: for n <= 32 the upper half-wave updates
+      // Z's columns in the same instructions in which the lower half updates
+      // T's rows (three elements at a stride: a row of T across, a column of
+      // Z down)
+      const bool zsplit = n <= 32;
+      if (zsplit) {
+        const bool zl = lane >= 32;
+        const int c = zl ? lane - 32 : K + 1 + lane;
+        if (c < n) {
+          double* p0 = zl ? &Z[c][K + 1] : &T[K + 1][c];
+          const int st = zl ? 1 : AEDLD;
+          double tt = v0 * p0[0] + v1 * p0[st];
+          if (nr == 3) tt += v2 * p0[2 * st];
+          tt *= bt;
+          p0[0] -= tt * v0;
+          p0[st] -= tt * v1;
+          if (nr == 3) p0[2 * st] -= tt * v2;
+        }
+      } else {
+        for (int c = K + 1 + lane; c < n; c += 64) {
+          double tt = v0 * T[K + 1][c] + v1 * T[K + 2][c];
+          if (nr == 3) tt += v2 * T[K + 3][c];
+          tt *= bt;
+          T[K + 1][c] -= tt * v0;
+          T[K + 2][c] -= tt * v1;
+          if (nr == 3) T[K + 3][c] -= tt * v2;
+        }
       }
       if (K >= l && lane == 0) {
-        T[K + 1][K] = -al * sc;
+        T[K + 1][K] = beta;
         T[K + 2][K] = 0.0;
         if (nr == 3) T[K + 3][K] = 0.0;
       }
@@ -516,7 +552,7 @@ __device__ bool wave_schur(double (*T)[AEDLD], double (*Z)[AEDLD], int n) {
         T[r][K + 2] -= tt * v1;
         if (nr == 3) T[r][K + 3] -= tt * v2;
       }
-      for (int r = lane; r < n; r += 64) {
+      for (int r = lane; r < n && !zsplit; r += 64) {
         double tt = Z[r][K + 1] * v0 + Z[r][K + 2] * v1;
         if (nr == 3) tt += Z[r][K + 3] * v2;
         tt *= bt;
@@ -757,17 +793,7 @@ __device__ void chase_windowed(Shared& sh, Real* A, int ld, int l, int h, int m)
           z = sh.bx[grp][2];
         }
         if (nr == 2) z = 0.0;
-        const double sc = fabs(x) + fabs(y) + fabs(z);
-        if (sc != 0.0) {
-          refl = true;
-          const double xs = x / sc, ys = y / sc, zs = z / sc;
-          const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
-          v0 = xs + al;
-          v1 = ys;
-          v2 = zs;
-          bt = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
-          newsub = -al * sc;
-        }
+        refl = house3(x, y, z, v0, v1, v2, bt, newsub);
         if (refl && lt == 0) sh.rec[t - t0][grp] = ChaseRec{v0, v1, v2, bt};
       }
       // a bulge entering at the top read the window's first rows, which its
@@ -1088,17 +1114,7 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
           z = sh.bx[grp][2];
         }
         if (nr == 2) z = 0.0;
-        const double sc = fabs(x) + fabs(y) + fabs(z);
-        if (sc != 0.0) {
-          refl = true;
-          const double xs = x / sc, ys = y / sc, zs = z / sc;
-          const double al = copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
-          v0 = xs + al;
-          v1 = ys;
-          v2 = zs;
-          bt = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
-          newsub = -al * sc;
-        }
+        refl = house3(x, y, z, v0, v1, v2, bt, newsub);
       }
       // a bulge entering at the top read the window's first rows, which its
       // own group rewrites below: let every wave finish reading first
