@@ -127,6 +127,19 @@ def test_previous_directions_ragged_chunks(weighted):
     _compare_step(offsets, 2, [1e-4, 1e-3, 1e-2], host, dev, old=old, n_old=2)
 
 
+def test_uneven_blocks_with_a_large_pencil():
+    """Uneven blocks as in the 40-block workload (sizes from about 100 to
+    2,000): one block of 1,100 parameters (pencil dimension 1,103: QR with
+    the widest early-deflation windows and 24 shifts a sweep), one previous
+    direction, two shifts, and an empty chunk between two ragged ones."""
+    offsets = [0, 107, 1207, 1500]
+    host, dev = _make(1500, 24000, 16, 7, 13000)
+    host.insert(1, tuple(None if a is None else a[:0] for a in host[0]))
+    dev.insert(1, tuple(None if a is None else a[:0] for a in dev[0]))
+    old = synth.old_directions(1, 1500, 5).numpy()
+    _compare_step(offsets, 4, [1e-3, 1e-2], host, dev, old=old, n_old=1)
+
+
 def test_multi_tile_blocks():
     """Blocks spanning several 64-wide tiles with ragged edges."""
     offsets = [0, 150, 341]
