@@ -60,6 +60,8 @@ struct blm_ctx {
   int64_t max_samples = 0;
   hipStream_t st = nullptr;
   int device = 0;
+  int n_cus = 0;                   // compute units of the device (0: unknown)
+  unsigned* d_hbar = nullptr;      // block solves: barrier counter and flag per pencil
   std::string err;
   int state = ST_CREATED;
 
@@ -375,6 +377,7 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_asm2, sizeof(AsmJob) * (size_t)NS);
   add((void**)&c->d_asm_x, sizeof(AsmJob));
   add((void**)&c->d_info1, 4 * EIG_INFO * (size_t)NS * NB);
+  add((void**)&c->d_hbar, 4 * 2 * (size_t)NS * NB);
   add((void**)&c->d_info2, 4 * EIG_INFO * (size_t)NS);
   add((void**)&c->d_ev1, 16 * (size_t)NS * NB * (NK + 1));
   add((void**)&c->d_ev2, 16 * (size_t)NS * 2);
@@ -719,6 +722,8 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
     delete c;
     return BLM_E_HIP;
   }
+  if (hipDeviceGetAttribute(&c->n_cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+    c->n_cus = 0;
   Plan P;
   plan(c, P);
   for (auto& it : P.items) {
@@ -977,7 +982,7 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   HIPCHK(c, hipGetLastError());
   mark(c, 3, true);
   mark(c, 4, false);
-  launch_eig(c->d_eig1, (int)ej.size(), c->st);
+  launch_eig_split(c->d_eig1, (int)ej.size(), c->n_cus, c->d_hbar, c->st);
   HIPCHK(c, hipGetLastError());
   mark(c, 4, true);
   std::vector<int32_t> info((size_t)EIG_INFO * NS * NB);

@@ -26,6 +26,12 @@ namespace blm {
 namespace {
 
 constexpr int NT = EIG_THREADS;
+constexpr int HKW_MAX = 8;            // workgroups per pencil in the distributed Hessenberg reduction
+// smallest pencil it takes (smaller ones stay on one workgroup); its
+// workspace, 2 d + 2 kw d doubles, fits in the 2 d^2 of W
+constexpr int HESS_MULTI_MIN = 256;
+static_assert(2 * HESS_MULTI_MIN >= 2 + 2 * HKW_MAX, "workspace of the distributed reduction");
+enum : int { PH_FRONT = 1, PH_HESS = 2, PH_BACK = 4 };
 constexpr int NW = NT / 64;
 constexpr double EPS = DBL_EPSILON;
 constexpr double DROP_TOL = 1e-12;
@@ -1446,6 +1452,249 @@ __device__ void back_transform_wave(const gdouble* V, const gdouble* tau, const 
 
 // An eigen-job with its buffers typed as global memory, so that every access
 // is a global (not flat) memory instruction and LDS waits never wait for them.
+// ------------------------------------- step 3, distributed over workgroups --
+// The one-pass Hessenberg reduction of hessenberg() with each pencil's rows
+// split over kw workgroups (a cooperative launch: all resident).  Per step
+// every workgroup forms, redundantly and in the same order (so identically),
+// beta = v^T p, q' and the next reflector from p (global, one entry per row,
+// written by the row's owner), the per-workgroup partials of A^T v (global)
+// and column k+1; then it updates its own rows and accumulates their part of
+// the next step's products.  p and the partials are double-buffered by step
+// parity; one barrier per step separates the steps.  The barrier is a
+// counter per pencil in global memory with a bounded wait: past the bound
+// the pencil's error flag is set and every workgroup leaves.
+
+constexpr int HQCH = 4;  // column chunks of 64 per row pass
+
+struct HessShared {
+  double cv[EIG_MAXD];        // v of step k
+  double cq[EIG_MAXD];        // q' of step k
+  double nv[EIG_MAXD];        // v of step k+1
+  double qw[NW][64 * HQCH];   // per-wave partials of A^T v for one column chunk
+  double red[NW];
+  int ok;
+};
+
+__device__ double hs_block_sum(HessShared& hs, double v) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) hs.red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += hs.red[w];
+  __syncthreads();
+  return t;
+}
+
+// barrier among the kw workgroups of a pencil: cnt counts arrivals, err is
+// the pencil's flag; returns false if the wait ran past its bound (or
+// another workgroup's did)
+__device__ bool pencil_barrier(HessShared& hs, unsigned* cnt, int* err, unsigned target) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(cnt, 1u);
+    int ok = 1;
+    for (unsigned spins = 0;; ++spins) {
+      if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spins > (1u << 22)) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    hs.ok = ok;
+  }
+  __syncthreads();
+  return hs.ok != 0;
+}
+
+// reflector of step k from column values in vec (rows k+1..d-1), as in
+// hess_reflector; only `writer` stores V row k and tau[k]
+__device__ double hess_reflector_hs(HessShared& hs, double* vec, gdouble* V, gdouble* tau, int k, int d,
+                                    double* beta_h, bool writer) {
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int i = k + 2 + tid; i < d; i += NT) part += vec[i] * vec[i];
+  const double sigma = hs_block_sum(hs, part);
+  const double alpha = vec[k + 1];
+  double tk = 0.0, v0 = 1.0;
+  if (sigma == 0.0) {
+    *beta_h = alpha;
+  } else {
+    const double nrm = sqrt(alpha * alpha + sigma);
+    const double bh = alpha <= 0.0 ? nrm : -nrm;
+    v0 = alpha - bh;
+    tk = (bh - alpha) / bh;
+    *beta_h = bh;
+  }
+  for (int i = tid; i < d; i += NT) {
+    const double vi = (i <= k) ? 0.0 : (i == k + 1) ? 1.0 : (sigma == 0.0 ? 0.0 : vec[i] / v0);
+    vec[i] = vi;
+    if (writer && i > k) V[(size_t)k * d + i] = vi;
+  }
+  if (writer && tid == 0) tau[k] = tk;
+  __syncthreads();
+  return tk;
+}
+
+// own rows [r0, r1): step k's update (UPD) and the next products (PROD)
+template <bool UPD, bool PROD>
+__device__ void hess_pass_rows(HessShared& hs, gdouble* A, int d, int k, int r0, int r1, double tk,
+                               double beta_h, const double* cv, const gdouble* Pc, const double* cq,
+                               const double* nv, gdouble* Pn, gdouble* Qn) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int QCH = HQCH;
+  const int j0 = k + 1, nj = d - j0;
+  for (int c0 = 0; c0 < nj; c0 += 64 * QCH) {
+    double qacc[QCH];
+#pragma unroll
+    for (int m = 0; m < QCH; ++m) qacc[m] = 0.0;
+    for (int i = r0 + wv; i < r1; i += 2 * NW) {
+      const int i2 = i + NW;
+      const bool has2 = i2 < r1;
+      gdouble* A1 = A + (size_t)i * d + j0;
+      gdouble* A2 = A + (size_t)(has2 ? i2 : i) * d + j0;
+      double a1[QCH], a2[QCH];
+#pragma unroll
+      for (int m = 0; m < QCH; ++m) {
+        const int jc = min(c0 + lane + 64 * m, nj - 1);
+        a1[m] = A1[jc];
+        a2[m] = A2[jc];
+      }
+      if (UPD) {
+        const double pi1 = Pc[i], pi2 = has2 ? Pc[i2] : 0.0;
+        const double vi1 = cv[i], vi2 = has2 ? cv[i2] : 0.0;
+#pragma unroll
+        for (int m = 0; m < QCH; ++m) {
+          const int j = c0 + lane + 64 * m;
+          const bool ok = j < nj;
+          const double vj = ok ? cv[j0 + j] : 0.0, qj = ok ? cq[j0 + j] : 0.0;
+          a1[m] = hess_upd(a1[m], tk, pi1, vj, vi1, qj);
+          a2[m] = hess_upd(a2[m], tk, pi2, vj, vi2, qj);
+          if (ok) {
+            A1[j] = a1[m];
+            if (has2) A2[j] = a2[m];
+          }
+        }
+      }
+      if (PROD) {
+        const double nv1 = nv[i], nv2 = has2 ? nv[i2] : 0.0;
+        double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < QCH; ++m) {
+          const int j = c0 + lane + 64 * m;
+          const bool ok = j < nj;
+          const double w = ok ? nv[j0 + j] : 0.0;
+          const double x1 = ok ? a1[m] : 0.0, x2 = ok ? a2[m] : 0.0;
+          p1 += x1 * w;
+          p2 += x2 * w;
+          qacc[m] += nv1 * x1 + nv2 * x2;
+        }
+        p1 = wave_sum(p1);
+        p2 = wave_sum(p2);
+        if (lane == 0) {
+          Pn[i] = (c0 == 0 ? 0.0 : Pn[i]) + p1;
+          if (has2) Pn[i2] = (c0 == 0 ? 0.0 : Pn[i2]) + p2;
+        }
+      }
+    }
+    if (PROD) {
+      // the waves' partials of this chunk summed in LDS in a fixed order;
+      // the workgroup's partial goes to global memory
+#pragma unroll
+      for (int m = 0; m < QCH; ++m) hs.qw[wv][lane + 64 * m] = qacc[m];
+      __syncthreads();
+      if (tid < 64 * QCH && c0 + tid < nj) {
+        double q = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) q += hs.qw[w][tid];
+        Qn[j0 + c0 + tid] = q;
+      }
+      __syncthreads();
+    }
+  }
+  if (UPD) {
+    for (int i = max(r0, k + 1) + tid; i < r1; i += NT) A[(size_t)i * d + k] = (i == k + 1) ? beta_h : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict__ jobs, int n_jobs, int kw,
+                                                        unsigned* __restrict__ bar) {
+  __shared__ HessShared hs;
+  const int job = blockIdx.x % n_jobs, part = blockIdx.x / n_jobs;
+  const EigJob& E = jobs[job];
+  const int d = E.d, tid = threadIdx.x;
+  gdouble* A = as_global(E.A);
+  gdouble* V = as_global(E.V);
+  gdouble* tau = as_global(E.tau);
+  gdouble* W = as_global(E.W);
+  BLM_GLOBAL int32_t* info = as_global(E.info);
+  if (d < HESS_MULTI_MIN || d > EIG_MAXD || info[0] != EIG_OK) return;
+  const uint64_t t_start = wall_clock64();
+  unsigned* cnt = bar + 2 * job;
+  int* err = (int*)(bar + 2 * job + 1);
+  const int r0 = (int)((int64_t)d * part / kw), r1 = (int)((int64_t)d * (part + 1) / kw);
+  const bool writer = part == 0;
+  // workspace: p [2][d], per-workgroup partials of A^T v [2][kw][d]
+  gdouble* Pb[2] = {W, W + d};
+  gdouble* Qb[2] = {W + 2 * (size_t)d, W + 2 * (size_t)d + (size_t)kw * d};
+  double* cv = hs.cv;
+  double* cq = hs.cq;
+  double* nv = hs.nv;
+  unsigned gen = 0;
+  // step 0: reflector from column 0, its products over the own rows
+  for (int i = tid; i < d; i += NT) cv[i] = (i >= 1) ? A[(size_t)i * d] : 0.0;
+  __syncthreads();
+  double beta_h = 0.0;
+  double tk = hess_reflector_hs(hs, cv, V, tau, 0, d, &beta_h, writer);
+  hess_pass_rows<false, true>(hs, A, d, 0, r0, r1, 0.0, 0.0, nullptr, nullptr, nullptr, cv, Pb[0],
+                              Qb[0] + (size_t)part * d);
+  if (!pencil_barrier(hs, cnt, err, kw * ++gen)) return;
+  for (int k = 0; k + 2 < d; ++k) {
+    const int cur = k & 1, nxt = cur ^ 1;
+    const gdouble* Pc = Pb[cur];
+    const gdouble* Qc = Qb[cur];
+    // beta = v^T p; q' = sum of the partials - tau beta v (fixed order);
+    // all loads of a column are issued before the sums
+    double bp = 0.0;
+    for (int j = k + 1 + tid; j < d; j += NT) {
+      double qp[HKW_MAX];
+#pragma unroll
+      for (int w = 0; w < HKW_MAX; ++w) qp[w] = (w < kw) ? Qc[(size_t)w * d + j] : 0.0;
+      bp += cv[j] * Pc[j];
+      double q = 0.0;
+#pragma unroll
+      for (int w = 0; w < HKW_MAX; ++w) q += qp[w];
+      cq[j] = q;
+    }
+    const double beta = hs_block_sum(hs, bp);
+    for (int j = k + 1 + tid; j < d; j += NT) cq[j] -= tk * beta * cv[j];
+    __syncthreads();
+    const bool next = k + 3 < d;
+    double tk_next = 0.0, bh_next = 0.0;
+    if (next) {
+      for (int i = tid; i < d; i += NT)
+        nv[i] = (i >= k + 2) ? hess_upd(A[(size_t)i * d + k + 1], tk, Pc[i], 1.0, cv[i], cq[k + 1]) : 0.0;
+      __syncthreads();
+      tk_next = hess_reflector_hs(hs, nv, V, tau, k + 1, d, &bh_next, writer);
+      hess_pass_rows<true, true>(hs, A, d, k, r0, r1, tk, beta_h, cv, Pc, cq, nv, Pb[nxt],
+                                 Qb[nxt] + (size_t)part * d);
+    } else {
+      hess_pass_rows<true, false>(hs, A, d, k, r0, r1, tk, beta_h, cv, Pc, cq, nullptr, nullptr, nullptr);
+    }
+    if (!pencil_barrier(hs, cnt, err, kw * ++gen)) return;
+    double* t = cv;
+    cv = nv;
+    nv = t;
+    tk = tk_next;
+    beta_h = bh_next;
+  }
+  if (writer && tid == 0) info[6] = (int32_t)((wall_clock64() - t_start));
+}
+
 struct GJob {
   int32_t d, mode, n_want, beta0, nbeta;
   gdouble *S, *A, *Hq, *V, *W, *vec, *wr, *wi, *tau, *out, *out_evals;
@@ -1481,28 +1730,39 @@ __device__ __forceinline__ void phase_mark(const GJob& J, uint64_t& t, int i) {
   t = now;
 }
 
-__global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs) {
+// phases: PH_FRONT Cholesky and congruence, PH_HESS the Hessenberg
+// reduction, PH_BACK the rest.  A launch runs the phases its mask names; a
+// pencil whose status is already an error skips the later ones.
+__global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs, int phases) {
   __shared__ Shared sh;
   const GJob J = global_view(jobs[blockIdx.x]);
   const int d = J.d, tid = threadIdx.x, wv = tid >> 6;
   uint64_t clk = wall_clock64();
-  if (tid == 0) {
-    sh.isc[2] = 0;
+  if (tid == 0) sh.isc[2] = 0;
+  if ((phases & PH_FRONT) && tid == 0)
     for (int i = 0; i < EIG_INFO; ++i) J.info[i] = 0;
-  }
   __syncthreads();
   if (d <= 0 || d > EIG_MAXD) return;
+  if (!(phases & PH_FRONT) && J.info[0] != EIG_OK) return;
 
-  int st = cholesky(sh, J.S, d);
-  if (st != EIG_OK) {
-    if (tid == 0) J.info[0] = st;
-    return;
+  int st = EIG_OK;
+  if (phases & PH_FRONT) {
+    st = cholesky(sh, J.S, d);
+    if (st != EIG_OK) {
+      if (tid == 0) J.info[0] = st;
+      return;
+    }
+    phase_mark(J, clk, 0);
+    congruence(sh, J.S, J.A, J.W, d);
+    phase_mark(J, clk, 1);
   }
-  phase_mark(J, clk, 0);
-  congruence(sh, J.S, J.A, J.W, d);
-  phase_mark(J, clk, 1);
-  hessenberg(sh, J.A, J.V, J.tau, J.W, d);
-  phase_mark(J, clk, 2);
+  // after a distributed reduction (PH_HESS not set) the small pencils it
+  // left out are reduced here
+  if ((phases & PH_HESS) || ((phases & PH_BACK) && d < HESS_MULTI_MIN)) {
+    hessenberg(sh, J.A, J.V, J.tau, J.W, d);
+    phase_mark(J, clk, 2);
+  }
+  if (!(phases & PH_BACK)) return;
   for (size_t i = tid; i < (size_t)d * d; i += NT) J.Hq[i] = J.A[i];
   __syncthreads();
   // norm of the Hessenberg matrix for the inverse-iteration pivot floor
@@ -1605,7 +1865,36 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
 
 void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st) {
   if (n_jobs <= 0) return;
-  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs);
+  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, PH_FRONT | PH_HESS | PH_BACK);
+}
+
+__global__ void fill_u32_kernel(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int n_cus, unsigned* d_bar, hipStream_t st) {
+  if (n_jobs <= 0) return true;
+  const int kw = min(HKW_MAX, n_cus / n_jobs);
+  if (kw < 2) {
+    launch_eig(d_jobs, n_jobs, st);
+    return true;
+  }
+  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_FRONT);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * n_jobs + 255) / 256), dim3(256), 0, st, d_bar, 2 * n_jobs);
+  int nj = n_jobs, k = kw;
+  void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&k, (void*)&d_bar};
+  const hipError_t e = hipLaunchCooperativeKernel((const void*)hess_multi_kernel, dim3(n_jobs * kw), dim3(NT),
+                                                  args, 0, st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // the workgroups cannot all be resident: the Hessenberg reduction one
+    // workgroup per pencil
+    hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)(PH_HESS | PH_BACK));
+    return false;
+  }
+  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_BACK);
+  return true;
 }
 
 }  // namespace blm

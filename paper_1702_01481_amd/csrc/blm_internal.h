@@ -189,5 +189,9 @@ void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool v
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st);
 void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);
+// the same with each pencil's Hessenberg reduction spread over several
+// workgroups (cooperative launch; d_bar: 2 n_jobs counters); returns false
+// if it had to fall back to one workgroup per pencil
+bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int n_cus, unsigned* d_bar, hipStream_t st);
 
 }  // namespace blm
