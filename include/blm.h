@@ -54,7 +54,8 @@ typedef enum {
   BLM_E_NOMEM = 4,      /* device allocation failed */
   BLM_E_S_NOT_PD = 5,   /* an overlap matrix is not positive definite */
   BLM_E_NONFINITE = 6,  /* NaN or Inf reached an eigenproblem */
-  BLM_E_NOCONV = 7      /* the QR iteration did not converge */
+  BLM_E_NOCONV = 7,     /* the QR iteration did not converge */
+  BLM_E_TIMEOUT = 8     /* workgroups sharing a block eigenproblem stopped waiting for each other */
 } blm_status;
 
 typedef enum {
@@ -165,7 +166,13 @@ blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chu
  * part of the best directions, orthonormalised, as B^(b) (Eq. 6).
  * Synchronises the stream.  Optional host outputs:
  *   h_evals [n_shifts][N_B][N_K + 1][2]  lowest eigenvalues (re, im)
- *   h_kept  [n_shifts][N_B]             directions kept per block */
+ *   h_kept  [n_shifts][N_B]             directions kept per block
+ * Pencils of 256 or more dimensions are reduced to Hessenberg form by
+ * several workgroups each, which meet at a barrier after every elimination
+ * step; a wait there gives up after BLM_SYNC_SPIN_LIMIT polls (environment,
+ * read by blm_create; default 4194304) and the call then returns
+ * BLM_E_TIMEOUT.  Errors: BLM_E_S_NOT_PD, BLM_E_NONFINITE, BLM_E_NOCONV,
+ * BLM_E_TIMEOUT name the first failing block. */
 blm_status blm_solve_blocks(blm_ctx* ctx, double* h_evals, int32_t* h_kept);
 
 /* Pass 2: projects the same samples onto every shift's kept directions and

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libblm.so")
 
 BLM_OK = 0
 STATUS_NAMES = {0: "BLM_OK", 1: "BLM_E_ARG", 2: "BLM_E_STATE", 3: "BLM_E_HIP", 4: "BLM_E_NOMEM",
-                5: "BLM_E_S_NOT_PD", 6: "BLM_E_NONFINITE", 7: "BLM_E_NOCONV"}
+                5: "BLM_E_S_NOT_PD", 6: "BLM_E_NONFINITE", 7: "BLM_E_NOCONV", 8: "BLM_E_TIMEOUT"}
 FLAG_COMPLEX_ENERGY, FLAG_PAIR_KEPT, FLAG_SMALL_ALPHA = 1, 2, 4
 
 PRECISIONS = {"fp64": 0, "bf16x2": 1, "bf16x3": 2, "fp8": 3}

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -62,6 +63,7 @@ struct blm_ctx {
   int device = 0;
   int n_cus = 0;                   // compute units of the device (0: unknown)
   unsigned* d_hbar = nullptr;      // block solves: barrier counter and flag per pencil
+  unsigned spin_limit = 1u << 22;  // polls of a workgroup barrier before it gives up
   std::string err;
   int state = ST_CREATED;
 
@@ -609,6 +611,7 @@ const char* blm_status_string(blm_status s) {
     case BLM_E_S_NOT_PD: return "overlap matrix not positive definite";
     case BLM_E_NONFINITE: return "non-finite value in an eigenproblem";
     case BLM_E_NOCONV: return "QR iteration did not converge";
+    case BLM_E_TIMEOUT: return "workgroups of a block eigenproblem timed out waiting for each other";
   }
   return "unknown status";
 }
@@ -724,6 +727,7 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
   }
   if (hipDeviceGetAttribute(&c->n_cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
     c->n_cus = 0;
+  if (const char* e = getenv("BLM_SYNC_SPIN_LIMIT")) c->spin_limit = (unsigned)strtoul(e, nullptr, 10);
   Plan P;
   plan(c, P);
   for (auto& it : P.items) {
@@ -938,11 +942,16 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
 static blm_status eig_status(blm_ctx* c, int st, const char* what) {
   if (st == EIG_OK) return BLM_OK;
   char buf[160];
-  const char* m = st == EIG_NOT_PD ? "overlap not positive definite"
-                  : st == EIG_NONFINITE ? "non-finite values" : "QR did not converge";
+  const char* m = st == EIG_NOT_PD      ? "overlap not positive definite"
+                  : st == EIG_NONFINITE ? "non-finite values"
+                  : st == EIG_SYNC      ? "a workgroup barrier timed out"
+                                        : "QR did not converge";
   snprintf(buf, sizeof buf, "%s: %s", what, m);
   c->err = buf;
-  return st == EIG_NOT_PD ? BLM_E_S_NOT_PD : st == EIG_NONFINITE ? BLM_E_NONFINITE : BLM_E_NOCONV;
+  return st == EIG_NOT_PD      ? BLM_E_S_NOT_PD
+         : st == EIG_NONFINITE ? BLM_E_NONFINITE
+         : st == EIG_SYNC      ? BLM_E_TIMEOUT
+                               : BLM_E_NOCONV;
 }
 
 blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
@@ -982,7 +991,7 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   HIPCHK(c, hipGetLastError());
   mark(c, 3, true);
   mark(c, 4, false);
-  launch_eig_split(c->d_eig1, (int)ej.size(), c->n_cus, c->d_hbar, c->st);
+  launch_eig_split(c->d_eig1, (int)ej.size(), c->n_cus, c->d_hbar, c->spin_limit, c->st);
   HIPCHK(c, hipGetLastError());
   mark(c, 4, true);
   std::vector<int32_t> info((size_t)EIG_INFO * NS * NB);

@@ -1489,7 +1489,7 @@ __device__ double hs_block_sum(HessShared& hs, double v) {
 // barrier among the kw workgroups of a pencil: cnt counts arrivals, err is
 // the pencil's flag; returns false if the wait ran past its bound (or
 // another workgroup's did)
-__device__ bool pencil_barrier(HessShared& hs, unsigned* cnt, int* err, unsigned target) {
+__device__ bool pencil_barrier(HessShared& hs, unsigned* cnt, int* err, unsigned target, unsigned spin_limit) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -1497,7 +1497,7 @@ __device__ bool pencil_barrier(HessShared& hs, unsigned* cnt, int* err, unsigned
     int ok = 1;
     for (unsigned spins = 0;; ++spins) {
       if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spins > (1u << 22)) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spins >= spin_limit) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
@@ -1622,7 +1622,7 @@ __device__ void hess_pass_rows(HessShared& hs, gdouble* A, int d, int k, int r0,
 }
 
 __global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict__ jobs, int n_jobs, int kw,
-                                                        unsigned* __restrict__ bar) {
+                                                        unsigned* __restrict__ bar, unsigned spin_limit) {
   __shared__ HessShared hs;
   const int job = blockIdx.x % n_jobs, part = blockIdx.x / n_jobs;
   const EigJob& E = jobs[job];
@@ -1652,7 +1652,10 @@ __global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict
   double tk = hess_reflector_hs(hs, cv, V, tau, 0, d, &beta_h, writer);
   hess_pass_rows<false, true>(hs, A, d, 0, r0, r1, 0.0, 0.0, nullptr, nullptr, nullptr, cv, Pb[0],
                               Qb[0] + (size_t)part * d);
-  if (!pencil_barrier(hs, cnt, err, kw * ++gen)) return;
+  if (!pencil_barrier(hs, cnt, err, kw * ++gen, spin_limit)) {
+    if (tid == 0) info[0] = EIG_SYNC;
+    return;
+  }
   for (int k = 0; k + 2 < d; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
     const gdouble* Pc = Pb[cur];
@@ -1685,7 +1688,10 @@ __global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict
     } else {
       hess_pass_rows<true, false>(hs, A, d, k, r0, r1, tk, beta_h, cv, Pc, cq, nullptr, nullptr, nullptr);
     }
-    if (!pencil_barrier(hs, cnt, err, kw * ++gen)) return;
+    if (!pencil_barrier(hs, cnt, err, kw * ++gen, spin_limit)) {
+      if (tid == 0) info[0] = EIG_SYNC;
+      return;
+    }
     double* t = cv;
     cv = nv;
     nv = t;
@@ -1873,7 +1879,8 @@ __global__ void fill_u32_kernel(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int n_cus, unsigned* d_bar, hipStream_t st) {
+bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int n_cus, unsigned* d_bar, unsigned spin_limit,
+                      hipStream_t st) {
   if (n_jobs <= 0) return true;
   const int kw = min(HKW_MAX, n_cus / n_jobs);
   if (kw < 2) {
@@ -1883,7 +1890,7 @@ bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int n_cus, unsigned* d_b
   hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_FRONT);
   hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * n_jobs + 255) / 256), dim3(256), 0, st, d_bar, 2 * n_jobs);
   int nj = n_jobs, k = kw;
-  void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&k, (void*)&d_bar};
+  void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&k, (void*)&d_bar, (void*)&spin_limit};
   const hipError_t e = hipLaunchCooperativeKernel((const void*)hess_multi_kernel, dim3(n_jobs * kw), dim3(NT),
                                                   args, 0, st);
   if (e != hipSuccess) {

@@ -161,7 +161,8 @@ enum EigStatus : int32_t {
   EIG_OK = 0,
   EIG_NOT_PD = 1,
   EIG_NONFINITE = 2,
-  EIG_NOCONV = 3
+  EIG_NOCONV = 3,
+  EIG_SYNC = 4  // a workgroup barrier of the distributed Hessenberg reduction ran past its bound
 };
 
 constexpr int EIG_THREADS = 1024;
@@ -192,6 +193,7 @@ void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);
 // the same with each pencil's Hessenberg reduction spread over several
 // workgroups (cooperative launch; d_bar: 2 n_jobs counters); returns false
 // if it had to fall back to one workgroup per pencil
-bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int n_cus, unsigned* d_bar, hipStream_t st);
+bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int n_cus, unsigned* d_bar, unsigned spin_limit,
+                      hipStream_t st);
 
 }  // namespace blm

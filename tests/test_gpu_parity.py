@@ -232,6 +232,30 @@ def test_error_paths():
     ctx.close()
 
 
+def test_barrier_timeout_is_reported(monkeypatch):
+    """A 301-dimensional pencil is reduced to Hessenberg form by several
+    workgroups; with a poll bound of zero their first barrier gives up, every
+    workgroup exits and the solve reports BLM_E_TIMEOUT.  A context with the
+    default bound then solves the same samples."""
+    blm = _blm()
+    _, dev = _make(300, 3000, 4, 3, 3000)
+    monkeypatch.setenv("BLM_SYNC_SPIN_LIMIT", "0")
+    ctx = blm.BLM(300, [0, 300], 2, 0, [1e-3], 3000)
+    monkeypatch.delenv("BLM_SYNC_SPIN_LIMIT")
+    ctx.begin_step()
+    ctx.build(dev)
+    with pytest.raises(blm.BLMError) as ei:
+        ctx.solve()
+    assert ei.value.status == 8
+    ctx.close()
+    ctx = blm.BLM(300, [0, 300], 2, 0, [1e-3], 3000)
+    ctx.begin_step()
+    ctx.build(dev)
+    ev, kept = ctx.solve()
+    assert np.all(np.isfinite(ev)) and kept.min() >= 1
+    ctx.close()
+
+
 # --------------------------------------------------------- mixed precision --
 
 def test_pack_bf16_split_is_accurate():
