@@ -991,7 +991,7 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   HIPCHK(c, hipGetLastError());
   mark(c, 3, true);
   mark(c, 4, false);
-  launch_eig_split(c->d_eig1, (int)ej.size(), c->n_cus, c->d_hbar, c->spin_limit, c->st);
+  launch_eig_split(c->d_eig1, (int)ej.size(), dm, c->n_cus, c->d_hbar, c->spin_limit, c->st);
   HIPCHK(c, hipGetLastError());
   mark(c, 4, true);
   std::vector<int32_t> info((size_t)EIG_INFO * NS * NB);

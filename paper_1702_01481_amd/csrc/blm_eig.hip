@@ -31,7 +31,7 @@ constexpr int HKW_MAX = 8;            // workgroups per pencil in the distribute
 // workspace, 2 d + 2 kw d doubles, fits in the 2 d^2 of W
 constexpr int HESS_MULTI_MIN = 256;
 static_assert(2 * HESS_MULTI_MIN >= 2 + 2 * HKW_MAX, "workspace of the distributed reduction");
-enum : int { PH_FRONT = 1, PH_HESS = 2, PH_BACK = 4 };
+enum : int { PH_CHOL = 1, PH_HESS = 2, PH_BACK = 4, PH_CONG = 8, PH_ALL = 15 };
 constexpr int NW = NT / 64;
 constexpr double EPS = DBL_EPSILON;
 constexpr double DROP_TOL = 1e-12;
@@ -1452,6 +1452,123 @@ __device__ void back_transform_wave(const gdouble* V, const gdouble* tau, const 
 
 // An eigen-job with its buffers typed as global memory, so that every access
 // is a global (not flat) memory instruction and LDS waits never wait for them.
+// ------------------------------------- step 2, distributed over workgroups --
+// The congruence A <- L^-1 A L^-T with no synchronisation inside a launch.
+// The columns of X = L^-1 A are independent right-hand sides: the first
+// launch gives each workgroup a slice of at most CSW columns.  Row i of
+// A = X L^-T is L^-1 applied to row i of X: the second launch gives each
+// workgroup the same slice of rows, which it transposes into those columns
+// of W, solves and transposes back.  Blocking and summation order are those
+// of lower_solve_rows.
+constexpr int CSW = 64;   // columns per slice: one lane each
+
+struct CongShared {
+  double xs[CB][CSW];     // the slice's rows of the current diagonal block
+  double ld[CB][CB];      // diagonal block of L
+};
+
+// X[:, c0:c1] <- L^-1 X[:, c0:c1] for a row-major n x n X, c1 - c0 <= CSW
+__device__ void lower_solve_slice(CongShared& cs, const gdouble* Lm, gdouble* X, int n, int c0, int c1) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int w = c1 - c0;
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    const int kb = min(CB, n - k0);
+    // diagonal block: wave 0, one lane per column, rows in order; the other
+    // waves stage nothing and wait
+    if (wv == 0) {
+      for (int t = lane; t < CB * CB; t += 64) {
+        const int m = t / CB, q = t % CB;
+        cs.ld[m][q] = (m < kb && q <= m) ? Lm[(size_t)(k0 + m) * n + k0 + q] : 1.0;
+      }
+      for (int m = 0; m < CB; ++m)
+        cs.xs[m][lane] = (m < kb && lane < w) ? X[(size_t)(k0 + m) * n + c0 + lane] : 0.0;
+      __builtin_amdgcn_wave_barrier();
+      for (int kk = 0; kk < kb; ++kk) {
+        double v = cs.xs[kk][lane];
+        for (int m = 0; m < kk; ++m) v -= cs.ld[kk][m] * cs.xs[m][lane];
+        v /= cs.ld[kk][kk];
+        cs.xs[kk][lane] = v;
+        if (lane < w) X[(size_t)(k0 + kk) * n + c0 + lane] = v;
+      }
+    }
+    __syncthreads();
+    // trailing rows, two per wave at a time; lanes over the slice's columns
+    for (int iv = k0 + kb + wv; iv < n; iv += 2 * NW) {
+      const int i = __builtin_amdgcn_readfirstlane(iv);
+      const int i2 = i + NW;
+      const bool has2 = i2 < n;
+      const int ib = has2 ? i2 : i;
+      double l1[CB], l2[CB];
+#pragma unroll
+      for (int m = 0; m < CB; ++m) {
+        l1[m] = (m < kb) ? Lm[(size_t)i * n + k0 + m] : 0.0;
+        l2[m] = (m < kb) ? Lm[(size_t)ib * n + k0 + m] : 0.0;
+      }
+      const int jc = min(lane, w - 1);
+      double a1 = X[(size_t)i * n + c0 + jc], a2 = X[(size_t)ib * n + c0 + jc];
+#pragma unroll
+      for (int m = 0; m < CB; ++m) {
+        a1 -= l1[m] * cs.xs[m][lane];
+        a2 -= l2[m] * cs.xs[m][lane];
+      }
+      if (lane < w) {
+        X[(size_t)i * n + c0 + lane] = a1;
+        if (has2) X[(size_t)i2 * n + c0 + lane] = a2;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool cong_slice(const EigJob& E, int n_jobs, int* job, int* c0, int* c1) {
+  *job = blockIdx.x % n_jobs;
+  const int part = blockIdx.x / n_jobs;
+  const int d = E.d;
+  if (d <= 0 || d > EIG_MAXD || E.info[0] != EIG_OK) return false;
+  const int ns = (d + CSW - 1) / CSW;
+  if (part >= ns) return false;
+  *c0 = (int)((int64_t)d * part / ns);
+  *c1 = (int)((int64_t)d * (part + 1) / ns);
+  return true;
+}
+
+// first launch: X = L^-1 A in place, one column slice per workgroup
+__global__ __launch_bounds__(NT) void cong_cols_kernel(const EigJob* __restrict__ jobs, int n_jobs) {
+  __shared__ CongShared cs;
+  const EigJob& E = jobs[blockIdx.x % n_jobs];
+  int job, c0, c1;
+  if (!cong_slice(E, n_jobs, &job, &c0, &c1)) return;
+  const uint64_t t0 = wall_clock64();
+  lower_solve_slice(cs, as_global(E.S), as_global(E.A), E.d, c0, c1);
+  if (c0 == 0 && threadIdx.x == 0) as_global(E.info)[5] = (int32_t)(wall_clock64() - t0);
+}
+
+// second launch: rows c0..c1-1 of A <- (L^-1 (rows of X)^T)^T through W
+__global__ __launch_bounds__(NT) void cong_rows_kernel(const EigJob* __restrict__ jobs, int n_jobs) {
+  __shared__ CongShared cs;
+  const EigJob& E = jobs[blockIdx.x % n_jobs];
+  int job, c0, c1;
+  if (!cong_slice(E, n_jobs, &job, &c0, &c1)) return;
+  const uint64_t t0 = wall_clock64();
+  const int d = E.d, w = c1 - c0, tid = threadIdx.x;
+  gdouble* A = as_global(E.A);
+  gdouble* W = as_global(E.W);
+  for (int t = tid; t < d * CSW; t += NT) {
+    const int j = t / CSW, i = t % CSW;
+    if (i < w) W[(size_t)j * d + c0 + i] = A[(size_t)(c0 + i) * d + j];
+  }
+  __syncthreads();
+  lower_solve_slice(cs, as_global(E.S), W, d, c0, c1);
+  for (int t = tid; t < w * d; t += NT) {
+    const int i = t / d, j = t % d;
+    A[(size_t)(c0 + i) * d + j] = W[(size_t)j * d + c0 + i];
+  }
+  if (c0 == 0 && tid == 0) {
+    BLM_GLOBAL int32_t* info = as_global(E.info);
+    info[5] += (int32_t)(wall_clock64() - t0);
+  }
+}
+
 // ------------------------------------- step 3, distributed over workgroups --
 // The one-pass Hessenberg reduction of hessenberg() with each pencil's rows
 // split over kw workgroups (a cooperative launch: all resident).  Per step
@@ -1736,7 +1853,7 @@ __device__ __forceinline__ void phase_mark(const GJob& J, uint64_t& t, int i) {
   t = now;
 }
 
-// phases: PH_FRONT Cholesky and congruence, PH_HESS the Hessenberg
+// phases: PH_CHOL Cholesky, PH_CONG congruence, PH_HESS the Hessenberg
 // reduction, PH_BACK the rest.  A launch runs the phases its mask names; a
 // pencil whose status is already an error skips the later ones.
 __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs, int phases) {
@@ -1745,20 +1862,22 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
   const int d = J.d, tid = threadIdx.x, wv = tid >> 6;
   uint64_t clk = wall_clock64();
   if (tid == 0) sh.isc[2] = 0;
-  if ((phases & PH_FRONT) && tid == 0)
+  if ((phases & PH_CHOL) && tid == 0)
     for (int i = 0; i < EIG_INFO; ++i) J.info[i] = 0;
   __syncthreads();
   if (d <= 0 || d > EIG_MAXD) return;
-  if (!(phases & PH_FRONT) && J.info[0] != EIG_OK) return;
+  if (!(phases & PH_CHOL) && J.info[0] != EIG_OK) return;
 
   int st = EIG_OK;
-  if (phases & PH_FRONT) {
+  if (phases & PH_CHOL) {
     st = cholesky(sh, J.S, d);
     if (st != EIG_OK) {
       if (tid == 0) J.info[0] = st;
       return;
     }
     phase_mark(J, clk, 0);
+  }
+  if (phases & PH_CONG) {
     congruence(sh, J.S, J.A, J.W, d);
     phase_mark(J, clk, 1);
   }
@@ -1871,7 +1990,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
 
 void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st) {
   if (n_jobs <= 0) return;
-  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, PH_FRONT | PH_HESS | PH_BACK);
+  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_ALL);
 }
 
 __global__ void fill_u32_kernel(unsigned* p, int n) {
@@ -1879,15 +1998,18 @@ __global__ void fill_u32_kernel(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int n_cus, unsigned* d_bar, unsigned spin_limit,
-                      hipStream_t st) {
+bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int d_max, int n_cus, unsigned* d_bar,
+                      unsigned spin_limit, hipStream_t st) {
   if (n_jobs <= 0) return true;
+  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_CHOL);
+  const int ns = max(1, (min(d_max, EIG_MAXD) + CSW - 1) / CSW);
+  hipLaunchKernelGGL(cong_cols_kernel, dim3(n_jobs * ns), dim3(NT), 0, st, d_jobs, n_jobs);
+  hipLaunchKernelGGL(cong_rows_kernel, dim3(n_jobs * ns), dim3(NT), 0, st, d_jobs, n_jobs);
   const int kw = min(HKW_MAX, n_cus / n_jobs);
   if (kw < 2) {
-    launch_eig(d_jobs, n_jobs, st);
+    hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)(PH_HESS | PH_BACK));
     return true;
   }
-  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_FRONT);
   hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * n_jobs + 255) / 256), dim3(256), 0, st, d_bar, 2 * n_jobs);
   int nj = n_jobs, k = kw;
   void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&k, (void*)&d_bar, (void*)&spin_limit};
