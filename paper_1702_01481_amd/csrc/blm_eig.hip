@@ -99,6 +99,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// value of v in lane src (src the same in every lane)
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const uint64_t b = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, src);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), src);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// modulus of x + i y; |x| when y is zero
+__device__ __forceinline__ double cmod(double x, double y) { return (y == 0.0) ? fabs(x) : hypot(x, y); }
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -1297,116 +1308,254 @@ __device__ int select_lowest(Shared& sh, const gdouble* wr, const gdouble* wi, i
 // ---------------------------------------------------------------- step 6 --
 // Inverse iteration on the Hessenberg matrix Hq for eigenvalue (sr, si):
 // LU of Hq - sigma I with adjacent-row pivoting, tiny pivots replaced by
-// eps3, three solves from a vector of ones.  Result (complex) in yr, yi.
+// eps3, three solves from a vector of ones (the first with U alone).  Result
+// (complex) in yr, yi.
+//
+// The factorisation runs in batches of IB steps.  Column j only changes in
+// steps k < j, and the step's pivot needs only column k, so one wave takes
+// the batch's IB columns through its steps (one column per lane, the carried
+// row in registers, the next rows' entries loaded PF steps ahead) and
+// records the multipliers and interchanges; then every thread takes one
+// column to the right of the batch through the same steps.  The back
+// substitution runs in blocks of IB rows from the bottom: all waves subtract
+// the solved part from the block's right-hand side and stage the block's
+// triangle in LDS; one wave solves the triangle.
+constexpr int IB = 64;   // steps per batch, rows per back-substitution block
+constexpr int PF = 8;    // steps whose row entries are loaded together
+static_assert(IB * IB <= EIG_MAXD, "triangle staging in v3/v4");
+
+// one factorisation step on a column: (c = carried row, f = fresh row) ->
+// U entry t and the new carried value
+__device__ __forceinline__ void lu_step(bool swp, double mr, double mi, double f_r, double f_i, double& c_r,
+                                        double& c_i, double& t_r, double& t_i) {
+  t_r = swp ? f_r : c_r;
+  t_i = swp ? f_i : c_i;
+  const double u_r = swp ? c_r : f_r, u_i = swp ? c_i : f_i;
+  c_r = u_r - (mr * t_r - mi * t_i);
+  c_i = u_i - (mr * t_i + mi * t_r);
+}
+
 __device__ void inverse_iteration(Shared& sh, const gdouble* Hq, gdouble* Wr, gdouble* Wi, int d,
                                   double sr, double si, double eps3, gdouble* yr, gdouble* yi) {
-  const int tid = threadIdx.x;
-  for (size_t t = tid; t < (size_t)d * d; t += NT) {
-    const int i = (int)(t / d), j = (int)(t % d);
-    const double v = (j + 1 >= i) ? Hq[t] : 0.0;
-    Wr[t] = (j == i) ? v - sr : v;
-    Wi[t] = (j == i) ? -si : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // carried row of the factorisation (row 0 of Hq - sigma I to start)
+  double* cr = sh.v3;
+  double* ci = sh.v4;
+  for (int j = tid; j < d; j += NT) {
+    cr[j] = Hq[j] - (j == 0 ? sr : 0.0);
+    ci[j] = (j == 0) ? -si : 0.0;
   }
   __syncthreads();
-  // multipliers and swaps kept in LDS: v1 = mult re, v2 = mult im, mark = swap
-  for (int k = 0; k + 1 < d; ++k) {
-    const double ar = Wr[(size_t)k * d + k], ai = Wi[(size_t)k * d + k];
-    const double br = Wr[(size_t)(k + 1) * d + k], bi = Wi[(size_t)(k + 1) * d + k];
-    const bool swp = hypot(br, bi) > hypot(ar, ai);
-    double pr = swp ? br : ar, pi = swp ? bi : ai;
-    const double orr = swp ? ar : br, oi = swp ? ai : bi;
-    if (hypot(pr, pi) < eps3) {
-      pr = eps3;
-      pi = 0.0;
+  for (int k0 = 0; k0 < d; k0 += IB) {
+    const int kend = min(k0 + IB, d - 1);   // steps k0 .. kend-1
+    if (wv == 0) {
+      const int jw = k0 + lane;
+      const bool in = jw < d;
+      double c_r = in ? cr[jw] : 0.0, c_i = in ? ci[jw] : 0.0;
+      for (int kg = k0; kg < kend; kg += PF) {
+        double fp[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+          const int k = kg + q;
+          fp[q] = (in && k < kend && jw >= k) ? Hq[(size_t)(k + 1) * d + jw] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+          const int k = kg + q;
+          if (k >= kend) break;
+          const double f_r = (jw == k + 1) ? fp[q] - sr : fp[q];
+          const double f_i = (jw == k + 1) ? -si : 0.0;
+          const int src = k - k0;
+          const double ar = lane_bcast(c_r, src), ai = lane_bcast(c_i, src);
+          const double br = lane_bcast(f_r, src), bi = lane_bcast(f_i, src);
+          const bool swp = cmod(br, bi) > cmod(ar, ai);
+          double pr = swp ? br : ar, pi = swp ? bi : ai;
+          const double orr = swp ? ar : br, oi = swp ? ai : bi;
+          if (cmod(pr, pi) < eps3) {
+            pr = eps3;
+            pi = 0.0;
+          }
+          const double den = pr * pr + pi * pi;
+          const double mr = (orr * pr + oi * pi) / den, mi = (oi * pr - orr * pi) / den;
+          if (lane == 0) {
+            sh.v1[k] = mr;
+            sh.v2[k] = mi;
+            sh.mark[k] = swp ? 1 : 0;
+          }
+          if (in && jw >= k) {
+            double t_r, t_i;
+            if (jw == k) {
+              t_r = pr;
+              t_i = pi;
+              c_r = 0.0;
+              c_i = 0.0;
+            } else {
+              lu_step(swp, mr, mi, f_r, f_i, c_r, c_i, t_r, t_i);
+            }
+            Wr[(size_t)k * d + jw] = t_r;
+            Wi[(size_t)k * d + jw] = t_i;
+          }
+        }
+      }
+      if (jw == d - 1) {
+        // the last pivot, after the last step
+        if (cmod(c_r, c_i) < eps3) {
+          c_r = eps3;
+          c_i = 0.0;
+        }
+        Wr[(size_t)(d - 1) * d + d - 1] = c_r;
+        Wi[(size_t)(d - 1) * d + d - 1] = c_i;
+      }
     }
-    const double den = pr * pr + pi * pi;
-    const double mr = (orr * pr + oi * pi) / den, mi = (oi * pr - orr * pi) / den;
     __syncthreads();
-    if (tid == 0) {
-      sh.v1[k] = mr;
-      sh.v2[k] = mi;
-      sh.mark[k] = swp ? 1 : 0;
-    }
-    for (int j = k + tid; j < d; j += NT) {
-      double tr, ti, ur, ui;
-      if (swp) {
-        tr = Wr[(size_t)(k + 1) * d + j];
-        ti = Wi[(size_t)(k + 1) * d + j];
-        ur = Wr[(size_t)k * d + j];
-        ui = Wi[(size_t)k * d + j];
-      } else {
-        tr = Wr[(size_t)k * d + j];
-        ti = Wi[(size_t)k * d + j];
-        ur = Wr[(size_t)(k + 1) * d + j];
-        ui = Wi[(size_t)(k + 1) * d + j];
+    // the batch's steps on the columns right of it
+    for (int j = k0 + IB + tid; j < d; j += NT) {
+      double c_r = cr[j], c_i = ci[j];
+      for (int kg = k0; kg < kend; kg += PF) {
+        double fp[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+          const int k = kg + q;
+          fp[q] = (k < kend) ? Hq[(size_t)(k + 1) * d + j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+          const int k = kg + q;
+          if (k >= kend) break;
+          const double f_r = (j == k + 1) ? fp[q] - sr : fp[q];
+          const double f_i = (j == k + 1) ? -si : 0.0;
+          double t_r, t_i;
+          lu_step(sh.mark[k] != 0, sh.v1[k], sh.v2[k], f_r, f_i, c_r, c_i, t_r, t_i);
+          Wr[(size_t)k * d + j] = t_r;
+          Wi[(size_t)k * d + j] = t_i;
+        }
       }
-      if (j == k) {
-        tr = pr;
-        ti = pi;
-      }
-      Wr[(size_t)k * d + j] = tr;
-      Wi[(size_t)k * d + j] = ti;
-      Wr[(size_t)(k + 1) * d + j] = (j == k) ? 0.0 : ur - (mr * tr - mi * ti);
-      Wi[(size_t)(k + 1) * d + j] = (j == k) ? 0.0 : ui - (mr * ti + mi * tr);
+      cr[j] = c_r;
+      ci[j] = c_i;
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    const size_t dd = (size_t)(d - 1) * d + d - 1;
-    if (hypot(Wr[dd], Wi[dd]) < eps3) {
-      Wr[dd] = eps3;
-      Wi[dd] = 0.0;
-    }
-  }
-  __syncthreads();
-  // right-hand side in yr/yi (global, owned per index by thread i % NT)
+  // right-hand side in yr/yi (global)
   for (int i = tid; i < d; i += NT) {
     yr[i] = 1.0;
     yi[i] = 0.0;
   }
   __syncthreads();
+  double* ub_r = sh.v3;   // a block's triangle: (l, q) at l * IB + (q ^ l)
+  double* ub_i = sh.v4;
+  double* part = sh.T;    // the block's right-hand side corrections (re, im)
   for (int it = 0; it < 3; ++it) {
     if (it > 0) {
-      // apply L^-1: sequential, by one thread
+      // apply L^-1 (interchanges and multipliers in order): one lane, from LDS
+      for (int i = tid; i < d; i += NT) {
+        sh.v3[i] = yr[i];
+        sh.v4[i] = yi[i];
+      }
+      __syncthreads();
       if (tid == 0) {
-        for (int k = 0; k + 1 < d; ++k) {
-          double r0 = yr[k], i0 = yi[k], r1 = yr[k + 1], i1 = yi[k + 1];
-          if (sh.mark[k]) {
-            const double tr = r0, ti = i0;
+        constexpr int LG = 8;   // steps whose operands are read together
+        double r0 = sh.v3[0], i0 = sh.v4[0];
+        for (int kg = 0; kg + 1 < d; kg += LG) {
+          double nr[LG], ni[LG], mr[LG], mi[LG];
+          bool sw[LG];
+#pragma unroll
+          for (int q = 0; q < LG; ++q) {
+            const int k = min(kg + q, d - 2);
+            nr[q] = sh.v3[k + 1];
+            ni[q] = sh.v4[k + 1];
+            mr[q] = sh.v1[k];
+            mi[q] = sh.v2[k];
+            sw[q] = sh.mark[k] != 0;
+          }
+#pragma unroll
+          for (int q = 0; q < LG; ++q) {
+            const int k = kg + q;
+            if (k + 1 >= d) break;
+            double r1 = nr[q], i1 = ni[q];
+            if (sw[q]) {
+              const double tr = r0, ti = i0;
+              r0 = r1;
+              i0 = i1;
+              r1 = tr;
+              i1 = ti;
+            }
+            r1 -= mr[q] * r0 - mi[q] * i0;
+            i1 -= mr[q] * i0 + mi[q] * r0;
+            yr[k] = r0;
+            yi[k] = i0;
             r0 = r1;
             i0 = i1;
-            r1 = tr;
-            i1 = ti;
           }
-          const double mr = sh.v1[k], mi = sh.v2[k];
-          r1 -= mr * r0 - mi * i0;
-          i1 -= mr * i0 + mi * r0;
-          yr[k] = r0;
-          yi[k] = i0;
-          yr[k + 1] = r1;
-          yi[k + 1] = i1;
         }
+        yr[d - 1] = r0;
+        yi[d - 1] = i0;
       }
       __syncthreads();
     }
-    // back substitution U y = b; entry i owned by thread i % NT
-    for (int k = d - 1; k >= 0; --k) {
-      if ((k % NT) == tid) {
-        const double ur = Wr[(size_t)k * d + k], ui = Wi[(size_t)k * d + k];
-        const double den = ur * ur + ui * ui;
-        const double br = yr[k], bi = yi[k];
-        const double xr = (br * ur + bi * ui) / den, xi = (bi * ur - br * ui) / den;
-        yr[k] = xr;
-        yi[k] = xi;
-        sh.sc[8] = xr;
-        sh.sc[9] = xi;
+    // back substitution U x = y, blocks of IB rows from the bottom
+    for (int r0 = ((d - 1) / IB) * IB; r0 >= 0; r0 -= IB) {
+      const int r1 = min(d, r0 + IB), nb = r1 - r0;
+      for (int t = tid; t < IB * IB; t += NT) {
+        const int l = t / IB, q = t % IB;
+        const bool ok = l < nb && q < nb && q >= l;
+        ub_r[l * IB + (q ^ l)] = ok ? Wr[(size_t)(r0 + l) * d + r0 + q] : 0.0;
+        ub_i[l * IB + (q ^ l)] = ok ? Wi[(size_t)(r0 + l) * d + r0 + q] : 0.0;
+      }
+      {
+        // rows wv, wv + NW, ... of the block together (IB / NW of them)
+        constexpr int RW = IB / NW;
+        double ar[RW], ai[RW];
+#pragma unroll
+        for (int h = 0; h < RW; ++h) ar[h] = ai[h] = 0.0;
+        for (int j = r1 + lane; j < d; j += 64) {
+          const double xr = yr[j], xi = yi[j];
+#pragma unroll
+          for (int h = 0; h < RW; ++h) {
+            const int l = min(wv + h * NW, nb - 1);
+            const double a = Wr[(size_t)(r0 + l) * d + j], b = Wi[(size_t)(r0 + l) * d + j];
+            ar[h] += a * xr - b * xi;
+            ai[h] += a * xi + b * xr;
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < RW; ++h) {
+          const int l = wv + h * NW;
+          const double sr_ = wave_sum(ar[h]), si_ = wave_sum(ai[h]);
+          if (lane == 0 && l < nb) {
+            part[2 * l] = sr_;
+            part[2 * l + 1] = si_;
+          }
+        }
       }
       __syncthreads();
-      const double xr = sh.sc[8], xi = sh.sc[9];
-      for (int i = tid; i < k; i += NT) {
-        const double ur = Wr[(size_t)i * d + k], ui = Wi[(size_t)i * d + k];
-        yr[i] -= ur * xr - ui * xi;
-        yi[i] -= ur * xi + ui * xr;
+      if (wv == 0) {
+        double y_r = 0.0, y_i = 0.0, g_r = 1.0, g_i = 0.0;
+        if (lane < nb) {
+          y_r = yr[r0 + lane] - part[2 * lane];
+          y_i = yi[r0 + lane] - part[2 * lane + 1];
+          // 1 / u_ll = conj(u_ll) / |u_ll|^2
+          const double ur = ub_r[lane * IB], ui = ub_i[lane * IB];
+          const double den = ur * ur + ui * ui;
+          g_r = ur / den;
+          g_i = -ui / den;
+        }
+        for (int q = nb - 1; q >= 0; --q) {
+          const double br = lane_bcast(y_r, q), bi = lane_bcast(y_i, q);
+          const double hr = lane_bcast(g_r, q), hi = lane_bcast(g_i, q);
+          const double xr = br * hr - bi * hi, xi = br * hi + bi * hr;
+          if (lane == q) {
+            y_r = xr;
+            y_i = xi;
+          } else if (lane < q) {
+            const double a = ub_r[lane * IB + (q ^ lane)], b = ub_i[lane * IB + (q ^ lane)];
+            y_r -= a * xr - b * xi;
+            y_i -= a * xi + b * xr;
+          }
+        }
+        if (lane < nb) {
+          yr[r0 + lane] = y_r;
+          yi[r0 + lane] = y_i;
+        }
       }
       __syncthreads();
     }
