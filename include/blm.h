@@ -165,7 +165,8 @@ blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chu
  * every shift, ranks the eigenvalues by real part and keeps the parameter
  * part of the best directions, orthonormalised, as B^(b) (Eq. 6).
  * Synchronises the stream.  Optional host outputs:
- *   h_evals [n_shifts][N_B][N_K + 1][2]  lowest eigenvalues (re, im)
+ *   h_evals [n_shifts][N_B][N_K + 1][2]  the N_K + 1 lowest eigenvalues by real part
+ *                                       (re, im); NaN where a pencil has fewer
  *   h_kept  [n_shifts][N_B]             directions kept per block
  * Pencils of 256 or more dimensions are reduced to Hessenberg form by
  * several workgroups each, which meet at a barrier after every elimination
@@ -189,6 +190,33 @@ blm_status blm_project(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks);
  * weight than pass 1. */
 blm_status blm_stage2(blm_ctx* ctx, double* d_update, double* h_energy, double* h_alpha,
                       uint32_t* h_flags);
+
+/* Batches: several independent optimisations (contexts) whose block solves
+ * share one eigensolver launch, and whose stage-two solves share another
+ * (Sec. II.B applied to each context on its own; nothing is shared between
+ * their estimates).  The builds and projections stay per context: each
+ * fills the device by itself.
+ *
+ * blm_batch_create takes n >= 1 distinct contexts created on the same
+ * device and stream (else BLM_E_ARG) and allocates the batch's job tables
+ * (BLM_E_NOMEM on failure).  The contexts stay owned by the caller and must
+ * outlive the batch; the batch keeps their order. */
+typedef struct blm_batch blm_batch;
+blm_status blm_batch_create(blm_ctx* const* ctxs, int32_t n, blm_batch** out);
+blm_status blm_batch_destroy(blm_batch* batch);
+
+/* blm_solve_blocks for every context of the batch.  h_evals and h_kept are
+ * NULL or arrays of n host pointers (each NULL or as for blm_solve_blocks).
+ * A context that is not ready returns BLM_E_STATE before anything runs;
+ * after the launch every context gets its results and the first error
+ * status is returned, its message in that context's blm_last_error. */
+blm_status blm_batch_solve_blocks(blm_batch* batch, double* const* h_evals, int32_t* const* h_kept);
+
+/* blm_stage2 for every context of the batch; each argument is NULL or an
+ * array of n pointers as for blm_stage2.  Errors as for
+ * blm_batch_solve_blocks. */
+blm_status blm_batch_stage2(blm_batch* batch, double* const* d_update, double* const* h_energy,
+                            double* const* h_alpha, uint32_t* const* h_flags);
 
 /* Diagnostics (valid after blm_solve_blocks).  Block b's normalised matrices
  * on the basis [Psi, Psi^{i,b}, Theta_jk (k != b, kept j, k-major)], with

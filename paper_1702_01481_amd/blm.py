@@ -27,6 +27,7 @@ EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_create"
             "blm_build_blocks", "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
             "blm_debug_eigvals", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
+            "blm_batch_create", "blm_batch_destroy", "blm_batch_solve_blocks", "blm_batch_stage2",
             "blm_last_error",
             "blm_status_string")
 TIMING_NAMES = ("theta_proj", "block_gram", "block_reduce", "block_assemble", "block_eig",
@@ -82,6 +83,11 @@ def load() -> C.CDLL:
     lib.blm_get_solver_stats.argtypes = [vp, C.POINTER(i32), i32]
     lib.blm_set_timing.argtypes = [vp, i32]
     lib.blm_get_timings.argtypes = [vp, dp, i32]
+    lib.blm_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
+    lib.blm_batch_destroy.argtypes = [vp]
+    lib.blm_batch_solve_blocks.argtypes = [vp, C.POINTER(dp), C.POINTER(C.POINTER(i32))]
+    lib.blm_batch_stage2.argtypes = [vp, C.POINTER(vp), C.POINTER(dp), C.POINTER(dp),
+                                     C.POINTER(C.POINTER(C.c_uint32))]
     lib.blm_last_error.argtypes = [vp]
     lib.blm_last_error.restype = C.c_char_p
     lib.blm_status_string.argtypes = [C.c_int]
@@ -350,6 +356,68 @@ class BLM:
         S = np.zeros((d.value, d.value))
         self._check(self.lib.blm_get_stage2_matrices(self.h, shift, _dptr(H), _dptr(S), C.byref(d)))
         return H, S
+
+
+class Batch:
+    """Several contexts (independent optimisations on the same stream) whose
+    block solves share one eigensolver launch, and whose stage-two solves
+    share another (blm_batch_*).  Builds and projections stay per context."""
+
+    def __init__(self, ctxs: Sequence[BLM]):
+        self.lib = load()
+        self.ctxs = list(ctxs)
+        n = len(self.ctxs)
+        arr = (C.c_void_p * n)(*[c.h.value for c in self.ctxs])
+        h = C.c_void_p()
+        st = self.lib.blm_batch_create(arr, n, C.byref(h))
+        if st != BLM_OK:
+            raise BLMError(st, self.lib.blm_status_string(st).decode())
+        self.h = h
+
+    def _check(self, st: int):
+        if st != BLM_OK:
+            msgs = [f"context {i}: {c.lib.blm_last_error(c.h).decode()}" for i, c in enumerate(self.ctxs)]
+            raise BLMError(st, "; ".join(m for m in msgs if not m.endswith(": ")))
+
+    def solve(self):
+        """[(evals, kept)] per context, as BLM.solve."""
+        outs = []
+        for c in self.ctxs:
+            ns, nb, nk = len(c.shifts), c.n_blocks, c.n_keep
+            outs.append((np.zeros((ns, nb, nk + 1, 2)), np.zeros((ns, nb), dtype=np.int32)))
+        n = len(self.ctxs)
+        evp = (C.POINTER(C.c_double) * n)(*[_dptr(ev) for ev, _ in outs])
+        kp = (C.POINTER(C.c_int32) * n)(*[k.ctypes.data_as(C.POINTER(C.c_int32)) for _, k in outs])
+        self._check(self.lib.blm_batch_solve_blocks(self.h, evp, kp))
+        return [(ev[..., 0] + 1j * ev[..., 1], k) for ev, k in outs]
+
+    def stage2(self, want_update: bool = True):
+        """[(update or None, energy, alpha ratio, flags)] per context, as BLM.stage2."""
+        outs = []
+        for c in self.ctxs:
+            ns = len(c.shifts)
+            upd = torch.empty(ns, c.n_params, dtype=torch.float64, device="cuda") if want_update else None
+            outs.append((upd, np.zeros(ns), np.zeros(ns), np.zeros(ns, dtype=np.uint32)))
+        n = len(self.ctxs)
+        up = (C.c_void_p * n)(*[o[0].data_ptr() if o[0] is not None else None for o in outs])
+        ep = (C.POINTER(C.c_double) * n)(*[_dptr(o[1]) for o in outs])
+        ap = (C.POINTER(C.c_double) * n)(*[_dptr(o[2]) for o in outs])
+        fp = (C.POINTER(C.c_uint32) * n)(*[o[3].ctypes.data_as(C.POINTER(C.c_uint32)) for o in outs])
+        self._check(self.lib.blm_batch_stage2(self.h, up, ep, ap, fp))
+        for c in self.ctxs:
+            c._keep = []
+        return outs
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.blm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def debug_eigvals(H: torch.Tensor, S: torch.Tensor, stream=None) -> np.ndarray:

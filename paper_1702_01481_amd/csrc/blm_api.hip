@@ -954,12 +954,18 @@ static blm_status eig_status(blm_ctx* c, int st, const char* what) {
                                : BLM_E_NOCONV;
 }
 
-blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
-  if (!c) return BLM_E_ARG;
+}  // extern "C"
+
+namespace {
+
+// Block solves in three parts, so that several contexts can share one
+// eigensolver launch: assembly of the shifted pencils (jobs returned with
+// their dimensions), the launch, then the results and the stage-two tables.
+blm_status solve_begin(blm_ctx* c, std::vector<EigJob>& ej, int* dm_out) {
   if (c->state != ST_BUILT) return fail(c, BLM_E_STATE, "blm_solve_blocks needs blm_build_blocks first");
-  const int NB = c->NB, NS = c->NS, NK = c->NK;
+  const int NB = c->NB, NS = c->NS;
   std::vector<AsmJob> asmj;
-  std::vector<EigJob> ej = c->eig1;
+  ej = c->eig1;
   int dm = 1;
   for (int sh = 0; sh < NS; ++sh)
     for (int b = 0; b < NB; ++b) {
@@ -983,17 +989,18 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
       dm = std::max(dm, d);
     }
   HIPCHK(c, hipMemcpyAsync(c->d_asm1, asmj.data(), sizeof(AsmJob) * asmj.size(), hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->d_eig1, ej.data(), sizeof(EigJob) * ej.size(), hipMemcpyHostToDevice, c->st));
   const int gy = std::min(256, std::max(1, (int)(((size_t)dm * dm + 255) / 256 / 8)));
   mark(c, 3, false);
   hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)asmj.size(), gy), dim3(256), 0, c->st, c->d_asm1,
                      c->accS, c->accH, c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2max);
   HIPCHK(c, hipGetLastError());
   mark(c, 3, true);
-  mark(c, 4, false);
-  launch_eig_split(c->d_eig1, (int)ej.size(), dm, c->n_cus, c->d_hbar, c->spin_limit, c->st);
-  HIPCHK(c, hipGetLastError());
-  mark(c, 4, true);
+  *dm_out = dm;
+  return BLM_OK;
+}
+
+blm_status solve_end(blm_ctx* c, double* h_evals, int32_t* h_kept) {
+  const int NB = c->NB, NS = c->NS, NK = c->NK;
   std::vector<int32_t> info((size_t)EIG_INFO * NS * NB);
   std::vector<double> ev((size_t)2 * NS * NB * (NK + 1));
   HIPCHK(c, hipMemcpyAsync(info.data(), c->d_info1, 4 * info.size(), hipMemcpyDeviceToHost, c->st));
@@ -1072,6 +1079,24 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   return BLM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
+  if (!c) return BLM_E_ARG;
+  std::vector<EigJob> ej;
+  int dm = 1;
+  blm_status s = solve_begin(c, ej, &dm);
+  if (s != BLM_OK) return s;
+  HIPCHK(c, hipMemcpyAsync(c->d_eig1, ej.data(), sizeof(EigJob) * ej.size(), hipMemcpyHostToDevice, c->st));
+  mark(c, 4, false);
+  launch_eig_split(c->d_eig1, (int)ej.size(), dm, c->n_cus, c->d_hbar, c->spin_limit, c->st);
+  HIPCHK(c, hipGetLastError());
+  mark(c, 4, true);
+  return solve_end(c, h_evals, h_kept);
+}
+
 blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   if (!c) return BLM_E_ARG;
   if (c->state != ST_SOLVED && c->state != ST_PROJECTED)
@@ -1107,9 +1132,12 @@ blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   return BLM_OK;
 }
 
-blm_status blm_stage2(blm_ctx* c, double* d_update, double* h_energy, double* h_alpha,
-                      uint32_t* h_flags) {
-  if (!c) return BLM_E_ARG;
+}  // extern "C"
+
+namespace {
+
+// Stage two in the same three parts as the block solves.
+blm_status stage2_begin(blm_ctx* c, std::vector<EigJob>& ej, int* dm_out) {
   if (c->state != ST_PROJECTED) return fail(c, BLM_E_STATE, "blm_stage2 needs blm_project first");
   if (c->n_pass2 != c->n_pass1)
     return fail(c, BLM_E_STATE, "pass 2 saw a different number of samples than pass 1");
@@ -1121,7 +1149,7 @@ blm_status blm_stage2(blm_ctx* c, double* d_update, double* h_energy, double* h_
   if (!(std::fabs(w1 - w2) <= 1e-12 * std::fabs(w1)) || !(w1 > 0.0))
     return fail(c, BLM_E_STATE, "pass 2 total weight differs from pass 1 (or is not positive)");
   std::vector<AsmJob> asmj;
-  std::vector<EigJob> ej = c->eig2;
+  ej = c->eig2;
   int dm = 1;
   for (int sh = 0; sh < NS; ++sh) {
     const int d = (int)c->idx2[sh].size();
@@ -1136,15 +1164,20 @@ blm_status blm_stage2(blm_ctx* c, double* d_update, double* h_energy, double* h_
     asmj.push_back(A);
     dm = std::max(dm, d);
   }
+  (void)NB;
   mark(c, 8, false);
   HIPCHK(c, hipMemcpyAsync(c->d_asm2, asmj.data(), sizeof(AsmJob) * NS, hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->d_eig2, ej.data(), sizeof(EigJob) * NS, hipMemcpyHostToDevice, c->st));
   const int gy = std::min(64, std::max(1, (int)(((size_t)dm * dm + 255) / 256 / 8)));
   hipLaunchKernelGGL(assemble_kernel, dim3(NS, gy), dim3(256), 0, c->st, c->d_asm2, c->accS, c->accH,
                      c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2);
   HIPCHK(c, hipGetLastError());
-  launch_eig(c->d_eig2, NS, c->st);
-  HIPCHK(c, hipGetLastError());
+  *dm_out = dm;
+  return BLM_OK;
+}
+
+blm_status stage2_end(blm_ctx* c, const std::vector<EigJob>& ej, double* d_update, double* h_energy,
+                      double* h_alpha, uint32_t* h_flags) {
+  const int NS = c->NS, NB = c->NB;
   std::vector<int32_t> info((size_t)EIG_INFO * NS);
   std::vector<double> ev((size_t)4 * NS);
   HIPCHK(c, hipMemcpyAsync(info.data(), c->d_info2, 4 * info.size(), hipMemcpyDeviceToHost, c->st));
@@ -1200,6 +1233,23 @@ blm_status blm_stage2(blm_ctx* c, double* d_update, double* h_energy, double* h_
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->state = ST_DONE;
   return BLM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+blm_status blm_stage2(blm_ctx* c, double* d_update, double* h_energy, double* h_alpha,
+                      uint32_t* h_flags) {
+  if (!c) return BLM_E_ARG;
+  std::vector<EigJob> ej;
+  int dm = 1;
+  blm_status s = stage2_begin(c, ej, &dm);
+  if (s != BLM_OK) return s;
+  HIPCHK(c, hipMemcpyAsync(c->d_eig2, ej.data(), sizeof(EigJob) * ej.size(), hipMemcpyHostToDevice, c->st));
+  launch_eig(c->d_eig2, (int)ej.size(), c->st);
+  HIPCHK(c, hipGetLastError());
+  return stage2_end(c, ej, d_update, h_energy, h_alpha, h_flags);
 }
 
 blm_status blm_get_block_matrices(blm_ctx* c, int32_t block, int32_t shift, double* h_H, double* h_S,
@@ -1312,6 +1362,111 @@ blm_status blm_debug_eigvals(const double* d_H, const double* d_S, int32_t d, do
     h_evals[2 * i + 1] = wi[i];
   }
   return BLM_OK;
+}
+
+// ------------------------------------------------------------------ batches --
+// Several contexts (independent optimisations) whose block solves, and whose
+// stage-two solves, share one eigensolver launch each.
+struct blm_batch {
+  std::vector<blm_ctx*> ctx;
+  hipStream_t st = nullptr;
+  int n_cus = 0;
+  unsigned spin_limit = 1u << 22;
+  EigJob* d_eig1 = nullptr;   // every context's block pencils
+  EigJob* d_eig2 = nullptr;   // every context's stage-two pencils
+  unsigned* d_hbar = nullptr; // barrier counter and flag per block pencil
+};
+
+blm_status blm_batch_create(blm_ctx* const* ctxs, int32_t n, blm_batch** out) {
+  if (!ctxs || !out || n < 1) return BLM_E_ARG;
+  *out = nullptr;
+  int n1 = 0, n2 = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return BLM_E_ARG;
+    if (ctxs[i]->st != ctxs[0]->st || ctxs[i]->device != ctxs[0]->device) return BLM_E_ARG;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return BLM_E_ARG;
+    n1 += ctxs[i]->NS * ctxs[i]->NB;
+    n2 += ctxs[i]->NS;
+  }
+  blm_batch* b = new blm_batch;
+  b->ctx.assign(ctxs, ctxs + n);
+  b->st = ctxs[0]->st;
+  b->n_cus = ctxs[0]->n_cus;
+  b->spin_limit = ctxs[0]->spin_limit;
+  if (hipMalloc((void**)&b->d_eig1, sizeof(EigJob) * n1) != hipSuccess ||
+      hipMalloc((void**)&b->d_eig2, sizeof(EigJob) * n2) != hipSuccess ||
+      hipMalloc((void**)&b->d_hbar, 4 * 2 * (size_t)n1) != hipSuccess) {
+    (void)hipFree(b->d_eig1);
+    (void)hipFree(b->d_eig2);
+    (void)hipFree(b->d_hbar);
+    delete b;
+    return BLM_E_NOMEM;
+  }
+  *out = b;
+  return BLM_OK;
+}
+
+blm_status blm_batch_destroy(blm_batch* b) {
+  if (!b) return BLM_E_ARG;
+  (void)hipFree(b->d_eig1);
+  (void)hipFree(b->d_eig2);
+  (void)hipFree(b->d_hbar);
+  delete b;
+  return BLM_OK;
+}
+
+blm_status blm_batch_solve_blocks(blm_batch* b, double* const* h_evals, int32_t* const* h_kept) {
+  if (!b) return BLM_E_ARG;
+  const int n = (int)b->ctx.size();
+  std::vector<EigJob> all;
+  int dm = 1;
+  for (int i = 0; i < n; ++i) {
+    std::vector<EigJob> ej;
+    int d = 1;
+    blm_status s = solve_begin(b->ctx[i], ej, &d);
+    if (s != BLM_OK) return s;
+    all.insert(all.end(), ej.begin(), ej.end());
+    dm = std::max(dm, d);
+  }
+  blm_ctx* c0 = b->ctx[0];
+  HIPCHK(c0, hipMemcpyAsync(b->d_eig1, all.data(), sizeof(EigJob) * all.size(), hipMemcpyHostToDevice, b->st));
+  for (blm_ctx* c : b->ctx) mark(c, 4, false);
+  launch_eig_split(b->d_eig1, (int)all.size(), dm, b->n_cus, b->d_hbar, b->spin_limit, b->st);
+  HIPCHK(c0, hipGetLastError());
+  for (blm_ctx* c : b->ctx) mark(c, 4, true);
+  blm_status first = BLM_OK;
+  for (int i = 0; i < n; ++i) {
+    const blm_status s = solve_end(b->ctx[i], h_evals ? h_evals[i] : nullptr, h_kept ? h_kept[i] : nullptr);
+    if (s != BLM_OK && first == BLM_OK) first = s;
+  }
+  return first;
+}
+
+blm_status blm_batch_stage2(blm_batch* b, double* const* d_update, double* const* h_energy,
+                            double* const* h_alpha, uint32_t* const* h_flags) {
+  if (!b) return BLM_E_ARG;
+  const int n = (int)b->ctx.size();
+  std::vector<std::vector<EigJob>> per(n);
+  std::vector<EigJob> all;
+  for (int i = 0; i < n; ++i) {
+    int d = 1;
+    blm_status s = stage2_begin(b->ctx[i], per[i], &d);
+    if (s != BLM_OK) return s;
+    all.insert(all.end(), per[i].begin(), per[i].end());
+  }
+  blm_ctx* c0 = b->ctx[0];
+  HIPCHK(c0, hipMemcpyAsync(b->d_eig2, all.data(), sizeof(EigJob) * all.size(), hipMemcpyHostToDevice, b->st));
+  launch_eig(b->d_eig2, (int)all.size(), b->st);
+  HIPCHK(c0, hipGetLastError());
+  blm_status first = BLM_OK;
+  for (int i = 0; i < n; ++i) {
+    const blm_status s = stage2_end(b->ctx[i], per[i], d_update ? d_update[i] : nullptr,
+                                    h_energy ? h_energy[i] : nullptr, h_alpha ? h_alpha[i] : nullptr,
+                                    h_flags ? h_flags[i] : nullptr);
+    if (s != BLM_OK && first == BLM_OK) first = s;
+  }
+  return first;
 }
 
 }  // extern "C"

@@ -1223,8 +1223,11 @@ __device__ int select_lowest(Shared& sh, const gdouble* wr, const gdouble* wi, i
   for (int i = tid; i < d; i += NT) sh.mark[i] = 0;
   if (tid == 0) sh.sel_n = 0;
   __syncthreads();
+  // eigenvalues are ranked until max_entries are listed; those taken while
+  // fewer than `want` directions are held are the selected ones
   int held = 0, n_sel = 0, n_ev = 0;
-  while (held < want && n_sel < EIG_MAXSEL && n_ev < max_entries) {
+  while (n_ev < max_entries && (held >= want || n_sel < EIG_MAXSEL)) {
+    const bool take = held < want;
     // argmin over unmarked of (wr asc, wi desc, index asc)
     double br = INFINITY, bi = -INFINITY;
     int bidx = d;
@@ -1273,8 +1276,10 @@ __device__ int select_lowest(Shared& sh, const gdouble* wr, const gdouble* wi, i
     const double r = wr[ix], im = wi[ix];
     if (tid == 0) {
       sh.mark[ix] = 1;
-      sh.sel_r[n_sel] = r;
-      sh.sel_i[n_sel] = im;
+      if (take) {
+        sh.sel_r[n_sel] = r;
+        sh.sel_i[n_sel] = im;
+      }
       out_evals[2 * n_ev] = r;
       out_evals[2 * n_ev + 1] = im;
       if (im != 0.0) {
@@ -1291,15 +1296,15 @@ __device__ int select_lowest(Shared& sh, const gdouble* wr, const gdouble* wi, i
       }
     }
     __syncthreads();
-    n_sel += 1;
-    if (im != 0.0) {
-      held += 2;
-      n_ev += 2;
-    } else {
-      held += 1;
-      n_ev += 1;
+    if (take) {
+      n_sel += 1;
+      held += (im != 0.0) ? 2 : 1;
     }
+    n_ev += (im != 0.0) ? 2 : 1;
   }
+  // a pencil with fewer eigenvalues than entries
+  if (tid == 0)
+    for (int i = n_ev; i < max_entries; ++i) out_evals[2 * i] = out_evals[2 * i + 1] = __builtin_nan("");
   if (tid == 0) sh.sel_n = n_sel;
   __syncthreads();
   return n_sel;

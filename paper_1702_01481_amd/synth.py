@@ -112,12 +112,27 @@ def uniform_int_offsets(n_params: int, lo: int, hi: int, seed: int) -> np.ndarra
         sizes.append(s)
         left -= s
     if len(sizes) > 1 and sizes[-1] < lo:
-        sizes[-2] += sizes.pop()
+        last = sizes.pop()
+        sizes[-1] += last
     return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
 
 
+BATCH_SIZES = (2_000, 4_000, 6_000, 8_000, 10_000, 12_000, 16_000, 20_000)
+
+
+def batched_workloads(seed: int = 0, n_samples: int = 1_000_000) -> List[Workload]:
+    """Eight independent optimizations solved together: N_V from 2,000 to
+    20,000 (78,000 parameters in all), blocks drawn as uniform integers in
+    [500, 1,500], n_samples each (1,000,000 at full size) in 65,536-sample
+    chunks, rank 32, N_K=4, N_O=0, delta=1e-3; problem p draws from seed + p."""
+    return [Workload(f"batch{p}_{n}x{n_samples}", n, uniform_int_offsets(n, 500, 1500, seed + p), n_samples,
+                     65_536, 32, 4, 0, (1e-3,), seed=seed + p)
+            for p, n in enumerate(BATCH_SIZES)]
+
+
 def workload(name: str, seed: int = 0) -> Workload:
-    """The five synthetic workloads (sizes of the paper's problems and beyond).
+    """The four single-problem synthetic workloads (sizes of the paper's
+    problems and beyond; batched_workloads gives the eight-problem one).
 
     small     N_V=200 in 4x50, N_s=20,000 (one chunk), rank 8, N_K=3, delta=1e-3
     fp64      N_V=4,096 in 8x512, N_s=1,000,000 in 65,536-sample chunks, rank 32,

@@ -66,6 +66,11 @@ def _compare_step(offsets, n_keep, shifts, host, dev, old=None, n_old=0, mat_tol
             assert H.shape == p.H.shape
             assert _rel(S, p.S) <= mat_tol, (b, si, _rel(S, p.S))
             assert _rel(H, p.H + delta * p.P) <= mat_tol, (b, si, _rel(H, p.H + delta * p.P))
+            # the N_K + 1 lowest eigenvalues of the shifted pencil, ranked
+            lam = r.blocks[b].evals[orc.rank_order(r.blocks[b].evals)][: n_keep + 1]
+            got = ev[si, b, : len(lam)]
+            scale = np.abs(r.blocks[b].evals).max()
+            assert np.abs(got - lam).max() <= 1e-10 * scale, (b, si, got, lam)
             # kept span: same count, same projector
             B = ctx.directions(b, si)
             Bo = r.blocks[b].B

@@ -44,3 +44,18 @@ def test_workspace_bytes_and_argument_checks():
         blm.BLM.workspace_bytes(4096, off[::-1].copy(), 5, 1, [1e-3], 65536)
     with pytest.raises(blm.BLMError):
         blm.BLM.workspace_bytes(4096, off, 5, 1, [-1.0], 65536)
+
+
+def test_synthetic_partitions_cover_the_parameters():
+    """Block partitions of the synthetic workloads: contiguous, ascending,
+    from 0 to N_V; uniform-integer blocks within [lo, hi] except a merged
+    remainder (below lo) on the last block."""
+    from paper_1702_01481_amd import synth
+    for w in synth.batched_workloads(n_samples=1):
+        off = np.asarray(w.block_offsets)
+        sz = np.diff(off)
+        assert off[0] == 0 and off[-1] == w.n_params, (w.name, off[-1])
+        assert sz.min() >= 500 and sz[:-1].max() <= 1500 and sz[-1] < 2000, (w.name, sz)
+    assert sum(w.n_params for w in synth.batched_workloads(n_samples=1)) == 78_000
+    off = synth.loguniform_offsets(30_000, 40, 100.0, 2000.0, 0)
+    assert off[0] == 0 and off[-1] == 30_000 and len(off) == 41 and np.all(np.diff(off) > 0)
