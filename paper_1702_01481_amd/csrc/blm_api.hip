@@ -64,6 +64,7 @@ struct blm_ctx {
   int n_cus = 0;                   // compute units of the device (0: unknown)
   unsigned* d_hbar = nullptr;      // block solves: barrier counter and flag per pencil
   unsigned spin_limit = 1u << 22;  // polls of a workgroup barrier before it gives up
+  int hess_wg = 8;                 // most workgroups per pencil in the Hessenberg reduction
   std::string err;
   int state = ST_CREATED;
 
@@ -728,6 +729,7 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
   if (hipDeviceGetAttribute(&c->n_cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
     c->n_cus = 0;
   if (const char* e = getenv("BLM_SYNC_SPIN_LIMIT")) c->spin_limit = (unsigned)strtoul(e, nullptr, 10);
+  if (const char* e = getenv("BLM_HESS_WORKGROUPS")) c->hess_wg = std::max(1, atoi(e));
   Plan P;
   plan(c, P);
   for (auto& it : P.items) {
@@ -1091,7 +1093,7 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   if (s != BLM_OK) return s;
   HIPCHK(c, hipMemcpyAsync(c->d_eig1, ej.data(), sizeof(EigJob) * ej.size(), hipMemcpyHostToDevice, c->st));
   mark(c, 4, false);
-  launch_eig_split(c->d_eig1, (int)ej.size(), dm, c->n_cus, c->d_hbar, c->spin_limit, c->st);
+  launch_eig_split(c->d_eig1, (int)ej.size(), dm, c->n_cus, c->hess_wg, c->d_hbar, c->spin_limit, c->st);
   HIPCHK(c, hipGetLastError());
   mark(c, 4, true);
   return solve_end(c, h_evals, h_kept);
@@ -1372,6 +1374,7 @@ struct blm_batch {
   hipStream_t st = nullptr;
   int n_cus = 0;
   unsigned spin_limit = 1u << 22;
+  int hess_wg = 8;
   EigJob* d_eig1 = nullptr;   // every context's block pencils
   EigJob* d_eig2 = nullptr;   // every context's stage-two pencils
   unsigned* d_hbar = nullptr; // barrier counter and flag per block pencil
@@ -1394,6 +1397,7 @@ blm_status blm_batch_create(blm_ctx* const* ctxs, int32_t n, blm_batch** out) {
   b->st = ctxs[0]->st;
   b->n_cus = ctxs[0]->n_cus;
   b->spin_limit = ctxs[0]->spin_limit;
+  b->hess_wg = ctxs[0]->hess_wg;
   if (hipMalloc((void**)&b->d_eig1, sizeof(EigJob) * n1) != hipSuccess ||
       hipMalloc((void**)&b->d_eig2, sizeof(EigJob) * n2) != hipSuccess ||
       hipMalloc((void**)&b->d_hbar, 4 * 2 * (size_t)n1) != hipSuccess) {
@@ -1432,7 +1436,7 @@ blm_status blm_batch_solve_blocks(blm_batch* b, double* const* h_evals, int32_t*
   blm_ctx* c0 = b->ctx[0];
   HIPCHK(c0, hipMemcpyAsync(b->d_eig1, all.data(), sizeof(EigJob) * all.size(), hipMemcpyHostToDevice, b->st));
   for (blm_ctx* c : b->ctx) mark(c, 4, false);
-  launch_eig_split(b->d_eig1, (int)all.size(), dm, b->n_cus, b->d_hbar, b->spin_limit, b->st);
+  launch_eig_split(b->d_eig1, (int)all.size(), dm, b->n_cus, b->hess_wg, b->d_hbar, b->spin_limit, b->st);
   HIPCHK(c0, hipGetLastError());
   for (blm_ctx* c : b->ctx) mark(c, 4, true);
   blm_status first = BLM_OK;

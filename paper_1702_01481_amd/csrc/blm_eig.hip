@@ -2152,14 +2152,14 @@ __global__ void fill_u32_kernel(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int d_max, int n_cus, unsigned* d_bar,
+bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int d_max, int n_cus, int max_kw, unsigned* d_bar,
                       unsigned spin_limit, hipStream_t st) {
   if (n_jobs <= 0) return true;
   hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_CHOL);
   const int ns = max(1, (min(d_max, EIG_MAXD) + CSW - 1) / CSW);
   hipLaunchKernelGGL(cong_cols_kernel, dim3(n_jobs * ns), dim3(NT), 0, st, d_jobs, n_jobs);
   hipLaunchKernelGGL(cong_rows_kernel, dim3(n_jobs * ns), dim3(NT), 0, st, d_jobs, n_jobs);
-  const int kw = min(HKW_MAX, n_cus / n_jobs);
+  const int kw = min(min(HKW_MAX, max_kw), n_cus / n_jobs);
   if (kw < 2) {
     hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)(PH_HESS | PH_BACK));
     return true;

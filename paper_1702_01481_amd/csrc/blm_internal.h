@@ -193,7 +193,7 @@ void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);
 // the same with each pencil's Hessenberg reduction spread over several
 // workgroups (cooperative launch; d_bar: 2 n_jobs counters); returns false
 // if it had to fall back to one workgroup per pencil
-bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int d_max, int n_cus, unsigned* d_bar,
+bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int d_max, int n_cus, int max_kw, unsigned* d_bar,
                       unsigned spin_limit, hipStream_t st);
 
 }  // namespace blm

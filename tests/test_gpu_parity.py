@@ -261,6 +261,35 @@ def test_barrier_timeout_is_reported(monkeypatch):
     ctx.close()
 
 
+def test_single_workgroup_hessenberg_gives_the_same_step(monkeypatch):
+    """BLM_HESS_WORKGROUPS=1 keeps every pencil on one workgroup (no
+    cooperative launch); the step equals the default one's to FP64
+    tolerances (only the rounding order of the reduction's sums differs)."""
+    blm = _blm()
+    _, dev = _make(300, 3000, 4, 5, 3000)
+    out = []
+    for env in (None, "1"):
+        if env is None:
+            monkeypatch.delenv("BLM_HESS_WORKGROUPS", raising=False)
+        else:
+            monkeypatch.setenv("BLM_HESS_WORKGROUPS", env)
+        ctx = blm.BLM(300, [0, 300], 3, 0, [1e-3], 3000)
+        monkeypatch.delenv("BLM_HESS_WORKGROUPS", raising=False)
+        ctx.begin_step()
+        ctx.build(dev)
+        ev, kept = ctx.solve()
+        ctx.project(dev)
+        upd, en, _, _ = ctx.stage2()
+        torch.cuda.synchronize()
+        out.append((ev, kept, upd.cpu().numpy(), en))
+        ctx.close()
+    (ev1, k1, u1, e1), (ev2, k2, u2, e2) = out
+    assert np.array_equal(k1, k2)
+    assert np.abs(ev1 - ev2).max() <= 1e-10 * np.abs(ev1).max()
+    assert abs(e1[0] - e2[0]) <= 1e-10 * abs(e1[0])
+    assert u1[0] @ u2[0] / (np.linalg.norm(u1[0]) * np.linalg.norm(u2[0])) >= 1 - 1e-10
+
+
 # --------------------------------------------------------- mixed precision --
 
 def test_pack_bf16_split_is_accurate():
