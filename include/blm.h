@@ -172,9 +172,10 @@ blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chu
  * several workgroups each, which meet at a barrier after every elimination
  * step; a wait there gives up after BLM_SYNC_SPIN_LIMIT polls (environment,
  * read by blm_create; default 4194304) and the call then returns
- * BLM_E_TIMEOUT.  BLM_HESS_WORKGROUPS (environment, read by blm_create;
- * default 8) caps the workgroups per pencil; 1 keeps every pencil on one
- * workgroup, with no cooperative launch.  Errors: BLM_E_S_NOT_PD, BLM_E_NONFINITE, BLM_E_NOCONV,
+ * BLM_E_TIMEOUT.  The Cholesky factorisations of the overlaps run the same
+ * way, one barrier per 16 columns.  BLM_HESS_WORKGROUPS (environment, read
+ * by blm_create; default 8) caps the workgroups per pencil in both; 1 keeps
+ * every pencil on one workgroup, with no cooperative launch.  Errors: BLM_E_S_NOT_PD, BLM_E_NONFINITE, BLM_E_NOCONV,
  * BLM_E_TIMEOUT name the first failing block. */
 blm_status blm_solve_blocks(blm_ctx* ctx, double* h_evals, int32_t* h_kept);
 

@@ -1760,7 +1760,7 @@ __device__ double hs_block_sum(HessShared& hs, double v) {
 // barrier among the kw workgroups of a pencil: cnt counts arrivals, err is
 // the pencil's flag; returns false if the wait ran past its bound (or
 // another workgroup's did)
-__device__ bool pencil_barrier(HessShared& hs, unsigned* cnt, int* err, unsigned target, unsigned spin_limit) {
+__device__ bool pencil_barrier(int& ok_slot, unsigned* cnt, int* err, unsigned target, unsigned spin_limit) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -1776,10 +1776,10 @@ __device__ bool pencil_barrier(HessShared& hs, unsigned* cnt, int* err, unsigned
       __builtin_amdgcn_s_sleep(2);
     }
     __threadfence();
-    hs.ok = ok;
+    ok_slot = ok;
   }
   __syncthreads();
-  return hs.ok != 0;
+  return ok_slot != 0;
 }
 
 // reflector of step k from column values in vec (rows k+1..d-1), as in
@@ -1923,7 +1923,7 @@ __global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict
   double tk = hess_reflector_hs(hs, cv, V, tau, 0, d, &beta_h, writer);
   hess_pass_rows<false, true>(hs, A, d, 0, r0, r1, 0.0, 0.0, nullptr, nullptr, nullptr, cv, Pb[0],
                               Qb[0] + (size_t)part * d);
-  if (!pencil_barrier(hs, cnt, err, kw * ++gen, spin_limit)) {
+  if (!pencil_barrier(hs.ok, cnt, err, kw * ++gen, spin_limit)) {
     if (tid == 0) info[0] = EIG_SYNC;
     return;
   }
@@ -1959,7 +1959,7 @@ __global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict
     } else {
       hess_pass_rows<true, false>(hs, A, d, k, r0, r1, tk, beta_h, cv, Pc, cq, nullptr, nullptr, nullptr);
     }
-    if (!pencil_barrier(hs, cnt, err, kw * ++gen, spin_limit)) {
+    if (!pencil_barrier(hs.ok, cnt, err, kw * ++gen, spin_limit)) {
       if (tid == 0) info[0] = EIG_SYNC;
       return;
     }
@@ -1970,6 +1970,161 @@ __global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict
     beta_h = bh_next;
   }
   if (writer && tid == 0) info[6] = (int32_t)((wall_clock64() - t_start));
+}
+
+// ------------------------------------- step 1, distributed over workgroups --
+// Cholesky factorisation S = L L^T of each pencil's overlap on kw workgroups
+// (cooperative launch, row bands as in the Hessenberg reduction), blocked
+// and left-looking: panel k0 holds columns k0..k0+CPB-1.  Every workgroup
+// forms the panel's diagonal block D = S_kk - L_k,<k0 L_k,<k0^T and factors
+// it in LDS in the same order, so every one takes the same pivots (and
+// sees the same failure).  Each workgroup updates its own rows below the
+// panel (S_ik -= L_i,<k0 L_k,<k0^T, in place) and solves them against the
+// factor.  One barrier per panel makes those rows of L visible to the next
+// panel; only after it do the owners of the panel's own rows write its
+// factor over the diagonal block, which every workgroup has read by then.
+// Within the diagonal block the operations and their order are those of the
+// one-workgroup factorisation.
+constexpr int CPB = 16;     // columns per panel
+constexpr int CTOPW = 512;  // columns of the panel's top rows staged at a time
+
+struct CholShared {
+  double top[CPB][CTOPW];   // L[k0 + q][m0 + c]
+  double dg[CPB][CPB];      // the diagonal block, then its factor
+  double dsum[CPB * (CPB + 1) / 2];  // the diagonal block's sums over earlier columns
+  int st;
+  int ok;
+};
+
+__global__ __launch_bounds__(NT) void chol_multi_kernel(const EigJob* __restrict__ jobs, int n_jobs, int kw,
+                                                        unsigned* __restrict__ bar, unsigned spin_limit) {
+  __shared__ CholShared cs;
+  const int job = blockIdx.x % n_jobs, part = blockIdx.x / n_jobs;
+  const EigJob& E = jobs[job];
+  const int d = E.d, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  gdouble* S = as_global(E.S);
+  BLM_GLOBAL int32_t* info = as_global(E.info);
+  if (d <= 0 || d > EIG_MAXD) return;
+  const uint64_t t_start = wall_clock64();
+  unsigned* cnt = bar + 2 * job;
+  int* err = (int*)(bar + 2 * job + 1);
+  const int r0 = (int)((int64_t)d * part / kw), r1 = (int)((int64_t)d * (part + 1) / kw);
+  unsigned gen = 0;
+  for (int k0 = 0; k0 < d; k0 += CPB) {
+    const int kb = min(CPB, d - k0);
+    // (a) D's lower triangle: pair t = (q, p), p <= q, t = q (q + 1) / 2 + p
+    constexpr int NPAIR = CPB * (CPB + 1) / 2;
+    for (int t = tid; t < NPAIR; t += NT) cs.dsum[t] = 0.0;
+    const int rb0 = max(r0, k0 + kb);   // own rows below the panel
+    for (int m0 = 0; m0 < k0; m0 += CTOPW) {
+      const int cw = min(CTOPW, k0 - m0);
+      __syncthreads();
+      for (int t = tid; t < CPB * CTOPW; t += NT) {
+        const int q = t / CTOPW, c = t % CTOPW;
+        cs.top[q][c] = (q < kb && c < cw) ? S[(size_t)(k0 + q) * d + m0 + c] : 0.0;
+      }
+      __syncthreads();
+      for (int t = wv; t < NPAIR; t += NW) {
+        int q = 0;
+        while ((q + 1) * (q + 2) / 2 <= t) ++q;
+        const int pp = t - q * (q + 1) / 2;
+        double ps = 0.0;
+#pragma unroll 1
+        for (int c = lane; c < cw; c += 64) ps += cs.top[q][c] * cs.top[pp][c];
+        ps = wave_sum(ps);
+        if (lane == 0) cs.dsum[t] += ps;
+      }
+      // own rows below the panel: S[i][k0 + q] -= L[i][m0..] . top[q][..]
+      for (int iv = rb0 + wv; iv < r1; iv += NW) {
+        const int i = __builtin_amdgcn_readfirstlane(iv);
+        double acc[CPB];
+#pragma unroll
+        for (int q = 0; q < CPB; ++q) acc[q] = 0.0;
+#pragma unroll 1
+        for (int c = lane; c < cw; c += 64) {
+          const double x = S[(size_t)i * d + m0 + c];
+#pragma unroll
+          for (int q = 0; q < CPB; ++q) acc[q] += x * cs.top[q][c];
+        }
+#pragma unroll
+        for (int q = 0; q < CPB; ++q) acc[q] = wave_sum(acc[q]);
+        if (lane < kb) {
+          double mine = acc[0];
+#pragma unroll
+          for (int q = 1; q < CPB; ++q)
+            if (lane == q) mine = acc[q];
+          S[(size_t)i * d + k0 + lane] -= mine;
+        }
+      }
+    }
+    // D = S_kk - the sums; lower triangle in dg
+    __syncthreads();
+    for (int t = tid; t < NPAIR; t += NT) {
+      int q = 0;
+      while ((q + 1) * (q + 2) / 2 <= t) ++q;
+      const int pp = t - q * (q + 1) / 2;
+      cs.dg[q][pp] = (q < kb) ? S[(size_t)(k0 + q) * d + k0 + pp] - cs.dsum[t] : 0.0;
+    }
+    __syncthreads();
+    // (b) factor D in LDS: wave 0, lanes over rows, columns in order
+    if (wv == 0) {
+      int st = EIG_OK;
+      for (int j = 0; j < kb; ++j) {
+        double v = cs.dg[j][j];
+        for (int pp = 0; pp < j; ++pp) v -= cs.dg[j][pp] * cs.dg[j][pp];
+        if (!isfinite(v)) st = EIG_NONFINITE;
+        else if (!(v > 0.0)) st = EIG_NOT_PD;
+        if (st != EIG_OK) break;
+        const double piv = sqrt(v);
+        double x = 0.0;
+        if (lane > j && lane < kb) {
+          x = cs.dg[lane][j];
+          for (int pp = 0; pp < j; ++pp) x -= cs.dg[lane][pp] * cs.dg[j][pp];
+          x /= piv;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane > j && lane < kb) cs.dg[lane][j] = x;
+        if (lane == 0) cs.dg[j][j] = piv;
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (lane == 0) cs.st = st;
+    }
+    __syncthreads();
+    if (cs.st != EIG_OK) {
+      if (part == 0 && tid == 0) info[0] = cs.st;
+      return;
+    }
+    // (c) own rows below the panel: L[i][k0 + q] = (a_q - sum_p L[i][k0 + p] f[q][p]) / f[q][q],
+    // one wave per row, lane q holding entry q, the terms subtracted in p order
+    for (int iv = rb0 + wv; iv < r1; iv += NW) {
+      const int i = __builtin_amdgcn_readfirstlane(iv);
+      gdouble* Li = S + (size_t)i * d + k0;
+      double x = (lane < kb) ? Li[lane] : 0.0;
+      for (int q = 0; q < kb; ++q) {
+        if (lane == q) x /= cs.dg[q][q];
+        const double xq = lane_bcast(x, q);
+        if (lane > q && lane < kb) x -= xq * cs.dg[lane][q];
+      }
+      if (lane < kb) Li[lane] = x;
+    }
+    if (!pencil_barrier(cs.ok, cnt, err, kw * ++gen, spin_limit)) {
+      if (tid == 0) info[0] = EIG_SYNC;
+      return;
+    }
+    // every workgroup has read the panel's diagonal block: its factor into
+    // the rows this workgroup owns (nothing in this launch reads it back)
+    for (int t = tid; t < CPB * CPB; t += NT) {
+      const int q = t / CPB, pp = t % CPB;
+      if (q < kb && pp <= q && k0 + q >= r0 && k0 + q < r1) S[(size_t)(k0 + q) * d + k0 + pp] = cs.dg[q][pp];
+    }
+    __syncthreads();
+  }
+  if (part == 0 && tid == 0) info[4] = (int32_t)(wall_clock64() - t_start);
+}
+
+__global__ void eig_info_init_kernel(const EigJob* __restrict__ jobs, int n_jobs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_jobs * EIG_INFO) as_global(jobs[t / EIG_INFO].info)[t % EIG_INFO] = 0;
 }
 
 struct GJob {
@@ -2155,11 +2310,22 @@ __global__ void fill_u32_kernel(unsigned* p, int n) {
 bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int d_max, int n_cus, int max_kw, unsigned* d_bar,
                       unsigned spin_limit, hipStream_t st) {
   if (n_jobs <= 0) return true;
-  hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_CHOL);
+  const int kw = min(min(HKW_MAX, max_kw), n_cus / n_jobs);
+  bool chol_done = false;
+  if (kw >= 2) {
+    hipLaunchKernelGGL(eig_info_init_kernel, dim3((n_jobs * EIG_INFO + 255) / 256), dim3(256), 0, st, d_jobs,
+                       n_jobs);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * n_jobs + 255) / 256), dim3(256), 0, st, d_bar, 2 * n_jobs);
+    int nj = n_jobs, k = kw;
+    void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&k, (void*)&d_bar, (void*)&spin_limit};
+    chol_done = hipLaunchCooperativeKernel((const void*)chol_multi_kernel, dim3(n_jobs * kw), dim3(NT), args, 0,
+                                           st) == hipSuccess;
+    if (!chol_done) (void)hipGetLastError();
+  }
+  if (!chol_done) hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_CHOL);
   const int ns = max(1, (min(d_max, EIG_MAXD) + CSW - 1) / CSW);
   hipLaunchKernelGGL(cong_cols_kernel, dim3(n_jobs * ns), dim3(NT), 0, st, d_jobs, n_jobs);
   hipLaunchKernelGGL(cong_rows_kernel, dim3(n_jobs * ns), dim3(NT), 0, st, d_jobs, n_jobs);
-  const int kw = min(min(HKW_MAX, max_kw), n_cus / n_jobs);
   if (kw < 2) {
     hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)(PH_HESS | PH_BACK));
     return true;

@@ -146,7 +146,7 @@ struct EigJob {
   double* wi;           // [d]
   double* tau;          // [d]
   double* out;          // EIG_BLOCK: [n_want + 1][nbeta] rows; EIG_STAGE2: [2][d] (re, im)
-  double* out_evals;    // [n_want + 1][2] the used eigenvalues in rank order
+  double* out_evals;    // [n_want + 1][2] the lowest eigenvalues in rank order (NaN past the last)
   int32_t* info;        // [EIG_INFO]: [0] status, [1] rows/vectors produced, [2] flags,
                         // [3] QR iterations, [4..11] 100 MHz ticks per phase (Cholesky,
                         // congruence, Hessenberg, QR, selection, inverse iteration,
