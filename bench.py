@@ -127,6 +127,11 @@ def mixed_step(args, prec, w, chunks, old, offsets, shifts, n_samples, en64, upd
     log(f"packed {prec} storage")
     ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, n_samples, precision=prec)
     ctx.set_timing(True)
+    groups = None
+    if not args.no_autotune:
+        ctx.begin_step(old)
+        groups = ctx.autotune(split)
+        log(f"{prec} build: {groups} slice groups per tile")
 
     def step():
         ctx.begin_step(old)
@@ -163,6 +168,7 @@ def mixed_step(args, prec, w, chunks, old, offsets, shifts, n_samples, en64, upd
         "build_tflops": round(fl_build / (build_ms * 1e-3) / 1e12, 4),
         "gram_ms": round(pm["block_gram"], 3),
         "gram_algorithmic_tflops": round(fl_build / (pm["block_gram"] * 1e-3) / 1e12, 4),
+        "build_slice_groups": groups,
         "phase_ms": {k: round(v, 3) for k, v in pm.items()},
         "energy_rel_err_vs_fp64": rel,
         "update_cosine_vs_fp64": cos,
@@ -179,6 +185,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the heuristic slice-group count of the build instead of timing the candidates")
     ap.add_argument("--mixed", default="bf16x3,fp8",
                     help="comma-separated mixed precisions (bf16x3, bf16x2, fp8) also run on the same "
                          "samples, or none")
@@ -242,6 +250,11 @@ def main():
     upd, en0, _, _ = step(torch.zeros(w.n_old, w.n_params, dtype=torch.float64, device=dev))
     old = upd[1:2].clone().contiguous()
     log(f"history step done in {time.perf_counter() - t1:.3f} s: {ctx.timings()}")
+    groups = None
+    if not args.no_autotune:
+        ctx.begin_step(old)
+        groups = ctx.autotune(chunks)
+        log(f"fp64 build: {groups} slice groups per tile")
     for _ in range(args.warmup):
         step(old)
     torch.cuda.synchronize()
@@ -286,6 +299,7 @@ def main():
                    "n_old": w.n_old, "shifts": shifts, "precision": "fp64"},
         "build_tflops": round(fl_build / (build_ms * 1e-3) / 1e12, 4),
         "build_ms": round(build_ms, 3),
+        "build_slice_groups": groups,
         "phase_ms": {k: round(float(np.mean(v)), 3) for k, v in phase.items()},
         "block_eig_phase_ms_max": eig_phases,
         "energy": [float(x) for x in en],

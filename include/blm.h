@@ -161,6 +161,21 @@ blm_status blm_begin_step(blm_ctx* ctx, const double* d_old);
  * called any number of times per step. */
 blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks);
 
+/* Launch-shape autotuner for the block build.  The build's Gram kernel
+ * splits the sample axis of every output tile into G groups of 4,096-sample
+ * slices, summed afterwards in a fixed order; the best G depends on the
+ * device, the blocks and the storage.  This call times the kernel on the
+ * given chunks for each G in {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64} up
+ * to the context's limit (one settling launch and one timed launch each,
+ * HIP events on the context's stream), and later builds of this context
+ * use the fastest.  It writes only the Theta projection of the chunks and
+ * scratch tiles: the step's accumulated estimates are unchanged, so it may
+ * run between blm_begin_step and the first blm_build_blocks, or between
+ * builds.  Synchronises the stream.  h_groups (may be NULL): the chosen G.
+ * Returns BLM_E_STATE outside a build phase, BLM_E_ARG for empty or bad
+ * chunks. */
+blm_status blm_autotune_build(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks, int32_t* h_groups);
+
 /* Solves every block's shifted pencil (H_b + delta P_b) c = lambda S_b c for
  * every shift, ranks the eigenvalues by real part and keeps the parameter
  * part of the best directions, orthonormalised, as B^(b) (Eq. 6).

@@ -74,6 +74,7 @@ struct blm_ctx {
   std::vector<int> dmax;           // per block: largest pencil dimension
   int d2max = 0, n2max = 0;        // stage two
   int Pcap1 = 1, Pcap2 = 1, PcapM = 1;
+  int P_tuned[4] = {0, 0, 0, 0};   // slice groups chosen by blm_autotune_build, per build kind (0: heuristic)
   int max_slices = 0;
   int64_t* d_off = nullptr;
 
@@ -568,6 +569,17 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
 // kind: 0 FP64 kernel on FP64 storage, 1 FP64 kernel on split storage
 // (strips), 2 BF16 matrix-core kernel on split storage (main products),
 // 3 FP8 + BF16 matrix-core kernel on FP8 storage (main products)
+// the Gram launch of one build kind (0: FP64, 1: FP64 aux of a mixed build, 2: BF16 pieces, 3: FP8)
+// over the slice table on the device, into the partial tiles
+void launch_build_gram(blm_ctx* c, int kind, const GramJob* d_jobs, int n_jobs, int n_slices, int P, bool vec) {
+  if (kind == 2)
+    launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->pieces, c->partial, c->st);
+  else if (kind == 3)
+    launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->partial, c->st);
+  else
+    launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec && kind == 0, kind == 1, c->partial, c->st);
+}
+
 blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_base,
                     double* h_base, double* strip_base, int phase, bool vec, int kind = 0) {
   const int n_slices = (int)c->h_slices.size();
@@ -577,16 +589,10 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
   if (n_slices > c->max_slices) return fail(c, BLM_E_ARG, "too many slices in one call");
   HIPCHK(c, hipMemcpyAsync(c->d_slices, c->h_slices.data(), sizeof(Slice) * n_slices,
                            hipMemcpyHostToDevice, c->st));
-  const int P = choose_P(cap, n_jobs, n_slices);
+  int P = choose_P(cap, n_jobs, n_slices);
+  if (c->P_tuned[kind] > 0) P = std::max(1, std::min({c->P_tuned[kind], cap, std::max(1, n_slices)}));
   if (phase >= 0) mark(c, phase, false);
-  if (kind == 2)
-    launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->pieces,
-                     c->partial, c->st);
-  else if (kind == 3)
-    launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->partial, c->st);
-  else
-    launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec && kind == 0, kind == 1, c->partial,
-                c->st);
+  launch_build_gram(c, kind, d_jobs, n_jobs, n_slices, P, vec);
   HIPCHK(c, hipGetLastError());
   if (phase >= 0) {
     mark(c, phase, true);
@@ -595,6 +601,87 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
   launch_gram_reduce(d_jobs, n_jobs, P, c->partial, s_base, h_base, strip_base, c->NV, c->st);
   HIPCHK(c, hipGetLastError());
   if (phase >= 0) mark(c, phase + 1, true);
+  return BLM_OK;
+}
+
+// The aux columns of the chunks (Theta projection) and the build's slice
+// table (host side, c->h_slices), with the aux columns packed to the
+// build's storage per chunk.
+blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
+  blm_status s = run_dirproj(c, ch, n, c->d_theta_blk, c->NO > 0 ? c->NB : 0, c->d_theta_ptr, c->NO * c->NB,
+                             c->Xa, c->Ya, NAUX);
+  if (s != BLM_OK) return s;
+  c->h_slices.clear();
+  int64_t rb = 0, gbase = 0, g16base = 0;
+  int ci = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t ns = ch[i].n_samples;
+    if (ns == 0) continue;
+    uint8_t* xq = nullptr;
+    uint16_t* xr = nullptr;
+    float* xs = nullptr;
+    if (c->fp8) {
+      // this chunk's aux columns in FP8 storage, with their own scales
+      xq = c->auxQ + g16base * NAUX * 16;
+      xr = c->auxR + gbase * NAUX * 8;
+      xs = c->auxS + (size_t)ci * 2 * NAUX;
+      launch_pack_fp8(c->Xa + (size_t)rb * NAUX, ns, NAUX, NAUX, xq, xr, xs, NAUX, c->st);
+      launch_pack_fp8(c->Ya + (size_t)rb * NAUX, ns, NAUX, NAUX, xq + c->auxq_stride, xr + c->auxr_stride,
+                      xs + NAUX, NAUX, c->st);
+      HIPCHK(c, hipGetLastError());
+    }
+    if (c->pieces) {
+      // this chunk's aux columns as BF16 pieces, from an 8-sample group boundary
+      uint16_t* xp = c->auxP + gbase * NAUX * 8;
+      launch_pack_bf16(c->Xa + (size_t)rb * NAUX, ns, NAUX, NAUX, c->pieces, xp, NAUX, c->aux_pstride,
+                       c->st);
+      launch_pack_bf16(c->Ya + (size_t)rb * NAUX, ns, NAUX, NAUX, c->pieces,
+                       xp + (size_t)c->pieces * c->aux_pstride, NAUX, c->aux_pstride, c->st);
+      HIPCHK(c, hipGetLastError());
+    }
+    for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
+      Slice S{};
+      if (c->fp8) {
+        // slice starts are multiples of 16 samples
+        S.O = (const uint8_t*)ch[i].O + (size_t)(s0 / 16) * ch[i].ld * 16;
+        S.e = (const uint8_t*)ch[i].e + (size_t)(s0 / 16) * ch[i].ld * 16;
+        S.Or = (const uint16_t*)ch[i].O_res + (size_t)(s0 / 8) * ch[i].ld * 8;
+        S.er = (const uint16_t*)ch[i].e_res + (size_t)(s0 / 8) * ch[i].ld * 8;
+        S.Os = ch[i].O_scale;
+        S.es = ch[i].e_scale;
+        S.Xq = xq + (size_t)(s0 / 16) * NAUX * 16;
+        S.Yq = S.Xq + c->auxq_stride;
+        S.Xr = xr + (size_t)(s0 / 8) * NAUX * 8;
+        S.Yr = S.Xr + c->auxr_stride;
+        S.Xs = xs;
+        S.Ys = xs + NAUX;
+      } else if (c->pieces) {
+        // k-packed pieces: slice starts are multiples of 8 samples
+        S.O = (const uint16_t*)ch[i].O + (size_t)(s0 / 8) * ch[i].ld * 8;
+        S.e = (const uint16_t*)ch[i].e + (size_t)(s0 / 8) * ch[i].ld * 8;
+        S.pstride = ch[i].piece_stride;
+        S.pieces = c->pieces;
+      } else {
+        S.O = (const double*)ch[i].O + (size_t)s0 * ch[i].ld;
+        S.e = (const double*)ch[i].e + (size_t)s0 * ch[i].ld;
+      }
+      S.Xa = c->Xa + (size_t)(rb + s0) * NAUX;
+      S.Ya = c->Ya + (size_t)(rb + s0) * NAUX;
+      if (c->pieces) {
+        S.Xp = c->auxP + (size_t)(gbase + s0 / 8) * NAUX * 8;
+        S.Yp = S.Xp + (size_t)c->pieces * c->aux_pstride;
+        S.apstride = c->aux_pstride;
+      }
+      S.w = ch[i].w ? ch[i].w + s0 : nullptr;
+      S.ld = ch[i].ld;
+      S.n = std::min<int64_t>(SLICE, ns - s0);
+      c->h_slices.push_back(S);
+    }
+    rb += ns;
+    gbase += (ns + 7) / 8;
+    g16base += (ns + 15) / 16;
+    ++ci;
+  }
   return BLM_OK;
 }
 
@@ -848,80 +935,8 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   blm_status s = check_chunks(c, ch, n, &total);
   if (s != BLM_OK) return s;
   mark(c, 0, false);
-  s = run_dirproj(c, ch, n, c->d_theta_blk, c->NO > 0 ? c->NB : 0, c->d_theta_ptr, c->NO * c->NB,
-                  c->Xa, c->Ya, NAUX);
+  s = build_slices(c, ch, n);
   if (s != BLM_OK) return s;
-  c->h_slices.clear();
-  int64_t rb = 0, gbase = 0, g16base = 0;
-  int ci = 0;
-  for (int i = 0; i < n; ++i) {
-    const int64_t ns = ch[i].n_samples;
-    if (ns == 0) continue;
-    uint8_t* xq = nullptr;
-    uint16_t* xr = nullptr;
-    float* xs = nullptr;
-    if (c->fp8) {
-      // this chunk's aux columns in FP8 storage, with their own scales
-      xq = c->auxQ + g16base * NAUX * 16;
-      xr = c->auxR + gbase * NAUX * 8;
-      xs = c->auxS + (size_t)ci * 2 * NAUX;
-      launch_pack_fp8(c->Xa + (size_t)rb * NAUX, ns, NAUX, NAUX, xq, xr, xs, NAUX, c->st);
-      launch_pack_fp8(c->Ya + (size_t)rb * NAUX, ns, NAUX, NAUX, xq + c->auxq_stride, xr + c->auxr_stride,
-                      xs + NAUX, NAUX, c->st);
-      HIPCHK(c, hipGetLastError());
-    }
-    if (c->pieces) {
-      // this chunk's aux columns as BF16 pieces, from an 8-sample group boundary
-      uint16_t* xp = c->auxP + gbase * NAUX * 8;
-      launch_pack_bf16(c->Xa + (size_t)rb * NAUX, ns, NAUX, NAUX, c->pieces, xp, NAUX, c->aux_pstride,
-                       c->st);
-      launch_pack_bf16(c->Ya + (size_t)rb * NAUX, ns, NAUX, NAUX, c->pieces,
-                       xp + (size_t)c->pieces * c->aux_pstride, NAUX, c->aux_pstride, c->st);
-      HIPCHK(c, hipGetLastError());
-    }
-    for (int64_t s0 = 0; s0 < ns; s0 += SLICE) {
-      Slice S{};
-      if (c->fp8) {
-        // slice starts are multiples of 16 samples
-        S.O = (const uint8_t*)ch[i].O + (size_t)(s0 / 16) * ch[i].ld * 16;
-        S.e = (const uint8_t*)ch[i].e + (size_t)(s0 / 16) * ch[i].ld * 16;
-        S.Or = (const uint16_t*)ch[i].O_res + (size_t)(s0 / 8) * ch[i].ld * 8;
-        S.er = (const uint16_t*)ch[i].e_res + (size_t)(s0 / 8) * ch[i].ld * 8;
-        S.Os = ch[i].O_scale;
-        S.es = ch[i].e_scale;
-        S.Xq = xq + (size_t)(s0 / 16) * NAUX * 16;
-        S.Yq = S.Xq + c->auxq_stride;
-        S.Xr = xr + (size_t)(s0 / 8) * NAUX * 8;
-        S.Yr = S.Xr + c->auxr_stride;
-        S.Xs = xs;
-        S.Ys = xs + NAUX;
-      } else if (c->pieces) {
-        // k-packed pieces: slice starts are multiples of 8 samples
-        S.O = (const uint16_t*)ch[i].O + (size_t)(s0 / 8) * ch[i].ld * 8;
-        S.e = (const uint16_t*)ch[i].e + (size_t)(s0 / 8) * ch[i].ld * 8;
-        S.pstride = ch[i].piece_stride;
-        S.pieces = c->pieces;
-      } else {
-        S.O = (const double*)ch[i].O + (size_t)s0 * ch[i].ld;
-        S.e = (const double*)ch[i].e + (size_t)s0 * ch[i].ld;
-      }
-      S.Xa = c->Xa + (size_t)(rb + s0) * NAUX;
-      S.Ya = c->Ya + (size_t)(rb + s0) * NAUX;
-      if (c->pieces) {
-        S.Xp = c->auxP + (size_t)(gbase + s0 / 8) * NAUX * 8;
-        S.Yp = S.Xp + (size_t)c->pieces * c->aux_pstride;
-        S.apstride = c->aux_pstride;
-      }
-      S.w = ch[i].w ? ch[i].w + s0 : nullptr;
-      S.ld = ch[i].ld;
-      S.n = std::min<int64_t>(SLICE, ns - s0);
-      c->h_slices.push_back(S);
-    }
-    rb += ns;
-    gbase += (ns + 7) / 8;
-    g16base += (ns + 15) / 16;
-    ++ci;
-  }
   mark(c, 0, true);
   if (c->mixed()) {
     // FP64 aux Gram (timed in the strips slot), then the mixed-precision
@@ -938,6 +953,61 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   if (s != BLM_OK) return s;
   c->n_pass1 += total;
   c->state = ST_BUILT;
+  return BLM_OK;
+}
+
+blm_status blm_autotune_build(blm_ctx* c, const blm_chunk* ch, int32_t n, int32_t* h_groups) {
+  if (!c) return BLM_E_ARG;
+  if (c->state != ST_BEGUN && c->state != ST_BUILT)
+    return fail(c, BLM_E_STATE, "blm_autotune_build needs blm_begin_step first");
+  int64_t total = 0;
+  blm_status s = check_chunks(c, ch, n, &total);
+  if (s != BLM_OK) return s;
+  s = build_slices(c, ch, n);
+  if (s != BLM_OK) return s;
+  const int n_slices = (int)c->h_slices.size();
+  if (n_slices == 0) return fail(c, BLM_E_ARG, "blm_autotune_build needs samples");
+  if (n_slices > c->max_slices) return fail(c, BLM_E_ARG, "too many slices in one call");
+  HIPCHK(c, hipMemcpyAsync(c->d_slices, c->h_slices.data(), sizeof(Slice) * n_slices, hipMemcpyHostToDevice,
+                           c->st));
+  const int kind = c->fp8 ? 3 : c->pieces ? 2 : 0;
+  const GramJob* jobs = c->mixed() ? c->d_jobsM : c->d_jobs1;
+  const int n_jobs = c->mixed() ? c->n_jobsM : c->n_jobs1;
+  const int cap = std::max(1, std::min(c->mixed() ? c->PcapM : c->Pcap1, n_slices));
+  bool vec = kind == 0 && c->offsets_even;
+  for (const Slice& S : c->h_slices)
+    if ((S.ld & 1) || ((uintptr_t)S.O & 15) || ((uintptr_t)S.e & 15)) vec = false;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return fail(c, BLM_E_HIP, "hipEventCreate failed");
+  }
+  static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  int best = 0;
+  float best_ms = 0.0f;
+  blm_status r = BLM_OK;
+  for (int P : cand) {
+    if (P > cap) break;
+    // one launch to settle caches and clocks, one timed
+    launch_build_gram(c, kind, jobs, n_jobs, n_slices, P, vec);
+    float ms = 0.0f;
+    if (hipEventRecord(ev[0], c->st) != hipSuccess) r = BLM_E_HIP;
+    launch_build_gram(c, kind, jobs, n_jobs, n_slices, P, vec);
+    if (r == BLM_OK && (hipGetLastError() != hipSuccess || hipEventRecord(ev[1], c->st) != hipSuccess ||
+                        hipEventSynchronize(ev[1]) != hipSuccess ||
+                        hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+      r = BLM_E_HIP;
+    if (r != BLM_OK) break;
+    if (best == 0 || ms < best_ms) {
+      best = P;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (r != BLM_OK) return fail(c, r, "a tuning launch failed");
+  c->P_tuned[kind] = best;
+  if (h_groups) *h_groups = best;
   return BLM_OK;
 }
 

@@ -371,3 +371,38 @@ def test_mixed_step_against_fp64_oracle(precision, en_tol, cos_tol):
         assert rel_e <= en_tol, (si, rel_e)
         assert cos >= 1 - cos_tol, (si, cos)
     ctx.close()
+
+
+def test_autotuned_build_gives_the_same_step():
+    """blm_autotune_build leaves the step's estimates alone and changes only
+    how the build splits the sample axis; the build that follows sums the
+    same terms in another grouping (FP64 tolerances against the default)."""
+    blm = _blm()
+    host, dev = _make(300, 70_000, 4, 6, 35_000)
+    out = []
+    for tune in (False, True):
+        ctx = blm.BLM(300, [0, 100, 300], 3, 0, [1e-3], 70_000)
+        ctx.begin_step()
+        if tune:
+            g = ctx.autotune(dev)
+            assert g >= 1
+            ctx.build(dev[:1])                  # tuning between builds is allowed too
+            assert ctx.autotune(dev[1:]) >= 1
+            ctx.build(dev[1:])
+        else:
+            ctx.build(dev)
+        ctx.solve()
+        ctx.project(dev)
+        upd, en, _, _ = ctx.stage2()
+        torch.cuda.synchronize()
+        out.append((ctx.block_matrices(1, 0), upd.cpu().numpy(), en))
+        ctx.close()
+    (m1, u1, e1), (m2, u2, e2) = out
+    assert _rel(m2[0], m1[0]) <= 1e-13 and _rel(m2[1], m1[1]) <= 1e-13
+    assert abs(e1[0] - e2[0]) <= 1e-10 * abs(e1[0])
+    assert u1[0] @ u2[0] / (np.linalg.norm(u1[0]) * np.linalg.norm(u2[0])) >= 1 - 1e-10
+    ctx = blm.BLM(300, [0, 100, 300], 3, 0, [1e-3], 70_000)
+    with pytest.raises(blm.BLMError) as ei:
+        ctx.autotune(dev)                       # before blm_begin_step
+    assert ei.value.status == 2
+    ctx.close()
