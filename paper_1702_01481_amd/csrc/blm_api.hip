@@ -580,8 +580,12 @@ void launch_build_gram(blm_ctx* c, int kind, const GramJob* d_jobs, int n_jobs, 
     launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec && kind == 0, kind == 1, c->partial, c->st);
 }
 
+// tuned: the block build's main Gram launch, which takes the slice-group
+// count found by blm_autotune_build (the aux and stage-two Gram launches
+// keep the heuristic)
 blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_base,
-                    double* h_base, double* strip_base, int phase, bool vec, int kind = 0) {
+                    double* h_base, double* strip_base, int phase, bool vec, int kind = 0,
+                    bool tuned = false) {
   const int n_slices = (int)c->h_slices.size();
   if (n_slices == 0 || n_jobs == 0) return BLM_OK;
   for (const Slice& S : c->h_slices)
@@ -590,7 +594,7 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
   HIPCHK(c, hipMemcpyAsync(c->d_slices, c->h_slices.data(), sizeof(Slice) * n_slices,
                            hipMemcpyHostToDevice, c->st));
   int P = choose_P(cap, n_jobs, n_slices);
-  if (c->P_tuned[kind] > 0) P = std::max(1, std::min({c->P_tuned[kind], cap, std::max(1, n_slices)}));
+  if (tuned && c->P_tuned[kind] > 0) P = std::max(1, std::min({c->P_tuned[kind], cap, std::max(1, n_slices)}));
   if (phase >= 0) mark(c, phase, false);
   launch_build_gram(c, kind, d_jobs, n_jobs, n_slices, P, vec);
   HIPCHK(c, hipGetLastError());
@@ -946,9 +950,9 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     if (s != BLM_OK) return s;
     mark(c, 9, true);
     s = run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, c->accS, c->accH, c->strips, 1, false,
-                 c->fp8 ? 3 : 2);
+                 c->fp8 ? 3 : 2, true);
   } else {
-    s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even);
+    s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even, 0, true);
   }
   if (s != BLM_OK) return s;
   c->n_pass1 += total;
