@@ -70,11 +70,12 @@ def _fp8_stored(x):
 
 def _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th, transform=None):
     """Whole-sample sums for the sampled basis indices [0, pcols, th] of
-    block b and the stage-two rows [Psi, B^(b)], streamed chunk by chunk.
+    block b (no Theta column when k is None) and the stage-two rows
+    [Psi, B^(b)], streamed chunk by chunk.
     transform (optional) maps each chunk's sampled parameter columns to the
     values a reduced-precision storage stands for (column scales are per
     chunk); the Theta and stage-two sums then stay on the FP64 values."""
-    nidx = 2 + len(pcols)
+    nidx = (1 if k is None else 2) + len(pcols)
     nb = Bb.shape[0]
     sS = np.zeros((nidx, nidx))
     sH = np.zeros((nidx, nidx))
@@ -82,22 +83,24 @@ def _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th, transform=None):
     s2H = np.zeros((1 + nb, 1 + nb))
     N = 0
     cb = slice(int(offsets[b]), int(offsets[b + 1]))
-    ck = slice(int(offsets[k]), int(offsets[k + 1]))
     for O, e, EL in chunks:
         Ob = O[:, cb].cpu().numpy()
         eb = e[:, cb].cpu().numpy()
-        Ok = O[:, ck].cpu().numpy()
-        ek = e[:, ck].cpu().numpy()
         el = EL.cpu().numpy()
         n = Ob.shape[0]
         ones = np.ones(n)
-        t = Ok @ D[k][0]
-        u = ek @ D[k][0]
         Xp, Yp = Ob[:, pcols - 1], eb[:, pcols - 1]
         if transform is not None:
             Xp, Yp = transform(Xp), transform(Yp)
-        X = np.column_stack([ones, Xp, t])
-        Y = np.column_stack([el, Yp, u])
+        if k is None:
+            X = np.column_stack([ones, Xp])
+            Y = np.column_stack([el, Yp])
+        else:
+            ck = slice(int(offsets[k]), int(offsets[k + 1]))
+            t = O[:, ck].cpu().numpy() @ D[k][0]
+            u = e[:, ck].cpu().numpy() @ D[k][0]
+            X = np.column_stack([ones, Xp, t])
+            Y = np.column_stack([el, Yp, u])
         sS += X.T @ X
         sH += X.T @ Y
         y2 = np.column_stack([ones, Ob @ Bb.T])
