@@ -36,8 +36,11 @@ PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 (matrix and vector)
 # the sample-streaming kernels has changed.
 GRAM_TRAFFIC = {
     "source_sha256": "fe63129d3600dfb45d073795394d2f8584b76659fb4f2a0d1fb292d09c5b772c",
-    "fetch_kib": 234567316.0, "fetch_scale": 1.99996,
-    "write_kib": 408000.0, "write_scale": 1.0,
+    "fetch_scale": 1.99996, "write_scale": 1.0,
+    # slice groups per tile -> (FETCH_SIZE, WRITE_SIZE) KiB per launch
+    "by_groups": {1: (103081293.0, 27200.0), 2: (229860804.0, 54400.0), 3: (226578069.0, 81600.0),
+                  4: (233732360.0, 108800.0), 6: (235026371.0, 163200.0), 8: (236161220.0, 217600.0),
+                  12: (234686538.0, 326400.0), 15: (234257110.0, 408000.0)},
 }
 
 
@@ -57,11 +60,15 @@ def gram_source_digest():
     return hashlib.sha256(text[a:b].encode()).hexdigest()
 
 
-def gram_traffic_bytes():
-    if gram_source_digest() != GRAM_TRAFFIC["source_sha256"]:
-        return None
+def gram_traffic_bytes(groups):
+    """HBM bytes of one FP64 block-build launch with this many slice groups,
+    from the rocprofv3 counters taken on the same Gram-tile source; None if
+    the source has changed or the counters do not cover that launch shape."""
     t = GRAM_TRAFFIC
-    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    if gram_source_digest() != t["source_sha256"] or groups not in t["by_groups"]:
+        return None
+    fetch, write = t["by_groups"][groups]
+    return 1024.0 * (fetch * t["fetch_scale"] + write * t["write_scale"])
 
 
 def log(msg):
@@ -306,7 +313,7 @@ def main():
         "flags": [int(x) for x in fl],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
-                     "traffic": gram_traffic_bytes(),
+                     "traffic": gram_traffic_bytes(groups),
                      "kernel": "gram_kernel (block H/S build, FP64 MFMA 16x16x4)",
                      "flops_per_launch": fl_build},
     }

@@ -165,8 +165,9 @@ blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chu
  * splits the sample axis of every output tile into G groups of 4,096-sample
  * slices, summed afterwards in a fixed order; the best G depends on the
  * device, the blocks and the storage.  This call times the kernel on the
- * given chunks for each G in {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64} up
- * to the context's limit (one settling launch and one timed launch each,
+ * given chunks for each G in {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64} and
+ * the default count, up to the context's limit (one settling launch and
+ * one timed launch each,
  * HIP events on the context's stream), and later builds of this context
  * use the fastest.  It writes only the Theta projection of the chunks and
  * scratch tiles: the step's accumulated estimates are unchanged, so it may

@@ -986,7 +986,11 @@ blm_status blm_autotune_build(blm_ctx* c, const blm_chunk* ch, int32_t n, int32_
     if (ev[0]) (void)hipEventDestroy(ev[0]);
     return fail(c, BLM_E_HIP, "hipEventCreate failed");
   }
-  static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  // the candidates, and the heuristic's own count
+  std::vector<int> cand = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  cand.push_back(choose_P(cap, n_jobs, n_slices));
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
   int best = 0;
   float best_ms = 0.0f;
   blm_status r = BLM_OK;
