@@ -74,6 +74,7 @@ struct blm_ctx {
   std::vector<int> dmax;           // per block: largest pencil dimension
   int d2max = 0, n2max = 0;        // stage two
   int Pcap1 = 1, Pcap2 = 1, PcapM = 1;
+  int nd2max = 0;                  // most kept directions of any block (all shifts), last solve
   int P_tuned[4] = {0, 0, 0, 0};   // slice groups chosen by blm_autotune_build, per build kind (0: heuristic)
   int max_slices = 0;
   int64_t* d_off = nullptr;
@@ -525,8 +526,9 @@ blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) 
 }
 
 // One projection launch over all chunks of a call; returns via c->h_pchunks.
+// max_nd: the most directions of any block
 blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d_blocks,
-                       int n_blocks, const double* const* d_ptr, int n_dirs, double* Xo,
+                       int n_blocks, const double* const* d_ptr, int n_dirs, int max_nd, double* Xo,
                        double* Yo, int64_t ldo) {
   c->h_pchunks.clear();
   int tiles = 0;
@@ -561,7 +563,7 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
                            hipMemcpyHostToDevice, c->st));
   const int store = c->fp8 ? STORE_FP8 : c->pieces ? STORE_BF16 : STORE_F64;
   launch_dirproj(c->d_pchunks, (int)c->h_pchunks.size(), tiles, vec && store == STORE_F64, store,
-                 d_blocks, n_blocks, d_ptr, n_dirs, Xo, Yo, ldo, c->st);
+                 d_blocks, n_blocks, d_ptr, n_dirs, max_nd, Xo, Yo, ldo, c->st);
   HIPCHK(c, hipGetLastError());
   return BLM_OK;
 }
@@ -613,7 +615,7 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
 // build's storage per chunk.
 blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
   blm_status s = run_dirproj(c, ch, n, c->d_theta_blk, c->NO > 0 ? c->NB : 0, c->d_theta_ptr, c->NO * c->NB,
-                             c->Xa, c->Ya, NAUX);
+                             c->NO, c->Xa, c->Ya, NAUX);
   if (s != BLM_OK) return s;
   c->h_slices.clear();
   int64_t rb = 0, gbase = 0, g16base = 0;
@@ -1118,6 +1120,8 @@ blm_status solve_end(blm_ctx* c, double* h_evals, int32_t* h_kept) {
     }
     db[k].nd = (int)dp.size() - db[k].d0;
   }
+  c->nd2max = 0;
+  for (int k = 0; k < NB; ++k) c->nd2max = std::max(c->nd2max, db[k].nd);
   c->n2 = 1 + (int)dp.size();
   c->ld2 = (c->n2 + 1) & ~1;
   c->idx2.assign(NS, {});
@@ -1186,7 +1190,7 @@ blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   if (s != BLM_OK) return s;
   const int64_t ldo = c->ld2;
   mark(c, 5, false);
-  s = run_dirproj(c, ch, n, c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->n2 - 1, c->Yp, c->Zp, ldo);
+  s = run_dirproj(c, ch, n, c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->n2 - 1, c->nd2max, c->Yp, c->Zp, ldo);
   if (s != BLM_OK) return s;
   c->h_slices.clear();
   int64_t rb = 0;

@@ -188,7 +188,7 @@ void launch_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols
                      uint16_t* res, float* scale, int64_t ld_dst, hipStream_t st);
 void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
-                    int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st);
+                    int n_dirs, int max_nd, double* Xo, double* Yo, int64_t ldo, hipStream_t st);
 void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);
 // the same with each pencil's Hessenberg reduction spread over several
 // workgroups (cooperative launch; d_bar: 2 n_jobs counters); returns false

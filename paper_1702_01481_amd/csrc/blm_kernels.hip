@@ -661,6 +661,105 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
   }
 }
 
+// Split or FP8 storage when every block has at most PJ_SMALL directions (the
+// previous-step directions of Eq. 9, one or two per block): each thread
+// keeps FP64 sums for its 8 samples and its column of every 32-parameter
+// stage with plain FMAs, then one reduction over the 32 columns per block.
+// The matrix-core kernel would spend 15/16 of its products on padding
+// directions here (FP64 vector and matrix peaks are equal on this chip).
+// No LDS and no barriers.
+constexpr int PJ_SMALL = 2;
+
+template <int ST>
+__global__ __launch_bounds__(256) void dirproj_small_kernel(const ProjChunk* __restrict__ chunks, int n_chunks,
+                                                            const DirBlock* __restrict__ blocks, int n_blocks,
+                                                            const double* const* __restrict__ dir_ptr,
+                                                            int n_dirs, double* __restrict__ Xo,
+                                                            double* __restrict__ Yo, int64_t ldo) {
+  int ci = 0;
+  while (ci + 1 < n_chunks && chunks[ci + 1].tile0 <= (int)blockIdx.x) ++ci;
+  const ProjChunk C = chunks[ci];
+  const int64_t s0 = (int64_t)(blockIdx.x - C.tile0) * PJ_ROWS;
+  BLM_GLOBAL double* X = as_global(Xo) + C.row_base * ldo;
+  BLM_GLOBAL double* Y = as_global(Yo) + C.row_base * ldo;
+  const int tid = threadIdx.x;
+  // column 0 (the wave function itself: 1 and E_L) and the padding columns
+  for (int t = tid; t < PJ_ROWS * (int)ldo; t += blockDim.x) {
+    const int rr = t / (int)ldo, c = t % (int)ldo;
+    const int64_t s = s0 + rr;
+    if (s >= C.n) continue;
+    if (c == 0) {
+      X[s * ldo] = 1.0;
+      Y[s * ldo] = as_global(C.EL)[s];
+    } else if (c >= 1 + n_dirs) {
+      X[s * ldo + c] = 0.0;
+      Y[s * ldo + c] = 0.0;
+    }
+  }
+  const int col = tid & 31, g = tid >> 5;
+  const int64_t r0 = s0 + 8 * g;
+  for (int bi = 0; bi < n_blocks; ++bi) {
+    const DirBlock B = blocks[bi];
+    if (B.nd <= 0) continue;
+    double ao[PJ_SMALL][8], ae[PJ_SMALL][8];
+#pragma unroll
+    for (int dd = 0; dd < PJ_SMALL; ++dd)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ao[dd][k] = ae[dd][k] = 0.0;
+    const BLM_GLOBAL double* dr[PJ_SMALL];
+#pragma unroll
+    for (int dd = 0; dd < PJ_SMALL; ++dd) dr[dd] = as_global(dir_ptr[B.d0 + min(dd, B.nd - 1)]);
+    for (int p0 = 0; p0 < B.m; p0 += PJ_P) {
+      double o[8], e[8], d[PJ_SMALL];
+      const bool ok = r0 < C.n && p0 + col < B.m;
+      if (ok) {
+        if constexpr (ST == STORE_FP8) {
+          fp8_load8(C.O, C.Or, C.Os, C.ld, r0 >> 3, B.col0 + p0 + col, o);
+          fp8_load8(C.e, C.er, C.es, C.ld, r0 >> 3, B.col0 + p0 + col, e);
+        } else {
+          split_load8(C.O, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, o);
+          split_load8(C.e, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, e);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = e[k] = 0.0;
+      }
+#pragma unroll
+      for (int dd = 0; dd < PJ_SMALL; ++dd) d[dd] = (ok && dd < B.nd) ? dr[dd][p0 + col] : 0.0;
+#pragma unroll
+      for (int dd = 0; dd < PJ_SMALL; ++dd)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          ao[dd][k] += o[k] * d[dd];
+          ae[dd][k] += e[k] * d[dd];
+        }
+    }
+    // sums over the 32 columns (the lanes of one half wave)
+#pragma unroll
+    for (int dd = 0; dd < PJ_SMALL; ++dd)
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+          ao[dd][k] += __shfl_xor(ao[dd][k], off, 64);
+          ae[dd][k] += __shfl_xor(ae[dd][k], off, 64);
+        }
+    if (col == 0) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int64_t s = r0 + k;
+        if (s >= C.n) continue;
+#pragma unroll
+        for (int dd = 0; dd < PJ_SMALL; ++dd)
+          if (dd < B.nd) {
+            X[s * ldo + 1 + B.d0 + dd] = ao[dd][k];
+            Y[s * ldo + 1 + B.d0 + dd] = ae[dd][k];
+          }
+      }
+    }
+  }
+}
+
 // FP64 storage: each wave projects its own 16 samples with operands taken
 // straight from global memory (no LDS, no barriers).  In matrix-core product
 // j of a 32-parameter stage, lane group g = lane / 16 supplies parameter
@@ -805,9 +904,16 @@ __global__ __launch_bounds__(256) void dirproj64_kernel(const ProjChunk* __restr
 
 void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
-                    int n_dirs, double* Xo, double* Yo, int64_t ldo, hipStream_t st) {
+                    int n_dirs, int max_nd, double* Xo, double* Yo, int64_t ldo, hipStream_t st) {
   if (n_tiles <= 0) return;
-  if (store == STORE_BF16)
+  if (store != STORE_F64 && max_nd <= PJ_SMALL) {
+    if (store == STORE_BF16)
+      hipLaunchKernelGGL((dirproj_small_kernel<STORE_BF16>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks,
+                         d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+    else
+      hipLaunchKernelGGL((dirproj_small_kernel<STORE_FP8>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks,
+                         d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+  } else if (store == STORE_BF16)
     hipLaunchKernelGGL((dirproj_kernel<false, STORE_BF16>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
                        n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
   else if (store == STORE_FP8)
