@@ -1,6 +1,9 @@
-// Dense shifted generalised eigensolver for the BLM pencils, FP64, one
-// 1024-thread workgroup per pencil (H' c = lambda S c, S symmetric positive
-// definite, H' not symmetric):
+// Dense shifted generalised eigensolver for the BLM pencils, FP64
+// (H' c = lambda S c, S symmetric positive definite, H' not symmetric).
+// launch_eig runs every step on one 1024-thread workgroup per pencil;
+// launch_eig_split runs steps 1 to 3 on several workgroups per pencil
+// (cooperative launches for 1 and 3, independent slices for 2) and the
+// rest on one:
 //
 //   1. S = L L^T (Cholesky)                      -> BLM_E_S_NOT_PD if it fails
 //   2. A = L^-1 H' L^-T (two triangular solves)
@@ -26,7 +29,7 @@ namespace blm {
 namespace {
 
 constexpr int NT = EIG_THREADS;
-constexpr int HKW_MAX = 8;            // workgroups per pencil in the distributed Hessenberg reduction
+constexpr int HKW_MAX = 8;            // workgroups per pencil in the distributed Cholesky and Hessenberg steps
 // smallest pencil it takes (smaller ones stay on one workgroup); its
 // workspace, 2 d + 2 kw d doubles, fits in the 2 d^2 of W
 constexpr int HESS_MULTI_MIN = 256;
