@@ -212,8 +212,8 @@ def main():
         print(json.dumps({"copy_bytes": 8 * n, "launches": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sample "
-                                   "sharding is a design only (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding the samples over "
+                                   "several GPUs is designed but not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
