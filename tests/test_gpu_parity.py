@@ -132,6 +132,17 @@ def test_previous_directions_ragged_chunks(weighted):
     _compare_step(offsets, 2, [1e-4, 1e-3, 1e-2], host, dev, old=old, n_old=2)
 
 
+def test_sixteen_aux_columns():
+    """The most previous-step directions the library takes: 1 + N_O N_B = 16
+    aux columns (five uneven blocks, N_O = 3, one piece dropped), so every
+    block's pencil carries 12 Theta coordinates beside its own parameters."""
+    offsets = [0, 23, 60, 61, 118, 160]
+    host, dev = _make(160, 8000, 5, 8, 3000)
+    old = synth.old_directions(3, 160, 21).numpy()
+    old[2, 61:118] = 0.0
+    _compare_step(offsets, 2, [1e-3, 1e-2], host, dev, old=old, n_old=3)
+
+
 def test_uneven_blocks_with_a_large_pencil():
     """Uneven blocks as in the 40-block workload (sizes from about 100 to
     2,000): one block of 1,100 parameters (pencil dimension 1,103: QR with
