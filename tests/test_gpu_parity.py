@@ -417,3 +417,29 @@ def test_autotuned_build_gives_the_same_step():
         ctx.autotune(dev)                       # before blm_begin_step
     assert ei.value.status == 2
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp8"])
+def test_autotuned_mixed_build_gives_the_same_matrices(precision):
+    """The tuned slice-group count of the BF16 and FP8 pair kernels regroups
+    their FP64 sums of FP32 partials only: every block matrix equals the
+    default build's to 1e-12 in relative Frobenius norm."""
+    blm = _blm()
+    _, dev = _make(300, 70_000, 4, 7, 35_000)
+    if precision == "fp8":
+        data = [(blm.Fp8Samples(O), blm.Fp8Samples(e), EL) for O, e, EL, _ in dev]
+    else:
+        data = [(blm.SplitSamples(O, 3), blm.SplitSamples(e, 3), EL) for O, e, EL, _ in dev]
+    mats = []
+    for tune in (False, True):
+        ctx = blm.BLM(300, [0, 100, 300], 3, 0, [1e-3], 70_000, precision=precision)
+        ctx.begin_step()
+        if tune:
+            assert ctx.autotune(data) >= 1
+        ctx.build(data)
+        ctx.solve()
+        torch.cuda.synchronize()
+        mats.append([ctx.block_matrices(b, 0) for b in range(2)])
+        ctx.close()
+    for (H1, S1), (H2, S2) in zip(*mats):
+        assert _rel(H2, H1) <= 1e-12 and _rel(S2, S1) <= 1e-12, (_rel(H2, H1), _rel(S2, S1))
