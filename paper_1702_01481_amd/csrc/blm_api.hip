@@ -5,10 +5,11 @@
 //
 // Workspace layout in HBM (FP64 unless noted):
 //   D        [N_O][N_V]        orthonormalised previous-update pieces (Eq. 9)
-//   Xa, Ya   [max_samples][16] per-sample aux columns [1, t_s] and [E_L, u_s]
-//   accS     per block M_b x M_b  sum_s w O_b O_b^T (upper tiles), then 16x16 aux Gram
-//   accH     per block M_b x M_b  sum_s w O_b e_b^T, then 16x16 aux Gram (X^T W Y)
-//   strips   [3][16][N_V]       aux^T W O, aux^T W e, auxE^T W O   (Fig. 1, coupling strips)
+//   Xa, Ya   [max_samples][A]  per-sample aux columns [1, t_s] and [E_L, u_s], where
+//                               A = 1 + N_O N_B rounded up to a multiple of 16
+//   accS     per block M_b x M_b  sum_s w O_b O_b^T (upper tiles), then A x A aux Gram
+//   accH     per block M_b x M_b  sum_s w O_b e_b^T, then A x A aux Gram (X^T W Y)
+//   strips   [3][A][N_V]        aux^T W O, aux^T W e, auxE^T W O   (Fig. 1, coupling strips)
 //   partial  per (tile job, slice group) 3 x 64 x 64 partial tiles
 //   eig      per pencil: S, A, Hq, V (d^2 each), W (2 d^2), vectors, outputs
 //   Yp, Zp   [max_samples][n2] stage-two projections [1, B O_b ...], [E_L, B e_b ...]
@@ -70,6 +71,7 @@ struct blm_ctx {
 
   // derived sizes
   int64_t acc_elems = 0, aux_off = 0;
+  int NAP = NAUX;                  // aux columns, padded to whole groups of NAUX
   std::vector<int64_t> acc_off;
   std::vector<int> dmax;           // per block: largest pencil dimension
   int d2max = 0, n2max = 0;        // stage two
@@ -86,18 +88,19 @@ struct blm_ctx {
   int32_t* d_dkeep = nullptr;
   GramJob *d_jobs1 = nullptr, *d_jobs2 = nullptr;
   int n_jobs1 = 0, n_jobs2 = 0;
-  // mixed precision: jobs1 = FP64 strip + aux jobs, jobsM = BF16 main-product jobs
+  // mixed precision: jobs1 = FP64 aux job + strips of the aux groups after the
+  // first, jobsM = BF16 or FP8 main-product jobs (with the first group's strips)
   GramJob* d_jobsM = nullptr;
   int n_jobsM = 0;
   PairJob* d_pairsM = nullptr;   // BF16 build: pairs of main jobs sharing a row tile
   int n_pairsM = 0;
-  uint16_t* auxP = nullptr;      // BF16 build: aux columns as BF16 pieces (k-packed, ld 16)
+  uint16_t* auxP = nullptr;      // BF16 build: first aux group as BF16 pieces (k-packed, ld 16)
   int64_t aux_pstride = 0;       // elements between pieces of auxP (Xa pieces, then Ya pieces)
   int pieces = 0;                  // 0: FP64 path; 2 or 3: BF16 split pieces used
   bool fp8 = false;                // FP8 storage (e4m3 codes, BF16 residuals, column scales)
-  uint8_t* auxQ = nullptr;         // FP8 build: aux codes (k-packed by 16, ld 16), Xa then Ya
-  uint16_t* auxR = nullptr;        // FP8 build: aux residuals (k-packed by 8, ld 16), Xa then Ya
-  float* auxS = nullptr;           // FP8 build: aux column scales [chunk][Xa, Ya][16]
+  uint8_t* auxQ = nullptr;         // FP8 build: first aux group's codes (k-packed by 16, ld 16), Xa then Ya
+  uint16_t* auxR = nullptr;        // FP8 build: its residuals (k-packed by 8, ld 16), Xa then Ya
+  float* auxS = nullptr;           // FP8 build: its column scales [chunk][Xa, Ya][16]
   int64_t auxq_stride = 0, auxr_stride = 0;   // bytes / elements from the Xa to the Ya part
   bool mixed() const { return pieces != 0 || fp8; }
   Slice* d_slices = nullptr;
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict_
                                                        const double* __restrict__ accS,
                                                        const double* __restrict__ accH,
                                                        const double* __restrict__ strips,
-                                                       int64_t NV, int64_t aux_off,
+                                                       int64_t NV, int64_t aux_off, int nap,
                                                        const double* __restrict__ G2S,
                                                        const double* __restrict__ G2H,
                                                        int64_t ld2) {
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict_
       const int ax = (x == 0) ? J.aux_idx[0] : J.aux_idx[x > M ? x - M : 0];
       const int ay = (y == 0) ? J.aux_idx[0] : J.aux_idx[y > M ? y - M : 0];
       const int64_t p = x - 1, q = y - 1;
-      const size_t S0 = 0, S1 = (size_t)NAUX * NV, S2 = 2 * (size_t)NAUX * NV;
+      const size_t S0 = 0, S1 = (size_t)nap * NV, S2 = 2 * (size_t)nap * NV;
       if (px && py) {
         s = accS[J.acc_off + std::min(p, q) * M + std::max(p, q)];
         h = accH[J.acc_off + p * M + q];
@@ -240,8 +243,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict_
         s = strips[S0 + (size_t)ay * NV + J.off_b + p];
         h = strips[S2 + (size_t)ay * NV + J.off_b + p];
       } else {
-        s = accS[aux_off + std::min(ax, ay) * NAUX + std::max(ax, ay)];
-        h = accH[aux_off + ax * NAUX + ay];
+        s = accS[aux_off + std::min(ax, ay) * nap + std::max(ax, ay)];
+        h = accH[aux_off + ax * nap + ay];
       }
     }
     s *= inv;
@@ -287,8 +290,8 @@ blm_status validate(const blm_config* cfg, blm_ctx* c) {
     return fail(c, BLM_E_ARG, "n_params and n_blocks must be >= 1 and block_offsets set");
   if (cfg->n_keep < 1 || cfg->n_keep + 1 > EIG_MAXSEL)
     return fail(c, BLM_E_ARG, "n_keep must be in [1, 15]");
-  if (cfg->n_old < 0 || 1 + (int64_t)cfg->n_old * cfg->n_blocks > NAUX)
-    return fail(c, BLM_E_ARG, "1 + n_old * n_blocks must be <= 16");
+  if (cfg->n_old < 0 || 1 + (int64_t)cfg->n_old * cfg->n_blocks > NAUX_MAX)
+    return fail(c, BLM_E_ARG, "1 + n_old * n_blocks must be <= 64");
   if (cfg->n_shifts < 1 || !cfg->shifts) return fail(c, BLM_E_ARG, "need at least one shift");
   for (int i = 0; i < cfg->n_shifts; ++i)
     if (!(cfg->shifts[i] >= 0.0) || !std::isfinite(cfg->shifts[i]))
@@ -318,7 +321,7 @@ void plan(blm_ctx* c, Plan& P) {
   c->acc_off.assign(NB, 0);
   int64_t run = 0;
   c->dmax.assign(NB, 0);
-  int n_jobs1 = 0;
+  int n_jobs1 = 0, n_diag = 0;
   for (int b = 0; b < NB; ++b) {
     const int64_t M = c->off[b + 1] - c->off[b];
     c->acc_off[b] = run;
@@ -326,15 +329,19 @@ void plan(blm_ctx* c, Plan& P) {
     c->dmax[b] = (int)(1 + M + (int64_t)NO * (NB - 1));
     const int T = (int)((M + GT - 1) / GT);
     n_jobs1 += T * (T + 1) / 2;
+    n_diag += T;
   }
+  c->NAP = NAUX * ((1 + NO * NB + NAUX - 1) / NAUX);
+  const int n_xstrip = n_diag * (c->NAP / NAUX - 1);   // strip jobs of the aux groups after the first
   c->aux_off = run;
-  run += NAUX * NAUX;
+  run += (int64_t)c->NAP * c->NAP;
   c->acc_elems = run;
-  c->n_jobs1 = n_jobs1 + 1;
+  c->n_jobs1 = n_jobs1 + 1 + n_xstrip;
   c->n_jobsM = c->mixed() ? n_jobs1 : 0;
-  // mixed precision: the strips ride on the BF16 diagonal jobs; only the aux
-  // Gram stays on the FP64 kernel
-  if (c->mixed()) c->n_jobs1 = 1;
+  // mixed precision: the first aux group's strips ride on the BF16 or FP8
+  // diagonal jobs; the aux Gram and the other groups' strips stay on the
+  // FP64 kernel
+  if (c->mixed()) c->n_jobs1 = 1 + n_xstrip;
   const int64_t aux_groups = c->max_samples / 8 + MAX_CHUNKS;
   c->aux_pstride = c->pieces ? aux_groups * NAUX * 8 : 0;
   c->auxq_stride = c->fp8 ? (c->max_samples / 16 + MAX_CHUNKS) * NAUX * 16 : 0;
@@ -354,11 +361,11 @@ void plan(blm_ctx* c, Plan& P) {
   auto add = [&](void** slot, size_t bytes) { P.items.push_back({slot, std::max<size_t>(bytes, 8)}); };
   add((void**)&c->D, 8 * (size_t)std::max(NO, 1) * NV);
   add((void**)&c->d_dkeep, 4 * (size_t)std::max(NO * NB, 1));
-  add((void**)&c->Xa, 8 * (size_t)c->max_samples * NAUX);
-  add((void**)&c->Ya, 8 * (size_t)c->max_samples * NAUX);
+  add((void**)&c->Xa, 8 * (size_t)c->max_samples * c->NAP);
+  add((void**)&c->Ya, 8 * (size_t)c->max_samples * c->NAP);
   add((void**)&c->accS, 8 * (size_t)c->acc_elems);
   add((void**)&c->accH, 8 * (size_t)c->acc_elems);
-  add((void**)&c->strips, 8 * (size_t)3 * NAUX * NV);
+  add((void**)&c->strips, 8 * (size_t)3 * c->NAP * NV);
   add((void**)&c->partial, 8 * slots * 3 * GT * GT);
   add((void**)&c->d_off, 8 * (size_t)(NB + 1));
   add((void**)&c->d_jobs1, sizeof(GramJob) * (size_t)c->n_jobs1);
@@ -455,15 +462,30 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
         J.ld_out = M;
         J.strip_col = J.ci;
         if (!c->mixed()) jobs.push_back(J);
-        else main.push_back(J);   // all products, strips included, on the mixed-precision kernel
+        else main.push_back(J);   // all products, first strips included, on the mixed-precision kernel
       }
   }
   GramJob A{};
   A.kind = JOB_AUX;
-  A.mi = A.nj = NAUX;
+  A.mi = A.nj = c->NAP;
   A.s_off = A.h_off = c->aux_off;
-  A.ld_out = NAUX;
+  A.ld_out = c->NAP;
   jobs.push_back(A);
+  // the strips of every aux group after the first, per diagonal tile
+  for (int b = 0; b < c->NB; ++b) {
+    const int64_t M = c->off[b + 1] - c->off[b];
+    for (int64_t c0 = 0; c0 < M; c0 += GT)
+      for (int ag = NAUX; ag < c->NAP; ag += NAUX) {
+        GramJob X{};
+        X.kind = JOB_STRIP;
+        X.mi = X.nj = (int)std::min<int64_t>(GT, M - c0);
+        X.ci = X.cj = c->off[b] + c0;
+        X.ag = ag;
+        X.ld_out = M;
+        X.strip_col = X.ci;
+        jobs.push_back(X);
+      }
+  }
   c->n_jobs1 = (int)jobs.size();
   c->n_jobsM = (int)main.size();
   HIPCHK(c, hipMemcpy(c->d_jobs1, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice));
@@ -604,7 +626,7 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
     mark(c, phase, true);
     mark(c, phase + 1, false);
   }
-  launch_gram_reduce(d_jobs, n_jobs, P, c->partial, s_base, h_base, strip_base, c->NV, c->st);
+  launch_gram_reduce(d_jobs, n_jobs, P, c->partial, s_base, h_base, strip_base, c->NV, c->NAP, c->st);
   HIPCHK(c, hipGetLastError());
   if (phase >= 0) mark(c, phase + 1, true);
   return BLM_OK;
@@ -615,7 +637,7 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
 // build's storage per chunk.
 blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
   blm_status s = run_dirproj(c, ch, n, c->d_theta_blk, c->NO > 0 ? c->NB : 0, c->d_theta_ptr, c->NO * c->NB,
-                             c->NO, c->Xa, c->Ya, NAUX);
+                             c->NO, c->Xa, c->Ya, c->NAP);
   if (s != BLM_OK) return s;
   c->h_slices.clear();
   int64_t rb = 0, gbase = 0, g16base = 0;
@@ -627,21 +649,21 @@ blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
     uint16_t* xr = nullptr;
     float* xs = nullptr;
     if (c->fp8) {
-      // this chunk's aux columns in FP8 storage, with their own scales
+      // this chunk's first aux group in FP8 storage, with its own scales
       xq = c->auxQ + g16base * NAUX * 16;
       xr = c->auxR + gbase * NAUX * 8;
       xs = c->auxS + (size_t)ci * 2 * NAUX;
-      launch_pack_fp8(c->Xa + (size_t)rb * NAUX, ns, NAUX, NAUX, xq, xr, xs, NAUX, c->st);
-      launch_pack_fp8(c->Ya + (size_t)rb * NAUX, ns, NAUX, NAUX, xq + c->auxq_stride, xr + c->auxr_stride,
+      launch_pack_fp8(c->Xa + (size_t)rb * c->NAP, ns, c->NAP, NAUX, xq, xr, xs, NAUX, c->st);
+      launch_pack_fp8(c->Ya + (size_t)rb * c->NAP, ns, c->NAP, NAUX, xq + c->auxq_stride, xr + c->auxr_stride,
                       xs + NAUX, NAUX, c->st);
       HIPCHK(c, hipGetLastError());
     }
     if (c->pieces) {
-      // this chunk's aux columns as BF16 pieces, from an 8-sample group boundary
+      // this chunk's first aux group as BF16 pieces, from an 8-sample group boundary
       uint16_t* xp = c->auxP + gbase * NAUX * 8;
-      launch_pack_bf16(c->Xa + (size_t)rb * NAUX, ns, NAUX, NAUX, c->pieces, xp, NAUX, c->aux_pstride,
+      launch_pack_bf16(c->Xa + (size_t)rb * c->NAP, ns, c->NAP, NAUX, c->pieces, xp, NAUX, c->aux_pstride,
                        c->st);
-      launch_pack_bf16(c->Ya + (size_t)rb * NAUX, ns, NAUX, NAUX, c->pieces,
+      launch_pack_bf16(c->Ya + (size_t)rb * c->NAP, ns, c->NAP, NAUX, c->pieces,
                        xp + (size_t)c->pieces * c->aux_pstride, NAUX, c->aux_pstride, c->st);
       HIPCHK(c, hipGetLastError());
     }
@@ -671,8 +693,9 @@ blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
         S.O = (const double*)ch[i].O + (size_t)s0 * ch[i].ld;
         S.e = (const double*)ch[i].e + (size_t)s0 * ch[i].ld;
       }
-      S.Xa = c->Xa + (size_t)(rb + s0) * NAUX;
-      S.Ya = c->Ya + (size_t)(rb + s0) * NAUX;
+      S.Xa = c->Xa + (size_t)(rb + s0) * c->NAP;
+      S.Ya = c->Ya + (size_t)(rb + s0) * c->NAP;
+      S.ald = c->NAP;
       if (c->pieces) {
         S.Xp = c->auxP + (size_t)(gbase + s0 / 8) * NAUX * 8;
         S.Yp = S.Xp + (size_t)c->pieces * c->aux_pstride;
@@ -897,7 +920,7 @@ blm_status blm_begin_step(blm_ctx* c, const double* d_old) {
   if (!c) return BLM_E_ARG;
   HIPCHK(c, hipMemsetAsync(c->accS, 0, 8 * (size_t)c->acc_elems, c->st));
   HIPCHK(c, hipMemsetAsync(c->accH, 0, 8 * (size_t)c->acc_elems, c->st));
-  HIPCHK(c, hipMemsetAsync(c->strips, 0, 8 * (size_t)3 * NAUX * c->NV, c->st));
+  HIPCHK(c, hipMemsetAsync(c->strips, 0, 8 * (size_t)3 * c->NAP * c->NV, c->st));
   c->dkeep.assign((size_t)c->NB * c->NO, 0);
   if (c->NO > 0) {
     if (d_old) {
@@ -1074,7 +1097,7 @@ blm_status solve_begin(blm_ctx* c, std::vector<EigJob>& ej, int* dm_out) {
   const int gy = std::min(256, std::max(1, (int)(((size_t)dm * dm + 255) / 256 / 8)));
   mark(c, 3, false);
   hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)asmj.size(), gy), dim3(256), 0, c->st, c->d_asm1,
-                     c->accS, c->accH, c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2max);
+                     c->accS, c->accH, c->strips, c->NV, c->aux_off, c->NAP, c->G2S, c->G2H, (int64_t)c->n2max);
   HIPCHK(c, hipGetLastError());
   mark(c, 3, true);
   *dm_out = dm;
@@ -1253,7 +1276,7 @@ blm_status stage2_begin(blm_ctx* c, std::vector<EigJob>& ej, int* dm_out) {
   HIPCHK(c, hipMemcpyAsync(c->d_asm2, asmj.data(), sizeof(AsmJob) * NS, hipMemcpyHostToDevice, c->st));
   const int gy = std::min(64, std::max(1, (int)(((size_t)dm * dm + 255) / 256 / 8)));
   hipLaunchKernelGGL(assemble_kernel, dim3(NS, gy), dim3(256), 0, c->st, c->d_asm2, c->accS, c->accH,
-                     c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2);
+                     c->strips, c->NV, c->aux_off, c->NAP, c->G2S, c->G2H, (int64_t)c->n2);
   HIPCHK(c, hipGetLastError());
   *dm_out = dm;
   return BLM_OK;
@@ -1359,7 +1382,7 @@ blm_status blm_get_block_matrices(blm_ctx* c, int32_t block, int32_t shift, doub
   A.A = c->exA;
   HIPCHK(c, hipMemcpyAsync(c->d_asm_x, &A, sizeof A, hipMemcpyHostToDevice, c->st));
   hipLaunchKernelGGL(assemble_kernel, dim3(1, 64), dim3(256), 0, c->st, c->d_asm_x, c->accS, c->accH,
-                     c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2max);
+                     c->strips, c->NV, c->aux_off, c->NAP, c->G2S, c->G2H, (int64_t)c->n2max);
   HIPCHK(c, hipGetLastError());
   if (h_H) HIPCHK(c, hipMemcpyAsync(h_H, c->exA, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
   if (h_S) HIPCHK(c, hipMemcpyAsync(h_S, c->exS, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
@@ -1396,7 +1419,7 @@ blm_status blm_get_stage2_matrices(blm_ctx* c, int32_t shift, double* h_H2, doub
   A.A = c->exA;
   HIPCHK(c, hipMemcpyAsync(c->d_asm_x, &A, sizeof A, hipMemcpyHostToDevice, c->st));
   hipLaunchKernelGGL(assemble_kernel, dim3(1, 16), dim3(256), 0, c->st, c->d_asm_x, c->accS, c->accH,
-                     c->strips, c->NV, c->aux_off, c->G2S, c->G2H, (int64_t)c->n2);
+                     c->strips, c->NV, c->aux_off, c->NAP, c->G2S, c->G2H, (int64_t)c->n2);
   HIPCHK(c, hipGetLastError());
   if (h_H2) HIPCHK(c, hipMemcpyAsync(h_H2, c->exA, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
   if (h_S2) HIPCHK(c, hipMemcpyAsync(h_S2, c->exS, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));

@@ -27,27 +27,29 @@ typedef BLM_GLOBAL double gdouble;
 constexpr int GT = 64;        // output tile edge
 constexpr int GKS = 16;       // samples per LDS stage
 constexpr int GTHREADS = 256; // 4 waves, 2x2 of 32x32 sub-tiles
-constexpr int NAUX = 16;      // aux columns: [1 | Theta] and [E_L | Theta-energy], padded
+constexpr int NAUX = 16;      // aux columns per group: [1 | Theta] and [E_L | Theta-energy]
+constexpr int NAUX_MAX = GT;  // aux columns in all (1 + N_O N_B, padded to whole groups)
 constexpr int SLICE = 4096;   // samples per slice (unit of split-K work)
 
 enum JobKind : int32_t {
   JOB_OFF = 0,          // i < j: S_ij = O_i^T W O_j, H_ij = O_i^T W e_j, H_ji^T = e_i^T W O_j
-  JOB_DIAG = 1,         // i == j: S_ii, H_ii, plus strips aux^T W O_i, aux^T W e_i, auxE^T W O_i
+  JOB_DIAG = 1,         // i == j: S_ii, H_ii, plus the first aux group's strips aux^T W O_i,
+                        // aux^T W e_i, auxE^T W O_i
   JOB_DIAG_NOSTRIP = 2, // i == j without strips
-  JOB_AUX = 3,          // aux x aux: Xa^T W Xa, Xa^T W Ya (panels taken from the aux arrays)
-  JOB_STRIP = 4         // strips of a diagonal tile only (mixed precision: main products elsewhere)
+  JOB_AUX = 3,          // aux x aux: Xa^T W Xa, Xa^T W Ya (all aux columns, one tile)
+  JOB_STRIP = 4         // strips of one aux group over a diagonal tile's columns only
 };
 
 struct GramJob {
   int32_t kind;
   int32_t mi, nj;       // valid rows / cols of the tile (<= GT)
-  int32_t pad;
+  int32_t ag;           // JOB_DIAG, JOB_STRIP: first aux column of the strips' group (multiple of NAUX)
   int64_t ci, cj;       // first source column of tile i / tile j
   int64_t s_off;        // destination of S tile (i,j): s_base[s_off + r*ld_out + c]
   int64_t h_off;        // destination of H tile (i,j)
   int64_t ht_off;       // destination of H tile (j,i) (JOB_OFF): h_base[ht_off + c*ld_out + r]
   int64_t ld_out;
-  int64_t strip_col;    // JOB_DIAG: global parameter column of the strip's first column
+  int64_t strip_col;    // JOB_DIAG, JOB_STRIP: global parameter column of the strip's first column
 };
 
 // Two tile jobs of the BF16 build that share their row tile (jb < 0: none).
@@ -62,15 +64,15 @@ struct PairJob {
 struct Slice {
   const void* O;        // main panels: FP64 (row stride ld) or BF16 pieces (k-packed)
   const void* e;
-  const double* Xa;     // aux panels (row stride NAUX), already offset to the slice's first row
+  const double* Xa;     // aux panels (row stride ald), already offset to the slice's first row
   const double* Ya;
   const double* w;      // weights of the slice's first row, or nullptr
   int64_t ld;
   int64_t n;            // samples in the slice
   int64_t pstride;      // BF16 pieces: elements between pieces
-  int32_t pieces;       // 0: FP64 storage; 2 or 3: BF16 split pieces
-  int32_t pad;
-  // BF16 split storage only: the aux columns (Xa, Ya) as BF16 pieces in the
+  int32_t pieces;       // 0: FP64 or FP8 storage; 2 or 3: BF16 split pieces
+  int32_t ald;          // row stride of Xa, Ya: all aux columns, padded to whole groups
+  // BF16 split storage only: the first aux group (Xa, Ya) as BF16 pieces in the
   // k-packed layout with ld = NAUX, from the slice's first 8-sample group;
   // piece p of Xa at Xp + p * apstride (Ya likewise at Yp)
   const uint16_t* Xp;
@@ -79,7 +81,7 @@ struct Slice {
   // FP8 storage only (O, e then hold the e4m3 codes, k-packed by 16 samples:
   // element (s, x) at ((s / 16) * ld + x) * 16 + s % 16 bytes, from the
   // slice's first sample): BF16 residuals k-packed by 8, and the chunk's
-  // per-column power-of-two scales; the aux columns likewise with ld = NAUX
+  // per-column power-of-two scales; the first aux group likewise with ld = NAUX
   const uint16_t* Or;
   const uint16_t* er;
   const float* Os;
@@ -179,7 +181,7 @@ void launch_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncol
                       uint16_t* dst, int64_t ld_dst, int64_t pstride, hipStream_t st);
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
-                        hipStream_t st);
+                        int strip_rows, hipStream_t st);
 void launch_gram_fp8(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
                      const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st);
 // FP64 [n][ld_src] -> e4m3 codes (k-packed by 16), BF16 residuals (k-packed

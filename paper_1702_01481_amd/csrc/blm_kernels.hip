@@ -148,26 +148,28 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
   R.w = S.w ? as_global(S.w)[rc] : 1.0;
   R.valid = valid;
   if constexpr (KIND == JOB_AUX) {
-    const BLM_GLOBAL double* xa = as_global(S.Xa) + rc * NAUX;
-    const BLM_GLOBAL double* ya = as_global(S.Ya) + rc * NAUX;
+    const BLM_GLOBAL double* xa = as_global(S.Xa) + rc * S.ald;
+    const BLM_GLOBAL double* ya = as_global(S.Ya) + rc * S.ald;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int cc = min(lc + c, NAUX - 1);
+      const int cc = min(lc + c, J.mi - 1);
       R.a[c] = xa[cc];
       R.b[c] = R.a[c];
       R.f[c] = ya[cc];
       R.e[c] = 0.0;
     }
   } else if constexpr (SPLIT) {
-    // strip jobs on split storage (uniform weights): thread -> (panel,
-    // 8-sample group, column); 8 samples of one column of O (panel 0) or e
-    // (panel 1) land in a[0..3], e[0..3]
+    // strip jobs on BF16 split or FP8 storage (uniform weights): thread ->
+    // (panel, 8-sample group, column); 8 samples of one column of O (panel
+    // 0) or e (panel 1) land in a[0..3], e[0..3]
     const int pnl = tid >> 7, g = (tid >> 6) & 1, c = tid & 63;
     const int64_t r0 = ro + 8 * g;
     const bool ok = r0 < S.n && c < J.nj;
     const int64_t grp = (r0 < S.n ? r0 : S.n - 1) >> 3;
+    const int64_t col = J.cj + min(c, J.nj - 1);
     double v[8];
-    split_load8(pnl ? S.e : S.O, S.ld, S.pstride, S.pieces, grp, J.cj + min(c, J.nj - 1), v);
+    if (S.pieces > 0) split_load8(pnl ? S.e : S.O, S.ld, S.pstride, S.pieces, grp, col, v);
+    else fp8_load8(pnl ? S.e : S.O, pnl ? S.er : S.Or, pnl ? S.es : S.Os, S.ld, grp, col, v);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       R.a[k] = ok ? v[k] : 0.0;
@@ -202,8 +204,8 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
   }
   if constexpr (KIND == JOB_DIAG || KIND == JOB_STRIP) {
     const int acol = tid & 15;
-    R.x = as_global(S.Xa)[rc * NAUX + acol];
-    R.y = as_global(S.Ya)[rc * NAUX + acol];
+    R.x = as_global(S.Xa)[rc * S.ald + J.ag + acol];
+    R.y = as_global(S.Ya)[rc * S.ald + J.ag + acol];
   }
 }
 
@@ -374,7 +376,7 @@ __device__ __forceinline__ void gram_body(GramLds& L, const GramJob& J,
 
 // VEC: every job's columns are 16-byte aligned (even leading dimension and
 // tile origins, aligned panels), so full 64 x 64 tiles use 16-byte loads.
-// SPLIT: the jobs are strip jobs on BF16 split storage, plus the aux job.
+// SPLIT: the jobs are strip jobs on BF16 split or FP8 storage, plus the aux job.
 template <bool VEC, bool SPLIT>
 __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __restrict__ jobs,
                                                            int n_jobs,
@@ -426,7 +428,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
                                                           double* __restrict__ s_base,
                                                           double* __restrict__ h_base,
                                                           double* __restrict__ strip_base,
-                                                          int64_t strip_ld) {
+                                                          int64_t strip_ld, int strip_rows) {
   const int jid = blockIdx.x, qd = blockIdx.y;
   const GramJob J = jobs[jid];
   const bool strips = (J.kind == JOB_DIAG || J.kind == JOB_STRIP);
@@ -439,7 +441,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
       sum += partial[((size_t)jid * P + pp) * (size_t)(3 * GT * GT) + (size_t)qd * GT * GT + el];
     if (qd == 2 && strips) {
       const int sq = el / (NAUX * GT), a = (el / GT) % NAUX, c = el % GT;
-      if (c < J.mi) strip_base[(size_t)sq * NAUX * strip_ld + (size_t)a * strip_ld + J.strip_col + c] += sum;
+      if (c < J.mi)
+        strip_base[((size_t)sq * strip_rows + J.ag + a) * strip_ld + J.strip_col + c] += sum;
       continue;
     }
     const int row = el / GT, col = el % GT;
@@ -466,10 +469,10 @@ void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n
 
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
-                        hipStream_t st) {
+                        int strip_rows, hipStream_t st) {
   if (n_jobs <= 0) return;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(n_jobs, 3), dim3(256), 0, st, d_jobs, P, d_partial,
-                     s_base, h_base, strip_base, strip_ld);
+                     s_base, h_base, strip_base, strip_ld, strip_rows);
 }
 
 // ---------------------------------------------------------------------------

@@ -2,9 +2,10 @@
 30,000-parameter workload (40 uneven blocks, no previous direction) at their
 full parameter counts and block structure, with fewer samples than their
 full sizes (which do not fit in one GPU's HBM as FP64): 131,072 and 65,536
-samples.  The 16-block workload runs without its previous direction: with
-one, a block's aux columns would number 1 + N_O N_B = 17, one more than the
-library's 16.
+samples.  The 16-block workload runs with its previous direction (two
+steps: the first gives the direction): 1 + N_O N_B = 17 aux columns, so the
+Theta coordinate checked, block 15's piece, is aux column 16, the first of
+the second 16-column group.
 
 For each: the FP64 step against the oracle on sampled outputs of one block,
 computed from the same sample bytes (entries of S_b and H_b, Eq. 3 on the
@@ -132,7 +133,7 @@ def _run(name, n_samples, check_block, theta_block, n_old=None):
 
 @pytest.mark.timeout(600)
 def test_sixteen_blocks_of_1024():
-    _run("bf16", 131_072, check_block=5, theta_block=None, n_old=0)
+    _run("bf16", 131_072, check_block=5, theta_block=15)
 
 
 @pytest.mark.timeout(600)
