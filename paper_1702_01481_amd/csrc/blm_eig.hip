@@ -1848,9 +1848,14 @@ __device__ void hess_pass_rows(HessShared& hs, gdouble* A, int d, int k, int r0,
           const double vj = ok ? cv[j0 + j] : 0.0, qj = ok ? cq[j0 + j] : 0.0;
           a1[m] = hess_upd(a1[m], tk, pi1, vj, vi1, qj);
           a2[m] = hess_upd(a2[m], tk, pi2, vj, vi2, qj);
+          // column k+1 below row k+1 is not stored while the next reflector
+          // is formed: every workgroup reads its values from before this
+          // step for that (unordered with this store: no barrier between),
+          // and step k+1 overwrites them with beta and zeros
+          const bool hold = PROD && j == 0;
           if (ok) {
-            A1[j] = a1[m];
-            if (has2) A2[j] = a2[m];
+            if (!(hold && i >= k + 2)) A1[j] = a1[m];
+            if (has2 && !(hold && i2 >= k + 2)) A2[j] = a2[m];
           }
         }
       }
