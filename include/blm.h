@@ -86,7 +86,7 @@ typedef struct {
   int32_t n_blocks;              /* N_B >= 1 */
   const int64_t* block_offsets;  /* host [N_B + 1]: 0 = off[0] < off[1] < ... < off[N_B] = N_V */
   int32_t n_keep;                /* N_K >= 1 directions kept per block (Sec. II.B) */
-  int32_t n_old;                 /* N_O >= 0 previous updates used as Theta (Eq. 9); 1 + N_O N_B <= 64 */
+  int32_t n_old;                 /* N_O >= 0 previous updates used as Theta (Eq. 9); 1 + N_O N_B <= 512 */
   int32_t n_shifts;              /* >= 1 shifts solved together from one build */
   const double* shifts;          /* host [n_shifts], each >= 0 */
   int32_t precision;             /* blm_precision */

@@ -291,7 +291,7 @@ blm_status validate(const blm_config* cfg, blm_ctx* c) {
   if (cfg->n_keep < 1 || cfg->n_keep + 1 > EIG_MAXSEL)
     return fail(c, BLM_E_ARG, "n_keep must be in [1, 15]");
   if (cfg->n_old < 0 || 1 + (int64_t)cfg->n_old * cfg->n_blocks > NAUX_MAX)
-    return fail(c, BLM_E_ARG, "1 + n_old * n_blocks must be <= 64");
+    return fail(c, BLM_E_ARG, "1 + n_old * n_blocks must be <= 512");
   if (cfg->n_shifts < 1 || !cfg->shifts) return fail(c, BLM_E_ARG, "need at least one shift");
   for (int i = 0; i < cfg->n_shifts; ++i)
     if (!(cfg->shifts[i] >= 0.0) || !std::isfinite(cfg->shifts[i]))
@@ -333,15 +333,16 @@ void plan(blm_ctx* c, Plan& P) {
   }
   c->NAP = NAUX * ((1 + NO * NB + NAUX - 1) / NAUX);
   const int n_xstrip = n_diag * (c->NAP / NAUX - 1);   // strip jobs of the aux groups after the first
+  const int TA = (c->NAP + GT - 1) / GT;                  // aux Gram: TA x TA tile jobs
   c->aux_off = run;
   run += (int64_t)c->NAP * c->NAP;
   c->acc_elems = run;
-  c->n_jobs1 = n_jobs1 + 1 + n_xstrip;
+  c->n_jobs1 = n_jobs1 + TA * TA + n_xstrip;
   c->n_jobsM = c->mixed() ? n_jobs1 : 0;
   // mixed precision: the first aux group's strips ride on the BF16 or FP8
   // diagonal jobs; the aux Gram and the other groups' strips stay on the
   // FP64 kernel
-  if (c->mixed()) c->n_jobs1 = 1 + n_xstrip;
+  if (c->mixed()) c->n_jobs1 = TA * TA + n_xstrip;
   const int64_t aux_groups = c->max_samples / 8 + MAX_CHUNKS;
   c->aux_pstride = c->pieces ? aux_groups * NAUX * 8 : 0;
   c->auxq_stride = c->fp8 ? (c->max_samples / 16 + MAX_CHUNKS) * NAUX * 16 : 0;
@@ -465,12 +466,20 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
         else main.push_back(J);   // all products, first strips included, on the mixed-precision kernel
       }
   }
-  GramJob A{};
-  A.kind = JOB_AUX;
-  A.mi = A.nj = c->NAP;
-  A.s_off = A.h_off = c->aux_off;
-  A.ld_out = c->NAP;
-  jobs.push_back(A);
+  // the aux Gram: every (i, j) tile (S is read from its upper triangle, H
+  // is full)
+  for (int a0 = 0; a0 < c->NAP; a0 += GT)
+    for (int b0 = 0; b0 < c->NAP; b0 += GT) {
+      GramJob A{};
+      A.kind = JOB_AUX;
+      A.mi = std::min(GT, c->NAP - a0);
+      A.nj = std::min(GT, c->NAP - b0);
+      A.ci = a0;
+      A.cj = b0;
+      A.s_off = A.h_off = c->aux_off + (int64_t)a0 * c->NAP + b0;
+      A.ld_out = c->NAP;
+      jobs.push_back(A);
+    }
   // the strips of every aux group after the first, per diagonal tile
   for (int b = 0; b < c->NB; ++b) {
     const int64_t M = c->off[b + 1] - c->off[b];

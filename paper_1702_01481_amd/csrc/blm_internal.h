@@ -28,7 +28,7 @@ constexpr int GT = 64;        // output tile edge
 constexpr int GKS = 16;       // samples per LDS stage
 constexpr int GTHREADS = 256; // 4 waves, 2x2 of 32x32 sub-tiles
 constexpr int NAUX = 16;      // aux columns per group: [1 | Theta] and [E_L | Theta-energy]
-constexpr int NAUX_MAX = GT;  // aux columns in all (1 + N_O N_B, padded to whole groups)
+constexpr int NAUX_MAX = 512; // aux columns in all (1 + N_O N_B, padded to whole groups)
 constexpr int SLICE = 4096;   // samples per slice (unit of split-K work)
 
 enum JobKind : int32_t {
@@ -36,7 +36,7 @@ enum JobKind : int32_t {
   JOB_DIAG = 1,         // i == j: S_ii, H_ii, plus the first aux group's strips aux^T W O_i,
                         // aux^T W e_i, auxE^T W O_i
   JOB_DIAG_NOSTRIP = 2, // i == j without strips
-  JOB_AUX = 3,          // aux x aux: Xa^T W Xa, Xa^T W Ya (all aux columns, one tile)
+  JOB_AUX = 3,          // aux x aux tile (i, j): Xa_i^T W Xa_j, Xa_i^T W Ya_j (from the aux arrays)
   JOB_STRIP = 4         // strips of one aux group over a diagonal tile's columns only
 };
 

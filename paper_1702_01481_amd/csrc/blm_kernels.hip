@@ -152,10 +152,10 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
     const BLM_GLOBAL double* ya = as_global(S.Ya) + rc * S.ald;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int cc = min(lc + c, J.mi - 1);
-      R.a[c] = xa[cc];
-      R.b[c] = R.a[c];
-      R.f[c] = ya[cc];
+      const int64_t ca = J.ci + min(lc + c, J.mi - 1), cb = J.cj + min(lc + c, J.nj - 1);
+      R.a[c] = xa[ca];
+      R.b[c] = xa[cb];
+      R.f[c] = ya[cb];
       R.e[c] = 0.0;
     }
   } else if constexpr (SPLIT) {

@@ -5,8 +5,10 @@ columns in all.  The first 16 ride on the build's diagonal tiles; the rest
 are strip-only tiles on the FP64 kernel, one per 16-column group.
 
 FP64: 17 columns (the second group holds one), 41 (three groups, one piece
-dropped) and 64 (four full groups, the library's limit) against the oracle
-at the FP64 tolerances, through the whole step.  Mixed precision: the
+dropped), 64 (four full groups, one aux Gram tile) and 501 (the paper's
+largest setting, N_B = 100 with N_O = 5: 32 groups, an 8 x 8 grid of aux
+Gram tiles with a ragged last row and column) against the oracle at the
+FP64 tolerances, through the whole step.  Mixed precision: the
 BF16 hi/mid/lo and FP8 builds at 41 columns against the oracle's matrices
 (on the values the FP8 storage stands for), then the rest of the step.
 """
@@ -45,6 +47,17 @@ def test_aux_groups_fp64_step(name):
     host, dev = _make(n_params, 14000, 8, 12, 5000)
     old = _old(name, n_params, n_old)
     _compare_step(offsets, 3, [1e-3, 1e-2], host, dev, old=old, n_old=n_old)
+
+
+@pytest.mark.timeout(600)
+def test_paper_largest_aux_setting():
+    """100 blocks of 6 parameters with N_O = 5: 1 + N_O N_B = 501 aux
+    columns and pencils of dimension 1 + 6 + 5 * 99 = 502 (Eq. 10)."""
+    offsets = list(range(0, 601, 6))
+    print("[aux] 501 aux columns: 100 blocks, N_O = 5", flush=True)
+    host, dev = _make(600, 12000, 8, 12, 5000)
+    old = synth.old_directions(5, 600, 31).numpy()
+    _compare_step(offsets, 3, [1e-2], host, dev, old=old, n_old=5)
 
 
 def _fp8_values_of(x):

@@ -38,11 +38,11 @@ def test_workspace_bytes_and_argument_checks():
     assert 1e9 < b < 2e10
     small = blm.BLM.workspace_bytes(4096, off, 5, 1, [1e-3], 65536)
     assert small < b
-    # 1 + N_O N_B aux columns: 17 and 57 are taken, 65 is not
+    # 1 + N_O N_B aux columns: 17 and 505 are taken, 513 is not
     assert blm.BLM.workspace_bytes(4096, off, 5, 2, [1e-3], 65536) > small
-    assert blm.BLM.workspace_bytes(4096, off, 5, 7, [1e-3], 65536) > small
+    assert blm.BLM.workspace_bytes(4096, off, 5, 63, [1e-3], 65536) > small
     with pytest.raises(blm.BLMError):
-        blm.BLM.workspace_bytes(4096, off, 5, 8, [1e-3], 65536)      # 1 + N_O N_B = 65 > 64
+        blm.BLM.workspace_bytes(4096, off, 5, 64, [1e-3], 65536)     # 1 + N_O N_B = 513 > 512
     with pytest.raises(blm.BLMError):
         blm.BLM.workspace_bytes(4096, off[::-1].copy(), 5, 1, [1e-3], 65536)
     with pytest.raises(blm.BLMError):
