@@ -278,6 +278,27 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
 
+    # the same steps with the build replayed from one recorded HIP graph
+    ctx.capture_build(chunks)
+
+    def step_graph():
+        ctx.begin_step(old)
+        ctx.replay_build()
+        ctx.solve()
+        ctx.project(chunks)
+        return ctx.stage2()
+
+    step_graph()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, en_g, _, _ = step_graph()
+    torch.cuda.synchronize()
+    ms_graph = 1e3 * (time.perf_counter() - t0) / args.steps
+    graph_build = {"ms_per_step": round(ms_graph, 3),
+                   "energy_equal_to_eager": bool(np.array_equal(np.asarray(en_g), np.asarray(en)))}
+    log(f"replayed-build steps: {ms_graph:.1f} ms, {graph_build}")
+
     st = ctx.solver_stats()
     eig_phase_names = ("cholesky", "congruence", "hessenberg", "qr", "select", "inverse_iter",
                        "back_transform", "orthonormalise")
@@ -309,6 +330,7 @@ def main():
         "build_slice_groups": groups,
         "phase_ms": {k: round(float(np.mean(v)), 3) for k, v in phase.items()},
         "block_eig_phase_ms_max": eig_phases,
+        "graph_build": graph_build,
         "energy": [float(x) for x in en],
         "flags": [int(x) for x in fl],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64,

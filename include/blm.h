@@ -9,6 +9,8 @@
  *   blm_build_blocks*  first pass over the samples: every block's overlap S_b
  *                      and Hamiltonian H_b estimates (Eq. 3 on the one-block
  *                      basis of Eq. 4 / Eq. 10)
+ *                      (or blm_replay_build: the same, recorded once as a
+ *                      HIP graph by blm_capture_build)
  *   blm_solve_blocks   every block's shifted generalised eigenproblem, ranked,
  *                      kept directions B^(b) (Eq. 5 / Eq. 10, Eq. 6)
  *   blm_project*       second pass over the same samples: stage-two estimates
@@ -176,6 +178,25 @@ blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chu
  * Returns BLM_E_STATE outside a build phase, BLM_E_ARG for empty or bad
  * chunks. */
 blm_status blm_autotune_build(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks, int32_t* h_groups);
+
+/* A step's block build as one HIP graph (Eq. 3 on the Eq. 4 / Eq. 10 basis,
+ * as blm_build_blocks).  When every step presents the same chunk buffers
+ * (refilled with each step's samples), the build's launches (Theta
+ * projection, aux packing, Gram tiles, their sums) have fixed shapes:
+ * blm_capture_build records them for this chunk list, with device copies
+ * of its own of the launch tables, into a graph held by the context,
+ * without running anything and without changing the step's state; it
+ * replaces any earlier recording and synchronises the stream.  The graph
+ * holds kernel launches only.  blm_replay_build then runs it on the
+ * context's stream, with the effect of blm_build_blocks on the recorded
+ * chunks (same call-order rules; asynchronous).  The recorded chunk
+ * buffers, and their layout, must stay as they were at the recording
+ * while replays run; the autotuned launch shape is the one in force at
+ * the recording.  blm_replay_build returns BLM_E_STATE without a
+ * recording; blm_capture_build returns BLM_E_ARG for empty or bad chunks
+ * and BLM_E_HIP if the runtime refuses the capture. */
+blm_status blm_capture_build(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks);
+blm_status blm_replay_build(blm_ctx* ctx);
 
 /* Solves every block's shifted pencil (H_b + delta P_b) c = lambda S_b c for
  * every shift, ranks the eigenvalues by real part and keeps the parameter

@@ -24,7 +24,8 @@ FLAG_COMPLEX_ENERGY, FLAG_PAIR_KEPT, FLAG_SMALL_ALPHA = 1, 2, 4
 PRECISIONS = {"fp64": 0, "bf16x2": 1, "bf16x3": 2, "fp8": 3}
 
 EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_create", "blm_destroy", "blm_begin_step",
-            "blm_build_blocks", "blm_autotune_build", "blm_solve_blocks", "blm_project", "blm_stage2",
+            "blm_build_blocks", "blm_autotune_build", "blm_capture_build", "blm_replay_build",
+            "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
             "blm_debug_eigvals", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
             "blm_batch_create", "blm_batch_destroy", "blm_batch_solve_blocks", "blm_batch_stage2",
@@ -75,6 +76,8 @@ def load() -> C.CDLL:
     lib.blm_build_blocks.argtypes = [vp, C.POINTER(_Chunk), i32]
     lib.blm_solve_blocks.argtypes = [vp, dp, C.POINTER(i32)]
     lib.blm_autotune_build.argtypes = [vp, C.POINTER(_Chunk), i32, C.POINTER(i32)]
+    lib.blm_capture_build.argtypes = [vp, C.POINTER(_Chunk), i32]
+    lib.blm_replay_build.argtypes = [vp]
     lib.blm_project.argtypes = [vp, C.POINTER(_Chunk), i32]
     lib.blm_stage2.argtypes = [vp, vp, dp, dp, C.POINTER(C.c_uint32)]
     lib.blm_get_block_matrices.argtypes = [vp, i32, i32, dp, dp, C.POINTER(i32)]
@@ -292,6 +295,19 @@ class BLM:
     def build(self, chunks: Iterable):
         arr, n = self._chunks(chunks)
         self._check(self.lib.blm_build_blocks(self.h, arr, n))
+
+    def capture_build(self, chunks: Iterable):
+        """Records the build of these chunks as a HIP graph (blm_capture_build);
+        the chunks are kept alive with the recording."""
+        keep = self._keep
+        arr, n = self._chunks(chunks)
+        self._graph_keep = self._keep[len(keep):]
+        self._keep = keep
+        self._check(self.lib.blm_capture_build(self.h, arr, n))
+
+    def replay_build(self):
+        """Runs the recorded build (blm_replay_build)."""
+        self._check(self.lib.blm_replay_build(self.h))
 
     def autotune(self, chunks: Iterable) -> int:
         """Times the build's Gram kernel on these chunks for each slice-group

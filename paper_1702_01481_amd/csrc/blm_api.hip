@@ -105,6 +105,14 @@ struct blm_ctx {
   bool mixed() const { return pieces != 0 || fp8; }
   Slice* d_slices = nullptr;
   ProjChunk* d_pchunks = nullptr;
+  // recorded build (blm_capture_build): its own device tables, since other
+  // calls rewrite d_slices and d_pchunks; cap: launches are being recorded
+  // and take their tables from g_*; dry: tables are built, nothing launched
+  hipGraphExec_t gexec = nullptr;
+  Slice* g_slices = nullptr;
+  ProjChunk* g_pchunks = nullptr;
+  int64_t g_total = 0;
+  bool cap = false, dry = false;
   std::vector<ProjChunk> h_pchunks;
   bool offsets_even = false;
   DirBlock *d_theta_blk = nullptr, *d_dir2_blk = nullptr;
@@ -150,8 +158,12 @@ blm_status fail(blm_ctx* c, blm_status s, const std::string& m) {
 }
 
 // Records the start (end == false) or end of phase i on the context's stream.
+// device tables of the launches being issued or recorded
+Slice* slice_tab(const blm_ctx* c) { return c->cap ? c->g_slices : c->d_slices; }
+ProjChunk* pchunk_tab(const blm_ctx* c) { return c->cap ? c->g_pchunks : c->d_pchunks; }
+
 void mark(blm_ctx* c, int i, bool end) {
-  if (!c->timing) return;
+  if (!c->timing || c->cap) return;
   (void)hipEventRecord(c->ev[2 * i + (end ? 1 : 0)], c->st);
   if (end) c->ev_used[i] = true;
 }
@@ -589,11 +601,12 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
     rb += ns;
     if ((ch[i].ld & 1) || ((uintptr_t)ch[i].O & 15) || ((uintptr_t)ch[i].e & 15)) vec = false;
   }
-  if (c->h_pchunks.empty()) return BLM_OK;
-  HIPCHK(c, hipMemcpyAsync(c->d_pchunks, c->h_pchunks.data(), sizeof(ProjChunk) * c->h_pchunks.size(),
-                           hipMemcpyHostToDevice, c->st));
+  if (c->h_pchunks.empty() || c->dry) return BLM_OK;
+  if (!c->cap)
+    HIPCHK(c, hipMemcpyAsync(c->d_pchunks, c->h_pchunks.data(), sizeof(ProjChunk) * c->h_pchunks.size(),
+                             hipMemcpyHostToDevice, c->st));
   const int store = c->fp8 ? STORE_FP8 : c->pieces ? STORE_BF16 : STORE_F64;
-  launch_dirproj(c->d_pchunks, (int)c->h_pchunks.size(), tiles, vec && store == STORE_F64, store,
+  launch_dirproj(pchunk_tab(c), (int)c->h_pchunks.size(), tiles, vec && store == STORE_F64, store,
                  d_blocks, n_blocks, d_ptr, n_dirs, max_nd, Xo, Yo, ldo, c->st);
   HIPCHK(c, hipGetLastError());
   return BLM_OK;
@@ -606,11 +619,11 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
 // over the slice table on the device, into the partial tiles
 void launch_build_gram(blm_ctx* c, int kind, const GramJob* d_jobs, int n_jobs, int n_slices, int P, bool vec) {
   if (kind == 2)
-    launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->pieces, c->partial, c->st);
+    launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->pieces, c->partial, c->st);
   else if (kind == 3)
-    launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, c->d_slices, n_slices, P, c->partial, c->st);
+    launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->partial, c->st);
   else
-    launch_gram(d_jobs, n_jobs, c->d_slices, n_slices, P, vec && kind == 0, kind == 1, c->partial, c->st);
+    launch_gram(d_jobs, n_jobs, slice_tab(c), n_slices, P, vec && kind == 0, kind == 1, c->partial, c->st);
 }
 
 // tuned: the block build's main Gram launch, which takes the slice-group
@@ -624,8 +637,9 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
   for (const Slice& S : c->h_slices)
     if ((S.ld & 1) || ((uintptr_t)S.O & 15) || ((uintptr_t)S.e & 15)) vec = false;
   if (n_slices > c->max_slices) return fail(c, BLM_E_ARG, "too many slices in one call");
-  HIPCHK(c, hipMemcpyAsync(c->d_slices, c->h_slices.data(), sizeof(Slice) * n_slices,
-                           hipMemcpyHostToDevice, c->st));
+  if (!c->cap)
+    HIPCHK(c, hipMemcpyAsync(c->d_slices, c->h_slices.data(), sizeof(Slice) * n_slices,
+                             hipMemcpyHostToDevice, c->st));
   int P = choose_P(cap, n_jobs, n_slices);
   if (tuned && c->P_tuned[kind] > 0) P = std::max(1, std::min({c->P_tuned[kind], cap, std::max(1, n_slices)}));
   if (phase >= 0) mark(c, phase, false);
@@ -658,16 +672,18 @@ blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
     uint16_t* xr = nullptr;
     float* xs = nullptr;
     if (c->fp8) {
-      // this chunk's first aux group in FP8 storage, with its own scales
       xq = c->auxQ + g16base * NAUX * 16;
       xr = c->auxR + gbase * NAUX * 8;
       xs = c->auxS + (size_t)ci * 2 * NAUX;
+    }
+    if (c->fp8 && !c->dry) {
+      // this chunk's first aux group in FP8 storage, with its own scales
       launch_pack_fp8(c->Xa + (size_t)rb * c->NAP, ns, c->NAP, NAUX, xq, xr, xs, NAUX, c->st);
       launch_pack_fp8(c->Ya + (size_t)rb * c->NAP, ns, c->NAP, NAUX, xq + c->auxq_stride, xr + c->auxr_stride,
                       xs + NAUX, NAUX, c->st);
       HIPCHK(c, hipGetLastError());
     }
-    if (c->pieces) {
+    if (c->pieces && !c->dry) {
       // this chunk's first aux group as BF16 pieces, from an 8-sample group boundary
       uint16_t* xp = c->auxP + gbase * NAUX * 8;
       launch_pack_bf16(c->Xa + (size_t)rb * c->NAP, ns, c->NAP, NAUX, c->pieces, xp, NAUX, c->aux_pstride,
@@ -721,6 +737,16 @@ blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
     ++ci;
   }
   return BLM_OK;
+}
+
+void release_build_graph(blm_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->g_slices) (void)hipFree(c->g_slices);
+  if (c->g_pchunks) (void)hipFree(c->g_pchunks);
+  c->gexec = nullptr;
+  c->g_slices = nullptr;
+  c->g_pchunks = nullptr;
+  c->g_total = 0;
 }
 
 }  // namespace
@@ -816,6 +842,7 @@ blm_status blm_get_timings(blm_ctx* c, double* h_ms, int32_t n) {
 
 blm_status blm_destroy(blm_ctx* c) {
   if (!c) return BLM_OK;
+  release_build_graph(c);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (void* p : c->allocs) (void)hipFree(p);
@@ -965,6 +992,26 @@ blm_status blm_begin_step(blm_ctx* c, const double* d_old) {
   return BLM_OK;
 }
 
+// The launches of one block build on chunks already checked: aux columns
+// and slice table, then the Gram launches (issued on c->st, or recorded).
+static blm_status build_launches(blm_ctx* c, const blm_chunk* ch, int32_t n) {
+  mark(c, 0, false);
+  blm_status s = build_slices(c, ch, n);
+  if (s != BLM_OK) return s;
+  mark(c, 0, true);
+  if (c->mixed()) {
+    // FP64 aux Gram and further aux groups' strips (timed in the strips
+    // slot), then the mixed-precision products and first strips
+    mark(c, 9, false);
+    s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, -1, false, 1);
+    if (s != BLM_OK) return s;
+    mark(c, 9, true);
+    return run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, c->accS, c->accH, c->strips, 1, false,
+                    c->fp8 ? 3 : 2, true);
+  }
+  return run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even, 0, true);
+}
+
 blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   if (!c) return BLM_E_ARG;
   if (c->state != ST_BEGUN && c->state != ST_BUILT)
@@ -972,24 +1019,72 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   int64_t total = 0;
   blm_status s = check_chunks(c, ch, n, &total);
   if (s != BLM_OK) return s;
-  mark(c, 0, false);
-  s = build_slices(c, ch, n);
-  if (s != BLM_OK) return s;
-  mark(c, 0, true);
-  if (c->mixed()) {
-    // FP64 aux Gram (timed in the strips slot), then the mixed-precision
-    // products and strips
-    mark(c, 9, false);
-    s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, -1, false, 1);
-    if (s != BLM_OK) return s;
-    mark(c, 9, true);
-    s = run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, c->accS, c->accH, c->strips, 1, false,
-                 c->fp8 ? 3 : 2, true);
-  } else {
-    s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even, 0, true);
-  }
+  s = build_launches(c, ch, n);
   if (s != BLM_OK) return s;
   c->n_pass1 += total;
+  c->state = ST_BUILT;
+  return BLM_OK;
+}
+
+blm_status blm_capture_build(blm_ctx* c, const blm_chunk* ch, int32_t n) {
+  if (!c) return BLM_E_ARG;
+  int64_t total = 0;
+  blm_status s = check_chunks(c, ch, n, &total);
+  if (s != BLM_OK) return s;
+  release_build_graph(c);
+  // the tables, built without launching anything, into the graph's own
+  // device copies
+  c->dry = true;
+  s = build_slices(c, ch, n);
+  c->dry = false;
+  if (s != BLM_OK) return s;
+  if (c->h_slices.empty()) return fail(c, BLM_E_ARG, "blm_capture_build needs samples");
+  if ((int)c->h_slices.size() > c->max_slices) return fail(c, BLM_E_ARG, "too many slices in one call");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  HIPCHK(c, hipMalloc((void**)&c->g_slices, sizeof(Slice) * c->h_slices.size()));
+  HIPCHK(c, hipMalloc((void**)&c->g_pchunks, sizeof(ProjChunk) * std::max<size_t>(c->h_pchunks.size(), 1)));
+  HIPCHK(c, hipMemcpy(c->g_slices, c->h_slices.data(), sizeof(Slice) * c->h_slices.size(),
+                      hipMemcpyHostToDevice));
+  if (!c->h_pchunks.empty())
+    HIPCHK(c, hipMemcpy(c->g_pchunks, c->h_pchunks.data(), sizeof(ProjChunk) * c->h_pchunks.size(),
+                        hipMemcpyHostToDevice));
+  // record the launches on a stream of the library's own (the context's
+  // stream may be the null stream, which cannot be captured)
+  hipStream_t cs = nullptr;
+  HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipStream_t saved = c->st;
+  c->st = cs;
+  c->cap = true;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = build_launches(c, ch, n);
+    e = hipStreamEndCapture(cs, &g);
+  }
+  c->cap = false;
+  c->st = saved;
+  if (e == hipSuccess && s == BLM_OK) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (s == BLM_OK && e != hipSuccess) {
+    c->gexec = nullptr;
+    s = fail(c, BLM_E_HIP, std::string("build capture: ") + hipGetErrorString(e));
+  }
+  if (s != BLM_OK) {
+    release_build_graph(c);
+    return s;
+  }
+  c->g_total = total;
+  return BLM_OK;
+}
+
+blm_status blm_replay_build(blm_ctx* c) {
+  if (!c) return BLM_E_ARG;
+  if (!c->gexec) return fail(c, BLM_E_STATE, "blm_replay_build needs blm_capture_build first");
+  if (c->state != ST_BEGUN && c->state != ST_BUILT)
+    return fail(c, BLM_E_STATE, "blm_replay_build needs blm_begin_step first");
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->st));
+  c->n_pass1 += c->g_total;
   c->state = ST_BUILT;
   return BLM_OK;
 }
