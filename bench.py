@@ -35,12 +35,12 @@ PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 (matrix and vector)
 # the kernel source they were taken on: reported as null once the source of
 # the sample-streaming kernels has changed.
 GRAM_TRAFFIC = {
-    "source_sha256": "fe63129d3600dfb45d073795394d2f8584b76659fb4f2a0d1fb292d09c5b772c",
+    "source_sha256": "e0862e526e808d682e6cf1e90c02ba196dee91d6fcc7513e48642c7099e786e9",
     "fetch_scale": 1.99996, "write_scale": 1.0,
     # slice groups per tile -> (FETCH_SIZE, WRITE_SIZE) KiB per launch
-    "by_groups": {1: (103081293.0, 27200.0), 2: (229860804.0, 54400.0), 3: (226578069.0, 81600.0),
-                  4: (233732360.0, 108800.0), 6: (235026371.0, 163200.0), 8: (236161220.0, 217600.0),
-                  12: (234686538.0, 326400.0), 15: (234257110.0, 408000.0)},
+    "by_groups": {1: (105917921.0, 27200.0), 2: (240307347.0, 54400.0), 3: (239455190.0, 81600.0),
+                  4: (241274134.0, 108800.0), 6: (240285068.0, 163200.0), 8: (239882293.0, 217600.0),
+                  12: (237532008.0, 326400.0), 15: (236475832.0, 408000.0)},
 }
 
 
