@@ -296,6 +296,12 @@ class BLM:
         arr, n = self._chunks(chunks)
         self._check(self.lib.blm_build_blocks(self.h, arr, n))
 
+    def drop_chunk_refs(self):
+        """Forgets the chunks kept alive for queued work (they are otherwise
+        held until the next begin_step); only once the stream has passed
+        the calls that read them, e.g. after torch.cuda.synchronize()."""
+        self._keep = [k for k in self._keep if isinstance(k, torch.Tensor)]   # the step's old directions
+
     def capture_build(self, chunks: Iterable):
         """Records the build of these chunks as a HIP graph (blm_capture_build);
         the chunks are kept alive with the recording."""

@@ -739,7 +739,9 @@ blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
   return BLM_OK;
 }
 
+// (a replay may still run on the context's stream: it reads the tables)
 void release_build_graph(blm_ctx* c) {
+  if (c->gexec) (void)hipStreamSynchronize(c->st);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->g_slices) (void)hipFree(c->g_slices);
   if (c->g_pchunks) (void)hipFree(c->g_pchunks);
