@@ -175,6 +175,17 @@ def test_aligned_full_tiles(weighted):
     _compare_step(offsets, 4, [1e-4, 1e-2], host, dev, old=old, n_old=1)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_full_tiles_at_odd_and_even_origins(weighted):
+    """Blocks starting at odd and at even columns, with an even leading
+    dimension, full and ragged tiles in one launch (an odd block origin
+    keeps the whole build on the general load path)."""
+    offsets = [0, 65, 193, 322, 450]
+    host, dev = _make(450, 20007, 8, 13, 7001, weighted=weighted)
+    old = synth.old_directions(1, 450, 6).numpy()
+    _compare_step(offsets, 4, [1e-3], host, dev, old=old, n_old=1)
+
+
 def test_dyadic_inputs_are_bit_exact():
     """Small-integer samples: every partial sum is exact, so the block
     matrices must equal the oracle's bit for bit (N_s a power of two)."""
