@@ -237,6 +237,16 @@ def streamed_target(args):
     t_gen = 0.0
     for c in ctxs.values():
         c.begin_step()
+    groups = {}
+    if not args.no_autotune:
+        # launch shape of each context's build, timed on the first chunk
+        O, e, EL = gen.chunk(0, sizes[0])
+        for p in precs:
+            groups[p] = ctxs[p].autotune([stored(p, O, e, EL)])
+            torch.cuda.synchronize()
+            ctxs[p].drop_chunk_refs()
+        del O, e, EL
+        log(f"streamed: slice groups per tile {groups}")
     out = {}
     for pas in (1, 2):
         for i, n in enumerate(sizes):
@@ -275,6 +285,7 @@ def streamed_target(args):
         step = sum(ms[p].values())
         upd, en = out[p][0].double().cpu().numpy(), out[p][1]
         r = {"step_ms": round(step, 1), "phase_ms": {k: round(v, 1) for k, v in ms[p].items()},
+             "build_slice_groups": groups.get(p),
              "build_tflops": round(fl / (ms[p]["build"] * 1e-3) / 1e12, 2), "energy": [float(x) for x in en]}
         if p != "fp64":
             worst = 0.0
