@@ -192,7 +192,8 @@ blm_status blm_autotune_build(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_c
  * chunks (same call-order rules; asynchronous).  The recorded chunk
  * buffers, and their layout, must stay as they were at the recording
  * while replays run; the autotuned launch shape is the one in force at
- * the recording.  blm_replay_build returns BLM_E_STATE without a
+ * the recording.  Event timing (blm_set_timing) does not cover a replayed
+ * build: its phases keep the last call-by-call build's times.  blm_replay_build returns BLM_E_STATE without a
  * recording; blm_capture_build returns BLM_E_ARG for empty or bad chunks
  * and BLM_E_HIP if the runtime refuses the capture. */
 blm_status blm_capture_build(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks);
