@@ -305,10 +305,10 @@ class BLM:
     def capture_build(self, chunks: Iterable):
         """Records the build of these chunks as a HIP graph (blm_capture_build);
         the chunks are kept alive with the recording."""
-        keep = self._keep
+        n0 = len(self._keep)
         arr, n = self._chunks(chunks)
-        self._graph_keep = self._keep[len(keep):]
-        self._keep = keep
+        self._graph_keep = self._keep[n0:]
+        del self._keep[n0:]
         self._check(self.lib.blm_capture_build(self.h, arr, n))
 
     def replay_build(self):

@@ -62,3 +62,26 @@ def test_synthetic_partitions_cover_the_parameters():
     assert sum(w.n_params for w in synth.batched_workloads(n_samples=1)) == 78_000
     off = synth.loguniform_offsets(30_000, 40, 100.0, 2000.0, 0)
     assert off[0] == 0 and off[-1] == 30_000 and len(off) == 41 and np.all(np.diff(off) > 0)
+
+
+def test_recorded_build_keeps_its_chunks():
+    """BLM.capture_build holds the recorded chunks for as long as the
+    recording (they are read at every replay), apart from the chunks a
+    step keeps until its next begin_step; no GPU call is made."""
+    import types
+
+    import torch
+    old = torch.zeros(1, 4, dtype=torch.float64)
+    o = types.SimpleNamespace(_keep=[old], h=None, _check=lambda st: None,
+                              lib=types.SimpleNamespace(blm_capture_build=lambda *a: 0))
+
+    def _chunks(chunks):
+        o._keep.extend(chunks)
+        return None, len(chunks)
+
+    o._chunks = _chunks
+    blm.BLM.capture_build(o, [("O0", "e0", "E0"), ("O1", "e1", "E1")])
+    assert o._graph_keep == [("O0", "e0", "E0"), ("O1", "e1", "E1")]
+    assert len(o._keep) == 1 and o._keep[0] is old
+    blm.BLM.drop_chunk_refs(o)
+    assert o._graph_keep and len(o._keep) == 1 and o._keep[0] is old
