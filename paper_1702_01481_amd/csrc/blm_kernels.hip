@@ -498,14 +498,23 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
     // thread -> (8-sample group g, parameter col): 8 samples of O and of e
     const int col = tid & 31, g = tid >> 5;
     const int64_t r0 = s0 + 8 * g;
-    if (r0 < C.n && p0 + col < B.m) {
-      if constexpr (ST == STORE_FP8) {
-        fp8_load8(C.O, C.Or, C.Os, C.ld, r0 >> 3, B.col0 + p0 + col, R.o);
-        fp8_load8(C.e, C.er, C.es, C.ld, r0 >> 3, B.col0 + p0 + col, R.e);
-      } else {
-        split_load8(C.O, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.o);
-        split_load8(C.e, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.e);
+    const bool ok = r0 < C.n && p0 + col < B.m;
+    if constexpr (ST == STORE_FP8) {
+      // loads at a clamped (in-bounds) group and column, then zeros outside:
+      // no divergent branch, whose merged values the compiler kept in scratch
+      const int64_t grp = min(r0, C.n - 1) >> 3;
+      const int64_t cc = B.col0 + min(p0 + col, B.m - 1);
+      double o[8], e[8];
+      fp8_load8(C.O, C.Or, C.Os, C.ld, grp, cc, o);
+      fp8_load8(C.e, C.er, C.es, C.ld, grp, cc, e);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        R.o[k] = ok ? o[k] : 0.0;
+        R.e[k] = ok ? e[k] : 0.0;
       }
+    } else if (ok) {
+      split_load8(C.O, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.o);
+      split_load8(C.e, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, R.e);
     } else {
 #pragma unroll
       for (int k = 0; k < 8; ++k) R.o[k] = R.e[k] = 0.0;
