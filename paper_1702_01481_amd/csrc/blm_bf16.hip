@@ -7,9 +7,11 @@
 // v_mfma_f32_16x16x32_bf16 (exact products, FP32 sums).  FP32 accumulators
 // are added into FP64 registers after every 32 samples, and the slices are summed
 // in FP64 by the same fixed-order reduction as the FP64 path.  These are the
-// block estimates of Eq. 3 on the one-block basis (Eq. 4 / Eq. 10); the
-// columns of the wave function itself and of the previous directions stay
-// in FP64 (strip jobs of the FP64 kernel).
+// block estimates of Eq. 3 on the one-block basis (Eq. 4 / Eq. 10).  The
+// first 16 aux columns (the wave function itself and previous directions)
+// are packed to BF16 pieces per chunk, and diagonal pairs compute their
+// coupling strips of Fig. 1 here; the aux Gram and further aux groups'
+// strips run on the FP64 kernel.
 //
 // Storage ("k-packed"): element (s, x) of piece p is at
 // base + p * pstride + ((s / 8) * ld + x) * 8 + s % 8.  A lane's matrix-core

@@ -14,8 +14,10 @@
 // itself.  FP32 accumulators are scaled by s_x s_y (exact) and added into FP64
 // registers every 256 samples and at every slice boundary (scales change
 // with the chunk).  These are the block estimates of Eq. 3 on the one-block basis
-// (Eq. 4 / Eq. 10), including the coupling strips of Fig. 1: the aux columns
-// (wave function and previous directions) are stored the same way, per chunk.
+// (Eq. 4 / Eq. 10), including the coupling strips of Fig. 1 for the first 16
+// aux columns (wave function and previous directions), which are stored the
+// same way per chunk; the aux Gram and further aux groups' strips run on the
+// FP64 kernel.
 //
 // Storage (k-packed): codes of (s, x) at ((s / 16) * ld + x) * 16 + s % 16
 // bytes, residuals at ((s / 8) * ld + x) * 8 + s % 8 (uint16), so that one
