@@ -3,8 +3,10 @@
 //  * gram_kernel: weighted Gram tiles C = X^T diag(w) Y over sample slices
 //    on the FP64 matrix cores (v_mfma_f64_16x16x4).  This is the Monte Carlo
 //    estimate of Eq. 3 restricted to each parameter block (the green
-//    elements of Fig. 1: S_b and H_b of the one-block basis, Eq. 4 / Eq. 10)
-//    and, in the second pass, the stage-two estimates of Eq. 7.
+//    elements of Fig. 1: S_b and H_b of the one-block basis, Eq. 4 / Eq. 10),
+//    their coupling strips and the aux Gram (the blue elements; strips of
+//    aux groups after the first also on BF16 split and FP8 storage), and,
+//    in the second pass, the stage-two estimates of Eq. 7.
 //  * gram_reduce_kernel: fixed-order sum of the per-slice partial tiles into
 //    the FP64 accumulators (no floating-point atomics: bitwise
 //    reproducible).
