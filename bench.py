@@ -35,12 +35,12 @@ PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 (matrix and vector)
 # the kernel source they were taken on: reported as null once the source of
 # the sample-streaming kernels has changed.
 GRAM_TRAFFIC = {
-    "source_sha256": "e0862e526e808d682e6cf1e90c02ba196dee91d6fcc7513e48642c7099e786e9",
+    "source_sha256": "1a56fb76c4b017650cccf6aae070ef4dc7be90c19d5a0afae7db0c99d0141eaf",
     "fetch_scale": 1.99996, "write_scale": 1.0,
     # slice groups per tile -> (FETCH_SIZE, WRITE_SIZE) KiB per launch
-    "by_groups": {1: (105917921.0, 27200.0), 2: (240307347.0, 54400.0), 3: (239455190.0, 81600.0),
-                  4: (241274134.0, 108800.0), 6: (240285068.0, 163200.0), 8: (239882293.0, 217600.0),
-                  12: (237532008.0, 326400.0), 15: (236475832.0, 408000.0)},
+    "by_groups": {1: (105547398.0, 27200.0), 2: (232260251.0, 54400.0), 3: (228676125.0, 81600.0),
+                  4: (232234152.0, 108800.0), 6: (231994179.0, 163200.0), 8: (232752414.0, 217600.0),
+                  12: (231145542.0, 326400.0), 15: (230106212.0, 408000.0)},
 }
 
 

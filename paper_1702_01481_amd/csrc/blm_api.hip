@@ -344,7 +344,8 @@ void plan(blm_ctx* c, Plan& P) {
     n_diag += T;
   }
   c->NAP = NAUX * ((1 + NO * NB + NAUX - 1) / NAUX);
-  const int n_xstrip = n_diag * (c->NAP / NAUX - 1);   // strip jobs of the aux groups after the first
+  // strip-only jobs of the aux groups after the first, STRIP_GROUPS groups each
+  const int n_xstrip = n_diag * ((c->NAP / NAUX - 1 + STRIP_GROUPS - 1) / STRIP_GROUPS);
   const int TA = (c->NAP + GT - 1) / GT;                  // aux Gram: TA x TA tile jobs
   c->aux_off = run;
   run += (int64_t)c->NAP * c->NAP;
@@ -492,16 +493,18 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
       A.ld_out = c->NAP;
       jobs.push_back(A);
     }
-  // the strips of every aux group after the first, per diagonal tile
+  // the strips of every aux group after the first, per diagonal tile, up to
+  // STRIP_GROUPS groups per job (one read of the tile's panels)
   for (int b = 0; b < c->NB; ++b) {
     const int64_t M = c->off[b + 1] - c->off[b];
     for (int64_t c0 = 0; c0 < M; c0 += GT)
-      for (int ag = NAUX; ag < c->NAP; ag += NAUX) {
+      for (int ag = NAUX; ag < c->NAP; ag += STRIP_GROUPS * NAUX) {
         GramJob X{};
         X.kind = JOB_STRIP;
         X.mi = X.nj = (int)std::min<int64_t>(GT, M - c0);
         X.ci = X.cj = c->off[b] + c0;
         X.ag = ag;
+        X.ng = std::min(STRIP_GROUPS, (c->NAP - ag) / NAUX);
         X.ld_out = M;
         X.strip_col = X.ci;
         jobs.push_back(X);

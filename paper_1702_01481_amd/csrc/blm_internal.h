@@ -29,6 +29,7 @@ constexpr int GKS = 16;       // samples per LDS stage
 constexpr int GTHREADS = 256; // 4 waves, 2x2 of 32x32 sub-tiles
 constexpr int NAUX = 16;      // aux columns per group: [1 | Theta] and [E_L | Theta-energy]
 constexpr int NAUX_MAX = 512; // aux columns in all (1 + N_O N_B, padded to whole groups)
+constexpr int STRIP_GROUPS = 4;  // aux groups per strip-only job (one read of the tile's panels)
 constexpr int SLICE = 4096;   // samples per slice (unit of split-K work)
 
 enum JobKind : int32_t {
@@ -37,13 +38,15 @@ enum JobKind : int32_t {
                         // aux^T W e_i, auxE^T W O_i
   JOB_DIAG_NOSTRIP = 2, // i == j without strips
   JOB_AUX = 3,          // aux x aux tile (i, j): Xa_i^T W Xa_j, Xa_i^T W Ya_j (from the aux arrays)
-  JOB_STRIP = 4         // strips of one aux group over a diagonal tile's columns only
+  JOB_STRIP = 4         // strips of up to STRIP_GROUPS aux groups over a diagonal tile's columns only
 };
 
 struct GramJob {
   int32_t kind;
   int32_t mi, nj;       // valid rows / cols of the tile (<= GT)
   int32_t ag;           // JOB_DIAG, JOB_STRIP: first aux column of the strips' group (multiple of NAUX)
+  int32_t ng;           // JOB_STRIP: aux groups of NAUX columns from ag (1..STRIP_GROUPS)
+  int32_t pad2;
   int64_t ci, cj;       // first source column of tile i / tile j
   int64_t s_off;        // destination of S tile (i,j): s_base[s_off + r*ld_out + c]
   int64_t h_off;        // destination of H tile (i,j)

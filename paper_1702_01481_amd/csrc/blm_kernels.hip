@@ -97,7 +97,7 @@ __device__ __forceinline__ void fp8_load8(const void* codes, const uint16_t* res
 // instruction uses a loaded value before the next stage's products.
 struct StageRegs {
   double a[4], e[4], b[4], f[4];
-  double x, y;
+  double x[STRIP_GROUPS], y[STRIP_GROUPS];   // aux (1, Theta), (E_L, Theta energy); one per group
   double w;             // sample weight (of the clamped row)
   bool valid;           // the row is inside the slice
 };
@@ -204,10 +204,19 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
       }
     }
   }
-  if constexpr (KIND == JOB_DIAG || KIND == JOB_STRIP) {
+  if constexpr (KIND == JOB_DIAG) {
     const int acol = tid & 15;
-    R.x = as_global(S.Xa)[rc * S.ald + J.ag + acol];
-    R.y = as_global(S.Ya)[rc * S.ald + J.ag + acol];
+    R.x[0] = as_global(S.Xa)[rc * S.ald + J.ag + acol];
+    R.y[0] = as_global(S.Ya)[rc * S.ald + J.ag + acol];
+  } else if constexpr (KIND == JOB_STRIP) {
+    // the job's groups (a group past J.ng loads the last one again)
+    const int acol = tid & 15;
+#pragma unroll
+    for (int g = 0; g < STRIP_GROUPS; ++g) {
+      const int64_t col = J.ag + NAUX * min(g, J.ng - 1) + acol;
+      R.x[g] = as_global(S.Xa)[rc * S.ald + col];
+      R.y[g] = as_global(S.Ya)[rc * S.ald + col];
+    }
   }
 }
 
@@ -238,6 +247,7 @@ __device__ __forceinline__ void gram_body(GramLds& L, const GramJob& J,
   const int i16 = lane & 15, k4 = lane >> 4;
   constexpr bool STRIPS = KIND == JOB_DIAG || KIND == JOB_STRIP;
   constexpr bool MAIN = KIND != JOB_STRIP;
+  const int ng = (KIND == JOB_STRIP) ? __builtin_amdgcn_readfirstlane(J.ng) : 1;
 
   d4 P0[2][2], P1[2][2], P2[2][2];
 #pragma unroll
@@ -280,10 +290,19 @@ __device__ __forceinline__ void gram_body(GramLds& L, const GramJob& J,
         sF[nb][lr][lc + c] = f[c];
       }
     }
-    if constexpr (STRIPS) {
+    if constexpr (KIND == JOB_STRIP) {
+      // a strip-only job has no row panels: its aux groups go where they
+      // would be (64 columns, STRIP_GROUPS groups of 16)
       const double w = R.valid ? R.w : 0.0;
-      sX[nb][lr][tid & 15] = R.x * w;
-      sY[nb][lr][tid & 15] = R.y * w;
+#pragma unroll
+      for (int g = 0; g < STRIP_GROUPS; ++g) {
+        sA[nb][lr][NAUX * g + (tid & 15)] = R.x[g] * w;
+        sE[nb][lr][NAUX * g + (tid & 15)] = R.y[g] * w;
+      }
+    } else if constexpr (STRIPS) {
+      const double w = R.valid ? R.w : 0.0;
+      sX[nb][lr][tid & 15] = R.x[0] * w;
+      sY[nb][lr][tid & 15] = R.y[0] * w;
     }
   };
   auto compute = [&](int buf) {
@@ -310,7 +329,19 @@ __device__ __forceinline__ void gram_body(GramLds& L, const GramJob& J,
           P2[1][1] = mfma_f64(e1, b1, P2[1][1]);
         }
       }
-      if constexpr (STRIPS) {
+      if constexpr (KIND == JOB_STRIP) {
+        // group g's three products in the accumulators of sub-tile (g / 2, g % 2)
+        const double bs = sB[buf][kr][16 * wv + i16], fs = sF[buf][kr][16 * wv + i16];
+#pragma unroll
+        for (int g = 0; g < STRIP_GROUPS; ++g) {
+          if (g < ng) {
+            const double xs = sA[buf][kr][NAUX * g + i16], ys = sE[buf][kr][NAUX * g + i16];
+            P0[g >> 1][g & 1] = mfma_f64(xs, bs, P0[g >> 1][g & 1]);   // aux^T W O_i
+            P1[g >> 1][g & 1] = mfma_f64(xs, fs, P1[g >> 1][g & 1]);   // aux^T W e_i
+            P2[g >> 1][g & 1] = mfma_f64(ys, bs, P2[g >> 1][g & 1]);   // auxE^T W O_i
+          }
+        }
+      } else if constexpr (STRIPS) {
         const double xs = sX[buf][kr][i16], ys = sY[buf][kr][i16];
         const double bs = sB[buf][kr][16 * wv + i16], fs = sF[buf][kr][16 * wv + i16];
         P2[0][0] = mfma_f64(xs, bs, P2[0][0]);   // aux^T W O_i
@@ -363,7 +394,21 @@ __device__ __forceinline__ void gram_body(GramLds& L, const GramJob& J,
           if (KIND == JOB_OFF) base[2 * GT * GT + row * GT + col] = P2[x][y][rr];
         }
   }
-  if constexpr (STRIPS) {
+  if constexpr (KIND == JOB_STRIP) {
+    // strips of the job's groups: product q in slot q, [NAUX * ng][GT]
+#pragma unroll
+    for (int g = 0; g < STRIP_GROUPS; ++g) {
+      if (g >= ng) continue;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int a = NAUX * g + 4 * rr + k4;
+        const int c = 16 * wv + i16;
+        base[0 * GT * GT + a * GT + c] = P0[g >> 1][g & 1][rr];
+        base[1 * GT * GT + a * GT + c] = P1[g >> 1][g & 1][rr];
+        base[2 * GT * GT + a * GT + c] = P2[g >> 1][g & 1][rr];
+      }
+    }
+  } else if constexpr (STRIPS) {
     // strips: [3][NAUX][GT] in the third slot
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
@@ -433,9 +478,20 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
                                                           int64_t strip_ld, int strip_rows) {
   const int jid = blockIdx.x, qd = blockIdx.y;
   const GramJob J = jobs[jid];
-  const bool strips = (J.kind == JOB_DIAG || J.kind == JOB_STRIP);
+  if (J.kind == JOB_STRIP) {
+    // product qd of the job's groups: [NAUX * ng][GT] in slot qd
+    const int n_st = NAUX * J.ng * GT;
+    for (int el = threadIdx.x; el < n_st; el += blockDim.x) {
+      double sum = 0.0;
+      for (int pp = 0; pp < P; ++pp)
+        sum += partial[((size_t)jid * P + pp) * (size_t)(3 * GT * GT) + (size_t)qd * GT * GT + el];
+      const int a = el / GT, c = el % GT;
+      if (c < J.mi) strip_base[((size_t)qd * strip_rows + J.ag + a) * strip_ld + J.strip_col + c] += sum;
+    }
+    return;
+  }
+  const bool strips = J.kind == JOB_DIAG;
   if (qd == 2 && J.kind != JOB_OFF && !strips) return;
-  if (qd < 2 && J.kind == JOB_STRIP) return;
   const int n_el = (qd == 2 && strips) ? 3 * NAUX * GT : GT * GT;
   for (int el = threadIdx.x; el < n_el; el += blockDim.x) {
     double sum = 0.0;
