@@ -35,12 +35,12 @@ PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 (matrix and vector)
 # the kernel source they were taken on: reported as null once the source of
 # the sample-streaming kernels has changed.
 GRAM_TRAFFIC = {
-    "source_sha256": "1a56fb76c4b017650cccf6aae070ef4dc7be90c19d5a0afae7db0c99d0141eaf",
+    "source_sha256": "efb1445a42c5dedbd4054a361353706c5d16088e674403c757e64cff90ba5875",
     "fetch_scale": 1.99996, "write_scale": 1.0,
     # slice groups per tile -> (FETCH_SIZE, WRITE_SIZE) KiB per launch
-    "by_groups": {1: (105547398.0, 27200.0), 2: (232260251.0, 54400.0), 3: (228676125.0, 81600.0),
-                  4: (232234152.0, 108800.0), 6: (231994179.0, 163200.0), 8: (232752414.0, 217600.0),
-                  12: (231145542.0, 326400.0), 15: (230106212.0, 408000.0)},
+    "by_groups": {1: (105566351.0, 27200.0), 2: (230332281.0, 54400.0), 3: (229755819.0, 81600.0),
+                  4: (233044943.0, 108800.0), 6: (231931632.0, 163200.0), 8: (232274965.0, 217600.0),
+                  12: (231207027.0, 326400.0), 15: (230408402.0, 408000.0)},
 }
 
 

@@ -365,7 +365,9 @@ void plan(blm_ctx* c, Plan& P) {
   const int T2 = (c->n2max + GT - 1) / GT;
   const int n_jobs2max = T2 * (T2 + 1) / 2;
   c->Pcap1 = std::max(1, std::min(64, (4096 + c->n_jobs1 - 1) / c->n_jobs1));
-  c->Pcap2 = std::max(1, std::min(64, (4096 + n_jobs2max - 1) / n_jobs2max));
+  // stage two has few tiles (3 at 121 coordinates): up to one slice group
+  // per 4,096-sample slice, so that its launch fills the chip
+  c->Pcap2 = std::max(1, std::min(512, (4096 + n_jobs2max - 1) / n_jobs2max));
   c->PcapM = c->n_jobsM ? std::max(1, std::min(64, (4096 + c->n_jobsM - 1) / c->n_jobsM)) : 1;
   const size_t slots = std::max({(size_t)c->n_jobs1 * c->Pcap1, (size_t)n_jobs2max * c->Pcap2,
                                  (size_t)c->n_jobsM * c->PcapM});

@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
   if (J.kind == JOB_STRIP) {
     // product qd of the job's groups: [NAUX * ng][GT] in slot qd
     const int n_st = NAUX * J.ng * GT;
-    for (int el = threadIdx.x; el < n_st; el += blockDim.x) {
+    for (int el = blockIdx.z * blockDim.x + threadIdx.x; el < n_st; el += blockDim.x * gridDim.z) {
       double sum = 0.0;
       for (int pp = 0; pp < P; ++pp)
         sum += partial[((size_t)jid * P + pp) * (size_t)(3 * GT * GT) + (size_t)qd * GT * GT + el];
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
   const bool strips = J.kind == JOB_DIAG;
   if (qd == 2 && J.kind != JOB_OFF && !strips) return;
   const int n_el = (qd == 2 && strips) ? 3 * NAUX * GT : GT * GT;
-  for (int el = threadIdx.x; el < n_el; el += blockDim.x) {
+  for (int el = blockIdx.z * blockDim.x + threadIdx.x; el < n_el; el += blockDim.x * gridDim.z) {
     double sum = 0.0;
     for (int pp = 0; pp < P; ++pp)
       sum += partial[((size_t)jid * P + pp) * (size_t)(3 * GT * GT) + (size_t)qd * GT * GT + el];
@@ -529,7 +529,10 @@ void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* 
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
                         int strip_rows, hipStream_t st) {
   if (n_jobs <= 0) return;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(n_jobs, 3), dim3(256), 0, st, d_jobs, P, d_partial,
+  // the elements of a tile split over gridDim.z when there are many slice
+  // groups to sum (each element is still summed by one thread, in order)
+  const int z = std::min(16, std::max(1, P / 8));
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(n_jobs, 3, z), dim3(256), 0, st, d_jobs, P, d_partial,
                      s_base, h_base, strip_base, strip_ld, strip_rows);
 }
 
