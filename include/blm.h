@@ -281,6 +281,32 @@ blm_status blm_get_stage2_matrices(blm_ctx* ctx, int32_t shift, double* h_H2, do
 blm_status blm_debug_eigvals(const double* d_H, const double* d_S, int32_t d, double* h_evals,
                              void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * eigenvalues as blm_debug_eigvals (same kernels, same order, bit for bit)
+ * of a dense pencil H c = lambda S c with S symmetric positive definite,
+ * without any device allocation: the solver's scratch (one pencil's
+ * workspace, about 12.8 MB) is a static device array of the library, one
+ * copy per device, held until the process ends.
+ *   d_H, d_S   device [d][d] row-major, caller-owned, read only
+ *   d          1 <= d <= BLM_STATIC_MAXD, else BLM_E_ARG (nothing runs)
+ *   d_evals    device [d][2] (re, im) in the solver's order; NaN on failure
+ *   d_status   device int32: the solve's blm_status (BLM_OK, BLM_E_S_NOT_PD,
+ *              BLM_E_NONFINITE or BLM_E_NOCONV), written by the last kernel
+ *   stream     hipStream_t of the device current at the call (NULL = null stream)
+ * Asynchronous: returns after enqueueing three kernel launches (no copies,
+ * no memsets, no synchronisation); the return value reports only argument
+ * and launch errors.  The first call on a device resolves the scratch
+ * array's device address there (hipGetSymbolAddress, with that device
+ * current); a caller that captures graphs should make that first call
+ * before capturing.  Every call on a device shares its scratch, and the
+ * scratch keeps the last call's contents: calls that overlap on one device
+ * (on different streams, or replayed graphs in flight together) race, so
+ * serialise them on one stream. */
+#define BLM_STATIC_MAXD 512
+blm_status blm_pencil_eigvals_static(const double* d_H, const double* d_S, int32_t d, double* d_evals,
+                                     int32_t* d_status, void* stream);
+
 /* Per-phase timing with HIP events recorded on the context's stream
  * (off by default).  blm_get_timings synchronises the stream and writes, for
  * the most recent call of each kind, up to n of these durations in ms:

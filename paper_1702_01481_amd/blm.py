@@ -27,7 +27,7 @@ EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_create"
             "blm_build_blocks", "blm_autotune_build", "blm_capture_build", "blm_replay_build",
             "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
-            "blm_debug_eigvals", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
+            "blm_debug_eigvals", "blm_pencil_eigvals_static", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
             "blm_batch_create", "blm_batch_destroy", "blm_batch_solve_blocks", "blm_batch_stage2",
             "blm_last_error",
             "blm_status_string")
@@ -84,6 +84,7 @@ def load() -> C.CDLL:
     lib.blm_get_directions.argtypes = [vp, i32, i32, dp, C.POINTER(i32)]
     lib.blm_get_stage2_matrices.argtypes = [vp, i32, dp, dp, C.POINTER(i32)]
     lib.blm_debug_eigvals.argtypes = [vp, vp, i32, dp, vp]
+    lib.blm_pencil_eigvals_static.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.blm_get_solver_stats.argtypes = [vp, C.POINTER(i32), i32]
     lib.blm_set_timing.argtypes = [vp, i32]
     lib.blm_get_timings.argtypes = [vp, dp, i32]
@@ -465,3 +466,30 @@ def debug_eigvals(H: torch.Tensor, S: torch.Tensor, stream=None) -> np.ndarray:
     if st != BLM_OK:
         raise BLMError(st, lib.blm_status_string(st).decode())
     return out[:, 0] + 1j * out[:, 1]
+
+
+STATIC_MAXD = 512   # BLM_STATIC_MAXD
+
+
+def pencil_eigvals_static(H: torch.Tensor, S: torch.Tensor, evals: torch.Tensor, status: torch.Tensor,
+                          stream=None) -> None:
+    """blm_pencil_eigvals_static: the eigenvalues of debug_eigvals into the
+    caller's device tensors evals (float64 [d][2]) and status (int32 [1]),
+    with no device allocation by the library.  Asynchronous on the stream."""
+    lib = load()
+    _check_f64_dev(H, "H")
+    _check_f64_dev(S, "S")
+    _check_f64_dev(evals, "evals")
+    d = int(H.shape[0])
+    for t, name in ((H, "H"), (S, "S")):
+        if t.dim() != 2 or tuple(t.shape) != (d, d) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous [d][d] tensor")
+    if tuple(evals.shape) != (d, 2) or not evals.is_contiguous():
+        raise ValueError("evals must be a contiguous [d][2] tensor")
+    if status.dtype != torch.int32 or not status.is_cuda or status.numel() < 1:
+        raise TypeError("status must be an int32 device tensor")
+    st = lib.blm_pencil_eigvals_static(C.c_void_p(H.data_ptr()), C.c_void_p(S.data_ptr()), d,
+                                       C.c_void_p(evals.data_ptr()), C.c_void_p(status.data_ptr()),
+                                       C.c_void_p(_stream_handle(stream)))
+    if st != BLM_OK:
+        raise BLMError(st, lib.blm_status_string(st).decode())

@@ -85,3 +85,17 @@ def test_recorded_build_keeps_its_chunks():
     assert len(o._keep) == 1 and o._keep[0] is old
     blm.BLM.drop_chunk_refs(o)
     assert o._graph_keep and len(o._keep) == 1 and o._keep[0] is old
+
+
+def test_static_eigvals_rejects_sizes_beyond_its_scratch():
+    """blm_pencil_eigvals_static checks its arguments on the host before any
+    device call: a pencil above BLM_STATIC_MAXD, or d < 1, or a missing
+    pointer is BLM_E_ARG (no GPU needed)."""
+    if not os.path.exists(blm.LIB_PATH):
+        pytest.skip("libblm.so not built")
+    lib = blm.load()
+    fake = ctypes.c_void_p(256)      # never dereferenced: the size check comes first
+    assert lib.blm_pencil_eigvals_static(fake, fake, blm.STATIC_MAXD + 1, fake, fake, None) == 1
+    assert lib.blm_pencil_eigvals_static(fake, fake, 0, fake, fake, None) == 1
+    assert lib.blm_pencil_eigvals_static(None, fake, 8, fake, fake, None) == 1
+    assert lib.blm_pencil_eigvals_static(fake, fake, 8, fake, None, None) == 1
