@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of one blocked-linear-method step on one MI355X.
 
-Workload (FP64): N_V = 4,096 parameters in 8 blocks of 512, N_s = 1,000,000
-samples in 65,536-sample chunks (15 full + a 16,960 tail), low-rank synthetic
-derivative ratios (rank 32), N_K = 5 kept directions per block, N_O = 1
-previous-update direction, shifts {1e-4, 1e-3, 1e-2} solved together.
+Default workload (the 30,000-parameter target): N_V = 30,000 parameters in
+40 uneven blocks (log-uniform sizes in [100, 2,000], rescaled), N_s =
+4,000,000 samples in 65,536-sample chunks, rank-32 synthetic derivative
+ratios with a banded G, N_K = 4, N_O = 0, shift 1e-3.  FP64 for the
+headline (--steps, --warmup), then the same step with BF16 x3 split and FP8
+storage (--mixed, --mixed-steps, --mixed-warmup), compared with the FP64
+step.  The samples (1.9 TB as FP64) cannot all be resident, so they are
+made on the device chunk by chunk on a second stream while the library
+works (see target_bench); a step's time counts the library's calls only.
 
-A step is: begin_step (previous direction) -> build over all chunks ->
-block solves -> projection over all chunks -> stage two.  The sample chunks
-are generated on the device before timing and stay resident in HBM.  The
-previous direction is the update of one untimed step without history on the
-same data (shift 1e-3).
+--workload fp64: the 4,096-parameter workload (8 blocks of 512, 1,000,000
+samples, all resident in HBM, N_K = 5, N_O = 1, shifts {1e-4, 1e-3, 1e-2}).
 
-Prints one JSON line.  Value: build FLOP (the algorithmic count
-2 N_s sum_b [d_b^2 + d_b (d_b + 1)/2], d_b = 1 + M_b + N_O (N_B - 1)) per
-second of whole step time.
+A step is: begin_step -> build over all chunks -> block solves -> projection
+over all chunks -> stage two.  Prints one JSON line.  Value: build FLOP (the
+algorithmic count 2 N_s sum_b [d_b^2 + d_b (d_b + 1)/2], d_b = 1 + M_b +
+N_O (N_B - 1)) per second of whole step time.
 """
 from __future__ import annotations
 
@@ -26,50 +29,21 @@ import time
 
 import numpy as np
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "block H/S build TFLOP/s + BLM step ms; mixed vs FP64 at ≤1e-6 rel energy err"
 PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 (matrix and vector)
+PEAK_BF16 = 2500.0    # TFLOP/s, MI355X dense BF16 matrix
+PEAK_FP8 = 5000.0     # TFLOP/s, MI355X dense FP8 matrix
 
-# HBM bytes of one FP64 block-build launch on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
-# counter reads for a plain 2 GiB copy (FETCH x2, WRITE x1).  Valid only for
-# the kernel source they were taken on: reported as null once the source of
-# the sample-streaming kernels has changed.
-GRAM_TRAFFIC = {
-    "source_sha256": "efb1445a42c5dedbd4054a361353706c5d16088e674403c757e64cff90ba5875",
-    "fetch_scale": 1.99996, "write_scale": 1.0,
-    # slice groups per tile -> (FETCH_SIZE, WRITE_SIZE) KiB per launch
-    "by_groups": {1: (105566351.0, 27200.0), 2: (230332281.0, 54400.0), 3: (229755819.0, 81600.0),
-                  4: (233044943.0, 108800.0), 6: (231931632.0, 163200.0), 8: (232274965.0, 217600.0),
-                  12: (231207027.0, 326400.0), 15: (230408402.0, 408000.0)},
+# Mixed builds against the matrix-core peak of what they execute: the
+# algorithmic-flop rate at which the executed piece products would run at
+# their datatypes' peaks (BF16 x3: 6 BF16 products per algorithmic product;
+# BF16 x2: 3; FP8: one FP8 code product and three BF16 residual products).
+MIXED_PEAK = {
+    "bf16x3": (PEAK_BF16 / 6, "6 BF16 products per product (2.5 PFLOP/s each)"),
+    "bf16x2": (PEAK_BF16 / 3, "3 BF16 products per product"),
+    "fp8": (1.0 / (1.0 / PEAK_FP8 + 3.0 / PEAK_BF16), "1 FP8 (5.0 PFLOP/s) + 3 BF16 products per product"),
 }
-
-
-def gram_source_digest():
-    """SHA-256 of the Gram-tile section of the FP64 kernel source (from its
-    section header to the projection's): the counters below were taken on
-    that code, and are reported only while it is unchanged."""
-    import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1702_01481_amd", "csrc",
-                       "blm_kernels.hip")
-    try:
-        text = open(src).read()
-        a = text.index("// Gram tiles")
-        b = text.index("// projection onto per-block directions")
-    except (OSError, ValueError):
-        return None
-    return hashlib.sha256(text[a:b].encode()).hexdigest()
-
-
-def gram_traffic_bytes(groups):
-    """HBM bytes of one FP64 block-build launch with this many slice groups,
-    from the rocprofv3 counters taken on the same Gram-tile source; None if
-    the source has changed or the counters do not cover that launch shape."""
-    t = GRAM_TRAFFIC
-    if gram_source_digest() != t["source_sha256"] or groups not in t["by_groups"]:
-        return None
-    fetch, write = t["by_groups"][groups]
-    return 1024.0 * (fetch * t["fetch_scale"] + write * t["write_scale"])
-
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -185,146 +159,301 @@ def mixed_step(args, prec, w, chunks, old, offsets, shifts, n_samples, en64, upd
     }
 
 
-def streamed_target(args):
-    """The 30,000-parameter workload (40 uneven blocks, N_O = 0, delta = 1e-3)
-    at its full 4,000,000 samples, whose samples (1.9 TB as FP64) do not fit
-    in HBM: each 65,536-sample chunk is made on the device, handed to an FP64,
-    a BF16 x3 and an FP8 context in turn (the mixed storage packed from it
-    first) and dropped; the second pass makes the same chunks again.  Only
-    the library calls are timed, with events on the shared stream: the
-    generator and the producer-side packing are not part of the step."""
+class Feeder:
+    """Chunk source of one precision: chunk i is made on the device (and
+    packed to the leg's storage) on the library's stream, just before the
+    library call that reads it, so that no generator work runs beside a
+    timed call."""
+
+    def __init__(self, gen, prec, chunk, n_params):
+        import torch
+
+        from paper_1702_01481_amd import blm
+        f64 = torch.float64
+        self.gen, self.prec = gen, prec
+        self.O = torch.empty(chunk, n_params, dtype=f64, device="cuda")
+        self.e = torch.empty(chunk, n_params, dtype=f64, device="cuda")
+        self.EL = torch.empty(chunk, dtype=f64, device="cuda")
+        if prec == "fp64":
+            self.sO = self.se = None
+        elif prec == "fp8":
+            self.sO = blm.Fp8Samples.empty(chunk, n_params)
+            self.se = blm.Fp8Samples.empty(chunk, n_params)
+        else:
+            pieces = 3 if prec == "bf16x3" else 2
+            self.sO = blm.SplitSamples.empty(chunk, n_params, pieces)
+            self.se = blm.SplitSamples.empty(chunk, n_params, pieces)
+        torch.cuda.synchronize()
+
+    def make(self, index, n):
+        """Chunk `index` (n samples) in the leg's storage, ready on the stream."""
+        self.gen.chunk(index, n, out_O=self.O[:n], out_e=self.e[:n], out_EL=self.EL[:n])
+        if self.sO is not None:
+            self.sO.pack(self.O[:n])
+            self.se.pack(self.e[:n])
+            return (self.sO, self.se, self.EL[:n])
+        return (self.O[:n], self.e[:n], self.EL[:n])
+
+
+def chunk_flops(offsets, n_old, n):
+    return build_flops(offsets, n_old, n)
+
+
+def target_leg(args, prec, w, sizes, gen, steps, warmup):
+    """Warm-up and timed steps of one precision on the streamed workload.
+    Returns the leg's record (times from HIP events on the library's stream)
+    and the last step's update."""
     import torch
 
-    from paper_1702_01481_amd import blm, synth
-    w = synth.workload("uneven")
-    n_samples = args.streamed_samples or w.n_samples
+    from paper_1702_01481_amd import blm
     offsets, shifts = w.block_offsets, list(w.shifts)
-    gen = synth.SampleGenerator(w.n_params, w.rank, w.seed, sigma_E=w.sigma_E, device="cuda")
-    sizes, left = [], n_samples
-    while left > 0:
-        sizes.append(min(w.chunk, left))
-        left -= sizes[-1]
-    precs = ("fp64", "bf16x3", "fp8")
-    ctxs = {p: blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.chunk, precision=p) for p in precs}
-    ms = {p: {"build": 0.0, "solve": 0.0, "project": 0.0, "stage2": 0.0} for p in precs}
     st = torch.cuda.current_stream()
-    pending = []
+    feeder = Feeder(gen, prec, w.chunk, w.n_params)
+    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.chunk, stream=st, precision=prec)
+    ctx.set_timing(True)
+    groups = None
+    if not args.no_autotune:
+        ch = feeder.make(0, sizes[0])
+        ctx.begin_step()
+        groups = ctx.autotune([ch])
+        torch.cuda.synchronize()
+        log(f"{prec}: build autotuned on chunk 0: {groups} slice groups per tile")
 
-    def timed(p, phase, fn):
+    def timed(fn):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(st)
         r = fn()
         b.record(st)
-        pending.append((p, phase, a, b))
-        return r
+        return r, (a, b)
 
-    def settle():
-        torch.cuda.synchronize()
-        for p, phase, a, b in pending:
-            ms[p][phase] += a.elapsed_time(b)
-        pending.clear()
-        for c in ctxs.values():
-            c.drop_chunk_refs()
-
-    def stored(p, O, e, EL):
-        if p == "fp64":
-            return (O, e, EL)
-        if p == "bf16x3":
-            return (blm.SplitSamples(O, 3), blm.SplitSamples(e, 3), EL)
-        return (blm.Fp8Samples(O), blm.Fp8Samples(e), EL)
-
-    t_start = time.perf_counter()
-    t_gen = 0.0
-    for c in ctxs.values():
-        c.begin_step()
-    groups = {}
-    if not args.no_autotune:
-        # launch shape of each context's build, timed on the first chunk
-        O, e, EL = gen.chunk(0, sizes[0])
-        for p in precs:
-            groups[p] = ctxs[p].autotune([stored(p, O, e, EL)])
-            torch.cuda.synchronize()
-            ctxs[p].drop_chunk_refs()
-        del O, e, EL
-        log(f"streamed: slice groups per tile {groups}")
-    out = {}
-    for pas in (1, 2):
-        for i, n in enumerate(sizes):
-            t0 = time.perf_counter()
-            O, e, EL = gen.chunk(i, n)
-            torch.cuda.synchronize()
-            t_gen += time.perf_counter() - t0
-            for p in precs:
-                ch = [stored(p, O, e, EL)]
+    steps_out = []
+    for step in range(warmup + steps):
+        evs = {"build": [], "solve": [], "project": [], "stage2": []}
+        gram = []
+        w0 = time.perf_counter()
+        ctx.begin_step()
+        for pas in (1, 2):
+            for i, n in enumerate(sizes):
+                ch = feeder.make(i, n)
                 if pas == 1:
-                    timed(p, "build", lambda: ctxs[p].build(ch))
+                    _, ev = timed(lambda: ctx.build([ch]))
+                    evs["build"].append(ev)
+                    tm = ctx.timings()          # synchronises the stream
+                    gram.append((n, tm["block_gram"]))
                 else:
-                    timed(p, "project", lambda: ctxs[p].project(ch))
-                del ch
-            del O, e, EL
-            settle()
-            log(f"streamed pass {pas}: chunk {i + 1}/{len(sizes)}")
-        for p in precs:
-            t0 = time.perf_counter()
+                    _, ev = timed(lambda: ctx.project([ch]))
+                    evs["project"].append(ev)
+                ctx.drop_chunk_refs()      # the feeder's buffers outlive the step
             if pas == 1:
-                ctxs[p].solve()
+                _, ev = timed(ctx.solve)
+                evs["solve"].append(ev)
+                eig_ms = ctx.timings()["block_eig"]
             else:
-                out[p] = ctxs[p].stage2()
-            torch.cuda.synchronize()
-            ms[p]["solve" if pas == 1 else "stage2"] += 1e3 * (time.perf_counter() - t0)
-            log(f"streamed pass {pas}: {p} {'block solves' if pas == 1 else 'stage two'} done")
+                (upd, en, al, fl), ev = timed(ctx.stage2)
+                evs["stage2"].append(ev)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        phase = {k: sum(x.elapsed_time(y) for x, y in v) for k, v in evs.items()}
+        rec = {"ms": sum(phase.values()), "phase_ms": phase, "wall_s": wall, "gram": gram, "eig_ms": eig_ms,
+               "energy": [float(x) for x in en], "flags": [int(x) for x in fl]}
+        steps_out.append(rec)
+        kind = "warm-up" if step < warmup else "timed"
+        log(f"{prec} {kind} step {step + 1 if step < warmup else step + 1 - warmup}: {rec['ms']:.0f} ms in the "
+            f"library ({', '.join(f'{k} {v:.0f}' for k, v in phase.items())}), {wall:.1f} s wall, "
+            f"energy {rec['energy']}")
+    timed_steps = steps_out[warmup:]
+    upd_last = upd.double().cpu().numpy()
+    stats = ctx.solver_stats()
+    out = {"precision": prec, "steps": steps, "warmup": warmup, "build_slice_groups": groups}
+    out["ms_per_step"] = float(np.mean([r["ms"] for r in timed_steps]))
+    out["wall_s_per_step"] = float(np.mean([r["wall_s"] for r in timed_steps]))
+    out["phase_ms"] = {k: round(float(np.mean([r["phase_ms"][k] for r in timed_steps])), 3)
+                       for k in timed_steps[0]["phase_ms"]}
+    # the build's Gram kernel: algorithmic flops of every launch over its event-timed duration
+    fl_l = sum(build_flops(offsets, w.n_old, n) for r in timed_steps for n, _ in r["gram"])
+    ms_l = sum(g for r in timed_steps for _, g in r["gram"])
+    out["gram_launches"] = sum(len(r["gram"]) for r in timed_steps)
+    out["gram_ms_per_launch"] = ms_l / out["gram_launches"]
+    out["gram_tflops"] = fl_l / (ms_l * 1e-3) / 1e12
+    out["block_eig_ms"] = float(np.mean([r["eig_ms"] for r in timed_steps]))
+    names = ("cholesky", "congruence", "hessenberg", "qr", "select", "inverse_iter", "back_transform",
+             "orthonormalise")
+    out["block_eig_phase_ms_max"] = {k: round(float(stats[:, 4 + i].max()) / 1e5, 3) for i, k in enumerate(names)}
+    out["energy"] = timed_steps[-1]["energy"]
+    out["flags"] = timed_steps[-1]["flags"]
+    ctx.close()
+    del feeder
+    torch.cuda.empty_cache()
+    return out, upd_last
+
+
+def target_cpu_baseline(w, gen, n_rows):
+    """The oracle as it stands on the host cores, on a bounded sample of the
+    30,000-parameter workload: the 40 block estimates from the first n_rows
+    samples of chunk 0 (scaled to TFLOP/s), then the 40 block solves of
+    those estimates."""
+    import torch
+    from threadpoolctl import threadpool_info
+
+    from oracle import blm_oracle as orc
+    O, e, EL = gen.chunk(0, n_rows)
+    torch.cuda.synchronize()
+    O, e, EL = O.cpu().numpy(), e.cpu().numpy(), EL.cpu().numpy()
+    offsets = np.asarray(w.block_offsets)
+    t0 = time.perf_counter()
+    D = orc.previous_directions(None, offsets)
+    probs, _ = orc.block_problems([(O, e, EL, None)], offsets, D)
+    t_build = time.perf_counter() - t0
+    del O, e
+    t0 = time.perf_counter()
+    for p in probs:
+        orc.solve_block(p, w.shifts[0], w.n_keep)
+    t_solve = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": build_flops(offsets, 0, n_rows) / t_build / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"block estimates of all {w.n_blocks} blocks from the first {n_rows} samples at full N_V "
+                       f"({t_build:.2f} s), plus the {w.n_blocks} block solves of those estimates "
+                       f"({t_solve:.2f} s); host nproc={os.cpu_count()}")}
+
+
+def profile_traffic(kernel_key):
+    """HBM bytes per launch of a build kernel on this workload, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/ (a JSON block
+    there), or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_hbm.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        src = open(os.path.join(ROOT, rec["source"])).read()
+    except (OSError, AttributeError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src.encode()).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec
+
+
+def target_bench(args):
+    """The 30,000-parameter workload: 40 uneven blocks, 4,000,000 samples in
+    65,536-sample chunks, N_K = 4, delta = 1e-3.  Its samples (1.9 TB as
+    FP64) cannot all sit in HBM, so each pass makes them on the device chunk
+    by chunk, on the library's stream, just before the call that reads them
+    (the generator is counter-based: pass 2 sees the same bytes).  A step's
+    time is the sum of the HIP-event durations of its library calls: every
+    call starts with its samples resident in HBM, and no generator work runs
+    beside it."""
+    import torch
+
+    from paper_1702_01481_amd import synth
+    w = synth.workload("uneven")
+    n_samples = args.samples or w.n_samples
+    sizes, left = [], n_samples
+    while left > 0:
+        sizes.append(min(w.chunk, left))
+        left -= sizes[-1]
+    offsets = w.block_offsets
+    gen = w.generator("cuda")
+    torch.cuda.synchronize()
     fl = build_flops(offsets, w.n_old, n_samples)
-    res = {"workload": w.name if n_samples == w.n_samples else f"uneven_30000x{n_samples}",
-           "n_params": w.n_params, "n_blocks": w.n_blocks, "n_samples": n_samples, "chunk": w.chunk,
-           "n_keep": w.n_keep, "n_old": w.n_old, "shifts": shifts, "data": "synthetic, made on the device per chunk",
-           "build_flops": fl, "precisions": {}}
-    u64, e64 = out["fp64"][0].double().cpu().numpy(), out["fp64"][1]
-    mats64 = [ctxs["fp64"].block_matrices(b, 0) for b in range(w.n_blocks)]
-    step64 = sum(ms["fp64"].values())
-    for p in precs:
-        step = sum(ms[p].values())
-        upd, en = out[p][0].double().cpu().numpy(), out[p][1]
-        r = {"step_ms": round(step, 1), "phase_ms": {k: round(v, 1) for k, v in ms[p].items()},
-             "build_slice_groups": groups.get(p),
-             "build_tflops": round(fl / (ms[p]["build"] * 1e-3) / 1e12, 2), "energy": [float(x) for x in en]}
-        if p != "fp64":
-            worst = 0.0
-            for b in range(w.n_blocks):
-                H, S = ctxs[p].block_matrices(b, 0)
-                H6, S6 = mats64[b]
-                worst = max(worst, np.linalg.norm(S - S6) / np.linalg.norm(S6),
-                            np.linalg.norm(H - H6) / np.linalg.norm(H6))
-            r["block_matrix_rel_err_vs_fp64"] = worst
-            r["energy_rel_err_vs_fp64"] = [float(abs(en[i] - e64[i]) / abs(e64[i])) for i in range(len(shifts))]
-            r["update_cosine_vs_fp64"] = [float(u64[i] @ upd[i] / (np.linalg.norm(u64[i]) * np.linalg.norm(upd[i])))
-                                          for i in range(len(shifts))]
-            r["step_speedup_vs_fp64"] = round(step64 / step, 3)
-            r["build_speedup_vs_fp64"] = round(ms["fp64"]["build"] / ms[p]["build"], 3)
-        res["precisions"][p] = r
-    res["generator_s"] = round(t_gen, 1)
-    res["wall_s"] = round(time.perf_counter() - t_start, 1)
-    for c in ctxs.values():
-        c.close()
-    print(json.dumps(res))
+    fl_chunk = build_flops(offsets, w.n_old, w.chunk)
+    log(f"target workload: {w.n_params} parameters in {w.n_blocks} blocks, {n_samples} samples in {len(sizes)} "
+        f"chunks; {fl / 1e12:.1f} TFLOP of build per step")
+    res64, upd64 = target_leg(args, "fp64", w, sizes, gen, args.steps, args.warmup)
+    ms = res64["ms_per_step"]
+    build_ms = res64["phase_ms"]["build"]
+    tr = profile_traffic("gram_kernel_fp64_uneven_30000x4M")
+    out = {
+        "metric": METRIC,
+        "value": round(fl / (ms * 1e-3) / 1e12, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": f"synthetic, made on the device chunk by chunk (banded G, half-bandwidth {w.band})",
+        "config": {"workload": w.name if n_samples == w.n_samples else f"uneven_30000x{n_samples}",
+                   "n_params": w.n_params, "n_blocks": w.n_blocks, "n_samples": n_samples, "chunk": w.chunk,
+                   "rank": w.rank, "n_keep": w.n_keep, "n_old": w.n_old, "shifts": list(w.shifts),
+                   "g_half_bandwidth": w.band, "precision": "fp64"},
+        "timing": ("ms_per_step: sum of the HIP-event durations of a step's library calls (one build and one "
+                   "projection per chunk, the block solves, stage two); the generator runs between the calls on "
+                   "the same stream and is not included (wall_s_per_step includes it)"),
+        "wall_s_per_step": round(res64["wall_s_per_step"], 3),
+        "build_ms": round(build_ms, 3),
+        "build_tflops": round(fl / (build_ms * 1e-3) / 1e12, 4),
+        "build_slice_groups": res64["build_slice_groups"],
+        "phase_ms": res64["phase_ms"],
+        "block_eig_phase_ms_max": res64["block_eig_phase_ms_max"],
+        "energy": res64["energy"],
+        "flags": res64["flags"],
+        "roofline": {"bound": "mfma", "achieved": round(res64["gram_tflops"], 4), "peak": PEAK_FP64,
+                     "unit": "TFLOP/s", "frac": round(res64["gram_tflops"] / PEAK_FP64, 4),
+                     "traffic": (tr["bytes_per_launch"] if tr else None),
+                     "kernel": "gram_kernel (block H/S build, FP64 MFMA 16x16x4)",
+                     "flops_per_launch": fl_chunk,
+                     "launch_ms": round(res64["gram_ms_per_launch"], 3),
+                     "launches": res64["gram_launches"]},
+    }
+    if args.mixed != "none":
+        out["mixed"] = []
+        for prec in args.mixed.split(","):
+            if prec not in ("bf16x3", "bf16x2", "fp8"):
+                raise SystemExit(f"unknown mixed precision {prec}")
+            r, upd = target_leg(args, prec, w, sizes, gen, args.mixed_steps, args.mixed_warmup)
+            rel = [float(abs(a - b) / abs(b)) for a, b in zip(r["energy"], res64["energy"])]
+            cos = [float(upd[i] @ upd64[i] / (np.linalg.norm(upd[i]) * np.linalg.norm(upd64[i])))
+                   for i in range(len(rel))]
+            peak_alg, executed = MIXED_PEAK[prec]
+            tr = profile_traffic(f"gram_{prec}_uneven_30000x4M")
+            leg = {"precision": prec, "steps": r["steps"], "warmup": r["warmup"],
+                   "ms_per_step": round(r["ms_per_step"], 3), "wall_s_per_step": round(r["wall_s_per_step"], 3),
+                   "build_ms": r["phase_ms"]["build"],
+                   "build_tflops": round(fl / (r["phase_ms"]["build"] * 1e-3) / 1e12, 4),
+                   "build_slice_groups": r["build_slice_groups"], "phase_ms": r["phase_ms"],
+                   "roofline": {"bound": "mfma", "achieved": round(r["gram_tflops"], 4),
+                                "peak": peak_alg, "unit": "TFLOP/s (algorithmic)",
+                                "frac": round(r["gram_tflops"] / peak_alg, 4),
+                                "executed": executed,
+                                "traffic": (tr["bytes_per_launch"] if tr else None),
+                                "launch_ms": round(r["gram_ms_per_launch"], 3)},
+                   "energy_rel_err_vs_fp64": rel, "update_cosine_vs_fp64": cos,
+                   "step_speedup_vs_fp64": round(ms / r["ms_per_step"], 3),
+                   "build_speedup_vs_fp64": round(build_ms / r["phase_ms"]["build"], 3),
+                   "meets_1e-6": bool(max(rel) <= 1e-6 and min(cos) >= 0.9999)}
+            log(f"{prec}: step {r['ms_per_step']:.0f} ms, energy rel err {rel}, cosine {cos}")
+            out["mixed"].append(leg)
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = target_cpu_baseline(w, gen, args.cpu_rows)
+    print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--workload", default="uneven", choices=("uneven", "fp64"),
+                    help="uneven: the 30,000-parameter, 4M-sample target (streamed); fp64: 4,096 parameters, "
+                         "1M samples resident")
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--samples", type=int, default=1_000_000)
+    ap.add_argument("--samples", type=int, default=0, help="fewer samples than the workload's")
+    ap.add_argument("--mixed-steps", type=int, default=2, help="timed steps of each mixed leg (uneven)")
+    ap.add_argument("--mixed-warmup", type=int, default=1, help="warm-up steps of each mixed leg (uneven)")
+    ap.add_argument("--cpu-rows", type=int, default=16_384,
+                    help="samples of the oracle's timed block estimates (uneven)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the heuristic slice-group count of the build instead of timing the candidates")
     ap.add_argument("--mixed", default="bf16x3,fp8",
                     help="comma-separated mixed precisions (bf16x3, bf16x2, fp8) also run on the same "
                          "samples, or none")
-    ap.add_argument("--streamed", action="store_true",
-                    help="instead: one step of the 30,000-parameter, 4M-sample workload in FP64, BF16x3 "
-                         "and FP8, its chunks made on the device as they are needed")
-    ap.add_argument("--streamed-samples", type=int, default=0,
-                    help="with --streamed: fewer samples than the workload's 4,000,000")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy three times (the reference "
                          "for scaling HBM byte counters)")
@@ -351,10 +480,10 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
-    if args.streamed:
-        return streamed_target(args)
+    if args.workload == "uneven":
+        return target_bench(args)
     w = synth.workload("fp64")
-    n_samples = args.samples
+    n_samples = args.samples or w.n_samples
     offsets = w.block_offsets
     shifts = list(w.shifts)
     dev = torch.device("cuda")
@@ -465,7 +594,8 @@ def main():
         "flags": [int(x) for x in fl],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
-                     "traffic": gram_traffic_bytes(groups),
+                     "traffic": (lambda r: r["bytes_per_launch"] if r else None)(
+                         profile_traffic("gram_kernel_fp64_4096x1M")),
                      "kernel": "gram_kernel (block H/S build, FP64 MFMA 16x16x4)",
                      "flops_per_launch": fl_build},
     }

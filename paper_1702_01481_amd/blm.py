@@ -125,27 +125,48 @@ class SplitSamples:
 
     def __init__(self, src: torch.Tensor, pieces: int = 3, ncols: Optional[int] = None, stream=None):
         _check_f64_dev(src, "src")
-        if src.dim() != 2 or src.stride(1) != 1:
-            raise ValueError("src must be [n][ld] with unit column stride")
-        self.n = int(src.shape[0])
-        self.ncols = int(ncols if ncols is not None else src.shape[1])
+        self._alloc(int(src.shape[0]), int(ncols if ncols is not None else src.shape[1]), pieces, src.device)
+        self.pack(src, stream)
+
+    def _alloc(self, n_max: int, ncols: int, pieces: int, device):
+        self.n = self.n_max = n_max
+        self.ncols = ncols
         self.ld = self.ncols + (self.ncols & 1)
         self.pieces = int(pieces)
-        n8 = (self.n + 7) // 8
+        n8 = (self.n_max + 7) // 8
         self.piece_stride = n8 * 8 * self.ld
-        self.data = torch.empty(self.pieces * self.piece_stride, dtype=torch.int16, device=src.device)
-        st = load().blm_pack_bf16(C.c_void_p(src.data_ptr()), self.n, src.stride(0) if self.n else self.ncols,
+        self.data = torch.empty(self.pieces * self.piece_stride, dtype=torch.int16, device=device)
+
+    @classmethod
+    def empty(cls, n_max: int, ncols: int, pieces: int = 3, device="cuda") -> "SplitSamples":
+        """Storage for up to n_max samples, filled later by pack()."""
+        obj = cls.__new__(cls)
+        obj._alloc(int(n_max), int(ncols), pieces, torch.device(device))
+        return obj
+
+    def pack(self, src: torch.Tensor, stream=None):
+        """Refills the storage from FP64 samples src [n <= n_max][>= ncols]
+        (asynchronous on the stream)."""
+        _check_f64_dev(src, "src")
+        if src.dim() != 2 or src.stride(1) != 1:
+            raise ValueError("src must be [n][ld] with unit column stride")
+        n = int(src.shape[0])
+        if n > self.n_max or src.shape[1] < self.ncols:
+            raise ValueError("src does not fit the storage")
+        self.n = n
+        st = load().blm_pack_bf16(C.c_void_p(src.data_ptr()), n, src.stride(0) if n else self.ncols,
                                   self.ncols, self.pieces, C.c_void_p(self.data.data_ptr()), self.ld,
                                   self.piece_stride, C.c_void_p(_stream_handle(stream)))
         if st != BLM_OK:
             raise BLMError(st, "blm_pack_bf16 failed")
+        return self
 
     def to_numpy(self) -> np.ndarray:
         """Host copy of the pieces' sum (for checks): [n][ncols] float64."""
         raw = self.data.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
         pcs = raw.view(np.float32).astype(np.float64).reshape(self.pieces, -1)
         tot = pcs.sum(axis=0)
-        n8 = (self.n + 7) // 8
+        n8 = self.piece_stride // (8 * self.ld)
         arr = tot.reshape(n8, self.ld, 8).transpose(0, 2, 1).reshape(n8 * 8, self.ld)
         return arr[: self.n, : self.ncols]
 
@@ -157,24 +178,45 @@ class Fp8Samples:
 
     def __init__(self, src: torch.Tensor, ncols: Optional[int] = None, stream=None):
         _check_f64_dev(src, "src")
+        self._alloc(int(src.shape[0]), int(ncols if ncols is not None else src.shape[1]), src.device)
+        self.pack(src, stream)
+
+    def _alloc(self, n_max: int, ncols: int, device):
+        self.n = self.n_max = n_max
+        self.ncols = ncols
+        self.ld = self.ncols
+        n16, n8 = (self.n_max + 15) // 16, (self.n_max + 7) // 8
+        self.codes = torch.empty(n16 * 16 * self.ld, dtype=torch.uint8, device=device)
+        self.res = torch.empty(n8 * 8 * self.ld, dtype=torch.int16, device=device)
+        self.scale = torch.empty(self.ld, dtype=torch.float32, device=device)
+
+    @classmethod
+    def empty(cls, n_max: int, ncols: int, device="cuda") -> "Fp8Samples":
+        """Storage for up to n_max samples, filled later by pack()."""
+        obj = cls.__new__(cls)
+        obj._alloc(int(n_max), int(ncols), torch.device(device))
+        return obj
+
+    def pack(self, src: torch.Tensor, stream=None):
+        """Refills the storage from FP64 samples src [n <= n_max][>= ncols]
+        (asynchronous on the stream)."""
+        _check_f64_dev(src, "src")
         if src.dim() != 2 or src.stride(1) != 1:
             raise ValueError("src must be [n][ld] with unit column stride")
-        self.n = int(src.shape[0])
-        self.ncols = int(ncols if ncols is not None else src.shape[1])
-        self.ld = self.ncols
-        n16, n8 = (self.n + 15) // 16, (self.n + 7) // 8
-        self.codes = torch.empty(n16 * 16 * self.ld, dtype=torch.uint8, device=src.device)
-        self.res = torch.empty(n8 * 8 * self.ld, dtype=torch.int16, device=src.device)
-        self.scale = torch.empty(self.ld, dtype=torch.float32, device=src.device)
-        st = load().blm_pack_fp8(C.c_void_p(src.data_ptr()), self.n, src.stride(0) if self.n else self.ncols,
+        n = int(src.shape[0])
+        if n > self.n_max or src.shape[1] < self.ncols:
+            raise ValueError("src does not fit the storage")
+        self.n = n
+        st = load().blm_pack_fp8(C.c_void_p(src.data_ptr()), n, src.stride(0) if n else self.ncols,
                                  self.ncols, C.c_void_p(self.codes.data_ptr()), C.c_void_p(self.res.data_ptr()),
                                  C.c_void_p(self.scale.data_ptr()), self.ld, C.c_void_p(_stream_handle(stream)))
         if st != BLM_OK:
             raise BLMError(st, "blm_pack_fp8 failed")
+        return self
 
     def host_parts(self):
         """Host copies: codes [n][ncols] uint8, residual bits [n][ncols] uint16, scales [ncols]."""
-        n16, n8 = (self.n + 15) // 16, (self.n + 7) // 8
+        n16, n8 = (self.n_max + 15) // 16, (self.n_max + 7) // 8
         q = self.codes.cpu().numpy().reshape(n16, self.ld, 16).transpose(0, 2, 1).reshape(n16 * 16, self.ld)
         r = self.res.cpu().numpy().view(np.uint16).reshape(n8, self.ld, 8).transpose(0, 2, 1)
         r = r.reshape(n8 * 8, self.ld)

@@ -14,6 +14,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libblm.so")
+# the input generator of the banded-G synthetic model (not part of libblm)
+SYNTHGEN_SRC = os.path.join(HERE, "synthgen", "synth_gen.hip")
+SYNTHGEN_LIB = os.path.join(HERE, "synthgen", "libsynthgen.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -38,14 +41,20 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every HIP source into one shared library; returns its path."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, *sources(), "-o", tmp]
+def _compile(srcs, out, includes, verbose):
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, *[a for inc in includes for a in ("-I", inc)], *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles every HIP source of csrc/ into libblm.so, and the sample
+    generator into synthgen/libsynthgen.so; returns libblm's path."""
+    _compile(sources(), LIB, [INCLUDE, CSRC], verbose)
+    _compile([SYNTHGEN_SRC], SYNTHGEN_LIB, [], verbose)
     return LIB
 
 

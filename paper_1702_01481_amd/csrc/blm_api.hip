@@ -77,7 +77,7 @@ struct blm_ctx {
   int d2max = 0, n2max = 0;        // stage two
   int Pcap1 = 1, Pcap2 = 1, PcapM = 1;
   int nd2max = 0;                  // most kept directions of any block (all shifts), last solve
-  int P_tuned[4] = {0, 0, 0, 0};   // slice groups chosen by blm_autotune_build, per build kind (0: heuristic)
+  int P_tuned[5] = {0, 0, 0, 0, 0};   // slice groups chosen by blm_autotune_build, per build kind (0: heuristic)
   int max_slices = 0;
   int64_t* d_off = nullptr;
 
@@ -326,6 +326,8 @@ blm_status validate(const blm_config* cfg, blm_ctx* c) {
   return BLM_OK;
 }
 
+constexpr int PARTIAL_SLOTS = 65536;   // partial tiles the block build's slice groups may use
+
 // Fills the derived sizes and the list of allocations (pointer slot, bytes).
 void plan(blm_ctx* c, Plan& P) {
   const int NB = c->NB, NO = c->NO, NK = c->NK, NS = c->NS;
@@ -364,11 +366,13 @@ void plan(blm_ctx* c, Plan& P) {
   c->d2max = 1 + NB * (NK + 1);
   const int T2 = (c->n2max + GT - 1) / GT;
   const int n_jobs2max = T2 * (T2 + 1) / 2;
-  c->Pcap1 = std::max(1, std::min(64, (4096 + c->n_jobs1 - 1) / c->n_jobs1));
+  // slice groups the block build may take (the heuristic picks about 4,096
+  // workgroups; the autotuner may go up to 65,536 partial tiles, 6.4 GB)
+  c->Pcap1 = std::max(1, std::min(64, (PARTIAL_SLOTS + c->n_jobs1 - 1) / c->n_jobs1));
   // stage two has few tiles (3 at 121 coordinates): up to one slice group
   // per 4,096-sample slice, so that its launch fills the chip
   c->Pcap2 = std::max(1, std::min(512, (4096 + n_jobs2max - 1) / n_jobs2max));
-  c->PcapM = c->n_jobsM ? std::max(1, std::min(64, (4096 + c->n_jobsM - 1) / c->n_jobsM)) : 1;
+  c->PcapM = c->n_jobsM ? std::max(1, std::min(64, (PARTIAL_SLOTS + c->n_jobsM - 1) / c->n_jobsM)) : 1;
   const size_t slots = std::max({(size_t)c->n_jobs1 * c->Pcap1, (size_t)n_jobs2max * c->Pcap2,
                                  (size_t)c->n_jobsM * c->PcapM});
   c->max_slices = (int)(c->max_samples / SLICE) + 1024;
@@ -619,16 +623,17 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
 
 // kind: 0 FP64 kernel on FP64 storage, 1 FP64 kernel on split storage
 // (strips), 2 BF16 matrix-core kernel on split storage (main products),
-// 3 FP8 + BF16 matrix-core kernel on FP8 storage (main products)
-// the Gram launch of one build kind (0: FP64, 1: FP64 aux of a mixed build, 2: BF16 pieces, 3: FP8)
-// over the slice table on the device, into the partial tiles
+// 3 FP8 + BF16 matrix-core kernel on FP8 storage (main products),
+// 4 FP64 kernel, stage two: the Gram launch of one kind over the slice
+// table on the device, into the partial tiles
 void launch_build_gram(blm_ctx* c, int kind, const GramJob* d_jobs, int n_jobs, int n_slices, int P, bool vec) {
   if (kind == 2)
     launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->pieces, c->partial, c->st);
   else if (kind == 3)
     launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->partial, c->st);
   else
-    launch_gram(d_jobs, n_jobs, slice_tab(c), n_slices, P, vec && kind == 0, kind == 1, c->partial, c->st);
+    launch_gram(d_jobs, n_jobs, slice_tab(c), n_slices, P, vec && (kind == 0 || kind == 4), kind == 1, kind == 4,
+                c->partial, c->st);
 }
 
 // tuned: the block build's main Gram launch, which takes the slice-group
@@ -1142,6 +1147,7 @@ blm_status blm_autotune_build(blm_ctx* c, const blm_chunk* ch, int32_t n, int32_
                         hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
       r = BLM_E_HIP;
     if (r != BLM_OK) break;
+    if (getenv("BLM_AUTOTUNE_LOG")) fprintf(stderr, "blm_autotune_build: kind %d, %d slice groups: %.3f ms\n", kind, P, ms);
     if (best == 0 || ms < best_ms) {
       best = P;
       best_ms = ms;
@@ -1343,7 +1349,7 @@ blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     rb += ns;
   }
   mark(c, 5, true);
-  s = run_gram(c, c->d_jobs2, c->n_jobs2, c->Pcap2, c->G2S, c->G2H, nullptr, 6, true);
+  s = run_gram(c, c->d_jobs2, c->n_jobs2, c->Pcap2, c->G2S, c->G2H, nullptr, 6, true, 4);
   if (s != BLM_OK) return s;
   c->n_pass2 += total;
   c->state = ST_PROJECTED;

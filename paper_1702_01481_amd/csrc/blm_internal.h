@@ -175,8 +175,10 @@ constexpr int EIG_MAXD = 4096;
 constexpr int EIG_MAXSEL = 16;   // eigenvalues selected per problem (N_K + 1 <= this)
 
 // launchers (blm_kernels.hip / blm_eig.hip)
+// split: strip and aux jobs of a mixed build; stage2: the stage-two Gram
+// (its own kernel instantiation, named apart in traces)
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                 bool vec, bool split, double* d_partial, hipStream_t st);
+                 bool vec, bool split, bool stage2, double* d_partial, hipStream_t st);
 void launch_gram_bf16(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
                       const Slice* d_slices, int n_slices, int P, int pieces, double* d_partial,
                       hipStream_t st);

@@ -424,7 +424,9 @@ __device__ __forceinline__ void gram_body(GramLds& L, const GramJob& J,
 // VEC: every job's columns are 16-byte aligned (even leading dimension and
 // tile origins, aligned panels), so full 64 x 64 tiles use 16-byte loads.
 // SPLIT: the jobs are strip jobs on BF16 split or FP8 storage, plus the aux job.
-template <bool VEC, bool SPLIT>
+// STAGE2: the stage-two Gram (same code; its own instantiation, so that
+// kernel traces tell it from the block build by name).
+template <bool VEC, bool SPLIT, bool STAGE2>
 __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __restrict__ jobs,
                                                            int n_jobs,
                                                            const Slice* __restrict__ slices,
@@ -512,17 +514,24 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
 }
 
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                 bool vec, bool split, double* d_partial, hipStream_t st) {
+                 bool vec, bool split, bool stage2, double* d_partial, hipStream_t st) {
   if (n_jobs <= 0) return;
+  const dim3 grid(n_jobs * P), block(GTHREADS);
   if (split)
-    hipLaunchKernelGGL((gram_kernel<false, true>), dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs,
-                       n_jobs, d_slices, n_slices, P, d_partial);
+    hipLaunchKernelGGL((gram_kernel<false, true, false>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices, P,
+                       d_partial);
+  else if (stage2 && vec)
+    hipLaunchKernelGGL((gram_kernel<true, false, true>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices, P,
+                       d_partial);
+  else if (stage2)
+    hipLaunchKernelGGL((gram_kernel<false, false, true>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices,
+                       P, d_partial);
   else if (vec)
-    hipLaunchKernelGGL((gram_kernel<true, false>), dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs,
-                       n_jobs, d_slices, n_slices, P, d_partial);
+    hipLaunchKernelGGL((gram_kernel<true, false, false>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices,
+                       P, d_partial);
   else
-    hipLaunchKernelGGL((gram_kernel<false, false>), dim3(n_jobs * P), dim3(GTHREADS), 0, st, d_jobs,
-                       n_jobs, d_slices, n_slices, P, d_partial);
+    hipLaunchKernelGGL((gram_kernel<false, false, false>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices,
+                       P, d_partial);
 }
 
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,

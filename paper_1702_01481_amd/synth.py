@@ -12,7 +12,12 @@ low-rank Gaussian model:
     E_L,s = -10 + a . (O_s - mu) + sigma_E eps_s       a ~ N(0, 0.2^2)
     e_s   = E_L,s O_s + G (O_s - mu) + 0.05 eta_s      G symmetric, G_ij ~ N(0, 0.1^2)
 
-with z, xi, eps, eta standard normal.  Model parameters are drawn once per
+with z, xi, eps, eta standard normal.  G is dense, or banded (G_ij = 0 for
+|i - j| > band) for the 30,000-parameter workload, whose dense G(O - mu)
+term would cost 2 N_s N_V^2 flop per pass (7.2 PFLOP at 4M samples, far more
+than the method's own work); the banded model is made on the device by a
+fused generator (synthgen/libsynthgen.so: SplitMix64 counters, Box-Muller
+normals), chunk by chunk, as fast as it is consumed.  Model parameters are drawn once per
 seed; the sample draws of chunk c come from a generator seeded by
 (seed, c), so any chunk can be regenerated on its own, in any order, on the
 CPU or on a GPU.  CPU and GPU draws differ (torch's CPU and device
@@ -68,6 +73,7 @@ class Workload:
     shifts: Tuple[float, ...]
     sigma_E: float = 0.5
     seed: int = 0
+    band: Optional[int] = None          # half-bandwidth of G (None: dense)
 
     @property
     def n_blocks(self) -> int:
@@ -76,6 +82,11 @@ class Workload:
     def chunk_sizes(self) -> List[int]:
         full, tail = divmod(self.n_samples, self.chunk)
         return [self.chunk] * full + ([tail] if tail else [])
+
+    def generator(self, device="cpu") -> "SampleGenerator":
+        """The sample generator of this workload (its model, seed and G)."""
+        return SampleGenerator(self.n_params, self.rank, self.seed, sigma_E=self.sigma_E, device=device,
+                               band=self.band)
 
 
 def uniform_offsets(n_params: int, n_blocks: int) -> np.ndarray:
@@ -117,6 +128,8 @@ def uniform_int_offsets(n_params: int, lo: int, hi: int, seed: int) -> np.ndarra
     return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
 
 
+UNEVEN_BAND = 8      # half-bandwidth of G in the 30,000-parameter workload
+
 BATCH_SIZES = (2_000, 4_000, 6_000, 8_000, 10_000, 12_000, 16_000, 20_000)
 
 
@@ -139,7 +152,7 @@ def workload(name: str, seed: int = 0) -> Workload:
               N_K=5, N_O=1, delta in {1e-4, 1e-3, 1e-2}
     bf16      N_V=16,384 in 16x1,024, N_s=4,000,000, rank 64, N_K=5, N_O=1
     uneven    N_V=30,000 in 40 log-uniform blocks in [100, 2,000], N_s=4,000,000,
-              rank 32, N_K=4, N_O=0, delta=1e-3
+              rank 32, N_K=4, N_O=0, delta=1e-3; G banded (half-bandwidth 8)
     """
     if name == "small":
         return Workload("small_200x20k", 200, uniform_offsets(200, 4), 20_000, 65_536, 8, 3, 0,
@@ -152,7 +165,7 @@ def workload(name: str, seed: int = 0) -> Workload:
                         (1e-4, 1e-3, 1e-2), seed=seed)
     if name == "uneven":
         return Workload("uneven_30000x4M", 30000, loguniform_offsets(30000, 40, 100.0, 2000.0, seed),
-                        4_000_000, 65_536, 32, 4, 0, (1e-3,), seed=seed)
+                        4_000_000, 65_536, 32, 4, 0, (1e-3,), seed=seed, band=UNEVEN_BAND)
     raise KeyError(name)
 
 
@@ -161,15 +174,32 @@ def workload(name: str, seed: int = 0) -> Workload:
 # ----------------------------------------------------------------------------
 
 class SampleGenerator:
-    """Draws the model parameters (mu, L, a, G) once, then chunks on demand."""
+    """Draws the model parameters (mu, L, a, G) once, then chunks on demand.
+
+    band=None: dense G, everything drawn with torch generators on `device`.
+    band=b: G banded with half-bandwidth b.  The model parameters are drawn
+    on the CPU (the same values for every device) and the chunks are made
+    by the fused generator on a GPU, or by plain torch operations on the CPU
+    (other random streams: a comparison always hands both sides the same
+    bytes)."""
 
     def __init__(self, n_params: int, rank: int, seed: int = 0, sigma_E: float = 0.5,
-                 device: str | torch.device = "cpu"):
+                 device: str | torch.device = "cpu", band: Optional[int] = None):
         self.n_params, self.rank, self.seed, self.sigma_E = n_params, rank, seed, sigma_E
         self.device = torch.device(device)
-        dev = self.device
+        self.band = band
         f64 = torch.float64
         n = n_params
+        if band is not None:
+            cpu = "cpu"
+            self.mu = (0.1 * torch.randn(n, generator=_gen(cpu, seed, _S_MU), dtype=f64)).to(self.device)
+            self.L = (0.3 * torch.randn(n, rank, generator=_gen(cpu, seed, _S_L), dtype=f64)).to(self.device)
+            self.a = (0.2 * torch.randn(n, generator=_gen(cpu, seed, _S_A), dtype=f64)).to(self.device)
+            self.gband = banded_G(n, band, seed).to(self.device)
+            self.G = None
+            self._part = None
+            return
+        dev = self.device
         self.mu = 0.1 * torch.randn(n, generator=_gen(dev, seed, _S_MU), dtype=f64, device=dev)
         self.L = 0.3 * torch.randn(n, rank, generator=_gen(dev, seed, _S_L), dtype=f64, device=dev)
         self.a = 0.2 * torch.randn(n, generator=_gen(dev, seed, _S_A), dtype=f64, device=dev)
@@ -180,8 +210,14 @@ class SampleGenerator:
         del g, up
 
     def chunk(self, index: int, n_rows: int, out_O: Optional[torch.Tensor] = None,
-              out_e: Optional[torch.Tensor] = None):
-        """Samples of chunk `index`: O [n_rows][N_V], e [n_rows][N_V], E_L [n_rows]."""
+              out_e: Optional[torch.Tensor] = None, out_EL: Optional[torch.Tensor] = None):
+        """Samples of chunk `index`: O [n_rows][N_V], e [n_rows][N_V], E_L [n_rows]
+        (written into out_* when given: contiguous rows of N_V, or views with
+        unit column stride)."""
+        if self.band is not None:
+            if self.device.type == "cuda":
+                return self._chunk_banded_device(index, n_rows, out_O, out_e, out_EL)
+            return self._chunk_banded_cpu(index, n_rows, out_O, out_e, out_EL)
         dev, f64 = self.device, torch.float64
         g = _gen(dev, self.seed, _S_CHUNK0 + index)
         n = self.n_params
@@ -191,6 +227,9 @@ class SampleGenerator:
         dO.add_(torch.randn(n_rows, n, generator=g, dtype=f64, device=dev), alpha=0.1)
         eps = torch.randn(n_rows, generator=g, dtype=f64, device=dev)
         EL = -10.0 + dO @ self.a + self.sigma_E * eps
+        if out_EL is not None:
+            out_EL.copy_(EL)
+            EL = out_EL
         O = out_O if out_O is not None else torch.empty(n_rows, n, dtype=f64, device=dev)
         torch.add(dO, self.mu, out=O)
         e = out_e if out_e is not None else torch.empty(n_rows, n, dtype=f64, device=dev)
@@ -199,6 +238,105 @@ class SampleGenerator:
         e.addcmul_(EL[:, None], O)
         e.add_(torch.randn(n_rows, n, generator=g, dtype=f64, device=dev), alpha=0.05)
         return O, e, EL
+
+    def _chunk_banded_cpu(self, index, n_rows, out_O, out_e, out_EL):
+        f64 = torch.float64
+        g = _gen("cpu", self.seed, _S_CHUNK0 + index)
+        n = self.n_params
+        z = torch.randn(n_rows, self.rank, generator=g, dtype=f64)
+        dO = z @ self.L.T
+        dO.add_(torch.randn(n_rows, n, generator=g, dtype=f64), alpha=0.1)
+        EL = -10.0 + dO @ self.a + self.sigma_E * torch.randn(n_rows, generator=g, dtype=f64)
+        O = dO + self.mu
+        e = EL[:, None] * O + band_matvec(self.gband, dO)
+        e.add_(torch.randn(n_rows, n, generator=g, dtype=f64), alpha=0.05)
+        if out_O is not None:
+            out_O.copy_(O)
+            O = out_O
+        if out_e is not None:
+            out_e.copy_(e)
+            e = out_e
+        if out_EL is not None:
+            out_EL.copy_(EL)
+            EL = out_EL
+        return O, e, EL
+
+    def _chunk_banded_device(self, index, n_rows, out_O, out_e, out_EL):
+        import ctypes as C
+        dev, f64 = self.device, torch.float64
+        n = self.n_params
+        O = out_O if out_O is not None else torch.empty(n_rows, n, dtype=f64, device=dev)
+        e = out_e if out_e is not None else torch.empty(n_rows, n, dtype=f64, device=dev)
+        EL = out_EL if out_EL is not None else torch.empty(n_rows, dtype=f64, device=dev)
+        for t, name in ((O, "O"), (e, "e")):
+            if t.shape[0] < n_rows or t.shape[1] < n or t.stride(1) != 1 or t.dtype != f64:
+                raise ValueError(f"{name} must be float64 [>= {n_rows}][>= {n}] with unit column stride")
+        if O.stride(0) != e.stride(0):
+            raise ValueError("O and e must share their row stride")
+        n_tiles = (n + 255) // 256
+        if self._part is None or self._part.numel() < n_rows * n_tiles:
+            self._part = torch.empty(n_rows * n_tiles, dtype=f64, device=dev)
+        st = torch.cuda.current_stream(dev).cuda_stream
+        r = _synthgen().synth_gen_banded_chunk(
+            n_rows, n, self.rank, C.c_void_p(self.L.data_ptr()), C.c_void_p(self.mu.data_ptr()),
+            C.c_void_p(self.a.data_ptr()), self.band, C.c_void_p(self.gband.data_ptr()), float(self.sigma_E),
+            C.c_uint64(_seed_of(self.seed, _S_CHUNK0)), int(index), C.c_void_p(O.data_ptr()),
+            C.c_void_p(e.data_ptr()), O.stride(0), C.c_void_p(EL.data_ptr()), C.c_void_p(self._part.data_ptr()),
+            C.c_void_p(st))
+        if r != 0:
+            raise RuntimeError(f"synth_gen_banded_chunk failed ({r})")
+        return O, e, EL
+
+
+def banded_G(n: int, band: int, seed: int) -> torch.Tensor:
+    """Symmetric banded G as its diagonals: gband[i][band + k] = G_{i,i+k} for
+    |k| <= band (zero where i + k falls outside 0..n-1); G_{i,i+k} = G_{i+k,i}
+    ~ N(0, 0.1^2), drawn once per diagonal k >= 0 and mirrored."""
+    g = _gen("cpu", seed, _S_G)
+    gb = torch.zeros(n, 2 * band + 1, dtype=torch.float64)
+    for k in range(0, band + 1):
+        if k >= n:
+            break
+        d = 0.1 * torch.randn(n - k, generator=g, dtype=torch.float64)
+        gb[: n - k, band + k] = d          # G_{i, i+k}
+        if k:
+            gb[k:, band - k] = d           # G_{i, i-k} = G_{i-k, i}
+    return gb
+
+
+def band_matvec(gband: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """Rows of X times the banded G (plain torch, for the CPU generator):
+    out[s, i] = sum_k gband[i, band + k] X[s, i + k]."""
+    n = X.shape[1]
+    band = (gband.shape[1] - 1) // 2
+    out = torch.zeros_like(X)
+    for k in range(-band, band + 1):
+        if abs(k) >= n:
+            continue
+        lo, hi = max(0, -k), min(n, n - k)      # columns i with 0 <= i + k < n
+        out[:, lo:hi] += gband[lo:hi, band + k] * X[:, lo + k:hi + k]
+    return out
+
+
+_synthgen_lib = None
+
+
+def _synthgen():
+    """libsynthgen.so (built by build_lib next to this module)."""
+    global _synthgen_lib
+    if _synthgen_lib is None:
+        import ctypes as C
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "synthgen", "libsynthgen.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} not built; run python -m paper_1702_01481_amd.build_lib")
+        lib = C.CDLL(path)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        lib.synth_gen_banded_chunk.argtypes = [i64, i64, i32, vp, vp, vp, i32, vp, C.c_double, C.c_uint64, i64,
+                                               vp, vp, i64, vp, vp, vp]
+        lib.synth_gen_banded_chunk.restype = C.c_int
+        _synthgen_lib = lib
+    return _synthgen_lib
 
 
 def weights(n_rows: int, seed: int, index: int = 0, device="cpu") -> torch.Tensor:

@@ -35,7 +35,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _chunks(w, n_samples):
-    gen = synth.SampleGenerator(w.n_params, w.rank, w.seed, sigma_E=w.sigma_E, device="cuda")
+    gen = w.generator("cuda")
     chunks, left, i = [], n_samples, 0
     while left > 0:
         n = min(w.chunk, left)
