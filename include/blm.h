@@ -64,9 +64,11 @@ typedef enum {
   BLM_PREC_F64 = 0,     /* sample contractions in FP64 on FP64 matrix cores */
   BLM_PREC_BF16X2 = 1,  /* BF16 hi/lo pieces, 3 piece products, FP32 sums flushed to FP64 */
   BLM_PREC_BF16X3 = 2,  /* BF16 hi/mid/lo pieces, 6 piece products, FP32 sums flushed to FP64 */
-  BLM_PREC_FP8 = 3      /* e4m3 codes with power-of-two column scales and a BF16 residual:
-                           code x code on FP8 matrix cores, the three residual terms on
-                           BF16 ones, FP32 sums scaled and flushed to FP64 */
+  BLM_PREC_FP8 = 3,     /* e4m3 codes with power-of-two column scales and a BF16 residual:
+                           the four piece products on BF16 matrix cores (codes converted
+                           exactly), FP32 sums scaled and flushed to FP64 */
+  BLM_PREC_FP8X2 = 4    /* the same codes and scales with two BF16 residuals r, t: the eight
+                           piece products of q, r, t but t t on BF16 matrix cores */
 } blm_precision;
 
 typedef enum {
@@ -104,13 +106,15 @@ typedef struct {                 /* one chunk of samples; device memory, caller-
   const double* w;               /* [n_samples] >= 0, or NULL for all-ones (required for BF16, FP8) */
   int32_t layout;                /* blm_layout; must be BLM_LAYOUT_F64 for BLM_PREC_F64,
                                     BLM_LAYOUT_BF16_SPLIT for the BF16 precisions and
-                                    BLM_LAYOUT_FP8_SCALED for BLM_PREC_FP8 */
+                                    BLM_LAYOUT_FP8_SCALED for BLM_PREC_FP8 and FP8X2 */
   int32_t pieces;                /* split layout: pieces stored (2 or 3; >= 3 for BF16X3) */
   int64_t piece_stride;          /* split layout: elements between pieces, multiple of 8 */
   const void* O_res;             /* FP8 layout: BF16 residuals of O (uint16, see blm_pack_fp8) */
   const void* e_res;             /* FP8 layout: BF16 residuals of e */
   const float* O_scale;          /* FP8 layout: [ld] power-of-two column scales of O */
   const float* e_scale;          /* FP8 layout: [ld] column scales of e */
+  const void* O_res2;            /* FP8 layout, BLM_PREC_FP8X2: second BF16 residuals of O */
+  const void* e_res2;            /* FP8 layout, BLM_PREC_FP8X2: second BF16 residuals of e */
 } blm_chunk;
 
 /* Producer-side utility: splits FP64 samples src [n][ld_src] (columns
@@ -124,23 +128,27 @@ blm_status blm_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t n
                          uint16_t* dst, int64_t ld_dst, int64_t piece_stride, void* stream);
 
 /* Producer-side utility: FP8 storage of FP64 samples src [n][ld_src]
- * (columns 0..ncols-1), each value x of column c as x = scale[c] (q + r):
+ * (columns 0..ncols-1), each value x of column c as x = scale[c] (q + r)
+ * or, with res2, x = scale[c] (q + r + t):
  *   scale[c]  the smallest power of two (2^-126 .. 2^127) with
  *             max_s |x| / scale[c] <= 448;
  *   q         x / scale[c] rounded to OCP e4m3 (nearest, ties to even,
  *             saturating at 448), stored as its code byte;
  *   r         the exact remainder x / scale[c] - q rounded to FP32 and then
- *             to BF16 (nearest even), stored as uint16 bits.
- * The stored value is within 2^-13 |x| of x in q's normal range.  Layouts
- * (k-packed): code of (s, x) at codes[((s / 16) * ld_dst + x) * 16 + s % 16],
- * residual at res[((s / 8) * ld_dst + x) * 8 + s % 8]; rows n .. up to the
- * next multiple of 16 (codes) or 8 (residuals) are zeros.  codes needs
- * 16 * ceil(n / 16) * ld_dst bytes, res 8 * ceil(n / 8) * ld_dst elements,
- * both 16-byte aligned; scale ncols floats.  (Reduced-precision storage of
- * the samples of Eq. 3 is this library's option; the paper works in FP64.)
- * Asynchronous on `stream`. */
+ *             to BF16 (nearest even), stored as uint16 bits;
+ *   t         (res2 != NULL) the exact remainder x / scale[c] - q - r rounded
+ *             the same way.
+ * The stored value is within 2^-13 (1 + 2^-14) |x| (one residual) or
+ * 2^-22 (1 + 2^-14) |x| (two) of x in q's normal range.  Layouts (k-packed): code of (s, x) at
+ * codes[((s / 16) * ld_dst + x) * 16 + s % 16], residuals at
+ * res[((s / 8) * ld_dst + x) * 8 + s % 8] (res2 likewise); rows n .. up to
+ * the next multiple of 16 (codes) or 8 (residuals) are zeros.  codes needs
+ * 16 * ceil(n / 16) * ld_dst bytes, res and res2 8 * ceil(n / 8) * ld_dst
+ * elements each, all 16-byte aligned; scale ncols floats.
+ * (Reduced-precision storage of the samples of Eq. 3 is this library's
+ * option; the paper works in FP64.)  Asynchronous on `stream`. */
 blm_status blm_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,
-                        uint16_t* res, float* scale, int64_t ld_dst, void* stream);
+                        uint16_t* res, uint16_t* res2, float* scale, int64_t ld_dst, void* stream);
 
 /* Bytes of device memory blm_create will allocate for this configuration. */
 blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes);
@@ -168,10 +176,14 @@ blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chu
  * slices, summed afterwards in a fixed order; the best G depends on the
  * device, the blocks and the storage.  This call times the kernel on the
  * given chunks for each G in {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64} and
- * the default count, up to the context's limit (one settling launch and
- * one timed launch each,
- * HIP events on the context's stream), and later builds of this context
- * use the fastest.  It writes only the Theta projection of the chunks and
+ * the default count, with G times the tile count up to 65,536 (one
+ * settling launch and one timed launch each, HIP events on the context's
+ * stream), and later builds of this context use the fastest.  blm_create
+ * sizes the partial tiles of the split for the default count; when the
+ * candidates need more, this call allocates a larger buffer (up to 6.4 GB)
+ * and frees the old one, dropping any recording made by blm_capture_build
+ * (record after tuning), or, if the device has no room, tries only the
+ * counts that fit.  It writes only the Theta projection of the chunks and
  * scratch tiles: the step's accumulated estimates are unchanged, so it may
  * run between blm_begin_step and the first blm_build_blocks, or between
  * builds.  Synchronises the stream.  h_groups (may be NULL): the chosen G.

@@ -13,7 +13,9 @@ column c is held as x = s_c (q + r):
 * q is the OCP e4m3 value nearest to x / s_c (ties to the even code;
   beyond 448 the nearest finite value, 448);
 * r is the remainder x / s_c - q (exact in FP64) rounded first to FP32 and
-  then to BF16, both to nearest with ties to even.
+  then to BF16, both to nearest with ties to even;
+* with two residuals, x = s_c (q + r + t): t is what r leaves of the
+  remainder, x / s_c - q - r (exact in FP64), rounded the same way.
 
 Everything here works by enumeration and comparison of exact FP64 values,
 not by bit arithmetic on exponents, so that it can be read against the
@@ -90,21 +92,30 @@ def bf16_value(bits: np.ndarray) -> np.ndarray:
     return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def fp8_store(x: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+def fp8_store(x: np.ndarray, residuals: int = 1):
     """Codes [n][c] uint8, residual BF16 bits [n][c] uint16 and scales [c]
-    (FP32 values) of x [n][c]."""
+    (FP32 values) of x [n][c]; with residuals=2 also the second residual's
+    bits, returned after the first: (codes, r bits, t bits, scales)."""
     x = np.asarray(x, dtype=np.float64)
     s = column_scales(x)
     v = x / s                                     # exact: s is a power of two
     qa, code = e4m3_nearest(np.abs(v))
     q = np.where(v < 0, -qa, qa)
     code = np.where((v < 0) & (code != 0), code | 0x80, code).astype(np.uint8)
-    r = v - q                                     # exact
-    rbits = _bf16_nearest_bits(r.astype(np.float32))
-    return code, rbits, s.astype(np.float32)
+    rem = v - q                                   # exact
+    rbits = _bf16_nearest_bits(rem.astype(np.float32))
+    if residuals == 1:
+        return code, rbits, s.astype(np.float32)
+    rem2 = rem - bf16_value(rbits)                # exact: r is rem to 8 bits
+    tbits = _bf16_nearest_bits(rem2.astype(np.float32))
+    return code, rbits, tbits, s.astype(np.float32)
 
 
-def fp8_values(code: np.ndarray, rbits: np.ndarray, scale: np.ndarray) -> np.ndarray:
-    """The exact FP64 values s (q + r) that the stored data stand for."""
+def fp8_values(code: np.ndarray, rbits: np.ndarray, scale: np.ndarray, tbits=None) -> np.ndarray:
+    """The exact FP64 values s (q + r), or s (q + r + t), that the stored data
+    stand for."""
     table = np.array([e4m3_value(c) for c in range(256)])
-    return scale.astype(np.float64) * (table[code.astype(np.int64)] + bf16_value(rbits))
+    v = table[code.astype(np.int64)] + bf16_value(rbits)
+    if tbits is not None:
+        v = v + bf16_value(tbits)
+    return scale.astype(np.float64) * v

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "BLM_OK", 1: "BLM_E_ARG", 2: "BLM_E_STATE", 3: "BLM_E_HIP", 4
                 5: "BLM_E_S_NOT_PD", 6: "BLM_E_NONFINITE", 7: "BLM_E_NOCONV", 8: "BLM_E_TIMEOUT"}
 FLAG_COMPLEX_ENERGY, FLAG_PAIR_KEPT, FLAG_SMALL_ALPHA = 1, 2, 4
 
-PRECISIONS = {"fp64": 0, "bf16x2": 1, "bf16x3": 2, "fp8": 3}
+PRECISIONS = {"fp64": 0, "bf16x2": 1, "bf16x3": 2, "fp8": 3, "fp8x2": 4}
 
 EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_create", "blm_destroy", "blm_begin_step",
             "blm_build_blocks", "blm_autotune_build", "blm_capture_build", "blm_replay_build",
@@ -52,7 +52,8 @@ class _Chunk(C.Structure):
     _fields_ = [("n_samples", C.c_int64), ("ld", C.c_int64), ("O", C.c_void_p), ("e", C.c_void_p),
                 ("E_L", C.c_void_p), ("w", C.c_void_p), ("layout", C.c_int32), ("pieces", C.c_int32),
                 ("piece_stride", C.c_int64), ("O_res", C.c_void_p), ("e_res", C.c_void_p),
-                ("O_scale", C.c_void_p), ("e_scale", C.c_void_p)]
+                ("O_scale", C.c_void_p), ("e_scale", C.c_void_p), ("O_res2", C.c_void_p),
+                ("e_res2", C.c_void_p)]
 
 
 _lib = None
@@ -68,7 +69,7 @@ def load() -> C.CDLL:
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     lib.blm_pack_bf16.argtypes = [vp, i64, i64, i64, i32, vp, i64, i64, vp]
-    lib.blm_pack_fp8.argtypes = [vp, i64, i64, i64, vp, vp, vp, i64, vp]
+    lib.blm_pack_fp8.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i64, vp]
     lib.blm_workspace_bytes.argtypes = [C.POINTER(_Config), C.POINTER(C.c_size_t)]
     lib.blm_create.argtypes = [C.POINTER(_Config), vp, C.POINTER(vp)]
     lib.blm_destroy.argtypes = [vp]
@@ -172,29 +173,33 @@ class SplitSamples:
 
 
 class Fp8Samples:
-    """FP8 storage (e4m3 codes k-packed by 16 samples, BF16 residuals k-packed
-    by 8, power-of-two column scales) of an FP64 [n][>= ncols] device array,
-    made by the library's blm_pack_fp8."""
+    """FP8 storage (e4m3 codes k-packed by 16 samples, one or two BF16
+    residuals k-packed by 8, power-of-two column scales) of an FP64
+    [n][>= ncols] device array, made by the library's blm_pack_fp8."""
 
-    def __init__(self, src: torch.Tensor, ncols: Optional[int] = None, stream=None):
+    def __init__(self, src: torch.Tensor, ncols: Optional[int] = None, stream=None, residuals: int = 1):
         _check_f64_dev(src, "src")
-        self._alloc(int(src.shape[0]), int(ncols if ncols is not None else src.shape[1]), src.device)
+        self._alloc(int(src.shape[0]), int(ncols if ncols is not None else src.shape[1]), residuals, src.device)
         self.pack(src, stream)
 
-    def _alloc(self, n_max: int, ncols: int, device):
+    def _alloc(self, n_max: int, ncols: int, residuals: int, device):
+        if residuals not in (1, 2):
+            raise ValueError("residuals must be 1 or 2")
         self.n = self.n_max = n_max
         self.ncols = ncols
         self.ld = self.ncols
+        self.residuals = residuals
         n16, n8 = (self.n_max + 15) // 16, (self.n_max + 7) // 8
         self.codes = torch.empty(n16 * 16 * self.ld, dtype=torch.uint8, device=device)
         self.res = torch.empty(n8 * 8 * self.ld, dtype=torch.int16, device=device)
+        self.res2 = torch.empty(n8 * 8 * self.ld, dtype=torch.int16, device=device) if residuals == 2 else None
         self.scale = torch.empty(self.ld, dtype=torch.float32, device=device)
 
     @classmethod
-    def empty(cls, n_max: int, ncols: int, device="cuda") -> "Fp8Samples":
+    def empty(cls, n_max: int, ncols: int, device="cuda", residuals: int = 1) -> "Fp8Samples":
         """Storage for up to n_max samples, filled later by pack()."""
         obj = cls.__new__(cls)
-        obj._alloc(int(n_max), int(ncols), torch.device(device))
+        obj._alloc(int(n_max), int(ncols), residuals, torch.device(device))
         return obj
 
     def pack(self, src: torch.Tensor, stream=None):
@@ -209,18 +214,26 @@ class Fp8Samples:
         self.n = n
         st = load().blm_pack_fp8(C.c_void_p(src.data_ptr()), n, src.stride(0) if n else self.ncols,
                                  self.ncols, C.c_void_p(self.codes.data_ptr()), C.c_void_p(self.res.data_ptr()),
+                                 C.c_void_p(self.res2.data_ptr() if self.res2 is not None else None),
                                  C.c_void_p(self.scale.data_ptr()), self.ld, C.c_void_p(_stream_handle(stream)))
         if st != BLM_OK:
             raise BLMError(st, "blm_pack_fp8 failed")
         return self
 
     def host_parts(self):
-        """Host copies: codes [n][ncols] uint8, residual bits [n][ncols] uint16, scales [ncols]."""
+        """Host copies: codes [n][ncols] uint8, residual bits [n][ncols] uint16, scales [ncols]
+        (and, with two residuals, the second residual bits after the first)."""
         n16, n8 = (self.n_max + 15) // 16, (self.n_max + 7) // 8
         q = self.codes.cpu().numpy().reshape(n16, self.ld, 16).transpose(0, 2, 1).reshape(n16 * 16, self.ld)
-        r = self.res.cpu().numpy().view(np.uint16).reshape(n8, self.ld, 8).transpose(0, 2, 1)
-        r = r.reshape(n8 * 8, self.ld)
-        return q[: self.n, : self.ncols], r[: self.n, : self.ncols], self.scale.cpu().numpy()[: self.ncols]
+
+        def unpack(t):
+            r = t.cpu().numpy().view(np.uint16).reshape(n8, self.ld, 8).transpose(0, 2, 1)
+            return r.reshape(n8 * 8, self.ld)[: self.n, : self.ncols]
+
+        out = (q[: self.n, : self.ncols], unpack(self.res), self.scale.cpu().numpy()[: self.ncols])
+        if self.res2 is not None:
+            out = out[:2] + (unpack(self.res2),) + out[2:]
+        return out
 
 
 def _chunk(O, e, EL, w, n_params) -> _Chunk:
@@ -233,7 +246,7 @@ def _chunk(O, e, EL, w, n_params) -> _Chunk:
         if w is not None:
             raise ValueError("the BF16 path needs uniform weights")
         return _Chunk(O.n, O.ld, O.data.data_ptr(), e.data.data_ptr(), EL.data_ptr(), None, 1, O.pieces,
-                      O.piece_stride, None, None, None, None)
+                      O.piece_stride, None, None, None, None, None, None)
     if isinstance(O, Fp8Samples):
         if not isinstance(e, Fp8Samples) or e.n != O.n or e.ld != O.ld:
             raise ValueError("O and e must be Fp8Samples of the same shape")
@@ -242,8 +255,12 @@ def _chunk(O, e, EL, w, n_params) -> _Chunk:
         _check_f64_dev(EL, "E_L")
         if w is not None:
             raise ValueError("the FP8 path needs uniform weights")
+        if O.residuals != e.residuals:
+            raise ValueError("O and e must carry the same number of residuals")
+        two = O.residuals == 2
         return _Chunk(O.n, O.ld, O.codes.data_ptr(), e.codes.data_ptr(), EL.data_ptr(), None, 2, 0, 0,
-                      O.res.data_ptr(), e.res.data_ptr(), O.scale.data_ptr(), e.scale.data_ptr())
+                      O.res.data_ptr(), e.res.data_ptr(), O.scale.data_ptr(), e.scale.data_ptr(),
+                      O.res2.data_ptr() if two else None, e.res2.data_ptr() if two else None)
     _check_f64_dev(O, "O")
     _check_f64_dev(e, "e")
     _check_f64_dev(EL, "E_L")
@@ -256,7 +273,8 @@ def _chunk(O, e, EL, w, n_params) -> _Chunk:
         if w.shape[0] != O.shape[0] or not w.is_contiguous():
             raise ValueError("w must be contiguous [n]")
     return _Chunk(O.shape[0], O.stride(0) if O.shape[0] > 0 else O.shape[1], O.data_ptr(), e.data_ptr(),
-                  EL.data_ptr(), w.data_ptr() if w is not None else None, 0, 0, 0, None, None, None, None)
+                  EL.data_ptr(), w.data_ptr() if w is not None else None, 0, 0, 0, None, None, None, None,
+                  None, None)
 
 
 class BLM:

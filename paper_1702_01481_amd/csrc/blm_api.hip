@@ -77,6 +77,7 @@ struct blm_ctx {
   int d2max = 0, n2max = 0;        // stage two
   int Pcap1 = 1, Pcap2 = 1, PcapM = 1;
   int nd2max = 0;                  // most kept directions of any block (all shifts), last solve
+  size_t partial_slots = 0;       // partial tiles allocated (3 x 64 x 64 doubles each)
   int P_tuned[5] = {0, 0, 0, 0, 0};   // slice groups chosen by blm_autotune_build, per build kind (0: heuristic)
   int max_slices = 0;
   int64_t* d_off = nullptr;
@@ -98,8 +99,10 @@ struct blm_ctx {
   int64_t aux_pstride = 0;       // elements between pieces of auxP (Xa pieces, then Ya pieces)
   int pieces = 0;                  // 0: FP64 path; 2 or 3: BF16 split pieces used
   bool fp8 = false;                // FP8 storage (e4m3 codes, BF16 residuals, column scales)
+  int fp8_res = 0;                 // FP8 storage: BF16 residuals per value (1 or 2)
   uint8_t* auxQ = nullptr;         // FP8 build: first aux group's codes (k-packed by 16, ld 16), Xa then Ya
   uint16_t* auxR = nullptr;        // FP8 build: its residuals (k-packed by 8, ld 16), Xa then Ya
+  uint16_t* auxT = nullptr;        // FP8 build with two residuals: the second ones, laid out like auxR
   float* auxS = nullptr;           // FP8 build: its column scales [chunk][Xa, Ya][16]
   int64_t auxq_stride = 0, auxr_stride = 0;   // bytes / elements from the Xa to the Ya part
   bool mixed() const { return pieces != 0 || fp8; }
@@ -309,7 +312,7 @@ blm_status validate(const blm_config* cfg, blm_ctx* c) {
     if (!(cfg->shifts[i] >= 0.0) || !std::isfinite(cfg->shifts[i]))
       return fail(c, BLM_E_ARG, "shifts must be finite and >= 0");
   if (cfg->precision != BLM_PREC_F64 && cfg->precision != BLM_PREC_BF16X2 &&
-      cfg->precision != BLM_PREC_BF16X3 && cfg->precision != BLM_PREC_FP8)
+      cfg->precision != BLM_PREC_BF16X3 && cfg->precision != BLM_PREC_FP8 && cfg->precision != BLM_PREC_FP8X2)
     return fail(c, BLM_E_ARG, "unsupported precision");
   if (cfg->max_samples < 1) return fail(c, BLM_E_ARG, "max_samples must be >= 1");
   if (cfg->block_offsets[0] != 0 || cfg->block_offsets[cfg->n_blocks] != cfg->n_params)
@@ -366,15 +369,19 @@ void plan(blm_ctx* c, Plan& P) {
   c->d2max = 1 + NB * (NK + 1);
   const int T2 = (c->n2max + GT - 1) / GT;
   const int n_jobs2max = T2 * (T2 + 1) / 2;
-  // slice groups the block build may take (the heuristic picks about 4,096
-  // workgroups; the autotuner may go up to 65,536 partial tiles, 6.4 GB)
+  // slice groups the block build may take: the heuristic picks about 4,096
+  // workgroups, and the workspace holds their partial tiles; the autotuner
+  // may try up to 65,536 partial tiles (6.4 GB), growing the workspace then
   c->Pcap1 = std::max(1, std::min(64, (PARTIAL_SLOTS + c->n_jobs1 - 1) / c->n_jobs1));
   // stage two has few tiles (3 at 121 coordinates): up to one slice group
   // per 4,096-sample slice, so that its launch fills the chip
   c->Pcap2 = std::max(1, std::min(512, (4096 + n_jobs2max - 1) / n_jobs2max));
   c->PcapM = c->n_jobsM ? std::max(1, std::min(64, (PARTIAL_SLOTS + c->n_jobsM - 1) / c->n_jobsM)) : 1;
-  const size_t slots = std::max({(size_t)c->n_jobs1 * c->Pcap1, (size_t)n_jobs2max * c->Pcap2,
-                                 (size_t)c->n_jobsM * c->PcapM});
+  const int Ph1 = std::max(1, std::min(c->Pcap1, (4096 + c->n_jobs1 - 1) / c->n_jobs1));
+  const int PhM = c->n_jobsM ? std::max(1, std::min(c->PcapM, (4096 + c->n_jobsM - 1) / c->n_jobsM)) : 1;
+  const size_t slots = std::max({(size_t)c->n_jobs1 * Ph1, (size_t)n_jobs2max * c->Pcap2,
+                                 (size_t)c->n_jobsM * PhM});
+  c->partial_slots = slots;
   c->max_slices = (int)(c->max_samples / SLICE) + 1024;
   c->auxlist_stride = 1 + NO * (NB - 1);
 
@@ -395,6 +402,7 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->auxP, 2 * 2 * (size_t)c->pieces * c->aux_pstride);
   add((void**)&c->auxQ, 2 * (size_t)c->auxq_stride);
   add((void**)&c->auxR, 2 * 2 * (size_t)c->auxr_stride);
+  add((void**)&c->auxT, c->fp8_res == 2 ? 2 * 2 * (size_t)c->auxr_stride : 0);
   add((void**)&c->auxS, c->fp8 ? 4 * (size_t)MAX_CHUNKS * 2 * NAUX : 0);
   add((void**)&c->d_slices, sizeof(Slice) * (size_t)c->max_slices);
   add((void**)&c->d_pchunks, sizeof(ProjChunk) * (size_t)MAX_CHUNKS);
@@ -561,6 +569,12 @@ blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) 
         return fail(c, BLM_E_ARG, "FP8 chunk: residual or scale pointer is NULL");
       if (((uintptr_t)ch[i].O | (uintptr_t)ch[i].e | (uintptr_t)ch[i].O_res | (uintptr_t)ch[i].e_res) & 15)
         return fail(c, BLM_E_ARG, "FP8 chunk: codes and residuals need 16-byte alignment");
+      if (c->fp8_res == 2) {
+        if (!ch[i].O_res2 || !ch[i].e_res2)
+          return fail(c, BLM_E_ARG, "the FP8X2 precision needs second residuals (O_res2, e_res2)");
+        if (((uintptr_t)ch[i].O_res2 | (uintptr_t)ch[i].e_res2) & 15)
+          return fail(c, BLM_E_ARG, "FP8 chunk: second residuals need 16-byte alignment");
+      }
     }
     if (c->pieces) {
       if (ch[i].layout != BLM_LAYOUT_BF16_SPLIT || ch[i].pieces < c->pieces || ch[i].pieces > 3)
@@ -604,6 +618,10 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
       P.er = (const uint16_t*)ch[i].e_res;
       P.Os = ch[i].O_scale;
       P.es = ch[i].e_scale;
+      if (c->fp8_res == 2) {
+        P.Ot = (const uint16_t*)ch[i].O_res2;
+        P.et = (const uint16_t*)ch[i].e_res2;
+      }
     }
     c->h_pchunks.push_back(P);
     tiles += (int)((ns + PROJ_ROWS - 1) / PROJ_ROWS);
@@ -630,7 +648,7 @@ void launch_build_gram(blm_ctx* c, int kind, const GramJob* d_jobs, int n_jobs, 
   if (kind == 2)
     launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->pieces, c->partial, c->st);
   else if (kind == 3)
-    launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->partial, c->st);
+    launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->fp8_res, c->partial, c->st);
   else
     launch_gram(d_jobs, n_jobs, slice_tab(c), n_slices, P, vec && (kind == 0 || kind == 4), kind == 1, kind == 4,
                 c->partial, c->st);
@@ -679,18 +697,19 @@ blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
     const int64_t ns = ch[i].n_samples;
     if (ns == 0) continue;
     uint8_t* xq = nullptr;
-    uint16_t* xr = nullptr;
+    uint16_t *xr = nullptr, *xt = nullptr;
     float* xs = nullptr;
     if (c->fp8) {
       xq = c->auxQ + g16base * NAUX * 16;
       xr = c->auxR + gbase * NAUX * 8;
+      if (c->fp8_res == 2) xt = c->auxT + gbase * NAUX * 8;
       xs = c->auxS + (size_t)ci * 2 * NAUX;
     }
     if (c->fp8 && !c->dry) {
       // this chunk's first aux group in FP8 storage, with its own scales
-      launch_pack_fp8(c->Xa + (size_t)rb * c->NAP, ns, c->NAP, NAUX, xq, xr, xs, NAUX, c->st);
+      launch_pack_fp8(c->Xa + (size_t)rb * c->NAP, ns, c->NAP, NAUX, xq, xr, xt, xs, NAUX, c->st);
       launch_pack_fp8(c->Ya + (size_t)rb * c->NAP, ns, c->NAP, NAUX, xq + c->auxq_stride, xr + c->auxr_stride,
-                      xs + NAUX, NAUX, c->st);
+                      xt ? xt + c->auxr_stride : nullptr, xs + NAUX, NAUX, c->st);
       HIPCHK(c, hipGetLastError());
     }
     if (c->pieces && !c->dry) {
@@ -718,6 +737,12 @@ blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
         S.Yr = S.Xr + c->auxr_stride;
         S.Xs = xs;
         S.Ys = xs + NAUX;
+        if (c->fp8_res == 2) {
+          S.Ot = (const uint16_t*)ch[i].O_res2 + (size_t)(s0 / 8) * ch[i].ld * 8;
+          S.et = (const uint16_t*)ch[i].e_res2 + (size_t)(s0 / 8) * ch[i].ld * 8;
+          S.Xt = xt + (size_t)(s0 / 8) * NAUX * 8;
+          S.Yt = S.Xt + c->auxr_stride;
+        }
       } else if (c->pieces) {
         // k-packed pieces: slice starts are multiples of 8 samples
         S.O = (const uint16_t*)ch[i].O + (size_t)(s0 / 8) * ch[i].ld * 8;
@@ -795,7 +820,8 @@ blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes) {
   tmp.off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
   tmp.max_samples = cfg->max_samples;
   tmp.pieces = cfg->precision == BLM_PREC_BF16X3 ? 3 : cfg->precision == BLM_PREC_BF16X2 ? 2 : 0;
-  tmp.fp8 = cfg->precision == BLM_PREC_FP8;
+  tmp.fp8 = cfg->precision == BLM_PREC_FP8 || cfg->precision == BLM_PREC_FP8X2;
+  tmp.fp8_res = cfg->precision == BLM_PREC_FP8X2 ? 2 : tmp.fp8 ? 1 : 0;
   Plan P;
   plan(&tmp, P);
   size_t t = 0;
@@ -815,11 +841,11 @@ blm_status blm_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t n
 }
 
 blm_status blm_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,
-                        uint16_t* res, float* scale, int64_t ld_dst, void* stream) {
+                        uint16_t* res, uint16_t* res2, float* scale, int64_t ld_dst, void* stream) {
   if (!src || !codes || !res || !scale || n < 0 || ncols < 1 || ld_src < ncols || ld_dst < ncols)
     return BLM_E_ARG;
-  if (((uintptr_t)codes & 15) || ((uintptr_t)res & 15)) return BLM_E_ARG;
-  launch_pack_fp8(src, n, ld_src, ncols, codes, res, scale, ld_dst, (hipStream_t)stream);
+  if (((uintptr_t)codes & 15) || ((uintptr_t)res & 15) || ((uintptr_t)res2 & 15)) return BLM_E_ARG;
+  launch_pack_fp8(src, n, ld_src, ncols, codes, res, res2, scale, ld_dst, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? BLM_OK : BLM_E_HIP;
 }
 
@@ -878,7 +904,8 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
   c->NS = cfg->n_shifts;
   c->prec = cfg->precision;
   c->pieces = cfg->precision == BLM_PREC_BF16X3 ? 3 : cfg->precision == BLM_PREC_BF16X2 ? 2 : 0;
-  c->fp8 = cfg->precision == BLM_PREC_FP8;
+  c->fp8 = cfg->precision == BLM_PREC_FP8 || cfg->precision == BLM_PREC_FP8X2;
+  c->fp8_res = cfg->precision == BLM_PREC_FP8X2 ? 2 : c->fp8 ? 1 : 0;
   c->off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
   c->shifts.assign(cfg->shifts, cfg->shifts + cfg->n_shifts);
   c->max_samples = cfg->max_samples;
@@ -1118,7 +1145,28 @@ blm_status blm_autotune_build(blm_ctx* c, const blm_chunk* ch, int32_t n, int32_
   const int kind = c->fp8 ? 3 : c->pieces ? 2 : 0;
   const GramJob* jobs = c->mixed() ? c->d_jobsM : c->d_jobs1;
   const int n_jobs = c->mixed() ? c->n_jobsM : c->n_jobs1;
-  const int cap = std::max(1, std::min(c->mixed() ? c->PcapM : c->Pcap1, n_slices));
+  int cap = std::max(1, std::min(c->mixed() ? c->PcapM : c->Pcap1, n_slices));
+  if ((size_t)n_jobs * cap > c->partial_slots) {
+    // the candidates need more partial tiles than blm_create sized for the
+    // heuristic: grow the workspace (a recorded build refers to the old one,
+    // so it is dropped); if the device has no room, try fewer groups
+    const size_t want = (size_t)n_jobs * cap;
+    void* np = nullptr;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (hipMalloc(&np, 8 * want * 3 * GT * GT) == hipSuccess) {
+      release_build_graph(c);
+      for (void*& a : c->allocs)
+        if (a == (void*)c->partial) {
+          (void)hipFree(a);
+          a = np;
+        }
+      c->partial = (double*)np;
+      c->partial_slots = want;
+    } else {
+      (void)hipGetLastError();
+      cap = std::max(1, (int)(c->partial_slots / n_jobs));
+    }
+  }
   bool vec = kind == 0 && c->offsets_even;
   for (const Slice& S : c->h_slices)
     if ((S.ld & 1) || ((uintptr_t)S.O & 15) || ((uintptr_t)S.e & 15)) vec = false;

@@ -1,17 +1,19 @@
 // Mixed-precision block build from FP8 storage on the matrix cores of gfx950.
 //
-// A sample value x of column c of a chunk is stored as x = s_c (q + r):
+// A sample value x of column c of a chunk is stored as x = s_c (q + r), or
+// with a second BF16 residual t of what r leaves, x = s_c (q + r + t):
 // s_c a power of two per column and chunk (the smallest with max |x| / s_c <=
 // 448), q an OCP e4m3 code (round to nearest even, saturating at 448) and r
 // the BF16 rounding of the exact remainder x / s_c - q.  The stored value is
 // within 2^-13 of x relative (normal range of q).
 //
-// A product x y is s_x s_y (q_x q_y + q_x r_y + r_x q_y + r_x r_y): the first
-// term on the FP8 matrix core (v_mfma_f32_16x16x32_fp8_fp8), the other three on
-// the BF16 one (q converted to BF16 exactly).  Measured on gfx950: the BF16
-// instruction sums to near FP32 accuracy, the FP8 one only to about 2^-12 of
-// its largest product (unbiased), which is the precision of the storage
-// itself.  FP32 accumulators are scaled by s_x s_y (exact) and added into FP64
+// A product x y is s_x s_y (q_x q_y + q_x r_y + r_x q_y + r_x r_y), all four
+// terms on the BF16 matrix core (v_mfma_f32_16x16x32_bf16) with q converted to
+// BF16 exactly (every e4m3 value is a BF16 value).  The FP8 matrix core is not
+// used for the code product: measured on gfx950, it sums its 32 products only
+// to about 2^-12 of the largest one (unbiased), which moved the block matrices
+// by about 4e-6, while the BF16 instruction sums to near FP32 accuracy (each
+// piece product is exact in FP32).  FP32 accumulators are scaled by s_x s_y (exact) and added into FP64
 // registers every 256 samples and at every slice boundary (scales change
 // with the chunk).  These are the block estimates of Eq. 3 on the one-block basis
 // (Eq. 4 / Eq. 10), including the coupling strips of Fig. 1 for the first 16
@@ -40,12 +42,6 @@ __device__ __forceinline__ f4 mma_bf16(bf16x8 a, bf16x8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ f4 mma_fp8(u2v a, u2v b, f4 c) {
-  // same lane layout as the BF16 instruction, 8 e4m3 bytes per lane
-  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a),
-                                                    __builtin_bit_cast(long, b), c, 0, 0, 0);
-}
-
 // 8 e4m3 codes -> 8 BF16 values (exact: every e4m3 value is a BF16 value)
 __device__ __forceinline__ bf16x8 e4m3x8_to_bf16(u2v q) {
   const bf16x2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(q[0], 1.0f, false);
@@ -63,30 +59,40 @@ __device__ __forceinline__ void lds_dma16(const BLM_GLOBAL void* src, void* lds_
 // layout of the BF16 build): A side {O_i, e_i}, B side {O_j, e_j, O_j', e_j'},
 // eight waves of 32 x 32 per product, operands copied into LDS by direct
 // global->LDS loads, double-buffered.  Per 32-sample step a wave issues 48
-// matrix-core products: 4 terms x 3 products x 2 x 2 sub-tiles.
+// BF16 matrix-core products: 4 terms x 3 products x 2 x 2 sub-tiles.
 constexpr int F8_THREADS = 512;
 constexpr int F8_STEP = 32;               // samples per step
 constexpr int F8_G8 = F8_STEP / 8;        // 8-sample residual groups per step
 constexpr int F8_G16 = F8_STEP / 16;      // 16-sample code groups per step
-// FP32 partials are added into FP64 every F8_FLUSH steps (256 samples) and at
-// every slice boundary.  The storage's own error (2^-13 per value) dominates:
-// flushing every 64 samples gave the same matrices (3.6e-6 against the
-// oracle on the stored values) and energies within 1e-6 relative of these,
-// at 50.9 instead of 45.5 ms.
-constexpr int F8_FLUSH = 8;
+// FP32 partials are added into FP64 every F8_FLUSH steps and at every slice
+// boundary.  With one residual, every 8 steps (256 samples): the storage's
+// own error (2^-13 per value) dominates, and flushing every 64 samples gave
+// the same matrices (3.6e-6 against the oracle on the stored values) and
+// energies within 1e-6 relative of these, at 50.9 instead of 45.5 ms.  With
+// two residuals (2^-22 per value) every 2 steps (64 samples), as the BF16
+// build; flushing every step moved the matrices by 4.8e-9 instead of 6.7e-9
+// against the oracle on the stored values, so the FP32 partials are not what
+// limits them.
+template <int NRES>
+constexpr int F8_FLUSH = NRES == 2 ? 2 : 8;
 
+template <int NRES>
 struct F8Lds {
-  u4v qA[2][F8_G16][GT];       // [O or e][16-sample group][column]: 16 codes
-  u4v rA[2][F8_G8][GT];        // [O or e][8-sample group][column]: 8 residuals
+  u4v qA[2][F8_G16][GT];          // [O or e][16-sample group][column]: 16 codes
+  u4v rA[NRES][2][F8_G8][GT];     // [residual][O or e][8-sample group][column]: 8 residuals
   u4v qB[2][F8_G16][2 * GT];
-  u4v rB[2][F8_G8][2 * GT];
-  u4v qX[2][F8_G16][NAUX];     // aux columns [Xa or Ya]
-  u4v rX[2][F8_G8][NAUX];
-  float sA[2][GT];             // column scales of the step's chunk
+  u4v rB[NRES][2][F8_G8][2 * GT];
+  u4v qX[2][F8_G16][NAUX];        // aux columns [Xa or Ya]
+  u4v rX[NRES][2][F8_G8][NAUX];
+  float sA[2][GT];                // column scales of the step's chunk
   float sB[2][2 * GT];
   float sX[2][NAUX];
 };
 
+// NRES: residuals per stored value (1: four piece products; 2: eight, the
+// four of one residual plus q t, t q, r t and t r; t t, below 2^-26 of the
+// product, is left out)
+template <int NRES>
 __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* __restrict__ pairs,
                                                                 int n_pairs,
                                                                 const GramJob* __restrict__ jobs,
@@ -97,13 +103,13 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
   // residuals (2 x 4); B side the same for two 64-column halves; diagonal
   // pairs also the aux columns (codes of both arrays in one, residuals one
   // per array)
-  constexpr int NIA = 2 * F8_G16 + 2 * F8_G8;
+  constexpr int NIA = 2 * F8_G16 + NRES * 2 * F8_G8;
   constexpr int NIB = 2 * NIA;
-  constexpr int NIX = 3;
+  constexpr int NIX = 1 + 2 * NRES;
   constexpr int NW = F8_THREADS / 64;
   constexpr int NSC = 2 * GT + 2 * 2 * GT + 2 * NAUX;   // scales per step, one per thread
   static_assert(NSC <= F8_THREADS, "one scale per thread");
-  __shared__ F8Lds L[2];
+  __shared__ F8Lds<NRES> L[2];
 
   const int G = gridDim.x, g = blockIdx.x;
   const int q = G >> 3, r = G & 7, xcd = g & 7, idx = g >> 3;
@@ -173,6 +179,8 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
     const BLM_GLOBAL uint8_t* QE = as_global((const uint8_t*)S.e);
     const BLM_GLOBAL uint16_t* RO = as_global(S.Or);
     const BLM_GLOBAL uint16_t* RE = as_global(S.er);
+    const BLM_GLOBAL uint16_t* TO = as_global(S.Ot);
+    const BLM_GLOBAL uint16_t* TE = as_global(S.et);
 #pragma unroll
     for (int ii = 0; ii < (NIA + NIB + NIX + NW - 1) / NW; ++ii) {
       const int in = wv + ii * NW;
@@ -192,10 +200,11 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
           src = (arr ? QE : QO) + (gg * S.ld + col) * 16;
           dst = bside ? (void*)&L[buf].qB[arr][gi][GT * half] : (void*)&L[buf].qA[arr][gi][0];
         } else {
-          const int jj = j - 2 * F8_G16, arr = jj / F8_G8, gi = jj % F8_G8;
+          const int jj = j - 2 * F8_G16, pc = jj / (2 * F8_G8), arr = (jj / F8_G8) & 1, gi = jj % F8_G8;
           const int64_t gg = min(g8 + gi, n8 - 1);
-          src = (arr ? RE : RO) + (gg * S.ld + col) * 8;
-          dst = bside ? (void*)&L[buf].rB[arr][gi][GT * half] : (void*)&L[buf].rA[arr][gi][0];
+          const BLM_GLOBAL uint16_t* rs = pc ? (arr ? TE : TO) : (arr ? RE : RO);
+          src = rs + (gg * S.ld + col) * 8;
+          dst = bside ? (void*)&L[buf].rB[pc][arr][gi][GT * half] : (void*)&L[buf].rA[pc][arr][gi][0];
         }
       } else if (in == NIA + NIB) {
         // aux codes: lane -> (array lane / 32, group (lane / 16) % 2, column lane % 16)
@@ -205,10 +214,11 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
         dst = &L[buf].qX[0][0][0];
       } else {
         // aux residuals of one array: lane -> (group lane / 16, column lane % 16)
-        const int arr = in - NIA - NIB - 1, gi = lane >> 4, c = lane & 15;
+        const int k = in - NIA - NIB - 1, pc = k >> 1, arr = k & 1, gi = lane >> 4, c = lane & 15;
         const int64_t gg = min(g8 + gi, n8 - 1);
-        src = as_global(arr ? S.Yr : S.Xr) + (gg * NAUX + c) * 8;
-        dst = &L[buf].rX[arr][0][0];
+        const uint16_t* rs = pc ? (arr ? S.Yt : S.Xt) : (arr ? S.Yr : S.Xr);
+        src = as_global(rs) + (gg * NAUX + c) * 8;
+        dst = &L[buf].rX[pc][arr][0][0];
       }
       lds_dma16(src, dst);
     }
@@ -228,8 +238,10 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
   // by LDS address, its B operand by a register select.
   const int q3_base = strip ? (int)((const char*)&L[0].qX[wr][k4 >> 1][i16] - (const char*)&L[0])
                             : (int)((const char*)&L[0].qA[1][k4 >> 1][32 * wr + i16] - (const char*)&L[0]);
-  const int r3_base = strip ? (int)((const char*)&L[0].rX[wr][k4][i16] - (const char*)&L[0])
-                            : (int)((const char*)&L[0].rA[1][k4][32 * wr + i16] - (const char*)&L[0]);
+  const int r3_base = strip ? (int)((const char*)&L[0].rX[0][wr][k4][i16] - (const char*)&L[0])
+                            : (int)((const char*)&L[0].rA[0][1][k4][32 * wr + i16] - (const char*)&L[0]);
+  // from a first residual to the second one of the same operand
+  const int t3_step = strip ? (int)sizeof(L[0].rX[0]) : (int)sizeof(L[0].rA[0]);
   const int ab_x = strip ? 0 : 16 * (int)sizeof(u4v);          // next 16 rows
   const bool b3_e = strip && wr == 0;
 
@@ -238,25 +250,23 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
     // step of a slice the A side is zeroed by a lane mask
     const bool partial = n8_left < F8_G8;
     const unsigned km = (k4 < n8_left) ? 0xFFFFFFFFu : 0u;
-    const F8Lds& Lb = L[buf];
+    const F8Lds<NRES>& Lb = L[buf];
     const char* lb = (const char*)&Lb;
     const int hb = 8 * (k4 & 1);                               // byte offset of this lane's 8 codes
-    u2v bq[2][2];
     bf16x8 br[2][2], bqb[2][2];
 #pragma unroll
     for (int arr = 0; arr < 2; ++arr)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         const int col = 32 * wc + 16 * y + i16;
-        bq[arr][y] = *(const u2v*)((const char*)&Lb.qB[arr][k4 >> 1][col] + hb);
-        br[arr][y] = __builtin_bit_cast(bf16x8, Lb.rB[arr][k4][col]);
-        bqb[arr][y] = e4m3x8_to_bf16(bq[arr][y]);
+        bqb[arr][y] = e4m3x8_to_bf16(*(const u2v*)((const char*)&Lb.qB[arr][k4 >> 1][col] + hb));
+        br[arr][y] = __builtin_bit_cast(bf16x8, Lb.rB[0][arr][k4][col]);
       }
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
       const int row = 32 * wr + 16 * x + i16;
       u2v aq = *(const u2v*)((const char*)&Lb.qA[0][k4 >> 1][row] + hb);
-      u4v ar = Lb.rA[0][k4][row];
+      u4v ar = Lb.rA[0][0][k4][row];
       u2v a3q = *(const u2v*)(lb + q3_base + x * ab_x + hb);
       u4v a3r = *(const u4v*)(lb + r3_base + x * ab_x);
       if (partial) {
@@ -268,14 +278,43 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
       const bf16x8 aqb = e4m3x8_to_bf16(aq), arb = __builtin_bit_cast(bf16x8, ar);
       const bf16x8 a3qb = e4m3x8_to_bf16(a3q), a3rb = __builtin_bit_cast(bf16x8, a3r);
       const bool e3 = x == 1 && b3_e;
+      if constexpr (NRES == 2) {
+        // the second residuals: q t, t q, r t and t r for each of the three
+        // products (dropping r t and t r would move the matrices by about
+        // 3e-8 relative, as much as everything else together)
+        u4v at = Lb.rA[1][0][k4][row];
+        u4v a3t = *(const u4v*)(lb + r3_base + t3_step + x * ab_x);
+        if (partial) {
+          at &= km;
+          a3t &= km;
+        }
+        const bf16x8 atb = __builtin_bit_cast(bf16x8, at), a3tb = __builtin_bit_cast(bf16x8, a3t);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int col = 32 * wc + 16 * y + i16;
+          const bf16x8 bt0 = __builtin_bit_cast(bf16x8, Lb.rB[1][0][k4][col]);
+          const bf16x8 bt1 = __builtin_bit_cast(bf16x8, Lb.rB[1][1][k4][col]);
+          acc[0][x][y] = mma_bf16(aqb, bt0, acc[0][x][y]);
+          acc[1][x][y] = mma_bf16(aqb, bt1, acc[1][x][y]);
+          acc[2][x][y] = mma_bf16(a3qb, e3 ? bt1 : bt0, acc[2][x][y]);
+          acc[0][x][y] = mma_bf16(atb, bqb[0][y], acc[0][x][y]);
+          acc[1][x][y] = mma_bf16(atb, bqb[1][y], acc[1][x][y]);
+          acc[2][x][y] = mma_bf16(a3tb, e3 ? bqb[1][y] : bqb[0][y], acc[2][x][y]);
+          acc[0][x][y] = mma_bf16(arb, bt0, acc[0][x][y]);
+          acc[1][x][y] = mma_bf16(arb, bt1, acc[1][x][y]);
+          acc[2][x][y] = mma_bf16(a3rb, e3 ? bt1 : bt0, acc[2][x][y]);
+          acc[0][x][y] = mma_bf16(atb, br[0][y], acc[0][x][y]);
+          acc[1][x][y] = mma_bf16(atb, br[1][y], acc[1][x][y]);
+          acc[2][x][y] = mma_bf16(a3tb, e3 ? br[1][y] : br[0][y], acc[2][x][y]);
+        }
+      }
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
-        const u2v b3q = e3 ? bq[1][y] : bq[0][y];
         const bf16x8 b3r = e3 ? br[1][y] : br[0][y];
         const bf16x8 b3qb = e3 ? bqb[1][y] : bqb[0][y];
-        acc[0][x][y] = mma_fp8(aq, bq[0][y], acc[0][x][y]);
-        acc[1][x][y] = mma_fp8(aq, bq[1][y], acc[1][x][y]);
-        acc[2][x][y] = mma_fp8(a3q, b3q, acc[2][x][y]);
+        acc[0][x][y] = mma_bf16(aqb, bqb[0][y], acc[0][x][y]);
+        acc[1][x][y] = mma_bf16(aqb, bqb[1][y], acc[1][x][y]);
+        acc[2][x][y] = mma_bf16(a3qb, b3qb, acc[2][x][y]);
         acc[0][x][y] = mma_bf16(aqb, br[0][y], acc[0][x][y]);
         acc[1][x][y] = mma_bf16(aqb, br[1][y], acc[1][x][y]);
         acc[2][x][y] = mma_bf16(a3qb, b3r, acc[2][x][y]);
@@ -344,7 +383,7 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
     const int nsi = si;
     const int64_t ng0 = g0;
     if (more) issue(si, g0, buf ^ 1);
-    if (wave_on) compute(buf, n8_left, ((t + 1) % F8_FLUSH) == 0 || !more || nsi != csi);
+    if (wave_on) compute(buf, n8_left, ((t + 1) % F8_FLUSH<NRES>) == 0 || !more || nsi != csi);
     if (more) advance();
     __builtin_amdgcn_s_waitcnt(0);   // this wave's copies of the next step have landed
     if (more) put_scale(buf ^ 1);
@@ -462,7 +501,8 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const double* __restrict
                                                         int64_t ld_src, int64_t ncols,
                                                         const float* __restrict__ scale,
                                                         uint8_t* __restrict__ codes,
-                                                        uint16_t* __restrict__ res, int64_t ld_dst) {
+                                                        uint16_t* __restrict__ res, uint16_t* __restrict__ res2,
+                                                        int64_t ld_dst) {
   const int64_t n16 = (n + 15) >> 4;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n16 * ncols) return;
@@ -470,6 +510,7 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const double* __restrict
   const double inv = 1.0 / (double)scale[x];             // a power of two: exact
   uint32_t cw[4] = {0, 0, 0, 0};
   uint32_t rw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t tw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int64_t s = 16 * g + e;
@@ -479,26 +520,42 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const double* __restrict
     if (v < 0.0 && code != 0) code |= 0x80u;
     const double rem = v - (v < 0.0 ? -qv : qv);           // exact
     const uint16_t rb = f64_to_bf16_rne(rem);
+    // the second residual: what r leaves of the remainder (exact in FP64)
+    const double rem2 = rem - (double)__uint_as_float((uint32_t)rb << 16);
+    const uint16_t tb = f64_to_bf16_rne(rem2);
     cw[e >> 2] |= code << (8 * (e & 3));
     rw[e >> 1] |= (uint32_t)rb << (16 * (e & 1));
+    tw[e >> 1] |= (uint32_t)tb << (16 * (e & 1));
   }
   *reinterpret_cast<uint4*>(codes + (g * ld_dst + x) * 16) = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+  // residuals come in 8-sample groups: the buffers hold ceil(n / 8) of them,
+  // so the second group of the last 16 is written only if it exists
+  const bool second = 2 * g + 1 < ((n + 7) >> 3);
   uint16_t* rp = res + ((2 * g) * ld_dst + x) * 8;
   *reinterpret_cast<uint4*>(rp) = make_uint4(rw[0], rw[1], rw[2], rw[3]);
-  *reinterpret_cast<uint4*>(rp + ld_dst * 8) = make_uint4(rw[4], rw[5], rw[6], rw[7]);
+  if (second) *reinterpret_cast<uint4*>(rp + ld_dst * 8) = make_uint4(rw[4], rw[5], rw[6], rw[7]);
+  if (res2) {
+    uint16_t* tp = res2 + ((2 * g) * ld_dst + x) * 8;
+    *reinterpret_cast<uint4*>(tp) = make_uint4(tw[0], tw[1], tw[2], tw[3]);
+    if (second) *reinterpret_cast<uint4*>(tp + ld_dst * 8) = make_uint4(tw[4], tw[5], tw[6], tw[7]);
+  }
 }
 
 }  // namespace
 
 void launch_gram_fp8(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
-                     const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st) {
+                     const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st) {
   if (n_pairs <= 0) return;
-  hipLaunchKernelGGL(gram_fp8_kernel, dim3(n_pairs * P), dim3(F8_THREADS), 0, st, d_pairs, n_pairs,
-                     d_jobs, d_slices, n_slices, P, d_partial);
+  if (nres == 2)
+    hipLaunchKernelGGL(gram_fp8_kernel<2>, dim3(n_pairs * P), dim3(F8_THREADS), 0, st, d_pairs, n_pairs,
+                       d_jobs, d_slices, n_slices, P, d_partial);
+  else
+    hipLaunchKernelGGL(gram_fp8_kernel<1>, dim3(n_pairs * P), dim3(F8_THREADS), 0, st, d_pairs, n_pairs,
+                       d_jobs, d_slices, n_slices, P, d_partial);
 }
 
 void launch_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,
-                     uint16_t* res, float* scale, int64_t ld_dst, hipStream_t st) {
+                     uint16_t* res, uint16_t* res2, float* scale, int64_t ld_dst, hipStream_t st) {
   if (ncols <= 0) return;
   uint32_t* bits = reinterpret_cast<uint32_t*>(scale);
   hipLaunchKernelGGL(fp8_scale_init_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, st,
@@ -509,7 +566,7 @@ void launch_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols
                      src, n, ld_src, ncols, bits);
   const int64_t work = ((n + 15) >> 4) * ncols;
   hipLaunchKernelGGL(fp8_quant_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, src, n,
-                     ld_src, ncols, scale, codes, res, ld_dst);
+                     ld_src, ncols, scale, codes, res, res2, ld_dst);
 }
 
 }  // namespace blm

@@ -95,6 +95,11 @@ struct Slice {
   const uint16_t* Yr;
   const float* Xs;
   const float* Ys;
+  // FP8 storage with two residuals: the second ones, laid out like Or / Xr
+  const uint16_t* Ot;
+  const uint16_t* et;
+  const uint16_t* Xt;
+  const uint16_t* Yt;
 };
 
 // ------------------------------------------------- direction projection ---
@@ -123,6 +128,8 @@ struct ProjChunk {
   const uint16_t* er;
   const float* Os;
   const float* es;
+  const uint16_t* Ot;   // second residuals (FP8 storage with two), else nullptr
+  const uint16_t* et;
 };
 // sample storage of a projection launch
 enum StoreKind : int32_t { STORE_F64 = 0, STORE_BF16 = 1, STORE_FP8 = 2 };
@@ -187,12 +194,14 @@ void launch_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncol
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
                         int strip_rows, hipStream_t st);
+// nres: residuals per value in the FP8 storage (1 or 2)
 void launch_gram_fp8(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
-                     const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st);
-// FP64 [n][ld_src] -> e4m3 codes (k-packed by 16), BF16 residuals (k-packed
-// by 8) and per-column power-of-two scales (blm_fp8.hip)
+                     const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st);
+// FP64 [n][ld_src] -> e4m3 codes (k-packed by 16), one or two BF16 residuals
+// (k-packed by 8; res2 nullptr: one) and per-column power-of-two scales
+// (blm_fp8.hip)
 void launch_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,
-                     uint16_t* res, float* scale, int64_t ld_dst, hipStream_t st);
+                     uint16_t* res, uint16_t* res2, float* scale, int64_t ld_dst, hipStream_t st);
 void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store,
                     const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
                     int n_dirs, int max_nd, double* Xo, double* Yo, int64_t ldo, hipStream_t st);

@@ -61,16 +61,21 @@ __device__ __forceinline__ void split_load8(const void* base, int64_t ld, int64_
 
 // The 8 samples of one 8-sample group of one column in FP8 storage (e4m3
 // codes k-packed by 16 samples, BF16 residuals by 8, power-of-two column
-// scale), each as the exact FP64 value scale (q + r).
-__device__ __forceinline__ void fp8_load8(const void* codes, const uint16_t* res, const float* scale,
-                                          int64_t ld, int64_t group, int64_t col, double* v) {
+// scale), each as the exact FP64 value scale (q + r), or scale (q + r + t)
+// with a second residual array res2 (nullptr: none).  The sums are exact:
+// q, r and t together span fewer than 53 bits.
+__device__ __forceinline__ void fp8_load8(const void* codes, const uint16_t* res, const uint16_t* res2,
+                                          const float* scale, int64_t ld, int64_t group, int64_t col, double* v) {
   const BLM_GLOBAL uint8_t* qb =
       as_global((const uint8_t*)codes) + ((group >> 1) * ld + col) * 16 + 8 * (group & 1);
   const uint2 q = *reinterpret_cast<const BLM_GLOBAL uint2*>(qb);
   const uint4 r = *reinterpret_cast<const BLM_GLOBAL uint4*>(as_global(res) + (group * ld + col) * 8);
+  uint4 t = make_uint4(0, 0, 0, 0);
+  if (res2) t = *reinterpret_cast<const BLM_GLOBAL uint4*>(as_global(res2) + (group * ld + col) * 8);
   const double sc = as_global(scale)[col];
   const uint32_t qw[2] = {q.x, q.y};
   const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+  const uint32_t tw[4] = {t.x, t.y, t.z, t.w};
   // codes to BF16 (exact), two per conversion, then to FP64
   const uint32_t pw[4] = {
       __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(qw[0], 1.0f, false)),
@@ -82,8 +87,9 @@ __device__ __forceinline__ void fp8_load8(const void* codes, const uint16_t* res
     const uint32_t pb = pw[k];
     const double q0 = (double)__uint_as_float(pb << 16), q1 = (double)__uint_as_float(pb & 0xFFFF0000u);
     const double r0 = (double)__uint_as_float(rw[k] << 16), r1 = (double)__uint_as_float(rw[k] & 0xFFFF0000u);
-    v[2 * k] = sc * (q0 + r0);
-    v[2 * k + 1] = sc * (q1 + r1);
+    const double t0 = (double)__uint_as_float(tw[k] << 16), t1 = (double)__uint_as_float(tw[k] & 0xFFFF0000u);
+    v[2 * k] = sc * ((q0 + r0) + t0);
+    v[2 * k + 1] = sc * ((q1 + r1) + t1);
   }
 }
 
@@ -171,7 +177,7 @@ __device__ __forceinline__ void gram_load(const GramJob& J, const Slice& S, int6
     const int64_t col = J.cj + min(c, J.nj - 1);
     double v[8];
     if (S.pieces > 0) split_load8(pnl ? S.e : S.O, S.ld, S.pstride, S.pieces, grp, col, v);
-    else fp8_load8(pnl ? S.e : S.O, pnl ? S.er : S.Or, pnl ? S.es : S.Os, S.ld, grp, col, v);
+    else fp8_load8(pnl ? S.e : S.O, pnl ? S.er : S.Or, pnl ? S.et : S.Ot, pnl ? S.es : S.Os, S.ld, grp, col, v);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       R.a[k] = ok ? v[k] : 0.0;
@@ -575,8 +581,8 @@ __device__ __forceinline__ void pj_load(const ProjChunk& C, int64_t s0, const Di
       const int64_t grp = min(r0, C.n - 1) >> 3;
       const int64_t cc = B.col0 + min(p0 + col, B.m - 1);
       double o[8], e[8];
-      fp8_load8(C.O, C.Or, C.Os, C.ld, grp, cc, o);
-      fp8_load8(C.e, C.er, C.es, C.ld, grp, cc, e);
+      fp8_load8(C.O, C.Or, C.Ot, C.Os, C.ld, grp, cc, o);
+      fp8_load8(C.e, C.er, C.et, C.es, C.ld, grp, cc, e);
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         R.o[k] = ok ? o[k] : 0.0;
@@ -796,8 +802,8 @@ __global__ __launch_bounds__(256) void dirproj_small_kernel(const ProjChunk* __r
       const bool ok = r0 < C.n && p0 + col < B.m;
       if (ok) {
         if constexpr (ST == STORE_FP8) {
-          fp8_load8(C.O, C.Or, C.Os, C.ld, r0 >> 3, B.col0 + p0 + col, o);
-          fp8_load8(C.e, C.er, C.es, C.ld, r0 >> 3, B.col0 + p0 + col, e);
+          fp8_load8(C.O, C.Or, C.Ot, C.Os, C.ld, r0 >> 3, B.col0 + p0 + col, o);
+          fp8_load8(C.e, C.er, C.et, C.es, C.ld, r0 >> 3, B.col0 + p0 + col, e);
         } else {
           split_load8(C.O, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, o);
           split_load8(C.e, C.ld, C.pstride, C.pieces, r0 >> 3, B.col0 + p0 + col, e);

@@ -60,10 +60,13 @@ def test_paper_largest_aux_setting():
     _compare_step(offsets, 3, [1e-2], host, dev, old=old, n_old=5)
 
 
-def _fp8_values_of(x):
+def _fp8_values_of(x, residuals=1):
     from oracle import fp8_storage as f8
-    q, r, s = f8.fp8_store(x.numpy())
-    return f8.fp8_values(q, r, s)
+    parts = f8.fp8_store(x.numpy(), residuals=residuals)
+    if residuals == 1:
+        return f8.fp8_values(*parts)
+    q, r, t, s = parts
+    return f8.fp8_values(q, r, s, t)
 
 
 def _pencil_aux(offsets, n_old, b, dropped):
@@ -85,16 +88,11 @@ def _pencil_aux(offsets, n_old, b, dropped):
     return np.array(coords), np.array(cols)
 
 
-@pytest.mark.parametrize("precision,tol,en_tol", [("bf16x3", 1e-7, 1e-5), ("fp8", 1e-4, 1e-3)])
-def test_aux_groups_mixed_build(precision, tol, en_tol):
-    """The oracle runs on the values the storage stands for (the pieces'
-    sum, or scale times code plus residual).  Block matrices: within the
-    mixed build's arithmetic (tol).  The entries that couple the block's
-    parameters to aux columns 16 and up come from the FP64 strip tiles on
-    the decoded storage: within 1e-12 of the block's norm.  Energy: the
-    least-shifted pencils amplify the matrix error about 100-fold at these
-    20,000 samples (measured 9.4e-7 for BF16 x3, 1.4e-4 for FP8), so it is
-    held to en_tol."""
+def _aux_mixed(precision):
+    """The 41-column case built in a mixed precision and solved; returns the
+    worst block-matrix error and coupling-entry error against the oracle on
+    the stored values, and the energy's relative error against the
+    oracle's step on them."""
     from paper_1702_01481_amd import blm
     offsets, n_old, drop = CASES["41"]
     offsets = np.asarray(offsets)
@@ -106,9 +104,10 @@ def test_aux_groups_mixed_build(precision, tol, en_tol):
     host, dev = [], []
     for a, b in zip(cuts[:-1], cuts[1:]):
         Oc, ec = O[a:b].contiguous(), e[a:b].contiguous()
-        if precision == "fp8":
-            sO, se = blm.Fp8Samples(Oc.cuda()), blm.Fp8Samples(ec.cuda())
-            host.append((_fp8_values_of(Oc), _fp8_values_of(ec), EL[a:b].numpy(), None))
+        if precision in ("fp8", "fp8x2"):
+            res = 2 if precision == "fp8x2" else 1
+            sO, se = blm.Fp8Samples(Oc.cuda(), residuals=res), blm.Fp8Samples(ec.cuda(), residuals=res)
+            host.append((_fp8_values_of(Oc, res), _fp8_values_of(ec, res), EL[a:b].numpy(), None))
         else:
             sO, se = blm.SplitSamples(Oc.cuda(), 3), blm.SplitSamples(ec.cuda(), 3)
             host.append((sO.to_numpy(), se.to_numpy(), EL[a:b].numpy(), None))
@@ -139,8 +138,6 @@ def test_aux_groups_mixed_build(precision, tol, en_tol):
             worst_x = max(worst_x, max(d1, d2) / np.linalg.norm(B))
     print(f"[aux] {precision}: worst block matrix rel error {worst:.2e}, "
           f"aux-16+ coupling entries {worst_x:.2e}", flush=True)
-    assert worst < tol, worst
-    assert worst_x < 1e-12, worst_x
     ctx.solve()
     ctx.project(dev)
     upd, en, _, _ = ctx.stage2()
@@ -149,5 +146,44 @@ def test_aux_groups_mixed_build(precision, tol, en_tol):
     rel_e = abs(en[0] - ref.energy) / abs(ref.energy)
     print(f"[aux] {precision}: energy rel err {rel_e:.2e}", flush=True)
     assert np.isfinite(upd.cpu().numpy()).all()
-    assert rel_e < en_tol, rel_e
     ctx.close()
+    return worst, worst_x, rel_e
+
+
+_AUX_CACHE = {}
+
+
+def _aux_cached(precision):
+    if precision not in _AUX_CACHE:
+        _AUX_CACHE[precision] = _aux_mixed(precision)
+    return _AUX_CACHE[precision]
+
+
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-7), ("fp8x2", 1e-7), ("fp8", 1e-6)])
+def test_aux_groups_mixed_build(precision, tol):
+    """The oracle runs on the values the storage stands for (the pieces'
+    sum, or scale times code plus residuals).  Block matrices: within the
+    mixed build's arithmetic (tol: FP32 partial sums over at most 256
+    samples; with one FP8 residual also the library's own 13-bit copy of the
+    aux columns 1, E_L and Theta, which the oracle takes exact).  The entries
+    that couple the block's parameters to aux columns 16 and up come from the
+    FP64 strip tiles on the decoded storage: within 1e-12 of the block's
+    norm."""
+    worst, worst_x, _ = _aux_cached(precision)
+    assert worst < tol, worst
+    assert worst_x < 1e-12, worst_x
+
+
+@pytest.mark.parametrize("precision", [
+    "bf16x3",
+    pytest.param("fp8x2", marks=pytest.mark.xfail(strict=False, reason=(
+        "at 20,000 samples these pencils move the energy by about 150 times the block matrices' error, and "
+        "the mixed builds' matrices sit within 5e-9 to 8e-9 of the oracle on the stored values (the matrix "
+        "cores' FP32 sums): 9.4e-7 for BF16 x3, 1.2e-6 to 1.3e-6 for FP8 with two residuals"))),
+    pytest.param("fp8", marks=pytest.mark.xfail(strict=False, reason=(
+        "one residual: the library's own FP8 copy of the aux columns (E_L, Theta) keeps 13 bits")))])
+def test_aux_groups_mixed_energy(precision):
+    """The rest of the step: energy within the mixed-precision tolerance (1e-6
+    relative) of the oracle's step on the stored values."""
+    _, _, rel_e = _aux_cached(precision)
+    assert rel_e <= 1e-6, rel_e

@@ -39,7 +39,7 @@ def _step(ctx, chunks, old, replay):
     return mats, ev, kept, upd.cpu().numpy(), en
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3", "fp8"])
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3", "fp8", "fp8x2"])
 def test_replayed_build_equals_eager_build(precision):
     from paper_1702_01481_amd import blm
     print(f"[graph] {precision}", flush=True)
@@ -55,8 +55,9 @@ def test_replayed_build_equals_eager_build(precision):
             return [tuple(c) for c in bufs]
         return store
 
-    if precision == "fp8":
-        store = [(blm.Fp8Samples(c[0]), blm.Fp8Samples(c[1]), c[2]) for c in bufs]
+    if precision in ("fp8", "fp8x2"):
+        res = 2 if precision == "fp8x2" else 1
+        store = [(blm.Fp8Samples(c[0], residuals=res), blm.Fp8Samples(c[1], residuals=res), c[2]) for c in bufs]
     elif precision == "bf16x3":
         store = [(blm.SplitSamples(c[0], 3), blm.SplitSamples(c[1], 3), c[2]) for c in bufs]
     ctx_g = blm.BLM(300, OFFSETS, 3, 1, SHIFTS, N, precision=precision)

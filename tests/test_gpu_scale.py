@@ -63,9 +63,12 @@ def workload():
     torch.cuda.empty_cache()
 
 
-def _fp8_stored(x):
-    q, r, s = f8.fp8_store(x)
-    return f8.fp8_values(q, r, s)
+def _fp8_stored(x, residuals=1):
+    parts = f8.fp8_store(x, residuals=residuals)
+    if residuals == 1:
+        return f8.fp8_values(*parts)
+    q, r, t, s = parts
+    return f8.fp8_values(q, r, s, t)
 
 
 def _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th, transform=None):
@@ -230,31 +233,33 @@ def test_full_size_mixed_precision(workload):
     ctx.close()
 
 
-def test_full_size_fp8(workload):
-    """The same step on FP8 storage (e4m3 codes, column scales, BF16
-    residuals).  Sampled block-matrix entries against the oracle's sums of
-    the values the storage stands for (the oracle's own FP8 storage of the
-    same columns): within 1e-5 of the Frobenius norm, the remaining error
-    being the FP8 matrix core's ~12-bit sums.  (The Theta columns are
-    checked against stored values in the small FP8 build test.)
-    Energy and update against the FP64 step: the storage moves every sample
-    value by up to 2^-13 and the block matrices by about 2.4e-6 relative, so
-    for a shift at which every block keeps as many directions as in FP64,
-    energy within 2e-4 relative and update cosine above 0.999.  At a shift
-    where that perturbation moves the N_K cut (a near-degenerate pair at the
-    cut splitting into a real eigenvalue and a pair; it happens on this
-    workload at 1e-3), the step is a different BLM step: reported, not
-    compared.  That FP8 storage does not meet 1e-6 is the measured cost of
-    its 13-bit values."""
+@pytest.mark.parametrize("prec,residuals", [("fp8x2", 2), ("fp8", 1)])
+def test_full_size_fp8(workload, prec, residuals):
+    """The same step on FP8 storage (e4m3 codes, column scales, one or two
+    BF16 residuals).  Sampled block-matrix entries against the oracle's sums
+    of the values the storage stands for (the oracle's own FP8 storage of the
+    same columns): within 1e-7 of the Frobenius norm, the remaining error
+    being the FP32 partial sums (at most 256 samples, rounding within 2^-24
+    each).  (The Theta columns are checked against stored values in the
+    small FP8 build test.)  Energy and update against the FP64 step:
+    with two residuals (22 significant bits) at the mixed-precision
+    tolerance, energy within 1e-6 relative and update cosine at least
+    0.9999 at every shift.  With one residual (13 bits) the storage moves the
+    block matrices by about 1e-6 relative: energy within 1e-4 and cosine
+    above 0.999 at shifts where every block keeps as many directions as in
+    FP64; where the perturbation moves the N_K cut (a near-degenerate pair at
+    the cut splitting into a real eigenvalue and a pair) the step is a
+    different BLM step and is reported, not compared."""
     from paper_1702_01481_amd import blm
     if "old" not in workload:
         pytest.skip("needs the FP64 full-size step")
     w, chunks, old = workload["w"], workload["chunks"], workload["old"]
     offsets = np.asarray(w.block_offsets)
     shifts = list(w.shifts)
-    f8c = [(blm.Fp8Samples(O), blm.Fp8Samples(e), EL) for O, e, EL in chunks]
+    f8c = [(blm.Fp8Samples(O, residuals=residuals), blm.Fp8Samples(e, residuals=residuals), EL)
+           for O, e, EL in chunks]
     torch.cuda.synchronize()
-    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.n_samples, precision="fp8")
+    ctx = blm.BLM(w.n_params, offsets, w.n_keep, w.n_old, shifts, w.n_samples, precision=prec)
     upd, en, kept = _step(ctx, f8c, torch.from_numpy(old).cuda().contiguous())
     b, k, si = CHECK_BLOCK, THETA_BLOCK, SHIFT
     delta = shifts[si]
@@ -267,7 +272,8 @@ def test_full_size_fp8(workload):
     Bb = ctx.directions(b, si)
     rng = np.random.default_rng(13)
     pcols = np.sort(rng.choice(M, 6, replace=False)) + 1
-    sS, sH, _, _ = _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th, transform=_fp8_stored)
+    sS, sH, _, _ = _oracle_sums(chunks, offsets, b, k, D, Bb, pcols, th,
+                                transform=lambda x: _fp8_stored(x, residuals))
     idx = np.concatenate([[0], pcols])                # without the Theta column
     sS, sH = sS[:-1, :-1], sH[:-1, :-1]
     P = np.zeros((d, d))
@@ -275,8 +281,8 @@ def test_full_size_fp8(workload):
     H_un = H_gpu - delta * P
     eS = np.abs(S_gpu[np.ix_(idx, idx)] - sS).max() / np.linalg.norm(S_gpu)
     eH = np.abs(H_un[np.ix_(idx, idx)] - sH).max() / np.linalg.norm(H_un)
-    print(f"[scale] fp8 entries: S {eS:.2e}, H {eH:.2e} of the Frobenius norm", flush=True)
-    assert eS <= 1e-5 and eH <= 1e-5, (eS, eH)
+    print(f"[scale] {prec} entries: S {eS:.2e}, H {eH:.2e} of the Frobenius norm", flush=True)
+    assert eS <= 1e-7 and eH <= 1e-7, (eS, eH)
     compared = 0
     for s_i in range(len(shifts)):
         e64 = workload["energy"][s_i]
@@ -285,11 +291,16 @@ def test_full_size_fp8(workload):
         um = upd[s_i].cpu().numpy()
         cos = um @ u64 / (np.linalg.norm(um) * np.linalg.norm(u64))
         same_cut = np.array_equal(kept[s_i], workload["kept"][s_i])
-        print(f"[scale] fp8 shift {shifts[s_i]}: energy rel err {rel:.2e}, update cosine {cos:.10f}, "
+        print(f"[scale] {prec} shift {shifts[s_i]}: energy rel err {rel:.2e}, update cosine {cos:.10f}, "
               f"kept {kept[s_i].tolist()} vs FP64 {workload['kept'][s_i].tolist()}", flush=True)
-        if same_cut:
+        if residuals == 2:
+            assert same_cut, s_i
+            assert rel <= 1e-6, (s_i, rel)
+            assert cos >= 0.9999, (s_i, cos)
             compared += 1
-            assert rel <= 2e-4, (s_i, rel)
+        elif same_cut:
+            compared += 1
+            assert rel <= 1e-4, (s_i, rel)
             assert cos >= 0.999, (s_i, cos)
     assert compared >= 1
     ctx.close()
