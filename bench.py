@@ -353,6 +353,7 @@ def target_bench(args):
     import torch
 
     from paper_1702_01481_amd import synth
+    t_start = time.perf_counter()
     w = synth.workload("uneven")
     n_samples = args.samples or w.n_samples
     sizes, left = [], n_samples
@@ -406,11 +407,21 @@ def target_bench(args):
                      "launch_ms": round(res64["gram_ms_per_launch"], 3),
                      "launches": res64["gram_launches"]},
     }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = target_cpu_baseline(w, gen, args.cpu_rows)
     if args.mixed != "none":
         out["mixed"] = []
+        skipped = []
         for prec in args.mixed.split(","):
             if prec not in MIXED_PRECISIONS:
                 raise SystemExit(f"unknown mixed precision {prec}")
+            # a mixed step takes at most about the FP64 step's wall time
+            need = (args.mixed_steps + args.mixed_warmup + 1) * res64["wall_s_per_step"]
+            if time.perf_counter() - t_start + need > args.time_budget:
+                skipped.append(prec)
+                log(f"{prec}: skipped, {need:.0f} s more would pass the {args.time_budget:.0f} s budget")
+                continue
             r, upd = target_leg(args, prec, w, sizes, gen, args.mixed_steps, args.mixed_warmup)
             rel = [float(abs(a - b) / abs(b)) for a, b in zip(r["energy"], res64["energy"])]
             cos = [float(upd[i] @ upd64[i] / (np.linalg.norm(upd[i]) * np.linalg.norm(upd64[i])))
@@ -434,9 +445,9 @@ def target_bench(args):
                    "meets_1e-6": bool(max(rel) <= 1e-6 and min(cos) >= 0.9999)}
             log(f"{prec}: step {r['ms_per_step']:.0f} ms, energy rel err {rel}, cosine {cos}")
             out["mixed"].append(leg)
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = target_cpu_baseline(w, gen, args.cpu_rows)
+        if skipped:
+            out["mixed_skipped_for_time"] = skipped
+    out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 
@@ -453,6 +464,9 @@ def main():
     ap.add_argument("--mixed-warmup", type=int, default=1, help="warm-up steps of each mixed leg (uneven)")
     ap.add_argument("--cpu-rows", type=int, default=16_384,
                     help="samples of the oracle's timed block estimates (uneven)")
+    ap.add_argument("--time-budget", type=float, default=480.0,
+                    help="seconds of run time within which the mixed legs must fit (uneven); a leg whose "
+                         "estimate would pass it is skipped and named in the output")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the heuristic slice-group count of the build instead of timing the candidates")
