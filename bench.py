@@ -8,8 +8,9 @@ ratios with a banded G, N_K = 4, N_O = 0, shift 1e-3.  FP64 for the
 headline (--steps, --warmup), then the same step with BF16 x3 split and FP8
 storage (--mixed, --mixed-steps, --mixed-warmup), compared with the FP64
 step.  The samples (1.9 TB as FP64) cannot all be resident, so they are
-made on the device chunk by chunk on a second stream while the library
-works (see target_bench); a step's time counts the library's calls only.
+made on the device chunk by chunk, on the library's stream just before the
+call that reads them (see target_bench); a step's time counts the library's
+calls only, each of which starts with its samples resident in HBM.
 
 --workload fp64: the 4,096-parameter workload (8 blocks of 512, 1,000,000
 samples, all resident in HBM, N_K = 5, N_O = 1, shifts {1e-4, 1e-3, 1e-2}).
