@@ -341,20 +341,29 @@ class BLMResult:
 
 
 def blm_step(chunk_source: Callable[[], Iterable[tuple]], offsets, n_keep: int,
-             shifts: Sequence[float], old: Optional[np.ndarray] = None) -> Tuple[List[BLMResult], List[BlockProblem]]:
+             shifts: Sequence[float], old: Optional[np.ndarray] = None,
+             progress: Optional[Callable[[str], None]] = None) -> Tuple[List[BLMResult], List[BlockProblem]]:
     """One BLM iteration per shift (Sec. II.B): block estimates (first pass
     over the samples), block solves and kept directions, stage-two estimates
     (second pass over the same samples), stage-two solve and update.
-    chunk_source() must yield the same chunks each time it is called."""
+    chunk_source() must yield the same chunks each time it is called.
+    progress (optional) is called with a line of text after each phase and
+    each block solve; it does not change the result."""
+    say = progress if progress is not None else (lambda msg: None)
     offsets = np.asarray(offsets, dtype=np.int64)
     D = previous_directions(old, offsets)
     probs, _ = block_problems(chunk_source(), offsets, D)
+    say(f"block estimates of {len(probs)} blocks done")
     out = []
     for delta in shifts:
-        blocks = [solve_block(p, delta, n_keep) for p in probs]
+        blocks = []
+        for b, p in enumerate(probs):
+            blocks.append(solve_block(p, delta, n_keep))
+            say(f"shift {delta:g}: block {b} (d = {p.H.shape[0]}) solved")
         Bs = [r.B for r in blocks]
         H2, S2, _ = stage2_matrices(chunk_source(), offsets, Bs)
         out.append(BLMResult(blocks, H2, S2, stage2_solve(H2, S2, Bs, offsets, delta)))
+        say(f"shift {delta:g}: stage two done")
     return out, probs
 
 
