@@ -36,7 +36,10 @@ library routines, brute force, and the special cases in which the BLM reduces
 to the traditional linear method exactly).  The generic BLM update (N_K < M_b,
 noisy data, no previous direction equal to the LM step) is defined only by
 the algorithm itself; it is pinned through those special cases of the same
-code, not by an independent value.
+code, not by an independent value.  The excited-state target's functions
+(omega_*) are pinned the same way: brute force, the expansion in the energy
+estimates, planted exact eigenstates (ground and first excited) and the
+reductions of the BLM to the LM.
 """
 from __future__ import annotations
 
@@ -364,6 +367,119 @@ def blm_step(chunk_source: Callable[[], Iterable[tuple]], offsets, n_keep: int,
         H2, S2, _ = stage2_matrices(chunk_source(), offsets, Bs)
         out.append(BLMResult(blocks, H2, S2, stage2_solve(H2, S2, Bs, offsets, delta)))
         say(f"shift {delta:g}: stage two done")
+    return out, probs
+
+
+# ---------------------------------------------------------------------------
+# excited-state target Omega (Sec. II.B remark, Sec. III.D)
+# ---------------------------------------------------------------------------
+#
+# Omega = <Psi|(omega - H)|Psi> / <Psi|(omega - H)^2|Psi>; with omega inside
+# the gap its minimum is the first eigenstate above omega.  The BLM applies
+# to it with the pencil of Eq. 1 replaced by the Omega pencil on the same
+# basis: for basis functions Psi_i with sample ratios xbar_s (as obar_s for
+# the energy) and ybar_s (H applied, as ebar_s), let f_s = omega xbar_s - ybar_s
+# be the sample ratios of (omega - H) Psi_i.  Then
+#   A_ij = <Psi_i|(omega - H)|Psi_j>   estimated as sum_s w_s f_s,i xbar_s,j
+#          ((omega - H) applied to the left function),
+#   B_ij = <Psi_i|(omega - H)^2|Psi_j> estimated as sum_s w_s f_s,i f_s,j,
+# both divided by the total weight, and (A + delta P) c = lambda B c is solved
+# for its lowest eigenvalues, lambda estimating Omega.  With the left
+# application, an exact eigenstate in the span stays an exact eigenvector of
+# the sampled pencil (zero variance), as H c = E S c does for the energy.
+
+def _omega_pair(X, Y, w, omega):
+    F = omega * X - Y
+    Fw = F * w[:, None]
+    return Fw.T @ X, Fw.T @ F
+
+
+def omega_lm_matrices(chunks: Iterable[tuple], omega: float) -> Tuple[np.ndarray, np.ndarray, float]:
+    """A and B of the Omega target on the basis [Psi, Psi^1 .. Psi^N_V]
+    (the traditional LM's basis), divided by the total weight."""
+    A = B = None
+    W = 0.0
+    for O, e, EL, w in chunks:
+        n = O.shape[0]
+        w = _weights(w, n)
+        X = np.hstack([np.ones((n, 1)), O])
+        Y = np.hstack([np.asarray(EL).reshape(n, 1), e])
+        a_c, b_c = _omega_pair(X, Y, w, omega)
+        A = a_c if A is None else A + a_c
+        B = b_c if B is None else B + b_c
+        W += float(w.sum())
+    return A / W, B / W, W
+
+
+def omega_block_problems(chunks: Iterable[tuple], offsets: np.ndarray, D: List[np.ndarray],
+                         omega: float) -> Tuple[List[BlockProblem], float]:
+    """Per-block Omega pencils on the basis of Eq. 10 (as block_problems):
+    each BlockProblem holds A_b in place of H_b and B_b in place of S_b."""
+    nb = len(offsets) - 1
+    acc_A = [None] * nb
+    acc_B = [None] * nb
+    W = 0.0
+    for O, e, EL, w in chunks:
+        n = O.shape[0]
+        w = _weights(w, n)
+        T = [O[:, offsets[k]:offsets[k + 1]] @ D[k].T for k in range(nb)]
+        U = [e[:, offsets[k]:offsets[k + 1]] @ D[k].T for k in range(nb)]
+        for b in range(nb):
+            others = [k for k in range(nb) if k != b]
+            X = np.hstack([np.ones((n, 1)), O[:, offsets[b]:offsets[b + 1]]] + [T[k] for k in others])
+            Y = np.hstack([np.asarray(EL).reshape(n, 1), e[:, offsets[b]:offsets[b + 1]]]
+                          + [U[k] for k in others])
+            a_c, b_c = _omega_pair(X, Y, w, omega)
+            acc_A[b] = a_c if acc_A[b] is None else acc_A[b] + a_c
+            acc_B[b] = b_c if acc_B[b] is None else acc_B[b] + b_c
+        W += float(w.sum())
+    probs = []
+    for b in range(nb):
+        M = int(offsets[b + 1] - offsets[b])
+        theta = [(k, j) for k in range(nb) if k != b for j in range(D[k].shape[0])]
+        d = 1 + M + len(theta)
+        P = np.zeros((d, d))
+        P[1:1 + M, 1:1 + M] = np.eye(M)
+        for a, (ka, ja) in enumerate(theta):
+            for c, (kc, jc) in enumerate(theta):
+                if ka == kc:
+                    P[1 + M + a, 1 + M + c] = D[ka][ja] @ D[kc][jc]
+        probs.append(BlockProblem(acc_A[b] / W, acc_B[b] / W, P, M, theta))
+    return probs, W
+
+
+def omega_stage2_matrices(chunks: Iterable[tuple], offsets: np.ndarray, Bs: List[np.ndarray],
+                          omega: float) -> Tuple[np.ndarray, np.ndarray, float]:
+    """A2 and B2 of the Omega target on the stage-two basis of Eq. 6."""
+    nb = len(offsets) - 1
+    A = B = None
+    W = 0.0
+    for O, e, EL, w in chunks:
+        n = O.shape[0]
+        w = _weights(w, n)
+        Y = np.hstack([np.ones((n, 1))] + [O[:, offsets[b]:offsets[b + 1]] @ Bs[b].T for b in range(nb)])
+        Z = np.hstack([np.asarray(EL).reshape(n, 1)] + [e[:, offsets[b]:offsets[b + 1]] @ Bs[b].T for b in range(nb)])
+        a_c, b_c = _omega_pair(Y, Z, w, omega)
+        A = a_c if A is None else A + a_c
+        B = b_c if B is None else B + b_c
+        W += float(w.sum())
+    return A / W, B / W, W
+
+
+def omega_blm_step(chunk_source: Callable[[], Iterable[tuple]], offsets, n_keep: int, shifts: Sequence[float],
+                   omega: float, old: Optional[np.ndarray] = None) -> Tuple[List[BLMResult], List[BlockProblem]]:
+    """One BLM iteration for the Omega target per shift: the steps of
+    blm_step with the Omega pencils.  step.energy is the stage-two estimate
+    of Omega; BLMResult.H2 / S2 hold A2 / B2."""
+    offsets = np.asarray(offsets, dtype=np.int64)
+    D = previous_directions(old, offsets)
+    probs, _ = omega_block_problems(chunk_source(), offsets, D, omega)
+    out = []
+    for delta in shifts:
+        blocks = [solve_block(p, delta, n_keep) for p in probs]
+        Bs = [r.B for r in blocks]
+        A2, B2, _ = omega_stage2_matrices(chunk_source(), offsets, Bs, omega)
+        out.append(BLMResult(blocks, A2, B2, stage2_solve(A2, B2, Bs, offsets, delta)))
     return out, probs
 
 

@@ -363,26 +363,36 @@ def dyadic_chunk(n_rows: int, n_params: int, seed: int, index: int = 0):
 
 
 def planted_zero_variance(dim_hilbert: int, n_params: int, seed: int, n_samples: int = 0):
-    """A finite Hilbert-space model whose tangent space holds the exact
-    ground state (the setting of the strong zero-variance principle).
+    """planted_eigenstate(..., state=0) without the spectrum: the ground
+    state planted; returns (O, e, EL, w, Delta, E0)."""
+    O, e, EL, w, delta, evals = planted_eigenstate(dim_hilbert, n_params, seed, 0, n_samples)
+    return O, e, EL, w, delta, float(evals[0])
+
+
+def planted_eigenstate(dim_hilbert: int, n_params: int, seed: int, state: int = 0, n_samples: int = 0):
+    """A finite Hilbert-space model whose tangent space holds an exact
+    eigenstate, the ground state (state 0) or an excited one (the setting of
+    the strong zero-variance principle).
 
     A random symmetric Hamiltonian matrix Hf on `dim_hilbert` basis states
-    has ground state phi0 (energy E0).  Psi is positive and bounded away from
-    zero; the derivative vectors Psi^x are random except the last, which is
-    solved for so that Psi + sum_x Delta_x Psi^x = phi0 for a random Delta.
+    has eigenstates phi_k (energies E_k, ascending).  Psi is positive and
+    bounded away from zero; the derivative vectors Psi^x are random except
+    the last, which is solved for so that Psi + sum_x Delta_x Psi^x is
+    phi_state (scaled) for a random Delta.
     Per basis state n: O[n, x] = Psi^x(n)/Psi(n), EL[n] = (Hf Psi)(n)/Psi(n),
     e[n, x] = (Hf Psi^x)(n)/Psi(n).
 
     n_samples == 0: exact enumeration, weights Psi(n)^2.
     n_samples > 0: states drawn uniformly, weights Psi(n)^2 / (1/dim).
-    Returns (O, e, EL, w, Delta, E0) as float64 numpy arrays / floats.
+    Returns (O, e, EL, w, Delta, evals) as float64 numpy arrays, evals the
+    whole spectrum of Hf.
     """
     g = _gen("cpu", seed, 0xC0FFEE)
     f64 = torch.float64
     A = torch.randn(dim_hilbert, dim_hilbert, generator=g, dtype=f64).numpy()
     Hf = 0.5 * (A + A.T)
     evals, evecs = np.linalg.eigh(Hf)
-    E0, phi0 = float(evals[0]), evecs[:, 0]
+    phi0 = evecs[:, state]
     psi = 1.0 + torch.rand(dim_hilbert, generator=g, dtype=f64).numpy()
     dpsi = 0.5 * torch.randn(n_params, dim_hilbert, generator=g, dtype=f64).numpy()
     delta = 0.3 * torch.randn(n_params, generator=g, dtype=f64).numpy()
@@ -395,7 +405,7 @@ def planted_zero_variance(dim_hilbert: int, n_params: int, seed: int, n_samples:
     e_all = ((Hf @ dpsi.T).T / psi).T
     if n_samples == 0:
         w = psi ** 2
-        return O_all, e_all, EL_all, w, delta, E0
+        return O_all, e_all, EL_all, w, delta, evals
     idx = torch.randint(0, dim_hilbert, (n_samples,), generator=g).numpy()
     w = psi[idx] ** 2 * dim_hilbert
-    return O_all[idx], e_all[idx], EL_all[idx], w, delta, E0
+    return O_all[idx], e_all[idx], EL_all[idx], w, delta, evals
