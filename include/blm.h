@@ -78,6 +78,27 @@ typedef enum {
                                 (see blm_pack_fp8) */
 } blm_layout;
 
+/* What a step minimises.
+ * BLM_TARGET_ENERGY: the energy, the pencil of Eq. 1 on each basis (Eq. 3
+ *   estimates: S = sum w obar obar^T, H = sum w obar ebar^T).
+ * BLM_TARGET_OMEGA: the excited-state target Omega = <(omega - H)> /
+ *   <(omega - H)^2> of Sec. III.D, whose minimum with omega inside the gap is
+ *   the first eigenstate above omega.  The BLM applies to it unchanged with
+ *   the Omega pencil on the same bases: with f_s = omega obar_s - ebar_s,
+ *   A = sum w f obar^T = omega S - H^T ((omega - H) applied to the left basis
+ *   function) and B = sum w f f^T = omega^2 S - omega (H + H^T) + E,
+ *   E = sum w ebar ebar^T, all divided by the total weight; the solves take
+ *   (A + delta P) c = lambda B c (B symmetric positive definite) and the
+ *   energies returned are the estimates lambda of Omega.  The left
+ *   application keeps an exact eigenstate in the span an exact eigenvector
+ *   of the sampled pencil, as H c = E S c does for the energy.  E costs a
+ *   second Gram pass over the same chunks inside each blm_build_blocks and
+ *   blm_project. */
+typedef enum {
+  BLM_TARGET_ENERGY = 0,
+  BLM_TARGET_OMEGA = 1
+} blm_target;
+
 /* Flags returned per shift by blm_stage2 (bit mask). */
 enum {
   BLM_FLAG_COMPLEX_ENERGY = 1u,   /* the stage-two lowest eigenvalue is complex; energy = real part */
@@ -95,6 +116,8 @@ typedef struct {
   const double* shifts;          /* host [n_shifts], each >= 0 */
   int32_t precision;             /* blm_precision */
   int64_t max_samples;           /* most samples in one build / project call (sum over its chunks) */
+  int32_t target;                /* blm_target (BLM_TARGET_ENERGY: 0) */
+  double omega;                  /* BLM_TARGET_OMEGA: the energy shift omega (finite); else unused */
 } blm_config;
 
 typedef struct {                 /* one chunk of samples; device memory, caller-owned */
@@ -153,6 +176,16 @@ blm_status blm_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t nc
 /* Bytes of device memory blm_create will allocate for this configuration. */
 blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes);
 
+/* The part of that workspace which holds the block estimates themselves
+ * (Sec. II.B, Fig. 1): each block's H_b and S_b sums (S in whole tiles),
+ * the aux Gram, and the coupling strips aux^T O, aux^T e and auxE^T O over
+ * all parameters (plus the Omega target's sums of ebar ebar^T in the same
+ * layout).  It is the storage the paper counts per process (N_V^2 / N_B +
+ * 3 N_V N_O (N_B - 1) elements of 8 bytes, 0.5 GB at N_V = 30,000, N_B = 100,
+ * N_O = 5), with whole S tiles and the aux columns padded to groups of 16.
+ * Computes without allocating; errors as blm_workspace_bytes. */
+blm_status blm_accumulator_bytes(const blm_config* cfg, size_t* bytes);
+
 /* Allocates the context and its device workspace.  stream is a hipStream_t
  * (NULL = the null stream).  The library owns the workspace until
  * blm_destroy. */
@@ -207,7 +240,8 @@ blm_status blm_autotune_build(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_c
  * the recording.  Event timing (blm_set_timing) does not cover a replayed
  * build: its phases keep the last call-by-call build's times.  blm_replay_build returns BLM_E_STATE without a
  * recording; blm_capture_build returns BLM_E_ARG for empty or bad chunks
- * and BLM_E_HIP if the runtime refuses the capture. */
+ * and BLM_E_HIP if the runtime refuses the capture; BLM_E_ARG too for a
+ * context of the Omega target (its build makes a second pass). */
 blm_status blm_capture_build(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chunks);
 blm_status blm_replay_build(blm_ctx* ctx);
 
@@ -274,7 +308,8 @@ blm_status blm_batch_stage2(blm_batch* batch, double* const* d_update, double* c
 /* Diagnostics (valid after blm_solve_blocks).  Block b's normalised matrices
  * on the basis [Psi, Psi^{i,b}, Theta_jk (k != b, kept j, k-major)], with
  * the shift of index `shift` added to H.  h_H, h_S: host [dim][dim] row-major;
- * *dim receives the dimension (call with h_H == NULL to query it). */
+ * *dim receives the dimension (call with h_H == NULL to query it).  For the
+ * Omega target, the pencil solved: A + delta P in h_H and B in h_S. */
 blm_status blm_get_block_matrices(blm_ctx* ctx, int32_t block, int32_t shift, double* h_H,
                                   double* h_S, int32_t* dim);
 
@@ -283,7 +318,8 @@ blm_status blm_get_directions(blm_ctx* ctx, int32_t block, int32_t shift, double
                               int32_t* n_rows);
 
 /* Stage-two matrices of a shift (valid after blm_project + blm_stage2),
- * normalised, unshifted: basis [Psi, B^(0) rows, B^(1) rows, ...]. */
+ * normalised, unshifted: basis [Psi, B^(0) rows, B^(1) rows, ...].  For the
+ * Omega target, A2 in h_H2 and B2 in h_S2. */
 blm_status blm_get_stage2_matrices(blm_ctx* ctx, int32_t shift, double* h_H2, double* h_S2,
                                    int32_t* dim);
 

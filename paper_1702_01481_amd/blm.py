@@ -23,7 +23,7 @@ FLAG_COMPLEX_ENERGY, FLAG_PAIR_KEPT, FLAG_SMALL_ALPHA = 1, 2, 4
 
 PRECISIONS = {"fp64": 0, "bf16x2": 1, "bf16x3": 2, "fp8": 3, "fp8x2": 4}
 
-EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_create", "blm_destroy", "blm_begin_step",
+EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_accumulator_bytes", "blm_create", "blm_destroy", "blm_begin_step",
             "blm_build_blocks", "blm_autotune_build", "blm_capture_build", "blm_replay_build",
             "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
@@ -45,7 +45,11 @@ class _Config(C.Structure):
     _fields_ = [("n_params", C.c_int64), ("n_blocks", C.c_int32),
                 ("block_offsets", C.POINTER(C.c_int64)), ("n_keep", C.c_int32),
                 ("n_old", C.c_int32), ("n_shifts", C.c_int32), ("shifts", C.POINTER(C.c_double)),
-                ("precision", C.c_int32), ("max_samples", C.c_int64)]
+                ("precision", C.c_int32), ("max_samples", C.c_int64), ("target", C.c_int32),
+                ("omega", C.c_double)]
+
+
+TARGETS = {"energy": 0, "omega": 1}
 
 
 class _Chunk(C.Structure):
@@ -71,6 +75,7 @@ def load() -> C.CDLL:
     lib.blm_pack_bf16.argtypes = [vp, i64, i64, i64, i32, vp, i64, i64, vp]
     lib.blm_pack_fp8.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i64, vp]
     lib.blm_workspace_bytes.argtypes = [C.POINTER(_Config), C.POINTER(C.c_size_t)]
+    lib.blm_accumulator_bytes.argtypes = [C.POINTER(_Config), C.POINTER(C.c_size_t)]
     lib.blm_create.argtypes = [C.POINTER(_Config), vp, C.POINTER(vp)]
     lib.blm_destroy.argtypes = [vp]
     lib.blm_begin_step.argtypes = [vp, vp]
@@ -281,7 +286,10 @@ class BLM:
     """One BLM optimisation context (blm_create .. blm_destroy)."""
 
     def __init__(self, n_params: int, block_offsets: Sequence[int], n_keep: int, n_old: int,
-                 shifts: Sequence[float], max_samples: int, stream=None, precision: str = "fp64"):
+                 shifts: Sequence[float], max_samples: int, stream=None, precision: str = "fp64",
+                 target: str = "energy", omega: float = 0.0):
+        """target "omega": the excited-state target with energy shift omega
+        (blm_target in blm.h); energies are then estimates of Omega."""
         self.lib = load()
         self.n_params = int(n_params)
         self.offsets = np.ascontiguousarray(block_offsets, dtype=np.int64)
@@ -292,7 +300,8 @@ class BLM:
         self.precision = precision
         self._cfg = _Config(self.n_params, self.n_blocks, self.offsets.ctypes.data_as(C.POINTER(C.c_int64)),
                             self.n_keep, self.n_old, len(self.shifts), _dptr(self.shifts),
-                            PRECISIONS[precision], self.max_samples)
+                            PRECISIONS[precision], self.max_samples, TARGETS[target], float(omega))
+        self.target, self.omega = target, float(omega)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         self._check(self.lib.blm_create(C.byref(self._cfg), C.c_void_p(_stream_handle(self.stream)), C.byref(h)),
@@ -310,14 +319,29 @@ class BLM:
 
     @staticmethod
     def workspace_bytes(n_params, block_offsets, n_keep, n_old, shifts, max_samples,
-                        precision: str = "fp64") -> int:
+                        precision: str = "fp64", target: str = "energy") -> int:
         lib = load()
         off = np.ascontiguousarray(block_offsets, dtype=np.int64)
         sh = np.ascontiguousarray(shifts, dtype=np.float64)
         cfg = _Config(n_params, len(off) - 1, off.ctypes.data_as(C.POINTER(C.c_int64)), n_keep, n_old,
-                      len(sh), _dptr(sh), PRECISIONS[precision], max_samples)
+                      len(sh), _dptr(sh), PRECISIONS[precision], max_samples, TARGETS[target], 0.0)
         out = C.c_size_t()
         st = lib.blm_workspace_bytes(C.byref(cfg), C.byref(out))
+        if st != BLM_OK:
+            raise BLMError(st, lib.blm_status_string(st).decode())
+        return int(out.value)
+
+    @staticmethod
+    def accumulator_bytes(n_params, block_offsets, n_keep, n_old, shifts, max_samples,
+                          precision: str = "fp64", target: str = "energy") -> int:
+        """Bytes of the block estimates' accumulators (blm_accumulator_bytes)."""
+        lib = load()
+        off = np.ascontiguousarray(block_offsets, dtype=np.int64)
+        sh = np.ascontiguousarray(shifts, dtype=np.float64)
+        cfg = _Config(n_params, len(off) - 1, off.ctypes.data_as(C.POINTER(C.c_int64)), n_keep, n_old,
+                      len(sh), _dptr(sh), PRECISIONS[precision], max_samples, TARGETS[target], 0.0)
+        out = C.c_size_t()
+        st = lib.blm_accumulator_bytes(C.byref(cfg), C.byref(out))
         if st != BLM_OK:
             raise BLMError(st, lib.blm_status_string(st).decode())
         return int(out.value)

@@ -135,6 +135,12 @@ struct blm_ctx {
   double* d_coef = nullptr;        // [NS][NB][EIG_MAXSEL]
   int32_t* d_blk_of = nullptr;     // [NV]
   double* d_wsum = nullptr;        // [2] pass-1 and pass-2 total weight
+  // excited-state target: the sums of ebar ebar^T, laid out as accS (block
+  // tiles and aux Gram), strips and G2S, from a second Gram pass
+  int target = BLM_TARGET_ENERGY;
+  double omega = 0.0;
+  double *accE = nullptr, *stripsE = nullptr, *G2E = nullptr;
+  std::vector<Slice> h_slices_e;   // slice table of the second pass
 
   // step state
   std::vector<int> dkeep;          // [NB][NO]
@@ -218,49 +224,74 @@ __global__ __launch_bounds__(256) void theta_mgs_kernel(double* D, int64_t NV, i
   }
 }
 
+// Where a pencil's entries come from: the block accumulators (and, for the
+// Omega target, the sums of ebar ebar^T in the same layouts) and the
+// stage-two Gram.
+struct AsmSrc {
+  const double *accS, *accH, *strips, *G2S, *G2H;
+  const double *accE, *stripsE, *G2E;
+  int64_t NV, aux_off, ld2;
+  int32_t nap, target;
+  double omega;
+};
+
+// Unnormalised S and H entries (x, y) of a pencil, from accumulators laid
+// out as accS / accH / strips / G2S / G2H.
+__device__ __forceinline__ void asm_fetch(const AsmJob& J, int x, int y, const double* __restrict__ accS,
+                                          const double* __restrict__ accH, const double* __restrict__ strips,
+                                          const double* __restrict__ G2S, const double* __restrict__ G2H,
+                                          const AsmSrc& R, double& s, double& h) {
+  if (J.kind == 1) {
+    const int a = J.idx2[x], b = J.idx2[y];
+    s = G2S[(size_t)std::min(a, b) * R.ld2 + std::max(a, b)];
+    h = G2H[(size_t)a * R.ld2 + b];
+    return;
+  }
+  const int M = J.M;
+  const bool px = (x >= 1 && x <= M), py = (y >= 1 && y <= M);
+  const int ax = (x == 0) ? J.aux_idx[0] : J.aux_idx[x > M ? x - M : 0];
+  const int ay = (y == 0) ? J.aux_idx[0] : J.aux_idx[y > M ? y - M : 0];
+  const int64_t p = x - 1, q = y - 1;
+  const size_t S0 = 0, S1 = (size_t)R.nap * R.NV, S2 = 2 * (size_t)R.nap * R.NV;
+  if (px && py) {
+    s = accS[J.acc_off + std::min(p, q) * M + std::max(p, q)];
+    h = accH[J.acc_off + p * M + q];
+  } else if (!px && py) {
+    s = strips[S0 + (size_t)ax * R.NV + J.off_b + q];
+    h = strips[S1 + (size_t)ax * R.NV + J.off_b + q];
+  } else if (px && !py) {
+    s = strips[S0 + (size_t)ay * R.NV + J.off_b + p];
+    h = strips[S2 + (size_t)ay * R.NV + J.off_b + p];
+  } else {
+    s = accS[R.aux_off + std::min(ax, ay) * R.nap + std::max(ax, ay)];
+    h = accH[R.aux_off + ax * R.nap + ay];
+  }
+}
+
 // Pencil assembly from the accumulators, normalised by the total weight,
-// with the diagonal shift on every coordinate but Psi's.
-__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs,
-                                                       const double* __restrict__ accS,
-                                                       const double* __restrict__ accH,
-                                                       const double* __restrict__ strips,
-                                                       int64_t NV, int64_t aux_off, int nap,
-                                                       const double* __restrict__ G2S,
-                                                       const double* __restrict__ G2H,
-                                                       int64_t ld2) {
+// with the diagonal shift on every coordinate but Psi's.  Energy target:
+// (H + delta P, S).  Omega target: (A + delta P, B) with A = omega S - H^T
+// and B = omega^2 S - omega (H + H^T) + E, E from the second pass.
+__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, AsmSrc R) {
   const AsmJob J = jobs[blockIdx.x];
   const int d = J.d;
   const size_t n = (size_t)d * d;
-  const double W = (J.kind == 0) ? accS[aux_off] : G2S[0];
+  const double W = (J.kind == 0) ? R.accS[R.aux_off] : R.G2S[0];
   const double inv = 1.0 / W;
   for (size_t t = (size_t)blockIdx.y * blockDim.x + threadIdx.x; t < n;
        t += (size_t)gridDim.y * blockDim.x) {
     const int x = (int)(t / d), y = (int)(t % d);
     double s, h;
-    if (J.kind == 1) {
-      const int a = J.idx2[x], b = J.idx2[y];
-      s = G2S[(size_t)std::min(a, b) * ld2 + std::max(a, b)];
-      h = G2H[(size_t)a * ld2 + b];
-    } else {
-      const int M = J.M;
-      const bool px = (x >= 1 && x <= M), py = (y >= 1 && y <= M);
-      const int ax = (x == 0) ? J.aux_idx[0] : J.aux_idx[x > M ? x - M : 0];
-      const int ay = (y == 0) ? J.aux_idx[0] : J.aux_idx[y > M ? y - M : 0];
-      const int64_t p = x - 1, q = y - 1;
-      const size_t S0 = 0, S1 = (size_t)nap * NV, S2 = 2 * (size_t)nap * NV;
-      if (px && py) {
-        s = accS[J.acc_off + std::min(p, q) * M + std::max(p, q)];
-        h = accH[J.acc_off + p * M + q];
-      } else if (!px && py) {
-        s = strips[S0 + (size_t)ax * NV + J.off_b + q];
-        h = strips[S1 + (size_t)ax * NV + J.off_b + q];
-      } else if (px && !py) {
-        s = strips[S0 + (size_t)ay * NV + J.off_b + p];
-        h = strips[S2 + (size_t)ay * NV + J.off_b + p];
-      } else {
-        s = accS[aux_off + std::min(ax, ay) * nap + std::max(ax, ay)];
-        h = accH[aux_off + ax * nap + ay];
-      }
+    asm_fetch(J, x, y, R.accS, R.accH, R.strips, R.G2S, R.G2H, R, s, h);
+    if (R.target == BLM_TARGET_OMEGA) {
+      double s_t, h_t, e, e_h;
+      asm_fetch(J, y, x, R.accS, R.accH, R.strips, R.G2S, R.G2H, R, s_t, h_t);   // h_t = H[y][x]
+      asm_fetch(J, x, y, R.accE, R.accE, R.stripsE, R.G2E, R.G2E, R, e, e_h);   // e = E[x][y]
+      const double w = R.omega;
+      const double a = w * s - h_t;                       // A = omega S - H^T
+      const double b = (w * w) * s - w * (h + h_t) + e;   // B = omega^2 S - omega (H + H^T) + E
+      h = a;
+      s = b;
     }
     s *= inv;
     h *= inv;
@@ -268,6 +299,25 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict_
     J.S[t] = s;
     J.A[t] = h;
   }
+}
+
+AsmSrc asm_src(const blm_ctx* c, int64_t ld2) {
+  AsmSrc R{};
+  R.accS = c->accS;
+  R.accH = c->accH;
+  R.strips = c->strips;
+  R.G2S = c->G2S;
+  R.G2H = c->G2H;
+  R.accE = c->accE;
+  R.stripsE = c->stripsE;
+  R.G2E = c->G2E;
+  R.NV = c->NV;
+  R.aux_off = c->aux_off;
+  R.ld2 = ld2;
+  R.nap = c->NAP;
+  R.target = c->target;
+  R.omega = c->omega;
+  return R;
 }
 
 // update[s][x] = sum_r coef[s][b][r] B^(s,b)_r[x - off_b]  (Eq. 8)
@@ -315,6 +365,10 @@ blm_status validate(const blm_config* cfg, blm_ctx* c) {
       cfg->precision != BLM_PREC_BF16X3 && cfg->precision != BLM_PREC_FP8 && cfg->precision != BLM_PREC_FP8X2)
     return fail(c, BLM_E_ARG, "unsupported precision");
   if (cfg->max_samples < 1) return fail(c, BLM_E_ARG, "max_samples must be >= 1");
+  if (cfg->target != BLM_TARGET_ENERGY && cfg->target != BLM_TARGET_OMEGA)
+    return fail(c, BLM_E_ARG, "unknown target");
+  if (cfg->target == BLM_TARGET_OMEGA && !std::isfinite(cfg->omega))
+    return fail(c, BLM_E_ARG, "omega must be finite");
   if (cfg->block_offsets[0] != 0 || cfg->block_offsets[cfg->n_blocks] != cfg->n_params)
     return fail(c, BLM_E_ARG, "block_offsets must run from 0 to n_params");
   for (int b = 0; b < cfg->n_blocks; ++b) {
@@ -393,6 +447,10 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->accS, 8 * (size_t)c->acc_elems);
   add((void**)&c->accH, 8 * (size_t)c->acc_elems);
   add((void**)&c->strips, 8 * (size_t)3 * c->NAP * NV);
+  const bool om = c->target == BLM_TARGET_OMEGA;
+  add((void**)&c->accE, om ? 8 * (size_t)c->acc_elems : 0);
+  add((void**)&c->stripsE, om ? 8 * (size_t)3 * c->NAP * NV : 0);
+  add((void**)&c->G2E, om ? 8 * (size_t)c->n2max * c->n2max : 0);
   add((void**)&c->partial, 8 * slots * 3 * GT * GT);
   add((void**)&c->d_off, 8 * (size_t)(NB + 1));
   add((void**)&c->d_jobs1, sizeof(GramJob) * (size_t)c->n_jobs1);
@@ -822,11 +880,32 @@ blm_status blm_workspace_bytes(const blm_config* cfg, size_t* bytes) {
   tmp.pieces = cfg->precision == BLM_PREC_BF16X3 ? 3 : cfg->precision == BLM_PREC_BF16X2 ? 2 : 0;
   tmp.fp8 = cfg->precision == BLM_PREC_FP8 || cfg->precision == BLM_PREC_FP8X2;
   tmp.fp8_res = cfg->precision == BLM_PREC_FP8X2 ? 2 : tmp.fp8 ? 1 : 0;
+  tmp.target = cfg->target;
   Plan P;
   plan(&tmp, P);
   size_t t = 0;
   for (auto& it : P.items) t += (it.second + 255) / 256 * 256;
   *bytes = t + eig_total_bytes(&tmp);
+  return BLM_OK;
+}
+
+blm_status blm_accumulator_bytes(const blm_config* cfg, size_t* bytes) {
+  blm_ctx tmp;
+  blm_status s = validate(cfg, &tmp);
+  if (s != BLM_OK) return s;
+  if (!bytes) return BLM_E_ARG;
+  tmp.NV = cfg->n_params;
+  tmp.NB = cfg->n_blocks;
+  tmp.NK = cfg->n_keep;
+  tmp.NO = cfg->n_old;
+  tmp.NS = cfg->n_shifts;
+  tmp.off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
+  tmp.max_samples = cfg->max_samples;
+  tmp.target = cfg->target;
+  Plan P;
+  plan(&tmp, P);
+  const size_t one = 8 * ((size_t)2 * tmp.acc_elems + (size_t)3 * tmp.NAP * tmp.NV);
+  *bytes = tmp.target == BLM_TARGET_OMEGA ? one + 8 * ((size_t)tmp.acc_elems + (size_t)3 * tmp.NAP * tmp.NV) : one;
   return BLM_OK;
 }
 
@@ -909,6 +988,8 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
   c->off.assign(cfg->block_offsets, cfg->block_offsets + cfg->n_blocks + 1);
   c->shifts.assign(cfg->shifts, cfg->shifts + cfg->n_shifts);
   c->max_samples = cfg->max_samples;
+  c->target = cfg->target;
+  c->omega = cfg->omega;
   c->st = (hipStream_t)stream;
   c->offsets_even = true;
   for (int64_t o : c->off)
@@ -996,6 +1077,10 @@ blm_status blm_begin_step(blm_ctx* c, const double* d_old) {
   HIPCHK(c, hipMemsetAsync(c->accS, 0, 8 * (size_t)c->acc_elems, c->st));
   HIPCHK(c, hipMemsetAsync(c->accH, 0, 8 * (size_t)c->acc_elems, c->st));
   HIPCHK(c, hipMemsetAsync(c->strips, 0, 8 * (size_t)3 * c->NAP * c->NV, c->st));
+  if (c->target == BLM_TARGET_OMEGA) {
+    HIPCHK(c, hipMemsetAsync(c->accE, 0, 8 * (size_t)c->acc_elems, c->st));
+    HIPCHK(c, hipMemsetAsync(c->stripsE, 0, 8 * (size_t)3 * c->NAP * c->NV, c->st));
+  }
   c->dkeep.assign((size_t)c->NB * c->NO, 0);
   if (c->NO > 0) {
     if (d_old) {
@@ -1033,22 +1118,58 @@ blm_status blm_begin_step(blm_ctx* c, const double* d_old) {
 
 // The launches of one block build on chunks already checked: aux columns
 // and slice table, then the Gram launches (issued on c->st, or recorded).
+// The slice table of the Omega target's second pass: e in place of O and
+// the aux columns [E_L, u] in place of [1, t], in every storage, so that
+// the Gram launches' first product, with its strips and the aux Gram, sums
+// ebar ebar^T.
+static void swap_to_e(std::vector<Slice>& v) {
+  for (Slice& S : v) {
+    S.O = S.e;
+    S.Xa = S.Ya;
+    S.Xp = S.Yp;
+    S.Or = S.er;
+    S.Os = S.es;
+    S.Ot = S.et;
+    S.Xq = S.Yq;
+    S.Xr = S.Yr;
+    S.Xs = S.Ys;
+    S.Xt = S.Yt;
+  }
+}
+
+// The Gram launches of one build pass into the given accumulators (h
+// nullptr: the H products are not kept).
+static blm_status build_grams(blm_ctx* c, double* accS, double* accH, double* strips, bool timed) {
+  if (c->mixed()) {
+    // FP64 aux Gram and further aux groups' strips (timed in the strips
+    // slot), then the mixed-precision products and first strips
+    if (timed) mark(c, 9, false);
+    blm_status s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, accS, accH, strips, -1, false, 1);
+    if (s != BLM_OK) return s;
+    if (timed) mark(c, 9, true);
+    return run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, accS, accH, strips, timed ? 1 : -1, false,
+                    c->fp8 ? 3 : 2, true);
+  }
+  return run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, accS, accH, strips, timed ? 1 : -1, c->offsets_even, 0,
+                  true);
+}
+
 static blm_status build_launches(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   mark(c, 0, false);
   blm_status s = build_slices(c, ch, n);
   if (s != BLM_OK) return s;
   mark(c, 0, true);
-  if (c->mixed()) {
-    // FP64 aux Gram and further aux groups' strips (timed in the strips
-    // slot), then the mixed-precision products and first strips
-    mark(c, 9, false);
-    s = run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, -1, false, 1);
-    if (s != BLM_OK) return s;
-    mark(c, 9, true);
-    return run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, c->accS, c->accH, c->strips, 1, false,
-                    c->fp8 ? 3 : 2, true);
-  }
-  return run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, c->accS, c->accH, c->strips, 1, c->offsets_even, 0, true);
+  s = build_grams(c, c->accS, c->accH, c->strips, true);
+  if (s != BLM_OK || c->target != BLM_TARGET_OMEGA) return s;
+  // second pass over the same chunks: sum w ebar ebar^T (the table is
+  // swapped in, not edited, so that the first pass's upload source stays
+  // as it was)
+  c->h_slices_e = c->h_slices;
+  swap_to_e(c->h_slices_e);
+  std::swap(c->h_slices, c->h_slices_e);
+  s = build_grams(c, c->accE, nullptr, c->stripsE, false);
+  std::swap(c->h_slices, c->h_slices_e);
+  return s;
 }
 
 blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
@@ -1067,6 +1188,7 @@ blm_status blm_build_blocks(blm_ctx* c, const blm_chunk* ch, int32_t n) {
 
 blm_status blm_capture_build(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   if (!c) return BLM_E_ARG;
+  if (c->target == BLM_TARGET_OMEGA) return fail(c, BLM_E_ARG, "recorded builds are for the energy target");
   int64_t total = 0;
   blm_status s = check_chunks(c, ch, n, &total);
   if (s != BLM_OK) return s;
@@ -1262,7 +1384,7 @@ blm_status solve_begin(blm_ctx* c, std::vector<EigJob>& ej, int* dm_out) {
   const int gy = std::min(256, std::max(1, (int)(((size_t)dm * dm + 255) / 256 / 8)));
   mark(c, 3, false);
   hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)asmj.size(), gy), dim3(256), 0, c->st, c->d_asm1,
-                     c->accS, c->accH, c->strips, c->NV, c->aux_off, c->NAP, c->G2S, c->G2H, (int64_t)c->n2max);
+                     asm_src(c, c->n2max));
   HIPCHK(c, hipGetLastError());
   mark(c, 3, true);
   *dm_out = dm;
@@ -1345,6 +1467,7 @@ blm_status solve_end(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   HIPCHK(c, hipMemcpyAsync(c->d_jobs2, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemsetAsync(c->G2S, 0, 8 * (size_t)n2 * n2, c->st));
   HIPCHK(c, hipMemsetAsync(c->G2H, 0, 8 * (size_t)n2 * n2, c->st));
+  if (c->target == BLM_TARGET_OMEGA) HIPCHK(c, hipMemsetAsync(c->G2E, 0, 8 * (size_t)n2 * n2, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->n_pass2 = 0;
   c->state = ST_SOLVED;
@@ -1399,6 +1522,15 @@ blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   mark(c, 5, true);
   s = run_gram(c, c->d_jobs2, c->n_jobs2, c->Pcap2, c->G2S, c->G2H, nullptr, 6, true, 4);
   if (s != BLM_OK) return s;
+  if (c->target == BLM_TARGET_OMEGA) {
+    // sum w zbar zbar^T: the projections of e on both sides
+    c->h_slices_e = c->h_slices;
+    for (Slice& S : c->h_slices_e) S.O = S.e;
+    std::swap(c->h_slices, c->h_slices_e);
+    s = run_gram(c, c->d_jobs2, c->n_jobs2, c->Pcap2, c->G2E, nullptr, nullptr, -1, true, 4);
+    std::swap(c->h_slices, c->h_slices_e);
+    if (s != BLM_OK) return s;
+  }
   c->n_pass2 += total;
   c->state = ST_PROJECTED;
   return BLM_OK;
@@ -1440,8 +1572,7 @@ blm_status stage2_begin(blm_ctx* c, std::vector<EigJob>& ej, int* dm_out) {
   mark(c, 8, false);
   HIPCHK(c, hipMemcpyAsync(c->d_asm2, asmj.data(), sizeof(AsmJob) * NS, hipMemcpyHostToDevice, c->st));
   const int gy = std::min(64, std::max(1, (int)(((size_t)dm * dm + 255) / 256 / 8)));
-  hipLaunchKernelGGL(assemble_kernel, dim3(NS, gy), dim3(256), 0, c->st, c->d_asm2, c->accS, c->accH,
-                     c->strips, c->NV, c->aux_off, c->NAP, c->G2S, c->G2H, (int64_t)c->n2);
+  hipLaunchKernelGGL(assemble_kernel, dim3(NS, gy), dim3(256), 0, c->st, c->d_asm2, asm_src(c, c->n2));
   HIPCHK(c, hipGetLastError());
   *dm_out = dm;
   return BLM_OK;
@@ -1546,8 +1677,7 @@ blm_status blm_get_block_matrices(blm_ctx* c, int32_t block, int32_t shift, doub
   A.S = c->exS;
   A.A = c->exA;
   HIPCHK(c, hipMemcpyAsync(c->d_asm_x, &A, sizeof A, hipMemcpyHostToDevice, c->st));
-  hipLaunchKernelGGL(assemble_kernel, dim3(1, 64), dim3(256), 0, c->st, c->d_asm_x, c->accS, c->accH,
-                     c->strips, c->NV, c->aux_off, c->NAP, c->G2S, c->G2H, (int64_t)c->n2max);
+  hipLaunchKernelGGL(assemble_kernel, dim3(1, 64), dim3(256), 0, c->st, c->d_asm_x, asm_src(c, c->n2max));
   HIPCHK(c, hipGetLastError());
   if (h_H) HIPCHK(c, hipMemcpyAsync(h_H, c->exA, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
   if (h_S) HIPCHK(c, hipMemcpyAsync(h_S, c->exS, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
@@ -1583,8 +1713,7 @@ blm_status blm_get_stage2_matrices(blm_ctx* c, int32_t shift, double* h_H2, doub
   A.S = c->exS;
   A.A = c->exA;
   HIPCHK(c, hipMemcpyAsync(c->d_asm_x, &A, sizeof A, hipMemcpyHostToDevice, c->st));
-  hipLaunchKernelGGL(assemble_kernel, dim3(1, 16), dim3(256), 0, c->st, c->d_asm_x, c->accS, c->accH,
-                     c->strips, c->NV, c->aux_off, c->NAP, c->G2S, c->G2H, (int64_t)c->n2);
+  hipLaunchKernelGGL(assemble_kernel, dim3(1, 16), dim3(256), 0, c->st, c->d_asm_x, asm_src(c, c->n2));
   HIPCHK(c, hipGetLastError());
   if (h_H2) HIPCHK(c, hipMemcpyAsync(h_H2, c->exA, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));
   if (h_S2) HIPCHK(c, hipMemcpyAsync(h_S2, c->exS, 8 * (size_t)d * d, hipMemcpyDeviceToHost, c->st));

@@ -500,6 +500,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
   }
   const bool strips = J.kind == JOB_DIAG;
   if (qd == 2 && J.kind != JOB_OFF && !strips) return;
+  if (!h_base && (qd == 1 || (qd == 2 && !strips))) return;   // H products not kept
   const int n_el = (qd == 2 && strips) ? 3 * NAUX * GT : GT * GT;
   for (int el = blockIdx.z * blockDim.x + threadIdx.x; el < n_el; el += blockDim.x * gridDim.z) {
     double sum = 0.0;

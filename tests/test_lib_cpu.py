@@ -99,3 +99,44 @@ def test_static_eigvals_rejects_sizes_beyond_its_scratch():
     assert lib.blm_pencil_eigvals_static(fake, fake, 0, fake, fake, None) == 1
     assert lib.blm_pencil_eigvals_static(None, fake, 8, fake, fake, None) == 1
     assert lib.blm_pencil_eigvals_static(fake, fake, 8, fake, None, None) == 1
+
+
+def test_accumulators_hold_the_papers_storage_count():
+    """The block estimates' storage at the paper's setting (Sec. II.B:
+    N_V = 30,000, N_B = 100, N_O = 5 gives 0.5 GB per process): the
+    library's accumulators within 5% of the oracle's count of that storage
+    (tests/golden/paper_memory.json pins the count itself); the library
+    keeps whole S tiles and aux columns padded to groups of 16."""
+    if not os.path.exists(blm.LIB_PATH):
+        pytest.skip("libblm.so not built")
+    import json
+
+    from oracle import blm_oracle as orc
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_memory.json")))["blm"]
+    off = np.linspace(0, g["n_params"], g["n_blocks"] + 1).astype(np.int64)
+    lib_b = blm.BLM.accumulator_bytes(g["n_params"], off, 4, g["n_old"], [1e-3], 65536)
+    paper_b = orc.blm_matrix_bytes(g["n_params"], g["n_blocks"], g["n_old"])
+    assert abs(lib_b / paper_b - 1) <= 0.05, (lib_b, paper_b)
+    assert round(lib_b / 1e9, g["digits"]) == g["gigabytes"]
+    assert lib_b < blm.BLM.workspace_bytes(g["n_params"], off, 4, g["n_old"], [1e-3], 65536)
+
+
+def test_omega_target_configuration():
+    """The excited-state target: more workspace (the second pass's sums),
+    unknown targets and a non-finite omega refused."""
+    if not os.path.exists(blm.LIB_PATH):
+        pytest.skip("libblm.so not built")
+    off = np.array([0, 100, 250, 400])
+    e = blm.BLM.workspace_bytes(400, off, 2, 1, [1e-3], 4096)
+    o = blm.BLM.workspace_bytes(400, off, 2, 1, [1e-3], 4096, target="omega")
+    assert o > e
+    assert (blm.BLM.accumulator_bytes(400, off, 2, 1, [1e-3], 4096, target="omega")
+            > blm.BLM.accumulator_bytes(400, off, 2, 1, [1e-3], 4096))
+    lib = blm.load()
+    sh = np.array([1e-3])
+    offs = np.ascontiguousarray(off, dtype=np.int64)
+    for target, omega in ((7, 0.0), (1, float("nan")), (1, float("inf"))):
+        cfg = blm._Config(400, 3, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 2, 1, 1,
+                          sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 4096, target, omega)
+        out = ctypes.c_size_t()
+        assert lib.blm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == 1   # BLM_E_ARG
