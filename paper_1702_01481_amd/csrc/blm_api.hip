@@ -95,6 +95,7 @@ struct blm_ctx {
   int n_jobsM = 0;
   PairJob* d_pairsM = nullptr;   // BF16 build: pairs of main jobs sharing a row tile
   int n_pairsM = 0;
+  int n_strip_pairsM = 0;        // the first n_strip_pairsM pairs start with a diagonal tile
   uint16_t* auxP = nullptr;      // BF16 build: first aux group as BF16 pieces (k-packed, ld 16)
   int64_t aux_pstride = 0;       // elements between pieces of auxP (Xa pieces, then Ya pieces)
   int pieces = 0;                  // 0: FP64 path; 2 or 3: BF16 split pieces used
@@ -595,6 +596,12 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
       pairs.push_back(pj);
       k += (pj.jb >= 0) ? 2 : 1;
     }
+    // pairs that start with a diagonal tile (coupling strips) first: the
+    // two groups are separate launches of separate kernel instantiations
+    std::stable_partition(pairs.begin(), pairs.end(),
+                          [&](const PairJob& pj) { return main[pj.ja].kind == JOB_DIAG; });
+    c->n_strip_pairsM = 0;
+    for (const PairJob& pj : pairs) c->n_strip_pairsM += main[pj.ja].kind == JOB_DIAG;
     c->n_pairsM = (int)pairs.size();
     HIPCHK(c, hipMemcpy(c->d_pairsM, pairs.data(), sizeof(PairJob) * pairs.size(), hipMemcpyHostToDevice));
   }
@@ -704,9 +711,11 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
 // table on the device, into the partial tiles
 void launch_build_gram(blm_ctx* c, int kind, const GramJob* d_jobs, int n_jobs, int n_slices, int P, bool vec) {
   if (kind == 2)
-    launch_gram_bf16(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->pieces, c->partial, c->st);
+    launch_gram_bf16(c->d_pairsM, c->n_strip_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->pieces,
+                     c->partial, c->st);
   else if (kind == 3)
-    launch_gram_fp8(c->d_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->fp8_res, c->partial, c->st);
+    launch_gram_fp8(c->d_pairsM, c->n_strip_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->fp8_res,
+                    c->partial, c->st);
   else
     launch_gram(d_jobs, n_jobs, slice_tab(c), n_slices, P, vec && (kind == 0 || kind == 4), kind == 1, kind == 4,
                 c->partial, c->st);

@@ -79,7 +79,13 @@ __device__ __forceinline__ void lds_dma16(const BLM_GLOBAL void* src, u4v* lds_b
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
 }
 
-template <int PIECES>
+// STRIPS: the launch holds the pairs whose first job is a diagonal tile
+// (coupling strips and their aux copies); the pairs without are a launch of
+// their own, whose kernel needs fewer registers (no strip selects): with
+// the strip logic it kept a value in scratch, and the wait for that reload
+// (a vector-memory count) also waited for the step's global-to-LDS copies,
+// so copies and products no longer overlapped.
+template <int PIECES, bool STRIPS>
 __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob* __restrict__ pairs,
                                                                  int n_pairs,
                                                                  const GramJob* __restrict__ jobs,
@@ -118,7 +124,7 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
   // Diagonal job with strips: the waves of its tile (wc < 2) compute the
   // coupling strips of Fig. 1 in the third product's registers:
   // aux^T O_i and aux^T e_i (wr = 0), auxE^T O_i (wr = 1), 16 x 32 each.
-  const bool pair_strips = JA.kind == JOB_DIAG;
+  const bool pair_strips = STRIPS && JA.kind == JOB_DIAG;
   const bool strip = pair_strips && !wave_b;
   const int n_instr = NIA + NIB + (pair_strips ? NIX : 0);
 
@@ -324,16 +330,25 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
       }
 }
 
-void launch_gram_bf16(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
+void launch_gram_bf16(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
                       const Slice* d_slices, int n_slices, int P, int pieces, double* d_partial,
                       hipStream_t st) {
-  if (n_pairs <= 0) return;
-  if (pieces == 3)
-    hipLaunchKernelGGL(gram_bf16_kernel<3>, dim3(n_pairs * P), dim3(BP_THREADS), 0, st, d_pairs,
-                       n_pairs, d_jobs, d_slices, n_slices, P, d_partial);
-  else
-    hipLaunchKernelGGL(gram_bf16_kernel<2>, dim3(n_pairs * P), dim3(BP_THREADS), 0, st, d_pairs,
-                       n_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+  const int n_plain = n_pairs - n_strip_pairs;
+  if (pieces == 3) {
+    if (n_strip_pairs > 0)
+      hipLaunchKernelGGL((gram_bf16_kernel<3, true>), dim3(n_strip_pairs * P), dim3(BP_THREADS), 0, st, d_pairs,
+                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+    if (n_plain > 0)
+      hipLaunchKernelGGL((gram_bf16_kernel<3, false>), dim3(n_plain * P), dim3(BP_THREADS), 0, st,
+                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+  } else {
+    if (n_strip_pairs > 0)
+      hipLaunchKernelGGL((gram_bf16_kernel<2, true>), dim3(n_strip_pairs * P), dim3(BP_THREADS), 0, st, d_pairs,
+                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+    if (n_plain > 0)
+      hipLaunchKernelGGL((gram_bf16_kernel<2, false>), dim3(n_plain * P), dim3(BP_THREADS), 0, st,
+                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -91,8 +91,10 @@ struct F8Lds {
 
 // NRES: residuals per stored value (1: four piece products; 2: eight, the
 // four of one residual plus q t, t q, r t and t r; t t, below 2^-26 of the
-// product, is left out)
-template <int NRES>
+// product, is left out).  STRIPS: the launch of the pairs whose first job is
+// a diagonal tile (coupling strips); the other pairs run an instantiation
+// without the strip logic, which needs fewer registers.
+template <int NRES, bool STRIPS>
 __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* __restrict__ pairs,
                                                                 int n_pairs,
                                                                 const GramJob* __restrict__ jobs,
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
   const bool wave_b = wc >= 2;
   const bool wave_on = !wave_b || has_b;
   const bool third = (wave_b ? JB.kind : JA.kind) == JOB_OFF;
-  const bool pair_strips = JA.kind == JOB_DIAG;
+  const bool pair_strips = STRIPS && JA.kind == JOB_DIAG;
   const bool strip = pair_strips && !wave_b;
   const int n_instr = NIA + NIB + (pair_strips ? NIX : 0);
 
@@ -543,15 +545,24 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const double* __restrict
 
 }  // namespace
 
-void launch_gram_fp8(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
+void launch_gram_fp8(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
                      const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st) {
-  if (n_pairs <= 0) return;
-  if (nres == 2)
-    hipLaunchKernelGGL(gram_fp8_kernel<2>, dim3(n_pairs * P), dim3(F8_THREADS), 0, st, d_pairs, n_pairs,
-                       d_jobs, d_slices, n_slices, P, d_partial);
-  else
-    hipLaunchKernelGGL(gram_fp8_kernel<1>, dim3(n_pairs * P), dim3(F8_THREADS), 0, st, d_pairs, n_pairs,
-                       d_jobs, d_slices, n_slices, P, d_partial);
+  const int n_plain = n_pairs - n_strip_pairs;
+  if (nres == 2) {
+    if (n_strip_pairs > 0)
+      hipLaunchKernelGGL((gram_fp8_kernel<2, true>), dim3(n_strip_pairs * P), dim3(F8_THREADS), 0, st, d_pairs,
+                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+    if (n_plain > 0)
+      hipLaunchKernelGGL((gram_fp8_kernel<2, false>), dim3(n_plain * P), dim3(F8_THREADS), 0, st,
+                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+  } else {
+    if (n_strip_pairs > 0)
+      hipLaunchKernelGGL((gram_fp8_kernel<1, true>), dim3(n_strip_pairs * P), dim3(F8_THREADS), 0, st, d_pairs,
+                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+    if (n_plain > 0)
+      hipLaunchKernelGGL((gram_fp8_kernel<1, false>), dim3(n_plain * P), dim3(F8_THREADS), 0, st,
+                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+  }
 }
 
 void launch_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,

@@ -186,7 +186,9 @@ constexpr int EIG_MAXSEL = 16;   // eigenvalues selected per problem (N_K + 1 <=
 // (its own kernel instantiation, named apart in traces)
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
                  bool vec, bool split, bool stage2, double* d_partial, hipStream_t st);
-void launch_gram_bf16(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
+// d_pairs: the n_strip_pairs pairs that start with a diagonal tile first,
+// then the others (each group is a launch of its own)
+void launch_gram_bf16(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
                       const Slice* d_slices, int n_slices, int P, int pieces, double* d_partial,
                       hipStream_t st);
 void launch_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncols, int pieces,
@@ -195,7 +197,7 @@ void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* 
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
                         int strip_rows, hipStream_t st);
 // nres: residuals per value in the FP8 storage (1 or 2)
-void launch_gram_fp8(const PairJob* d_pairs, int n_pairs, const GramJob* d_jobs,
+void launch_gram_fp8(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
                      const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st);
 // FP64 [n][ld_src] -> e4m3 codes (k-packed by 16), one or two BF16 residuals
 // (k-packed by 8; res2 nullptr: one) and per-column power-of-two scales
