@@ -211,7 +211,10 @@ blm_status blm_build_blocks(blm_ctx* ctx, const blm_chunk* chunks, int32_t n_chu
  * given chunks for each G in {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64} and
  * the default count, with G times the tile count up to 65,536 (one
  * settling launch and one timed launch each, HIP events on the context's
- * stream), and later builds of this context use the fastest.  blm_create
+ * stream), and later builds of this context use the fastest.  For the FP64
+ * build it also chooses the tile shape: one 64 x 64 tile per workgroup, or
+ * two tiles that share their row tile (64 x 128, the row panels read once
+ * for both); the mixed-precision builds always take pairs.  blm_create
  * sizes the partial tiles of the split for the default count; when the
  * candidates need more, this call allocates a larger buffer (up to 6.4 GB)
  * and frees the old one, dropping any recording made by blm_capture_build

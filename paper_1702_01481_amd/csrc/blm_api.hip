@@ -78,7 +78,7 @@ struct blm_ctx {
   int Pcap1 = 1, Pcap2 = 1, PcapM = 1;
   int nd2max = 0;                  // most kept directions of any block (all shifts), last solve
   size_t partial_slots = 0;       // partial tiles allocated (3 x 64 x 64 doubles each)
-  int P_tuned[5] = {0, 0, 0, 0, 0};   // slice groups chosen by blm_autotune_build, per build kind (0: heuristic)
+  int P_tuned[6] = {0, 0, 0, 0, 0, 0};   // slice groups chosen by blm_autotune_build, per build kind (0: heuristic)
   int max_slices = 0;
   int64_t* d_off = nullptr;
 
@@ -96,6 +96,12 @@ struct blm_ctx {
   PairJob* d_pairsM = nullptr;   // BF16 build: pairs of main jobs sharing a row tile
   int n_pairsM = 0;
   int n_strip_pairsM = 0;        // the first n_strip_pairsM pairs start with a diagonal tile
+  // FP64 build, second tile shape: the block tiles (the first n_main1 jobs
+  // of d_jobs1) as pairs sharing a row tile (64 x 128 per workgroup), strip
+  // pairs first; pairs64: build with them (chosen by blm_autotune_build)
+  PairJob* d_pairs64 = nullptr;
+  int n_main1 = 0, n_pairs64 = 0, n_strip_pairs64 = 0;
+  bool pairs64 = false;
   uint16_t* auxP = nullptr;      // BF16 build: first aux group as BF16 pieces (k-packed, ld 16)
   int64_t aux_pstride = 0;       // elements between pieces of auxP (Xa pieces, then Ya pieces)
   int pieces = 0;                  // 0: FP64 path; 2 or 3: BF16 split pieces used
@@ -458,6 +464,7 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_jobs2, sizeof(GramJob) * (size_t)n_jobs2max);
   add((void**)&c->d_jobsM, sizeof(GramJob) * (size_t)std::max(c->n_jobsM, 1));
   add((void**)&c->d_pairsM, sizeof(PairJob) * (size_t)std::max(c->n_jobsM, 1));
+  add((void**)&c->d_pairs64, c->mixed() ? 0 : sizeof(PairJob) * (size_t)std::max(n_jobs1, 1));
   add((void**)&c->auxP, 2 * 2 * (size_t)c->pieces * c->aux_pstride);
   add((void**)&c->auxQ, 2 * (size_t)c->auxq_stride);
   add((void**)&c->auxR, 2 * 2 * (size_t)c->auxr_stride);
@@ -586,6 +593,27 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
   c->n_jobs1 = (int)jobs.size();
   c->n_jobsM = (int)main.size();
   HIPCHK(c, hipMemcpy(c->d_jobs1, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice));
+  if (!c->mixed()) {
+    // the FP64 block tiles lead d_jobs1; consecutive tiles of one row tile
+    // pair up, pairs that start with a diagonal tile first
+    int nm = 0;
+    while (nm < (int)jobs.size() && (jobs[nm].kind == JOB_DIAG || jobs[nm].kind == JOB_OFF)) ++nm;
+    std::vector<PairJob> pairs;
+    for (int k = 0; k < nm;) {
+      PairJob pj{k, -1};
+      if (k + 1 < nm && jobs[k + 1].ci == jobs[k].ci) pj.jb = k + 1;
+      pairs.push_back(pj);
+      k += (pj.jb >= 0) ? 2 : 1;
+    }
+    std::stable_partition(pairs.begin(), pairs.end(),
+                          [&](const PairJob& pj) { return jobs[pj.ja].kind == JOB_DIAG; });
+    c->n_main1 = nm;
+    c->n_strip_pairs64 = 0;
+    for (const PairJob& pj : pairs) c->n_strip_pairs64 += jobs[pj.ja].kind == JOB_DIAG;
+    c->n_pairs64 = (int)pairs.size();
+    if (!pairs.empty())
+      HIPCHK(c, hipMemcpy(c->d_pairs64, pairs.data(), sizeof(PairJob) * pairs.size(), hipMemcpyHostToDevice));
+  }
   if (!main.empty()) {
     HIPCHK(c, hipMemcpy(c->d_jobsM, main.data(), sizeof(GramJob) * main.size(), hipMemcpyHostToDevice));
     // consecutive main jobs of one row tile (same first column) pair up
@@ -707,10 +735,14 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
 // kind: 0 FP64 kernel on FP64 storage, 1 FP64 kernel on split storage
 // (strips), 2 BF16 matrix-core kernel on split storage (main products),
 // 3 FP8 + BF16 matrix-core kernel on FP8 storage (main products),
-// 4 FP64 kernel, stage two: the Gram launch of one kind over the slice
+// 4 FP64 kernel, stage two, 5 FP64 pair kernel on FP64 storage (block tiles
+// in pairs sharing a row tile): the Gram launch of one kind over the slice
 // table on the device, into the partial tiles
 void launch_build_gram(blm_ctx* c, int kind, const GramJob* d_jobs, int n_jobs, int n_slices, int P, bool vec) {
-  if (kind == 2)
+  if (kind == 5)
+    launch_gram64_pairs(c->d_pairs64, c->n_strip_pairs64, c->n_pairs64, d_jobs, slice_tab(c), n_slices, P,
+                        c->partial, c->st);
+  else if (kind == 2)
     launch_gram_bf16(c->d_pairsM, c->n_strip_pairsM, c->n_pairsM, d_jobs, slice_tab(c), n_slices, P, c->pieces,
                      c->partial, c->st);
   else if (kind == 3)
@@ -1011,6 +1043,7 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
     c->n_cus = 0;
   if (const char* e = getenv("BLM_SYNC_SPIN_LIMIT")) c->spin_limit = (unsigned)strtoul(e, nullptr, 10);
   if (const char* e = getenv("BLM_HESS_WORKGROUPS")) c->hess_wg = std::max(1, atoi(e));
+  if (const char* e = getenv("BLM_FP64_PAIRS")) c->pairs64 = atoi(e) != 0;
   Plan P;
   plan(c, P);
   for (auto& it : P.items) {
@@ -1158,6 +1191,16 @@ static blm_status build_grams(blm_ctx* c, double* accS, double* accH, double* st
     if (timed) mark(c, 9, true);
     return run_gram(c, c->d_jobsM, c->n_jobsM, c->PcapM, accS, accH, strips, timed ? 1 : -1, false,
                     c->fp8 ? 3 : 2, true);
+  }
+  if (c->pairs64 && c->n_pairs64 > 0) {
+    // FP64 in tile pairs: aux Gram and further aux groups' strips on
+    // gram_kernel (timed in the strips slot), then the block tiles
+    if (timed) mark(c, 9, false);
+    blm_status s = run_gram(c, c->d_jobs1 + c->n_main1, c->n_jobs1 - c->n_main1, c->Pcap1, accS, accH, strips, -1,
+                            c->offsets_even, 0);
+    if (s != BLM_OK) return s;
+    if (timed) mark(c, 9, true);
+    return run_gram(c, c->d_jobs1, c->n_main1, c->Pcap1, accS, accH, strips, timed ? 1 : -1, false, 5, true);
   }
   return run_gram(c, c->d_jobs1, c->n_jobs1, c->Pcap1, accS, accH, strips, timed ? 1 : -1, c->offsets_even, 0,
                   true);
@@ -1311,31 +1354,51 @@ blm_status blm_autotune_build(blm_ctx* c, const blm_chunk* ch, int32_t n, int32_
   cand.push_back(choose_P(cap, n_jobs, n_slices));
   std::sort(cand.begin(), cand.end());
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-  int best = 0;
+  // tile shapes: the FP64 build also tries its block tiles in pairs that
+  // share a row tile (64 x 128 per workgroup, kind 5) against one tile per
+  // workgroup (64 x 64, kind 0); a pair launch is timed with the aux and
+  // strip-only jobs it leaves to gram_kernel
+  std::vector<int> shapes = {kind};
+  if (kind == 0 && c->n_pairs64 > 0 && !getenv("BLM_FP64_PAIRS")) shapes.push_back(5);
+  auto launch_shape = [&](int sk, int P) {
+    if (sk == 5) {
+      launch_build_gram(c, 0, c->d_jobs1 + c->n_main1, c->n_jobs1 - c->n_main1, n_slices, P, vec);
+      launch_build_gram(c, 5, c->d_jobs1, c->n_main1, n_slices, P, false);
+    } else {
+      launch_build_gram(c, sk, jobs, n_jobs, n_slices, P, vec);
+    }
+  };
+  int best = 0, best_kind = kind;
   float best_ms = 0.0f;
   blm_status r = BLM_OK;
-  for (int P : cand) {
-    if (P > cap) break;
-    // one launch to settle caches and clocks, one timed
-    launch_build_gram(c, kind, jobs, n_jobs, n_slices, P, vec);
-    float ms = 0.0f;
-    if (hipEventRecord(ev[0], c->st) != hipSuccess) r = BLM_E_HIP;
-    launch_build_gram(c, kind, jobs, n_jobs, n_slices, P, vec);
-    if (r == BLM_OK && (hipGetLastError() != hipSuccess || hipEventRecord(ev[1], c->st) != hipSuccess ||
-                        hipEventSynchronize(ev[1]) != hipSuccess ||
-                        hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
-      r = BLM_E_HIP;
-    if (r != BLM_OK) break;
-    if (getenv("BLM_AUTOTUNE_LOG")) fprintf(stderr, "blm_autotune_build: kind %d, %d slice groups: %.3f ms\n", kind, P, ms);
-    if (best == 0 || ms < best_ms) {
-      best = P;
-      best_ms = ms;
+  for (int sk : shapes) {
+    for (int P : cand) {
+      if (P > cap) break;
+      // one launch to settle caches and clocks, one timed
+      launch_shape(sk, P);
+      float ms = 0.0f;
+      if (hipEventRecord(ev[0], c->st) != hipSuccess) r = BLM_E_HIP;
+      launch_shape(sk, P);
+      if (r == BLM_OK && (hipGetLastError() != hipSuccess || hipEventRecord(ev[1], c->st) != hipSuccess ||
+                          hipEventSynchronize(ev[1]) != hipSuccess ||
+                          hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+        r = BLM_E_HIP;
+      if (r != BLM_OK) break;
+      if (getenv("BLM_AUTOTUNE_LOG"))
+        fprintf(stderr, "blm_autotune_build: kind %d, %d slice groups: %.3f ms\n", sk, P, ms);
+      if (best == 0 || ms < best_ms) {
+        best = P;
+        best_kind = sk;
+        best_ms = ms;
+      }
     }
+    if (r != BLM_OK) break;
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   if (r != BLM_OK) return fail(c, r, "a tuning launch failed");
-  c->P_tuned[kind] = best;
+  if (shapes.size() > 1) c->pairs64 = best_kind == 5;
+  c->P_tuned[best_kind] = best;
   if (h_groups) *h_groups = best;
   return BLM_OK;
 }

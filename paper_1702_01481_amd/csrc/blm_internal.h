@@ -196,6 +196,10 @@ void launch_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncol
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
                         double* s_base, double* h_base, double* strip_base, int64_t strip_ld,
                         int strip_rows, hipStream_t st);
+// FP64 block tiles in pairs sharing a row tile (blm_gram64.hip); d_pairs as
+// for launch_gram_bf16, indices into d_jobs
+void launch_gram64_pairs(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
+                         const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st);
 // nres: residuals per value in the FP8 storage (1 or 2)
 void launch_gram_fp8(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
                      const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st);
