@@ -284,8 +284,8 @@ blm_status blm_stage2(blm_ctx* ctx, double* d_update, double* h_energy, double* 
 /* Batches: several independent optimisations (contexts) whose block solves
  * share one eigensolver launch, and whose stage-two solves share another
  * (Sec. II.B applied to each context on its own; nothing is shared between
- * their estimates).  The builds and projections stay per context: each
- * fills the device by itself.
+ * their estimates).  Their block builds can share one Gram launch too
+ * (blm_batch_build); the projections stay per context.
  *
  * blm_batch_create takes n >= 1 distinct contexts created on the same
  * device and stream (else BLM_E_ARG) and allocates the batch's job tables
@@ -294,6 +294,17 @@ blm_status blm_stage2(blm_ctx* ctx, double* d_update, double* h_energy, double* 
 typedef struct blm_batch blm_batch;
 blm_status blm_batch_create(blm_ctx* const* ctxs, int32_t n, blm_batch** out);
 blm_status blm_batch_destroy(blm_batch* batch);
+
+/* blm_build_blocks for every context of the batch in one Gram launch (per
+ * kind: the FP64 build's tiles, or a mixed-precision build's FP64 aux jobs
+ * and then its BF16 or FP8 tile pairs): every context's jobs, each reading
+ * its own context's chunks, with one slice-group count for all.  chunks[i]
+ * (n_chunks[i] of them) are context i's, as for blm_build_blocks.  The
+ * contexts must share one storage (precision) and the energy target, else
+ * BLM_E_ARG; a context out of order returns BLM_E_STATE before anything
+ * runs.  The estimates equal each context's own blm_build_blocks up to the
+ * order of the FP64 sums over slice groups. */
+blm_status blm_batch_build(blm_batch* batch, const blm_chunk* const* chunks, const int32_t* n_chunks);
 
 /* blm_solve_blocks for every context of the batch.  h_evals and h_kept are
  * NULL or arrays of n host pointers (each NULL or as for blm_solve_blocks).

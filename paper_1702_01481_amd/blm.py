@@ -28,7 +28,7 @@ EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_accumul
             "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
             "blm_debug_eigvals", "blm_pencil_eigvals_static", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
-            "blm_batch_create", "blm_batch_destroy", "blm_batch_solve_blocks", "blm_batch_stage2",
+            "blm_batch_create", "blm_batch_destroy", "blm_batch_build", "blm_batch_solve_blocks", "blm_batch_stage2",
             "blm_last_error",
             "blm_status_string")
 TIMING_NAMES = ("theta_proj", "block_gram", "block_reduce", "block_assemble", "block_eig",
@@ -96,6 +96,7 @@ def load() -> C.CDLL:
     lib.blm_get_timings.argtypes = [vp, dp, i32]
     lib.blm_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
     lib.blm_batch_destroy.argtypes = [vp]
+    lib.blm_batch_build.argtypes = [vp, C.POINTER(C.POINTER(_Chunk)), C.POINTER(i32)]
     lib.blm_batch_solve_blocks.argtypes = [vp, C.POINTER(dp), C.POINTER(C.POINTER(i32))]
     lib.blm_batch_stage2.argtypes = [vp, C.POINTER(vp), C.POINTER(dp), C.POINTER(dp),
                                      C.POINTER(C.POINTER(C.c_uint32))]
@@ -476,8 +477,9 @@ class BLM:
 
 class Batch:
     """Several contexts (independent optimisations on the same stream) whose
-    block solves share one eigensolver launch, and whose stage-two solves
-    share another (blm_batch_*).  Builds and projections stay per context."""
+    block builds can share one Gram launch (build), whose block solves share
+    one eigensolver launch, and whose stage-two solves share another
+    (blm_batch_*).  Projections stay per context."""
 
     def __init__(self, ctxs: Sequence[BLM]):
         self.lib = load()
@@ -494,6 +496,18 @@ class Batch:
         if st != BLM_OK:
             msgs = [f"context {i}: {c.lib.blm_last_error(c.h).decode()}" for i, c in enumerate(self.ctxs)]
             raise BLMError(st, "; ".join(m for m in msgs if not m.endswith(": ")))
+
+    def build(self, chunk_lists: Sequence[Iterable]):
+        """blm_batch_build: chunk_lists[i] holds context i's chunks."""
+        n = len(self.ctxs)
+        assert len(chunk_lists) == n
+        arrs, counts = [], (C.c_int32 * n)()
+        for i, (ctx, chunks) in enumerate(zip(self.ctxs, chunk_lists)):
+            arr, m = ctx._chunks(chunks)
+            arrs.append(arr)
+            counts[i] = m
+        ptrs = (C.POINTER(_Chunk) * n)(*[C.cast(a, C.POINTER(_Chunk)) for a in arrs])
+        self._check(self.lib.blm_batch_build(self.h, ptrs, counts))
 
     def solve(self):
         """[(evals, kept)] per context, as BLM.solve."""

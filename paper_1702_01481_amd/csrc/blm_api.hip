@@ -96,6 +96,8 @@ struct blm_ctx {
   PairJob* d_pairsM = nullptr;   // BF16 build: pairs of main jobs sharing a row tile
   int n_pairsM = 0;
   int n_strip_pairsM = 0;        // the first n_strip_pairsM pairs start with a diagonal tile
+  std::vector<GramJob> h_jobs1, h_jobsM;   // host copies (batched builds merge them)
+  std::vector<PairJob> h_pairsM;
   // FP64 build, second tile shape: the block tiles (the first n_main1 jobs
   // of d_jobs1) as pairs sharing a row tile (64 x 128 per workgroup), strip
   // pairs first; pairs64: build with them (chosen by blm_autotune_build)
@@ -592,6 +594,8 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
   }
   c->n_jobs1 = (int)jobs.size();
   c->n_jobsM = (int)main.size();
+  c->h_jobs1 = jobs;
+  c->h_jobsM = main;
   HIPCHK(c, hipMemcpy(c->d_jobs1, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice));
   if (!c->mixed()) {
     // the FP64 block tiles lead d_jobs1; consecutive tiles of one row tile
@@ -631,6 +635,7 @@ blm_status upload_gram_jobs1(blm_ctx* c) {
     c->n_strip_pairsM = 0;
     for (const PairJob& pj : pairs) c->n_strip_pairsM += main[pj.ja].kind == JOB_DIAG;
     c->n_pairsM = (int)pairs.size();
+    c->h_pairsM = pairs;
     HIPCHK(c, hipMemcpy(c->d_pairsM, pairs.data(), sizeof(PairJob) * pairs.size(), hipMemcpyHostToDevice));
   }
   return BLM_OK;
@@ -1849,6 +1854,22 @@ struct blm_batch {
   EigJob* d_eig1 = nullptr;   // every context's block pencils
   EigJob* d_eig2 = nullptr;   // every context's stage-two pencils
   unsigned* d_hbar = nullptr; // barrier counter and flag per block pencil
+  // one Gram launch for every context's build (same storage, energy target):
+  // the contexts' job tables concatenated, each job tagged with its
+  // context's slice set; partial tiles of all jobs in one buffer
+  bool merged = false;
+  int kind = 0;                 // 0 FP64, 2 BF16 split, 3 FP8
+  int pieces = 0, fp8_res = 0, P = 1;
+  GramJob *d_jobs1 = nullptr, *d_jobsM = nullptr;
+  PairJob* d_pairsM = nullptr;
+  int n_jobs1 = 0, n_jobsM = 0, n_pairsM = 0, n_strip_pairsM = 0;
+  std::vector<int> off1, offM;  // first job of each context in the merged tables
+  Slice* d_slices = nullptr;
+  int max_slices = 0;
+  int2* d_sets = nullptr;
+  double* partial = nullptr;
+  std::vector<Slice> h_slices;
+  std::vector<int2> h_sets;
 };
 
 blm_status blm_batch_create(blm_ctx* const* ctxs, int32_t n, blm_batch** out) {
@@ -1878,6 +1899,67 @@ blm_status blm_batch_create(blm_ctx* const* ctxs, int32_t n, blm_batch** out) {
     delete b;
     return BLM_E_NOMEM;
   }
+  // merged build tables when every context builds with the same kernels
+  bool same = true;
+  for (int i = 0; i < n; ++i) {
+    const blm_ctx* c = ctxs[i];
+    same = same && c->target == BLM_TARGET_ENERGY && c->pieces == ctxs[0]->pieces && c->fp8 == ctxs[0]->fp8 &&
+           c->fp8_res == ctxs[0]->fp8_res;
+  }
+  if (same) {
+    std::vector<GramJob> j1, jm;
+    std::vector<PairJob> strip_pairs, plain_pairs;
+    for (int i = 0; i < n; ++i) {
+      const blm_ctx* c = ctxs[i];
+      b->off1.push_back((int)j1.size());
+      b->offM.push_back((int)jm.size());
+      for (GramJob J : c->h_jobs1) {
+        J.set = i;
+        j1.push_back(J);
+      }
+      const int om = (int)jm.size();
+      for (GramJob J : c->h_jobsM) {
+        J.set = i;
+        jm.push_back(J);
+      }
+      for (int k = 0; k < (int)c->h_pairsM.size(); ++k) {
+        PairJob pj = c->h_pairsM[k];
+        pj.ja += om;
+        if (pj.jb >= 0) pj.jb += om;
+        (k < c->n_strip_pairsM ? strip_pairs : plain_pairs).push_back(pj);
+      }
+      b->max_slices += c->max_slices;
+    }
+    std::vector<PairJob> pairs = strip_pairs;
+    pairs.insert(pairs.end(), plain_pairs.begin(), plain_pairs.end());
+    b->kind = ctxs[0]->fp8 ? 3 : ctxs[0]->pieces ? 2 : 0;
+    b->pieces = ctxs[0]->pieces;
+    b->fp8_res = ctxs[0]->fp8_res;
+    b->n_jobs1 = (int)j1.size();
+    b->n_jobsM = (int)jm.size();
+    b->n_pairsM = (int)pairs.size();
+    b->n_strip_pairsM = (int)strip_pairs.size();
+    // slice groups: about 4,096 workgroups in the largest launch
+    const int nj = std::max(b->n_jobs1, b->n_jobsM);
+    b->P = std::max(1, std::min(64, (4096 + nj - 1) / nj));
+    const size_t slots = (size_t)nj * b->P;
+    bool ok = hipMalloc((void**)&b->d_jobs1, sizeof(GramJob) * std::max<size_t>(j1.size(), 1)) == hipSuccess &&
+              hipMalloc((void**)&b->d_jobsM, sizeof(GramJob) * std::max<size_t>(jm.size(), 1)) == hipSuccess &&
+              hipMalloc((void**)&b->d_pairsM, sizeof(PairJob) * std::max<size_t>(pairs.size(), 1)) == hipSuccess &&
+              hipMalloc((void**)&b->d_slices, sizeof(Slice) * (size_t)b->max_slices) == hipSuccess &&
+              hipMalloc((void**)&b->d_sets, sizeof(int2) * (size_t)n) == hipSuccess &&
+              hipMalloc((void**)&b->partial, 8 * slots * 3 * GT * GT) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_jobs1, j1.data(), sizeof(GramJob) * j1.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && !jm.empty())
+      ok = hipMemcpy(b->d_jobsM, jm.data(), sizeof(GramJob) * jm.size(), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(b->d_pairsM, pairs.data(), sizeof(PairJob) * pairs.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      blm_batch_destroy(b);
+      return BLM_E_NOMEM;
+    }
+    b->merged = true;
+  }
   *out = b;
   return BLM_OK;
 }
@@ -1887,7 +1969,82 @@ blm_status blm_batch_destroy(blm_batch* b) {
   (void)hipFree(b->d_eig1);
   (void)hipFree(b->d_eig2);
   (void)hipFree(b->d_hbar);
+  (void)hipFree(b->d_jobs1);
+  (void)hipFree(b->d_jobsM);
+  (void)hipFree(b->d_pairsM);
+  (void)hipFree(b->d_slices);
+  (void)hipFree(b->d_sets);
+  (void)hipFree(b->partial);
   delete b;
+  return BLM_OK;
+}
+
+blm_status blm_batch_build(blm_batch* b, const blm_chunk* const* chunks, const int32_t* n_chunks) {
+  if (!b || !chunks || !n_chunks) return BLM_E_ARG;
+  const int n = (int)b->ctx.size();
+  blm_ctx* c0 = b->ctx[0];
+  if (!b->merged)
+    return fail(c0, BLM_E_ARG, "a batched build needs contexts of one storage and the energy target");
+  std::vector<int64_t> tot(n, 0);
+  for (int i = 0; i < n; ++i) {
+    blm_ctx* c = b->ctx[i];
+    if (c->state != ST_BEGUN && c->state != ST_BUILT)
+      return fail(c, BLM_E_STATE, "blm_batch_build needs blm_begin_step first");
+    blm_status s = check_chunks(c, chunks[i], n_chunks[i], &tot[i]);
+    if (s != BLM_OK) return s;
+  }
+  // every context's aux columns and slice table, then one table of all
+  b->h_slices.clear();
+  b->h_sets.assign(n, make_int2(0, 0));
+  bool vec = true;
+  for (int i = 0; i < n; ++i) {
+    blm_ctx* c = b->ctx[i];
+    blm_status s = build_slices(c, chunks[i], n_chunks[i]);
+    if (s != BLM_OK) return s;
+    b->h_sets[i] = make_int2((int)b->h_slices.size(), (int)c->h_slices.size());
+    b->h_slices.insert(b->h_slices.end(), c->h_slices.begin(), c->h_slices.end());
+    vec = vec && c->offsets_even;
+  }
+  for (const Slice& S : b->h_slices)
+    if ((S.ld & 1) || ((uintptr_t)S.O & 15) || ((uintptr_t)S.e & 15)) vec = false;
+  if ((int)b->h_slices.size() > b->max_slices) return fail(c0, BLM_E_ARG, "too many slices in one call");
+  if (b->h_slices.empty()) return BLM_OK;
+  HIPCHK(c0, hipMemcpyAsync(b->d_slices, b->h_slices.data(), sizeof(Slice) * b->h_slices.size(),
+                            hipMemcpyHostToDevice, b->st));
+  HIPCHK(c0, hipMemcpyAsync(b->d_sets, b->h_sets.data(), sizeof(int2) * n, hipMemcpyHostToDevice, b->st));
+  const int P = b->P;
+  const size_t tile = (size_t)3 * GT * GT;
+  for (blm_ctx* c : b->ctx) mark(c, 1, false);
+  // the FP64 jobs, or the mixed builds' FP64 aux and further-strip jobs
+  launch_gram(b->d_jobs1, b->n_jobs1, b->d_slices, 0, P, b->kind == 0 && vec, b->kind != 0, false, b->partial,
+              b->st, b->d_sets);
+  HIPCHK(c0, hipGetLastError());
+  for (int i = 0; i < n; ++i) {
+    blm_ctx* c = b->ctx[i];
+    launch_gram_reduce(c->d_jobs1, c->n_jobs1, P, b->partial + (size_t)b->off1[i] * P * tile, c->accS, c->accH,
+                       c->strips, c->NV, c->NAP, b->st);
+  }
+  if (b->kind != 0 && b->n_pairsM > 0) {
+    // the mixed-precision block tiles, in pairs
+    if (b->kind == 2)
+      launch_gram_bf16(b->d_pairsM, b->n_strip_pairsM, b->n_pairsM, b->d_jobsM, b->d_slices, 0, P, b->pieces,
+                       b->partial, b->st, b->d_sets);
+    else
+      launch_gram_fp8(b->d_pairsM, b->n_strip_pairsM, b->n_pairsM, b->d_jobsM, b->d_slices, 0, P, b->fp8_res,
+                      b->partial, b->st, b->d_sets);
+    HIPCHK(c0, hipGetLastError());
+    for (int i = 0; i < n; ++i) {
+      blm_ctx* c = b->ctx[i];
+      launch_gram_reduce(c->d_jobsM, c->n_jobsM, P, b->partial + (size_t)b->offM[i] * P * tile, c->accS, c->accH,
+                         c->strips, c->NV, c->NAP, b->st);
+    }
+  }
+  HIPCHK(c0, hipGetLastError());
+  for (blm_ctx* c : b->ctx) mark(c, 1, true);
+  for (int i = 0; i < n; ++i) {
+    b->ctx[i]->n_pass1 += tot[i];
+    b->ctx[i]->state = ST_BUILT;
+  }
   return BLM_OK;
 }
 

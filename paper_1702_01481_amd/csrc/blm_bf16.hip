@@ -91,7 +91,8 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
                                                                  const GramJob* __restrict__ jobs,
                                                                  const Slice* __restrict__ slices,
                                                                  int n_slices, int P,
-                                                                 double* __restrict__ partial) {
+                                                                 double* __restrict__ partial,
+    const int2* __restrict__ sets) {
   // wave instructions per step: one per (side, array, piece, group[, half]);
   // diagonal pairs also copy the aux columns (one per array and piece)
   constexpr int NIA = 2 * PIECES * BP_KG;              // A side, 64 columns each
@@ -108,6 +109,11 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
   const GramJob JA = jobs[PJ.ja];
   const bool has_b = PJ.jb >= 0;
   const GramJob JB = jobs[has_b ? PJ.jb : PJ.ja];
+  if (sets) {
+    const int2 ss = sets[JA.set];
+    slices += ss.x;
+    n_slices = ss.y;
+  }
 
   // The wave index is made provably wave-uniform, so that every per-wave
   // choice below (which products, which job) is a scalar branch: a
@@ -332,22 +338,22 @@ __global__ __launch_bounds__(BP_THREADS, 1) void gram_bf16_kernel(const PairJob*
 
 void launch_gram_bf16(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
                       const Slice* d_slices, int n_slices, int P, int pieces, double* d_partial,
-                      hipStream_t st) {
+                      hipStream_t st, const int2* d_sets) {
   const int n_plain = n_pairs - n_strip_pairs;
   if (pieces == 3) {
     if (n_strip_pairs > 0)
       hipLaunchKernelGGL((gram_bf16_kernel<3, true>), dim3(n_strip_pairs * P), dim3(BP_THREADS), 0, st, d_pairs,
-                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
     if (n_plain > 0)
       hipLaunchKernelGGL((gram_bf16_kernel<3, false>), dim3(n_plain * P), dim3(BP_THREADS), 0, st,
-                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
   } else {
     if (n_strip_pairs > 0)
       hipLaunchKernelGGL((gram_bf16_kernel<2, true>), dim3(n_strip_pairs * P), dim3(BP_THREADS), 0, st, d_pairs,
-                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
     if (n_plain > 0)
       hipLaunchKernelGGL((gram_bf16_kernel<2, false>), dim3(n_plain * P), dim3(BP_THREADS), 0, st,
-                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
   }
 }
 

@@ -100,7 +100,8 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
                                                                 const GramJob* __restrict__ jobs,
                                                                 const Slice* __restrict__ slices,
                                                                 int n_slices, int P,
-                                                                double* __restrict__ partial) {
+                                                                double* __restrict__ partial,
+    const int2* __restrict__ sets) {
   // wave instructions per step: A side codes (2 arrays x 2 groups) and
   // residuals (2 x 4); B side the same for two 64-column halves; diagonal
   // pairs also the aux columns (codes of both arrays in one, residuals one
@@ -121,6 +122,11 @@ __global__ __launch_bounds__(F8_THREADS, 1) void gram_fp8_kernel(const PairJob* 
   const GramJob JA = jobs[PJ.ja];
   const bool has_b = PJ.jb >= 0;
   const GramJob JB = jobs[has_b ? PJ.jb : PJ.ja];
+  if (sets) {
+    const int2 ss = sets[JA.set];
+    slices += ss.x;
+    n_slices = ss.y;
+  }
 
   // the wave index is provably uniform, so every per-wave choice is a scalar
   // branch: matrix-core instructions ignore the lane mask
@@ -546,22 +552,23 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const double* __restrict
 }  // namespace
 
 void launch_gram_fp8(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
-                     const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st) {
+                     const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st,
+                     const int2* d_sets) {
   const int n_plain = n_pairs - n_strip_pairs;
   if (nres == 2) {
     if (n_strip_pairs > 0)
       hipLaunchKernelGGL((gram_fp8_kernel<2, true>), dim3(n_strip_pairs * P), dim3(F8_THREADS), 0, st, d_pairs,
-                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
     if (n_plain > 0)
       hipLaunchKernelGGL((gram_fp8_kernel<2, false>), dim3(n_plain * P), dim3(F8_THREADS), 0, st,
-                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
   } else {
     if (n_strip_pairs > 0)
       hipLaunchKernelGGL((gram_fp8_kernel<1, true>), dim3(n_strip_pairs * P), dim3(F8_THREADS), 0, st, d_pairs,
-                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial);
+                         n_strip_pairs, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
     if (n_plain > 0)
       hipLaunchKernelGGL((gram_fp8_kernel<1, false>), dim3(n_plain * P), dim3(F8_THREADS), 0, st,
-                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+                         d_pairs + n_strip_pairs, n_plain, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
   }
 }
 

@@ -86,7 +86,8 @@ template <bool STRIPS>
 __global__ __launch_bounds__(PT, 1) void gram64_pair_kernel(const PairJob* __restrict__ pairs, int n_pairs,
                                                            const GramJob* __restrict__ jobs,
                                                            const Slice* __restrict__ slices, int n_slices,
-                                                           int P, double* __restrict__ partial) {
+                                                           int P, double* __restrict__ partial,
+    const int2* __restrict__ sets) {
   __shared__ PairLds L;
   // XCD-aware order (as gram_kernel): each XCD takes a contiguous range of
   // (slice group, pair) work items
@@ -98,6 +99,11 @@ __global__ __launch_bounds__(PT, 1) void gram64_pair_kernel(const PairJob* __res
   const GramJob JA = jobs[PJ.ja];
   const bool has_b = PJ.jb >= 0;
   const GramJob JB = jobs[has_b ? PJ.jb : PJ.ja];
+  if (sets) {
+    const int2 ss = sets[JA.set];
+    slices += ss.x;
+    n_slices = ss.y;
+  }
   const bool pair_strips = STRIPS && JA.kind == JOB_DIAG;
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -278,14 +284,15 @@ __global__ __launch_bounds__(PT, 1) void gram64_pair_kernel(const PairJob* __res
 }  // namespace
 
 void launch_gram64_pairs(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
-                         const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st) {
+                         const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st,
+                         const int2* d_sets) {
   const int n_plain = n_pairs - n_strip_pairs;
   if (n_strip_pairs > 0)
     hipLaunchKernelGGL(gram64_pair_kernel<true>, dim3(n_strip_pairs * P), dim3(PT), 0, st, d_pairs, n_strip_pairs,
-                       d_jobs, d_slices, n_slices, P, d_partial);
+                       d_jobs, d_slices, n_slices, P, d_partial, d_sets);
   if (n_plain > 0)
     hipLaunchKernelGGL(gram64_pair_kernel<false>, dim3(n_plain * P), dim3(PT), 0, st, d_pairs + n_strip_pairs,
-                       n_plain, d_jobs, d_slices, n_slices, P, d_partial);
+                       n_plain, d_jobs, d_slices, n_slices, P, d_partial, d_sets);
 }
 
 }  // namespace blm

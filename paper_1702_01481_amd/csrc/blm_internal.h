@@ -46,7 +46,8 @@ struct GramJob {
   int32_t mi, nj;       // valid rows / cols of the tile (<= GT)
   int32_t ag;           // JOB_DIAG, JOB_STRIP: first aux column of the strips' group (multiple of NAUX)
   int32_t ng;           // JOB_STRIP: aux groups of NAUX columns from ag (1..STRIP_GROUPS)
-  int32_t pad2;
+  int32_t set;          // launches over several contexts: the job's slice set (index into the
+                        // launch's table of (first slice, slice count)); 0 otherwise
   int64_t ci, cj;       // first source column of tile i / tile j
   int64_t s_off;        // destination of S tile (i,j): s_base[s_off + r*ld_out + c]
   int64_t h_off;        // destination of H tile (i,j)
@@ -184,13 +185,17 @@ constexpr int EIG_MAXSEL = 16;   // eigenvalues selected per problem (N_K + 1 <=
 // launchers (blm_kernels.hip / blm_eig.hip)
 // split: strip and aux jobs of a mixed build; stage2: the stage-two Gram
 // (its own kernel instantiation, named apart in traces)
+// d_sets (nullptr: every job reads slices [0, n_slices)): per slice set,
+// (first slice, slice count) in d_slices, for launches whose jobs belong to
+// several contexts (GramJob::set)
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                 bool vec, bool split, bool stage2, double* d_partial, hipStream_t st);
+                 bool vec, bool split, bool stage2, double* d_partial, hipStream_t st,
+                 const int2* d_sets = nullptr);
 // d_pairs: the n_strip_pairs pairs that start with a diagonal tile first,
 // then the others (each group is a launch of its own)
 void launch_gram_bf16(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
                       const Slice* d_slices, int n_slices, int P, int pieces, double* d_partial,
-                      hipStream_t st);
+                      hipStream_t st, const int2* d_sets = nullptr);
 void launch_pack_bf16(const double* src, int64_t n, int64_t ld_src, int64_t ncols, int pieces,
                       uint16_t* dst, int64_t ld_dst, int64_t pstride, hipStream_t st);
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
@@ -199,10 +204,12 @@ void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* 
 // FP64 block tiles in pairs sharing a row tile (blm_gram64.hip); d_pairs as
 // for launch_gram_bf16, indices into d_jobs
 void launch_gram64_pairs(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
-                         const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st);
+                         const Slice* d_slices, int n_slices, int P, double* d_partial, hipStream_t st,
+                         const int2* d_sets = nullptr);
 // nres: residuals per value in the FP8 storage (1 or 2)
 void launch_gram_fp8(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, const GramJob* d_jobs,
-                     const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st);
+                     const Slice* d_slices, int n_slices, int P, int nres, double* d_partial, hipStream_t st,
+                     const int2* d_sets = nullptr);
 // FP64 [n][ld_src] -> e4m3 codes (k-packed by 16), one or two BF16 residuals
 // (k-packed by 8; res2 nullptr: one) and per-column power-of-two scales
 // (blm_fp8.hip)

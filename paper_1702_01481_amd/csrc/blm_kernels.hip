@@ -464,7 +464,8 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
                                                            int n_jobs,
                                                            const Slice* __restrict__ slices,
                                                            int n_slices, int P,
-                                                           double* __restrict__ partial) {
+                                                           double* __restrict__ partial,
+                                                           const int2* __restrict__ sets) {
   // XCD-aware order: the hardware deals workgroups round-robin over the 8
   // XCDs; give each XCD a contiguous range of work items so that the tiles of
   // one block and one slice set (which share their sample panels) run on the
@@ -474,6 +475,11 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_kernel(const GramJob* __rest
   const int wid = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
   const int p = wid / n_jobs, jid = wid % n_jobs;
   const GramJob J = jobs[jid];
+  if (sets) {
+    const int2 ss = sets[J.set];
+    slices += ss.x;
+    n_slices = ss.y;
+  }
   __shared__ GramLds L;
   double* out = partial + ((size_t)jid * P + p) * (size_t)(3 * GT * GT);
   const bool full = VEC && J.mi == GT && J.nj == GT;
@@ -548,24 +554,24 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramJob* __restr
 }
 
 void launch_gram(const GramJob* d_jobs, int n_jobs, const Slice* d_slices, int n_slices, int P,
-                 bool vec, bool split, bool stage2, double* d_partial, hipStream_t st) {
+                 bool vec, bool split, bool stage2, double* d_partial, hipStream_t st, const int2* d_sets) {
   if (n_jobs <= 0) return;
   const dim3 grid(n_jobs * P), block(GTHREADS);
   if (split)
     hipLaunchKernelGGL((gram_kernel<false, true, false>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices, P,
-                       d_partial);
+                       d_partial, d_sets);
   else if (stage2 && vec)
     hipLaunchKernelGGL((gram_kernel<true, false, true>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices, P,
-                       d_partial);
+                       d_partial, d_sets);
   else if (stage2)
     hipLaunchKernelGGL((gram_kernel<false, false, true>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices,
-                       P, d_partial);
+                       P, d_partial, d_sets);
   else if (vec)
     hipLaunchKernelGGL((gram_kernel<true, false, false>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices,
-                       P, d_partial);
+                       P, d_partial, d_sets);
   else
     hipLaunchKernelGGL((gram_kernel<false, false, false>), grid, block, 0, st, d_jobs, n_jobs, d_slices, n_slices,
-                       P, d_partial);
+                       P, d_partial, d_sets);
 }
 
 void launch_gram_reduce(const GramJob* d_jobs, int n_jobs, int P, const double* d_partial,
