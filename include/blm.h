@@ -285,7 +285,8 @@ blm_status blm_stage2(blm_ctx* ctx, double* d_update, double* h_energy, double* 
  * share one eigensolver launch, and whose stage-two solves share another
  * (Sec. II.B applied to each context on its own; nothing is shared between
  * their estimates).  Their block builds can share one Gram launch too
- * (blm_batch_build); the projections stay per context.
+ * (blm_batch_build), and their projections one projection launch and one
+ * stage-two Gram launch (blm_batch_project).
  *
  * blm_batch_create takes n >= 1 distinct contexts created on the same
  * device and stream (else BLM_E_ARG) and allocates the batch's job tables
@@ -305,6 +306,15 @@ blm_status blm_batch_destroy(blm_batch* batch);
  * runs.  The estimates equal each context's own blm_build_blocks up to the
  * order of the FP64 sums over slice groups. */
 blm_status blm_batch_build(blm_batch* batch, const blm_chunk* const* chunks, const int32_t* n_chunks);
+
+/* blm_project for every context of the batch (Eq. 7 for each on its own):
+ * one launch projects every context's chunks onto that context's kept
+ * directions, and one Gram launch sums every context's stage-two estimates.
+ * chunks and n_chunks as for blm_batch_build; same storage and energy
+ * target, else BLM_E_ARG; a context whose block solves have not run returns
+ * BLM_E_STATE before anything runs.  The estimates equal each context's own
+ * blm_project up to the order of the FP64 sums over slice groups. */
+blm_status blm_batch_project(blm_batch* batch, const blm_chunk* const* chunks, const int32_t* n_chunks);
 
 /* blm_solve_blocks for every context of the batch.  h_evals and h_kept are
  * NULL or arrays of n host pointers (each NULL or as for blm_solve_blocks).

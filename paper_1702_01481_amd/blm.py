@@ -28,7 +28,7 @@ EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_accumul
             "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
             "blm_debug_eigvals", "blm_pencil_eigvals_static", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
-            "blm_batch_create", "blm_batch_destroy", "blm_batch_build", "blm_batch_solve_blocks", "blm_batch_stage2",
+            "blm_batch_create", "blm_batch_destroy", "blm_batch_build", "blm_batch_project", "blm_batch_solve_blocks", "blm_batch_stage2",
             "blm_last_error",
             "blm_status_string")
 TIMING_NAMES = ("theta_proj", "block_gram", "block_reduce", "block_assemble", "block_eig",
@@ -497,8 +497,7 @@ class Batch:
             msgs = [f"context {i}: {c.lib.blm_last_error(c.h).decode()}" for i, c in enumerate(self.ctxs)]
             raise BLMError(st, "; ".join(m for m in msgs if not m.endswith(": ")))
 
-    def build(self, chunk_lists: Sequence[Iterable]):
-        """blm_batch_build: chunk_lists[i] holds context i's chunks."""
+    def _chunk_tables(self, chunk_lists):
         n = len(self.ctxs)
         assert len(chunk_lists) == n
         arrs, counts = [], (C.c_int32 * n)()
@@ -506,8 +505,16 @@ class Batch:
             arr, m = ctx._chunks(chunks)
             arrs.append(arr)
             counts[i] = m
-        ptrs = (C.POINTER(_Chunk) * n)(*[C.cast(a, C.POINTER(_Chunk)) for a in arrs])
-        self._check(self.lib.blm_batch_build(self.h, ptrs, counts))
+        self._keepalive = arrs
+        return (C.POINTER(_Chunk) * n)(*[C.cast(a, C.POINTER(_Chunk)) for a in arrs]), counts
+
+    def build(self, chunk_lists: Sequence[Iterable]):
+        """blm_batch_build: chunk_lists[i] holds context i's chunks."""
+        self._check(self.lib.blm_batch_build(self.h, *self._chunk_tables(chunk_lists)))
+
+    def project(self, chunk_lists: Sequence[Iterable]):
+        """blm_batch_project: chunk_lists[i] holds context i's chunks."""
+        self._check(self.lib.blm_batch_project(self.h, *self._chunk_tables(chunk_lists)))
 
     def solve(self):
         """[(evals, kept)] per context, as BLM.solve."""

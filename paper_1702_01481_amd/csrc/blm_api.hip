@@ -96,7 +96,7 @@ struct blm_ctx {
   PairJob* d_pairsM = nullptr;   // BF16 build: pairs of main jobs sharing a row tile
   int n_pairsM = 0;
   int n_strip_pairsM = 0;        // the first n_strip_pairsM pairs start with a diagonal tile
-  std::vector<GramJob> h_jobs1, h_jobsM;   // host copies (batched builds merge them)
+  std::vector<GramJob> h_jobs1, h_jobsM, h_jobs2;   // host copies (batched calls merge them)
   std::vector<PairJob> h_pairsM;
   // FP64 build, second tile shape: the block tiles (the first n_main1 jobs
   // of d_jobs1) as pairs sharing a row tile (64 x 128 per workgroup), strip
@@ -689,26 +689,31 @@ blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) 
   return BLM_OK;
 }
 
-// One projection launch over all chunks of a call; returns via c->h_pchunks.
-// max_nd: the most directions of any block
-blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d_blocks,
-                       int n_blocks, const double* const* d_ptr, int n_dirs, int max_nd, double* Xo,
-                       double* Yo, int64_t ldo) {
-  c->h_pchunks.clear();
-  int tiles = 0;
+// The projection table entries of one context's chunks, appended to out:
+// tiles and row bases count on from *tiles and 0; *vec is cleared when a
+// chunk cannot take 16-byte loads.
+void add_pchunks(const blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d_blocks, int n_blocks,
+                 const double* const* d_ptr, int n_dirs, double* Xo, double* Yo, int64_t ldo,
+                 std::vector<ProjChunk>& out, int* tiles, bool* vec) {
   int64_t rb = 0;
-  bool vec = c->offsets_even;
   for (int i = 0; i < n; ++i) {
     const int64_t ns = ch[i].n_samples;
     if (ns == 0) continue;
     ProjChunk P{};
+    P.blocks = d_blocks;
+    P.dir = d_ptr;
+    P.Xo = Xo;
+    P.Yo = Yo;
+    P.ldo = ldo;
+    P.n_blocks = n_blocks;
+    P.n_dirs = n_dirs;
     P.O = ch[i].O;
     P.e = ch[i].e;
     P.EL = ch[i].E_L;
     P.ld = ch[i].ld;
     P.n = ns;
     P.row_base = rb;
-    P.tile0 = tiles;
+    P.tile0 = *tiles;
     P.pieces = c->pieces;
     P.pstride = ch[i].piece_stride;
     if (c->fp8) {
@@ -721,18 +726,31 @@ blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
         P.et = (const uint16_t*)ch[i].e_res2;
       }
     }
-    c->h_pchunks.push_back(P);
-    tiles += (int)((ns + PROJ_ROWS - 1) / PROJ_ROWS);
+    out.push_back(P);
+    *tiles += (int)((ns + PROJ_ROWS - 1) / PROJ_ROWS);
     rb += ns;
-    if ((ch[i].ld & 1) || ((uintptr_t)ch[i].O & 15) || ((uintptr_t)ch[i].e & 15)) vec = false;
+    if ((ch[i].ld & 1) || ((uintptr_t)ch[i].O & 15) || ((uintptr_t)ch[i].e & 15)) *vec = false;
   }
+  if (!c->offsets_even) *vec = false;
+}
+
+int store_kind(const blm_ctx* c) { return c->fp8 ? STORE_FP8 : c->pieces ? STORE_BF16 : STORE_F64; }
+
+// One projection launch over all chunks of a call; returns via c->h_pchunks.
+// max_nd: the most directions of any block
+blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d_blocks,
+                       int n_blocks, const double* const* d_ptr, int n_dirs, int max_nd, double* Xo,
+                       double* Yo, int64_t ldo) {
+  c->h_pchunks.clear();
+  int tiles = 0;
+  bool vec = true;
+  add_pchunks(c, ch, n, d_blocks, n_blocks, d_ptr, n_dirs, Xo, Yo, ldo, c->h_pchunks, &tiles, &vec);
   if (c->h_pchunks.empty() || c->dry) return BLM_OK;
   if (!c->cap)
     HIPCHK(c, hipMemcpyAsync(c->d_pchunks, c->h_pchunks.data(), sizeof(ProjChunk) * c->h_pchunks.size(),
                              hipMemcpyHostToDevice, c->st));
-  const int store = c->fp8 ? STORE_FP8 : c->pieces ? STORE_BF16 : STORE_F64;
-  launch_dirproj(pchunk_tab(c), (int)c->h_pchunks.size(), tiles, vec && store == STORE_F64, store,
-                 d_blocks, n_blocks, d_ptr, n_dirs, max_nd, Xo, Yo, ldo, c->st);
+  const int store = store_kind(c);
+  launch_dirproj(pchunk_tab(c), (int)c->h_pchunks.size(), tiles, vec && store == STORE_F64, store, max_nd, c->st);
   HIPCHK(c, hipGetLastError());
   return BLM_OK;
 }
@@ -1537,6 +1555,7 @@ blm_status solve_end(blm_ctx* c, double* h_evals, int32_t* h_kept) {
       jobs.push_back(J);
     }
   c->n_jobs2 = (int)jobs.size();
+  c->h_jobs2 = jobs;
   HIPCHK(c, hipMemcpyAsync(c->d_dir2_blk, db.data(), sizeof(DirBlock) * NB, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->d_dir2_ptr, dp.data(), sizeof(double*) * std::max<size_t>(dp.size(), 1),
                            hipMemcpyHostToDevice, c->st));
@@ -1569,17 +1588,14 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   return solve_end(c, h_evals, h_kept);
 }
 
-blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
-  if (!c) return BLM_E_ARG;
-  if (c->state != ST_SOLVED && c->state != ST_PROJECTED)
-    return fail(c, BLM_E_STATE, "blm_project needs blm_solve_blocks first");
-  int64_t total = 0;
-  blm_status s = check_chunks(c, ch, n, &total);
-  if (s != BLM_OK) return s;
+}  // extern "C"
+
+namespace {
+
+// The stage-two slice table (c->h_slices) over the projected samples of the
+// chunks: rows of Yp (1, O . directions) and Zp (E_L, e . directions).
+void proj_slices(blm_ctx* c, const blm_chunk* ch, int n) {
   const int64_t ldo = c->ld2;
-  mark(c, 5, false);
-  s = run_dirproj(c, ch, n, c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->n2 - 1, c->nd2max, c->Yp, c->Zp, ldo);
-  if (s != BLM_OK) return s;
   c->h_slices.clear();
   int64_t rb = 0;
   for (int i = 0; i < n; ++i) {
@@ -1596,6 +1612,24 @@ blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
     }
     rb += ns;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
+  if (!c) return BLM_E_ARG;
+  if (c->state != ST_SOLVED && c->state != ST_PROJECTED)
+    return fail(c, BLM_E_STATE, "blm_project needs blm_solve_blocks first");
+  int64_t total = 0;
+  blm_status s = check_chunks(c, ch, n, &total);
+  if (s != BLM_OK) return s;
+  const int64_t ldo = c->ld2;
+  mark(c, 5, false);
+  s = run_dirproj(c, ch, n, c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->n2 - 1, c->nd2max, c->Yp, c->Zp, ldo);
+  if (s != BLM_OK) return s;
+  proj_slices(c, ch, n);
   mark(c, 5, true);
   s = run_gram(c, c->d_jobs2, c->n_jobs2, c->Pcap2, c->G2S, c->G2H, nullptr, 6, true, 4);
   if (s != BLM_OK) return s;
@@ -1870,6 +1904,12 @@ struct blm_batch {
   double* partial = nullptr;
   std::vector<Slice> h_slices;
   std::vector<int2> h_sets;
+  // one projection launch and one stage-two Gram launch for every context
+  ProjChunk* d_pchunks = nullptr;
+  std::vector<ProjChunk> h_pchunks;
+  GramJob* d_jobs2 = nullptr;   // the contexts' stage-two jobs, set per call
+  int P2 = 1;                   // slice groups of the stage-two launch
+  size_t partial_slots = 0;
 };
 
 blm_status blm_batch_create(blm_ctx* const* ctxs, int32_t n, blm_batch** out) {
@@ -1942,12 +1982,24 @@ blm_status blm_batch_create(blm_ctx* const* ctxs, int32_t n, blm_batch** out) {
     // slice groups: about 4,096 workgroups in the largest launch
     const int nj = std::max(b->n_jobs1, b->n_jobsM);
     b->P = std::max(1, std::min(64, (4096 + nj - 1) / nj));
-    const size_t slots = (size_t)nj * b->P;
+    // stage two: at most every context's largest job table
+    int nj2 = 0;
+    for (int i = 0; i < n; ++i) {
+      const int T2 = (ctxs[i]->n2max + GT - 1) / GT;
+      nj2 += T2 * (T2 + 1) / 2;
+    }
+    b->P2 = std::max(1, std::min(512, (4096 + nj2 - 1) / nj2));
+    const size_t slots = std::max((size_t)nj * b->P, (size_t)nj2 * b->P2);
+    b->partial_slots = slots;
+    size_t n_pchunks = 0;
+    for (int i = 0; i < n; ++i) n_pchunks += MAX_CHUNKS;
     bool ok = hipMalloc((void**)&b->d_jobs1, sizeof(GramJob) * std::max<size_t>(j1.size(), 1)) == hipSuccess &&
               hipMalloc((void**)&b->d_jobsM, sizeof(GramJob) * std::max<size_t>(jm.size(), 1)) == hipSuccess &&
               hipMalloc((void**)&b->d_pairsM, sizeof(PairJob) * std::max<size_t>(pairs.size(), 1)) == hipSuccess &&
               hipMalloc((void**)&b->d_slices, sizeof(Slice) * (size_t)b->max_slices) == hipSuccess &&
               hipMalloc((void**)&b->d_sets, sizeof(int2) * (size_t)n) == hipSuccess &&
+              hipMalloc((void**)&b->d_pchunks, sizeof(ProjChunk) * n_pchunks) == hipSuccess &&
+              hipMalloc((void**)&b->d_jobs2, sizeof(GramJob) * (size_t)nj2) == hipSuccess &&
               hipMalloc((void**)&b->partial, 8 * slots * 3 * GT * GT) == hipSuccess;
     ok = ok && hipMemcpy(b->d_jobs1, j1.data(), sizeof(GramJob) * j1.size(), hipMemcpyHostToDevice) == hipSuccess;
     if (ok && !jm.empty())
@@ -1975,6 +2027,8 @@ blm_status blm_batch_destroy(blm_batch* b) {
   (void)hipFree(b->d_slices);
   (void)hipFree(b->d_sets);
   (void)hipFree(b->partial);
+  (void)hipFree(b->d_pchunks);
+  (void)hipFree(b->d_jobs2);
   delete b;
   return BLM_OK;
 }
@@ -2044,6 +2098,91 @@ blm_status blm_batch_build(blm_batch* b, const blm_chunk* const* chunks, const i
   for (int i = 0; i < n; ++i) {
     b->ctx[i]->n_pass1 += tot[i];
     b->ctx[i]->state = ST_BUILT;
+  }
+  return BLM_OK;
+}
+
+blm_status blm_batch_project(blm_batch* b, const blm_chunk* const* chunks, const int32_t* n_chunks) {
+  if (!b || !chunks || !n_chunks) return BLM_E_ARG;
+  const int n = (int)b->ctx.size();
+  blm_ctx* c0 = b->ctx[0];
+  if (!b->merged)
+    return fail(c0, BLM_E_ARG, "a batched projection needs contexts of one storage and the energy target");
+  std::vector<int64_t> tot(n, 0);
+  for (int i = 0; i < n; ++i) {
+    blm_ctx* c = b->ctx[i];
+    if (c->state != ST_SOLVED && c->state != ST_PROJECTED)
+      return fail(c, BLM_E_STATE, "blm_batch_project needs the block solves first");
+    blm_status s = check_chunks(c, chunks[i], n_chunks[i], &tot[i]);
+    if (s != BLM_OK) return s;
+  }
+  // every context's samples onto its kept directions, in one launch
+  b->h_pchunks.clear();
+  int tiles = 0, max_nd = 0;
+  bool vec = true;
+  for (int i = 0; i < n; ++i) {
+    blm_ctx* c = b->ctx[i];
+    add_pchunks(c, chunks[i], n_chunks[i], c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->n2 - 1, c->Yp, c->Zp, c->ld2,
+                b->h_pchunks, &tiles, &vec);
+    max_nd = std::max(max_nd, c->nd2max);
+  }
+  for (blm_ctx* c : b->ctx) mark(c, 5, false);
+  if (!b->h_pchunks.empty()) {
+    HIPCHK(c0, hipMemcpyAsync(b->d_pchunks, b->h_pchunks.data(), sizeof(ProjChunk) * b->h_pchunks.size(),
+                              hipMemcpyHostToDevice, b->st));
+    const int store = store_kind(c0);
+    launch_dirproj(b->d_pchunks, (int)b->h_pchunks.size(), tiles, vec && store == STORE_F64, store, max_nd, b->st);
+    HIPCHK(c0, hipGetLastError());
+  }
+  for (blm_ctx* c : b->ctx) mark(c, 5, true);
+  // the stage-two sums of every context in one Gram launch: each job reads
+  // its own context's slices of projected samples
+  b->h_slices.clear();
+  b->h_sets.assign(n, make_int2(0, 0));
+  std::vector<GramJob> jobs;
+  std::vector<int> off(n, 0);
+  for (int i = 0; i < n; ++i) {
+    blm_ctx* c = b->ctx[i];
+    proj_slices(c, chunks[i], n_chunks[i]);
+    b->h_sets[i] = make_int2((int)b->h_slices.size(), (int)c->h_slices.size());
+    b->h_slices.insert(b->h_slices.end(), c->h_slices.begin(), c->h_slices.end());
+    off[i] = (int)jobs.size();
+    for (GramJob J : c->h_jobs2) {
+      J.set = i;
+      jobs.push_back(J);
+    }
+  }
+  bool vec2 = true;
+  for (const Slice& S : b->h_slices)
+    if ((S.ld & 1) || ((uintptr_t)S.O & 15) || ((uintptr_t)S.e & 15)) vec2 = false;
+  if ((int)b->h_slices.size() > b->max_slices) return fail(c0, BLM_E_ARG, "too many slices in one call");
+  const int P2 = std::max(1, std::min(b->P2, (4096 + (int)jobs.size() - 1) / std::max(1, (int)jobs.size())));
+  if ((size_t)jobs.size() * P2 > b->partial_slots) return fail(c0, BLM_E_ARG, "stage-two tables exceed the plan");
+  if (!b->h_slices.empty() && !jobs.empty()) {
+    HIPCHK(c0, hipMemcpyAsync(b->d_slices, b->h_slices.data(), sizeof(Slice) * b->h_slices.size(),
+                              hipMemcpyHostToDevice, b->st));
+    HIPCHK(c0, hipMemcpyAsync(b->d_sets, b->h_sets.data(), sizeof(int2) * n, hipMemcpyHostToDevice, b->st));
+    HIPCHK(c0, hipMemcpyAsync(b->d_jobs2, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice,
+                              b->st));
+    const size_t tile = (size_t)3 * GT * GT;
+    for (blm_ctx* c : b->ctx) mark(c, 6, false);
+    launch_gram(b->d_jobs2, (int)jobs.size(), b->d_slices, 0, P2, vec2, false, true, b->partial, b->st, b->d_sets);
+    HIPCHK(c0, hipGetLastError());
+    for (blm_ctx* c : b->ctx) {
+      mark(c, 6, true);
+      mark(c, 7, false);
+    }
+    for (int i = 0; i < n; ++i) {
+      blm_ctx* c = b->ctx[i];
+      launch_gram_reduce(c->d_jobs2, c->n_jobs2, P2, b->partial + (size_t)off[i] * P2 * tile, c->G2S, c->G2H,
+                         nullptr, c->NV, c->NAP, b->st);
+    }
+    HIPCHK(c0, hipGetLastError());
+    for (blm_ctx* c : b->ctx) mark(c, 7, true);
+  }
+  for (int i = 0; i < n; ++i) {
+    b->ctx[i]->n_pass2 += tot[i];
+    b->ctx[i]->state = ST_PROJECTED;
   }
   return BLM_OK;
 }

@@ -113,8 +113,17 @@ struct DirBlock {
 };
 
 // one chunk of a projection launch: its samples go to output rows
-// [row_base, row_base + n); workgroups [tile0, tile0 + ceil(n / 64)) cover it
+// [row_base, row_base + n) of Xo and Yo; workgroups [tile0, tile0 + ceil(n /
+// 64)) cover it.  The blocks, directions and outputs are per chunk, so that
+// one launch can serve the chunks of several contexts.
 struct ProjChunk {
+  const DirBlock* blocks;
+  const double* const* dir;   // the directions, indexed by DirBlock::d0 + t
+  double* Xo;                 // [rows][ldo]: column 0 is 1, then O . dir
+  double* Yo;                 // [rows][ldo]: column 0 is E_L, then e . dir
+  int64_t ldo;
+  int32_t n_blocks;
+  int32_t n_dirs;             // columns past 1 + n_dirs are written as zeros
   const void* O;
   const void* e;
   const double* EL;
@@ -215,9 +224,9 @@ void launch_gram_fp8(const PairJob* d_pairs, int n_strip_pairs, int n_pairs, con
 // (blm_fp8.hip)
 void launch_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t ncols, uint8_t* codes,
                      uint16_t* res, uint16_t* res2, float* scale, int64_t ld_dst, hipStream_t st);
-void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store,
-                    const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
-                    int n_dirs, int max_nd, double* Xo, double* Yo, int64_t ldo, hipStream_t st);
+// max_nd: the most directions of any block of any chunk
+void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store, int max_nd,
+                    hipStream_t st);
 void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);
 // the same with each pencil's Hessenberg reduction spread over several
 // workgroups (cooperative launch; d_bar: 2 n_jobs counters); returns false

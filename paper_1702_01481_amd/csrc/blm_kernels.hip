@@ -704,13 +704,7 @@ __device__ __forceinline__ void pj_store(double (*sO)[PJ_P + 1], double (*sE)[PJ
 }
 
 template <bool VEC, int ST>
-__global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restrict__ chunks,
-                                                      int n_chunks,
-                                                      const DirBlock* __restrict__ blocks,
-                                                      int n_blocks,
-                                                      const double* const* __restrict__ dir_ptr,
-                                                      int n_dirs, double* __restrict__ Xo,
-                                                      double* __restrict__ Yo, int64_t ldo) {
+__global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restrict__ chunks, int n_chunks) {
   __shared__ double sO[PJ_ROWS][PJ_P + 1];
   __shared__ double sE[PJ_ROWS][PJ_P + 1];
   __shared__ double sD[PJ_D][PJ_P + 1];
@@ -719,8 +713,12 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
   while (ci + 1 < n_chunks && chunks[ci + 1].tile0 <= (int)blockIdx.x) ++ci;
   const ProjChunk C = chunks[ci];
   const int64_t s0 = (int64_t)(blockIdx.x - C.tile0) * PJ_ROWS;
-  BLM_GLOBAL double* X = as_global(Xo) + C.row_base * ldo;
-  BLM_GLOBAL double* Y = as_global(Yo) + C.row_base * ldo;
+  const DirBlock* __restrict__ blocks = C.blocks;
+  const double* const* __restrict__ dir_ptr = C.dir;
+  const int n_blocks = C.n_blocks, n_dirs = C.n_dirs;
+  const int64_t ldo = C.ldo;
+  BLM_GLOBAL double* X = as_global(C.Xo) + C.row_base * ldo;
+  BLM_GLOBAL double* Y = as_global(C.Yo) + C.row_base * ldo;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i16 = lane & 15, k4 = lane >> 4;
 
@@ -793,17 +791,17 @@ __global__ __launch_bounds__(256) void dirproj_kernel(const ProjChunk* __restric
 constexpr int PJ_SMALL = 2;
 
 template <int ST>
-__global__ __launch_bounds__(256) void dirproj_small_kernel(const ProjChunk* __restrict__ chunks, int n_chunks,
-                                                            const DirBlock* __restrict__ blocks, int n_blocks,
-                                                            const double* const* __restrict__ dir_ptr,
-                                                            int n_dirs, double* __restrict__ Xo,
-                                                            double* __restrict__ Yo, int64_t ldo) {
+__global__ __launch_bounds__(256) void dirproj_small_kernel(const ProjChunk* __restrict__ chunks, int n_chunks) {
   int ci = 0;
   while (ci + 1 < n_chunks && chunks[ci + 1].tile0 <= (int)blockIdx.x) ++ci;
   const ProjChunk C = chunks[ci];
   const int64_t s0 = (int64_t)(blockIdx.x - C.tile0) * PJ_ROWS;
-  BLM_GLOBAL double* X = as_global(Xo) + C.row_base * ldo;
-  BLM_GLOBAL double* Y = as_global(Yo) + C.row_base * ldo;
+  const DirBlock* __restrict__ blocks = C.blocks;
+  const double* const* __restrict__ dir_ptr = C.dir;
+  const int n_blocks = C.n_blocks, n_dirs = C.n_dirs;
+  const int64_t ldo = C.ldo;
+  BLM_GLOBAL double* X = as_global(C.Xo) + C.row_base * ldo;
+  BLM_GLOBAL double* Y = as_global(C.Yo) + C.row_base * ldo;
   const int tid = threadIdx.x;
   // column 0 (the wave function itself: 1 and E_L) and the padding columns
   for (int t = tid; t < PJ_ROWS * (int)ldo; t += blockDim.x) {
@@ -957,19 +955,17 @@ __device__ __forceinline__ void pj64_block(const BLM_GLOBAL double* rO, const BL
 }
 
 template <bool VEC>
-__global__ __launch_bounds__(256) void dirproj64_kernel(const ProjChunk* __restrict__ chunks,
-                                                        int n_chunks,
-                                                        const DirBlock* __restrict__ blocks,
-                                                        int n_blocks,
-                                                        const double* const* __restrict__ dir_ptr,
-                                                        int n_dirs, double* __restrict__ Xo,
-                                                        double* __restrict__ Yo, int64_t ldo) {
+__global__ __launch_bounds__(256) void dirproj64_kernel(const ProjChunk* __restrict__ chunks, int n_chunks) {
   int ci = 0;
   while (ci + 1 < n_chunks && chunks[ci + 1].tile0 <= (int)blockIdx.x) ++ci;
   const ProjChunk C = chunks[ci];
   const int64_t s0 = (int64_t)(blockIdx.x - C.tile0) * PJ_ROWS;
-  BLM_GLOBAL double* X = as_global(Xo) + C.row_base * ldo;
-  BLM_GLOBAL double* Y = as_global(Yo) + C.row_base * ldo;
+  const DirBlock* __restrict__ blocks = C.blocks;
+  const double* const* __restrict__ dir_ptr = C.dir;
+  const int n_blocks = C.n_blocks, n_dirs = C.n_dirs;
+  const int64_t ldo = C.ldo;
+  BLM_GLOBAL double* X = as_global(C.Xo) + C.row_base * ldo;
+  BLM_GLOBAL double* Y = as_global(C.Yo) + C.row_base * ldo;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i16 = lane & 15, g = lane >> 4;
 
@@ -1024,29 +1020,22 @@ __global__ __launch_bounds__(256) void dirproj64_kernel(const ProjChunk* __restr
   }
 }
 
-void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store,
-                    const DirBlock* d_blocks, int n_blocks, const double* const* d_dir_ptr,
-                    int n_dirs, int max_nd, double* Xo, double* Yo, int64_t ldo, hipStream_t st) {
+void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store, int max_nd,
+                    hipStream_t st) {
   if (n_tiles <= 0) return;
   if (store != STORE_F64 && max_nd <= PJ_SMALL) {
     if (store == STORE_BF16)
-      hipLaunchKernelGGL((dirproj_small_kernel<STORE_BF16>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks,
-                         d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+      hipLaunchKernelGGL((dirproj_small_kernel<STORE_BF16>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks);
     else
-      hipLaunchKernelGGL((dirproj_small_kernel<STORE_FP8>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks,
-                         d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+      hipLaunchKernelGGL((dirproj_small_kernel<STORE_FP8>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks);
   } else if (store == STORE_BF16)
-    hipLaunchKernelGGL((dirproj_kernel<false, STORE_BF16>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
-                       n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+    hipLaunchKernelGGL((dirproj_kernel<false, STORE_BF16>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks);
   else if (store == STORE_FP8)
-    hipLaunchKernelGGL((dirproj_kernel<false, STORE_FP8>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
-                       n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+    hipLaunchKernelGGL((dirproj_kernel<false, STORE_FP8>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks);
   else if (vec)
-    hipLaunchKernelGGL((dirproj64_kernel<true>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
-                       n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+    hipLaunchKernelGGL((dirproj64_kernel<true>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks);
   else
-    hipLaunchKernelGGL((dirproj64_kernel<false>), dim3(n_tiles), dim3(256), 0, st, d_chunks,
-                       n_chunks, d_blocks, n_blocks, d_dir_ptr, n_dirs, Xo, Yo, ldo);
+    hipLaunchKernelGGL((dirproj64_kernel<false>), dim3(n_tiles), dim3(256), 0, st, d_chunks, n_chunks);
 }
 
 }  // namespace blm

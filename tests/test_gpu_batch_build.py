@@ -1,17 +1,20 @@
 """One Gram launch for the block builds of several independent optimisations
-(blm_batch_build): every context's tile jobs in one launch, each reading its
-own context's chunks (Eq. 3 for each context on its own).
+(blm_batch_build), and one projection launch plus one stage-two Gram launch
+for their projections (blm_batch_project): every context's jobs in one
+launch, each reading its own context's chunks (Eq. 3 and Eq. 7 for each
+context on its own).
 
 * Three contexts of different shapes (one to three blocks, one or two
   shifts), in FP64, BF16 x3 and FP8 with two residuals: every block matrix
-  of the batched build equals the context's own build up to the order of
-  the FP64 sums over slice groups (relative Frobenius 1e-13), and the rest
-  of the step, through the batch's shared solves, gives the same energies
-  (1e-10 relative) and updates (cosine 1 - 1e-10).
+  of the batched build, and every stage-two matrix of the batched
+  projection, equals the context's own up to the order of the FP64 sums
+  over slice groups (relative Frobenius 1e-13); the whole batched step
+  gives the same energies (1e-10 relative) and updates (cosine 1 - 1e-10).
 * The eight-problem workload (N_V from 2,000 to 20,000, 78,000 parameters)
-  at 16,384 samples per problem: one FP64 build launch for all eight against
-  eight builds (1e-13), with both timed and printed.
-* A batch of contexts with different storages refuses a batched build.
+  at 16,384 samples per problem: batched build and projection against eight
+  of each (1e-13), with both timed and printed.
+* A batch of contexts with different storages refuses a batched build and
+  a batched projection.
 """
 import time
 
@@ -90,9 +93,18 @@ def test_batched_build_equals_single_builds(prec):
         c.project([d])
         u, en, _, _ = c.stage2()
         res1.append((u.cpu().numpy(), en, k))
+    torch.cuda.synchronize()
     kept2 = [k for _, k in b.solve()]
-    for c, d in zip(batched, data):
-        c.project([d])
+    b.project([[d] for d in data])
+    torch.cuda.synchronize()
+    worst2 = 0.0
+    for (_, _, sh, _, _), c1, c2 in zip(PROBLEMS, single, batched):
+        for si in range(len(sh)):
+            A1, B1 = c1.stage2_matrices(si)
+            A2, B2 = c2.stage2_matrices(si)
+            worst2 = max(worst2, _rel(A2, A1), _rel(B2, B1))
+    print(f"[batch-build] {prec}: stage-two matrices of the batched projection within {worst2:.1e}", flush=True)
+    assert worst2 <= 1e-13, worst2
     out2 = b.stage2()
     torch.cuda.synchronize()
     for q, ((u1, e1, k1), (u2, e2, _, _), k2) in enumerate(zip(res1, out2, kept2)):
@@ -123,30 +135,51 @@ def test_eight_problems_in_one_build_launch():
 
     single, batched = contexts(), contexts()
     b = blm.Batch(batched)
-    times = {}
+    chunk_lists = [[d] for d in data]
+    t = {}
+
+    def clock(key, fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        t[key] = (time.perf_counter() - t0) * 1e3
+
     for rep in range(2):           # the second pass is timed
         for c in single + batched:
             c.begin_step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for c, d in zip(single, data):
-            c.build([d])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        b.build([[d] for d in data])
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        times = {"single": (t1 - t0) * 1e3, "batched": (t2 - t1) * 1e3}
-    worst = 0.0
+        clock("build1", lambda: [c.build([d]) for c, d in zip(single, data)])
+        clock("buildB", lambda: b.build(chunk_lists))
+    worst = worst2 = 0.0
     for w, c1, c2 in zip(ws, single, batched):
         for blk in range(w.n_blocks):
             H1, S1 = c1.block_matrices(blk, 0)
             H2, S2 = c2.block_matrices(blk, 0)
             worst = max(worst, _rel(S2, S1), _rel(H2, H1))
+    # the projection on its own: both sides build and solve per context, so
+    # that their kept directions are the same bits (a direction's sign, or
+    # its rotation within a near-degenerate pair, follows the last bits of
+    # the block matrices, which the order of the batched build's sums moves)
+    for rep in range(2):
+        for c in single + batched:
+            c.begin_step()
+        for c, d in zip(single + batched, data + data):
+            c.build([d])
+        for c in single + batched:
+            c.solve()
+        clock("proj1", lambda: [c.project([d]) for c, d in zip(single, data)])
+        clock("projB", lambda: b.project(chunk_lists))
+    for w, c1, c2 in zip(ws, single, batched):
+        for si in range(len(w.shifts)):
+            A1, B1 = c1.stage2_matrices(si)
+            A2, B2 = c2.stage2_matrices(si)
+            worst2 = max(worst2, _rel(A2, A1), _rel(B2, B1))
     print(f"[batch-build] eight problems, {sum(w.n_blocks for w in ws)} blocks, {ns} samples each: eight builds "
-          f"{times['single']:.1f} ms, one batched build {times['batched']:.1f} ms; matrices within {worst:.1e}",
+          f"{t['build1']:.1f} ms, one batched build {t['buildB']:.1f} ms (matrices within {worst:.1e}); eight "
+          f"projections {t['proj1']:.1f} ms, one batched projection {t['projB']:.1f} ms (within {worst2:.1e})",
           flush=True)
     assert worst <= 1e-13, worst
+    assert worst2 <= 1e-13, worst2
     b.close()
     for c in single + batched:
         c.close()
@@ -161,8 +194,12 @@ def test_mixed_storages_refuse_a_batched_build():
     b = blm.Batch([a, c])
     a.begin_step()
     c.begin_step()
+    lists = [[(O, e, EL)], [(blm.SplitSamples(O, 3), blm.SplitSamples(e, 3), EL)]]
     with pytest.raises(blm.BLMError) as ei:
-        b.build([[(O, e, EL)], [(blm.SplitSamples(O, 3), blm.SplitSamples(e, 3), EL)]])
+        b.build(lists)
+    assert ei.value.status == 1
+    with pytest.raises(blm.BLMError) as ei:
+        b.project(lists)
     assert ei.value.status == 1
     b.close()
     a.close()
