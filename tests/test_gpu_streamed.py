@@ -94,10 +94,12 @@ def test_sixteen_blocks_full_samples_bf16x3():
         assert coss[si] >= 0.9999, (si, coss[si])
 
 
-@pytest.mark.xfail(reason="the BF16 x3 block matrices sit about 2e-8 from FP64, a systematic floor of the matrix "
-                          "cores' FP32 partial sums that does not shrink with more samples (2.2e-8 at 131,072 "
-                          "samples, 1.9e-8 at 4,000,000), and these pencils move the energy by about 700 times "
-                          "that: 1.3e-5 measured at delta = 1e-4", strict=False)
+@pytest.mark.xfail(reason="the BF16 x3 block matrices sit about 2e-8 from FP64 (2.2e-8 at 131,072 samples, 1.9e-8 "
+                          "at 4,000,000): the rounding of the matrix cores' FP32 partial sums, which is unbiased "
+                          "but falls on couplings whose sums grow like their rounding errors, as the square root "
+                          "of the sample count, so more samples do not shrink it; the storage's own error is 50 "
+                          "times smaller; these pencils move the energy by about 700 times the matrices' error: "
+                          "1.3e-5 measured at delta = 1e-4", strict=False)
 def test_sixteen_blocks_full_samples_bf16x3_energy():
     if "energy_rel" not in _RESULT:
         pytest.skip("needs the streamed step")
