@@ -400,6 +400,29 @@ blm_status blm_get_timings(blm_ctx* ctx, double* h_ms, int32_t n);
  * of early deflations and of bulge chases. */
 blm_status blm_get_solver_stats(blm_ctx* ctx, int32_t* h_stats, int32_t n);
 
+/* Checkpoint of pass 1 (Sec. II.B: the block estimates are running sums
+ * over the samples, Eq. 3 on the one-block basis, so a step interrupted
+ * between chunks can resume from them).  The state is the FP64 sums of
+ * every block, the coupling strips and the aux Gram (Fig. 1; for the Omega
+ * target also the second pass's sums), the sample count of pass 1, and a
+ * fingerprint of the configuration and of the step's previous directions.
+ *
+ * blm_state_bytes: the size of the state of this context (host bytes).
+ * blm_export_state: after blm_begin_step and any number of
+ *   blm_build_blocks / blm_replay_build calls, before blm_solve_blocks
+ *   (else BLM_E_STATE); writes the state to the host buffer h_buf of
+ *   `bytes` >= blm_state_bytes (else BLM_E_ARG).  Synchronises the stream.
+ * blm_import_state: into a context created with the same configuration,
+ *   right after blm_begin_step with the same previous directions and before
+ *   any build (else BLM_E_STATE; a state of another configuration is
+ *   BLM_E_ARG).  Later builds add to the imported sums exactly as they
+ *   would have to the exporting context's, so the step's results are the
+ *   same bit for bit.  Synchronises the stream.  The buffer stays the
+ *   caller's. */
+blm_status blm_state_bytes(const blm_ctx* ctx, size_t* bytes);
+blm_status blm_export_state(blm_ctx* ctx, void* h_buf, size_t bytes);
+blm_status blm_import_state(blm_ctx* ctx, const void* h_buf, size_t bytes);
+
 const char* blm_last_error(const blm_ctx* ctx);
 const char* blm_status_string(blm_status s);
 

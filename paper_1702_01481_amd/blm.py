@@ -28,6 +28,7 @@ EXPORTED = ("blm_pack_bf16", "blm_pack_fp8", "blm_workspace_bytes", "blm_accumul
             "blm_solve_blocks", "blm_project", "blm_stage2",
             "blm_get_block_matrices", "blm_get_directions", "blm_get_stage2_matrices",
             "blm_debug_eigvals", "blm_pencil_eigvals_static", "blm_set_timing", "blm_get_timings", "blm_get_solver_stats",
+            "blm_state_bytes", "blm_export_state", "blm_import_state",
             "blm_batch_create", "blm_batch_destroy", "blm_batch_build", "blm_batch_project", "blm_batch_solve_blocks", "blm_batch_stage2",
             "blm_last_error",
             "blm_status_string")
@@ -449,6 +450,20 @@ class BLM:
         out = np.full(len(TIMING_NAMES), -1.0)
         self._check(self.lib.blm_get_timings(self.h, _dptr(out), len(out)))
         return {k: float(v) for k, v in zip(TIMING_NAMES, out)}
+
+    # -- checkpoint of pass 1 -----------------------------------------------
+    def export_state(self) -> np.ndarray:
+        """blm_export_state: the step's pass-1 sums and fingerprint, as bytes."""
+        n = C.c_size_t()
+        self._check(self.lib.blm_state_bytes(self.h, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self.lib.blm_export_state(self.h, buf.ctypes.data_as(C.c_void_p), C.c_size_t(buf.nbytes)))
+        return buf
+
+    def import_state(self, buf: np.ndarray):
+        """blm_import_state: right after begin_step, with the same previous directions."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.blm_import_state(self.h, buf.ctypes.data_as(C.c_void_p), C.c_size_t(buf.nbytes)))
 
     def block_matrices(self, block: int, shift: int = 0):
         d = C.c_int32()

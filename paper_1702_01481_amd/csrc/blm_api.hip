@@ -992,6 +992,145 @@ blm_status blm_pack_fp8(const double* src, int64_t n, int64_t ld_src, int64_t nc
   return hipGetLastError() == hipSuccess ? BLM_OK : BLM_E_HIP;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Header of an exported pass-1 state; the FP64 arrays follow it.
+struct StateHeader {
+  uint64_t magic;
+  int64_t version, target, NV, NB, NK, NO, NS, pieces, fp8, fp8_res, NAP;
+  double omega;
+  uint64_t cfg_hash;     // block offsets and shifts
+  uint64_t theta_hash;   // the step's previous directions after blm_begin_step
+  int64_t n_pass1, acc_elems, strip_elems;
+};
+constexpr uint64_t STATE_MAGIC = 0x31544154534d4c42ull;   // "BLMSTAT1"
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+int64_t state_strip_elems(const blm_ctx* c) { return (int64_t)3 * c->NAP * c->NV; }
+
+size_t state_size(const blm_ctx* c) {
+  const int64_t per = c->acc_elems * 2 + state_strip_elems(c);
+  const int64_t om = c->target == BLM_TARGET_OMEGA ? c->acc_elems + state_strip_elems(c) : 0;
+  return sizeof(StateHeader) + 8 * (size_t)(per + om);
+}
+
+// The header of this context's current step (theta_hash reads the step's
+// previous directions back from the device).
+blm_status state_header(blm_ctx* c, StateHeader* H) {
+  *H = StateHeader{};
+  H->magic = STATE_MAGIC;
+  H->version = 1;
+  H->target = c->target;
+  H->NV = c->NV;
+  H->NB = c->NB;
+  H->NK = c->NK;
+  H->NO = c->NO;
+  H->NS = c->NS;
+  H->pieces = c->pieces;
+  H->fp8 = c->fp8;
+  H->fp8_res = c->fp8_res;
+  H->NAP = c->NAP;
+  H->omega = c->omega;
+  uint64_t h = 0xcbf29ce484222325ull;
+  h = fnv1a(h, c->off.data(), 8 * c->off.size());
+  h = fnv1a(h, c->shifts.data(), 8 * c->shifts.size());
+  H->cfg_hash = h;
+  uint64_t t = 0xcbf29ce484222325ull;
+  if (c->NO > 0) {
+    std::vector<double> D((size_t)c->NO * c->NV);
+    HIPCHK(c, hipMemcpyAsync(D.data(), c->D, 8 * D.size(), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    t = fnv1a(t, D.data(), 8 * D.size());
+    t = fnv1a(t, c->dkeep.data(), sizeof(int) * c->dkeep.size());
+  }
+  H->theta_hash = t;
+  H->n_pass1 = c->n_pass1;
+  H->acc_elems = c->acc_elems;
+  H->strip_elems = state_strip_elems(c);
+  return BLM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+blm_status blm_state_bytes(const blm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return BLM_E_ARG;
+  *bytes = state_size(c);
+  return BLM_OK;
+}
+
+blm_status blm_export_state(blm_ctx* c, void* h_buf, size_t bytes) {
+  if (!c) return BLM_E_ARG;
+  if (!h_buf || bytes < state_size(c)) return fail(c, BLM_E_ARG, "state buffer missing or too small");
+  if (c->state != ST_BEGUN && c->state != ST_BUILT)
+    return fail(c, BLM_E_STATE, "blm_export_state needs a step in pass 1 (after blm_begin_step, before the solves)");
+  StateHeader H;
+  blm_status s = state_header(c, &H);
+  if (s != BLM_OK) return s;
+  std::memcpy(h_buf, &H, sizeof H);
+  char* p = (char*)h_buf + sizeof H;
+  auto put = [&](const double* d, int64_t n) -> blm_status {
+    HIPCHK(c, hipMemcpyAsync(p, d, 8 * (size_t)n, hipMemcpyDeviceToHost, c->st));
+    p += 8 * (size_t)n;
+    return BLM_OK;
+  };
+  if ((s = put(c->accS, c->acc_elems)) != BLM_OK || (s = put(c->accH, c->acc_elems)) != BLM_OK ||
+      (s = put(c->strips, H.strip_elems)) != BLM_OK)
+    return s;
+  if (c->target == BLM_TARGET_OMEGA &&
+      ((s = put(c->accE, c->acc_elems)) != BLM_OK || (s = put(c->stripsE, H.strip_elems)) != BLM_OK))
+    return s;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return BLM_OK;
+}
+
+blm_status blm_import_state(blm_ctx* c, const void* h_buf, size_t bytes) {
+  if (!c) return BLM_E_ARG;
+  if (!h_buf || bytes < sizeof(StateHeader)) return fail(c, BLM_E_ARG, "state buffer missing or too small");
+  if (c->state != ST_BEGUN || c->n_pass1 != 0)
+    return fail(c, BLM_E_STATE, "blm_import_state needs blm_begin_step and no build since");
+  StateHeader H, mine;
+  std::memcpy(&H, h_buf, sizeof H);
+  blm_status s = state_header(c, &mine);
+  if (s != BLM_OK) return s;
+  if (H.magic != mine.magic || H.version != mine.version || H.target != mine.target || H.NV != mine.NV ||
+      H.NB != mine.NB || H.NK != mine.NK || H.NO != mine.NO || H.NS != mine.NS || H.pieces != mine.pieces ||
+      H.fp8 != mine.fp8 || H.fp8_res != mine.fp8_res || H.NAP != mine.NAP || H.omega != mine.omega ||
+      H.cfg_hash != mine.cfg_hash || H.acc_elems != mine.acc_elems || H.strip_elems != mine.strip_elems)
+    return fail(c, BLM_E_ARG, "the state was exported from a context of another configuration");
+  if (bytes < state_size(c)) return fail(c, BLM_E_ARG, "state buffer too small");
+  if (H.theta_hash != mine.theta_hash)
+    return fail(c, BLM_E_STATE, "the step's previous directions differ from the exporting step's");
+  if (H.n_pass1 < 0) return fail(c, BLM_E_ARG, "the state's sample count is not valid");
+  const char* p = (const char*)h_buf + sizeof H;
+  auto get = [&](double* d, int64_t n) -> blm_status {
+    HIPCHK(c, hipMemcpyAsync(d, p, 8 * (size_t)n, hipMemcpyHostToDevice, c->st));
+    p += 8 * (size_t)n;
+    return BLM_OK;
+  };
+  if ((s = get(c->accS, c->acc_elems)) != BLM_OK || (s = get(c->accH, c->acc_elems)) != BLM_OK ||
+      (s = get(c->strips, H.strip_elems)) != BLM_OK)
+    return s;
+  if (c->target == BLM_TARGET_OMEGA &&
+      ((s = get(c->accE, c->acc_elems)) != BLM_OK || (s = get(c->stripsE, H.strip_elems)) != BLM_OK))
+    return s;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->n_pass1 = H.n_pass1;
+  c->state = H.n_pass1 > 0 ? ST_BUILT : ST_BEGUN;
+  return BLM_OK;
+}
+
 blm_status blm_get_solver_stats(blm_ctx* c, int32_t* h_stats, int32_t n) {
   if (!c || !h_stats || n < 0) return BLM_E_ARG;
   const int m = std::min<int>(n, (int)c->last_info1.size());
