@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libblm.so")
+# BLM_LIBRARY: another build of the same library (the sanitized host build)
+LIB_PATH = os.environ.get("BLM_LIBRARY") or os.path.join(_HERE, "libblm.so")
 
 BLM_OK = 0
 STATUS_NAMES = {0: "BLM_OK", 1: "BLM_E_ARG", 2: "BLM_E_STATE", 3: "BLM_E_HIP", 4: "BLM_E_NOMEM",

@@ -1,6 +1,7 @@
 """Builds libblm.so (all HIP sources under csrc/) for gfx950 with hipcc.
 
 Usage: python -m paper_1702_01481_amd.build_lib   (or build() from Python)
+       python -m paper_1702_01481_amd.build_lib --sanitize   (libblm_san.so, host code under ASan/UBSan)
 """
 from __future__ import annotations
 
@@ -50,6 +51,41 @@ def _compile(srcs, out, includes, verbose):
     os.replace(tmp, out)
 
 
+# host code under AddressSanitizer and UndefinedBehaviorSanitizer (device
+# code is built as usual): a CPU check of the library's host logic, loaded
+# by a Python started with the sanitizer runtime preloaded and
+# BLM_LIBRARY pointing at it
+SAN_LIB = os.path.join(HERE, "libblm_san.so")
+SAN_FLAGS = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined",
+             "-shared-libsan"]
+
+
+def asan_runtime() -> str:
+    """Path of the sanitizer runtime to preload (clang's, which hipcc links against)."""
+    out = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = out.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        import glob
+        cands = glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+        if not cands:
+            raise RuntimeError("clang's AddressSanitizer runtime not found")
+        path = cands[0]
+    return path
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """libblm_san.so: the library with its host code under ASan and UBSan."""
+    tmp = SAN_LIB + ".tmp"
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + SAN_FLAGS
+    cmd = [hipcc(), *flags, "-I", INCLUDE, "-I", CSRC, *sources(), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 def build(verbose: bool = False) -> str:
     """Compiles every HIP source of csrc/ into libblm.so, and the sample
     generator into synthgen/libsynthgen.so; returns libblm's path."""
@@ -59,5 +95,8 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
-    print(LIB)
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        build(verbose="-v" in sys.argv)
+        print(LIB)
