@@ -65,7 +65,7 @@ struct blm_ctx {
   int n_cus = 0;                   // compute units of the device (0: unknown)
   unsigned* d_hbar = nullptr;      // block solves: barrier counter and flag per pencil
   unsigned spin_limit = 1u << 22;  // polls of a workgroup barrier before it gives up
-  int hess_wg = 8;                 // most workgroups per pencil in the Hessenberg reduction
+  int hess_wg = 16;                // most workgroups per pencil in the distributed Cholesky and Hessenberg
   std::string err;
   int state = ST_CREATED;
 
@@ -1719,9 +1719,8 @@ blm_status blm_solve_blocks(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   int dm = 1;
   blm_status s = solve_begin(c, ej, &dm);
   if (s != BLM_OK) return s;
-  HIPCHK(c, hipMemcpyAsync(c->d_eig1, ej.data(), sizeof(EigJob) * ej.size(), hipMemcpyHostToDevice, c->st));
   mark(c, 4, false);
-  launch_eig_split(c->d_eig1, (int)ej.size(), dm, c->n_cus, c->hess_wg, c->d_hbar, c->spin_limit, c->st);
+  launch_eig_split(ej.data(), c->d_eig1, (int)ej.size(), dm, c->n_cus, c->hess_wg, c->d_hbar, c->spin_limit, c->st);
   HIPCHK(c, hipGetLastError());
   mark(c, 4, true);
   return solve_end(c, h_evals, h_kept);
@@ -2023,7 +2022,7 @@ struct blm_batch {
   hipStream_t st = nullptr;
   int n_cus = 0;
   unsigned spin_limit = 1u << 22;
-  int hess_wg = 8;
+  int hess_wg = 16;
   EigJob* d_eig1 = nullptr;   // every context's block pencils
   EigJob* d_eig2 = nullptr;   // every context's stage-two pencils
   unsigned* d_hbar = nullptr; // barrier counter and flag per block pencil
@@ -2340,9 +2339,9 @@ blm_status blm_batch_solve_blocks(blm_batch* b, double* const* h_evals, int32_t*
     dm = std::max(dm, d);
   }
   blm_ctx* c0 = b->ctx[0];
-  HIPCHK(c0, hipMemcpyAsync(b->d_eig1, all.data(), sizeof(EigJob) * all.size(), hipMemcpyHostToDevice, b->st));
   for (blm_ctx* c : b->ctx) mark(c, 4, false);
-  launch_eig_split(b->d_eig1, (int)all.size(), dm, b->n_cus, b->hess_wg, b->d_hbar, b->spin_limit, b->st);
+  launch_eig_split(all.data(), b->d_eig1, (int)all.size(), dm, b->n_cus, b->hess_wg, b->d_hbar, b->spin_limit,
+                   b->st);
   HIPCHK(c0, hipGetLastError());
   for (blm_ctx* c : b->ctx) mark(c, 4, true);
   blm_status first = BLM_OK;

@@ -29,7 +29,7 @@ namespace blm {
 namespace {
 
 constexpr int NT = EIG_THREADS;
-constexpr int HKW_MAX = 8;            // workgroups per pencil in the distributed Cholesky and Hessenberg steps
+constexpr int HKW_MAX = 16;           // workgroups per pencil in the distributed Cholesky and Hessenberg steps
 // smallest pencil it takes (smaller ones stay on one workgroup); its
 // workspace, 2 d + 2 kw d doubles, fits in the 2 d^2 of W
 constexpr int HESS_MULTI_MIN = 256;
@@ -1900,11 +1900,27 @@ __device__ void hess_pass_rows(HessShared& hs, gdouble* A, int d, int k, int r0,
   }
 }
 
-__global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict__ jobs, int n_jobs, int kw,
+// The pencil of workgroup g of a launch with several workgroups per pencil
+// (ranges [mw0, mw0 + mkw) in job order): binary search; *part: the
+// workgroup's index within its pencil.
+__device__ __forceinline__ int pencil_of(const EigJob* __restrict__ jobs, int n_jobs, int g, int* part) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].mw0 <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  *part = g - jobs[lo].mw0;
+  return lo;
+}
+
+__global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict__ jobs, int n_jobs,
                                                         unsigned* __restrict__ bar, unsigned spin_limit) {
   __shared__ HessShared hs;
-  const int job = blockIdx.x % n_jobs, part = blockIdx.x / n_jobs;
+  int part;
+  const int job = pencil_of(jobs, n_jobs, blockIdx.x, &part);
   const EigJob& E = jobs[job];
+  const int kw = E.mkw;
   const int d = E.d, tid = threadIdx.x;
   gdouble* A = as_global(E.A);
   gdouble* V = as_global(E.V);
@@ -1949,7 +1965,8 @@ __global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict
       bp += cv[j] * Pc[j];
       double q = 0.0;
 #pragma unroll
-      for (int w = 0; w < HKW_MAX; ++w) q += qp[w];
+      for (int w = 0; w < HKW_MAX; ++w)
+        if (w < kw) q += qp[w];
       cq[j] = q;
     }
     const double beta = hs_block_sum(hs, bp);
@@ -2004,11 +2021,13 @@ struct CholShared {
   int ok;
 };
 
-__global__ __launch_bounds__(NT) void chol_multi_kernel(const EigJob* __restrict__ jobs, int n_jobs, int kw,
+__global__ __launch_bounds__(NT) void chol_multi_kernel(const EigJob* __restrict__ jobs, int n_jobs,
                                                         unsigned* __restrict__ bar, unsigned spin_limit) {
   __shared__ CholShared cs;
-  const int job = blockIdx.x % n_jobs, part = blockIdx.x / n_jobs;
+  int part;
+  const int job = pencil_of(jobs, n_jobs, blockIdx.x, &part);
   const EigJob& E = jobs[job];
+  const int kw = E.mkw;
   const int d = E.d, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   gdouble* S = as_global(E.S);
   BLM_GLOBAL int32_t* info = as_global(E.info);
@@ -2315,34 +2334,72 @@ __global__ void fill_u32_kernel(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int d_max, int n_cus, int max_kw, unsigned* d_bar,
-                      unsigned spin_limit, hipStream_t st) {
+// Workgroups per pencil for the distributed Cholesky and Hessenberg steps:
+// every pencil one, then the remaining CUs one at a time to the pencil whose
+// estimated time is longest, d^3 / kw (its row passes) + 5e4 d (its
+// barriers, one per step, in the same units), up to max_kw (HKW_MAX for
+// pencils of 1,024 or more, 8 for smaller ones, where a barrier among more
+// workgroups costs more than their shorter bands save).  Returns the
+// launch's workgroup count, 0 when there are too few CUs for two per pencil.
+static int plan_split(EigJob* jobs, int n_jobs, int n_cus, int max_kw) {
+  if (n_jobs <= 0 || max_kw < 2 || n_cus / n_jobs < 2) return 0;
+  std::vector<int> kw(n_jobs, 1);
+  auto t_est = [&](int j, int k) {
+    const double d = jobs[j].d;
+    return d * d * d / k + 5e4 * d;
+  };
+  auto cap = [&](int j) { return min(max_kw, jobs[j].d >= 1024 ? HKW_MAX : 8); };
+  for (int left = n_cus - n_jobs; left > 0; --left) {
+    int best = -1;
+    double tb = 0.0;
+    for (int j = 0; j < n_jobs; ++j) {
+      if (kw[j] >= cap(j)) continue;
+      const double t = t_est(j, kw[j]);
+      if (best < 0 || t > tb) {
+        best = j;
+        tb = t;
+      }
+    }
+    if (best < 0) break;
+    ++kw[best];
+  }
+  int g = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    jobs[j].mw0 = g;
+    jobs[j].mkw = kw[j];
+    g += kw[j];
+  }
+  return g;
+}
+
+bool launch_eig_split(EigJob* h_jobs, EigJob* d_jobs, int n_jobs, int d_max, int n_cus, int max_kw,
+                      unsigned* d_bar, unsigned spin_limit, hipStream_t st) {
   if (n_jobs <= 0) return true;
-  const int kw = min(min(HKW_MAX, max_kw), n_cus / n_jobs);
+  const int n_wg = plan_split(h_jobs, n_jobs, n_cus, min(HKW_MAX, max_kw));
+  if (hipMemcpyAsync(d_jobs, h_jobs, sizeof(EigJob) * n_jobs, hipMemcpyHostToDevice, st) != hipSuccess) return false;
   bool chol_done = false;
-  if (kw >= 2) {
+  if (n_wg > 0) {
     hipLaunchKernelGGL(eig_info_init_kernel, dim3((n_jobs * EIG_INFO + 255) / 256), dim3(256), 0, st, d_jobs,
                        n_jobs);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * n_jobs + 255) / 256), dim3(256), 0, st, d_bar, 2 * n_jobs);
-    int nj = n_jobs, k = kw;
-    void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&k, (void*)&d_bar, (void*)&spin_limit};
-    chol_done = hipLaunchCooperativeKernel((const void*)chol_multi_kernel, dim3(n_jobs * kw), dim3(NT), args, 0,
-                                           st) == hipSuccess;
+    int nj = n_jobs;
+    void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&d_bar, (void*)&spin_limit};
+    chol_done = hipLaunchCooperativeKernel((const void*)chol_multi_kernel, dim3(n_wg), dim3(NT), args, 0, st) ==
+                hipSuccess;
     if (!chol_done) (void)hipGetLastError();
   }
   if (!chol_done) hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)PH_CHOL);
   const int ns = max(1, (min(d_max, EIG_MAXD) + CSW - 1) / CSW);
   hipLaunchKernelGGL(cong_cols_kernel, dim3(n_jobs * ns), dim3(NT), 0, st, d_jobs, n_jobs);
   hipLaunchKernelGGL(cong_rows_kernel, dim3(n_jobs * ns), dim3(NT), 0, st, d_jobs, n_jobs);
-  if (kw < 2) {
+  if (n_wg == 0) {
     hipLaunchKernelGGL(eig_kernel, dim3(n_jobs), dim3(NT), 0, st, d_jobs, (int)(PH_HESS | PH_BACK));
     return true;
   }
   hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * n_jobs + 255) / 256), dim3(256), 0, st, d_bar, 2 * n_jobs);
-  int nj = n_jobs, k = kw;
-  void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&k, (void*)&d_bar, (void*)&spin_limit};
-  const hipError_t e = hipLaunchCooperativeKernel((const void*)hess_multi_kernel, dim3(n_jobs * kw), dim3(NT),
-                                                  args, 0, st);
+  int nj = n_jobs;
+  void* args[] = {(void*)&d_jobs, (void*)&nj, (void*)&d_bar, (void*)&spin_limit};
+  const hipError_t e = hipLaunchCooperativeKernel((const void*)hess_multi_kernel, dim3(n_wg), dim3(NT), args, 0, st);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     // the workgroups cannot all be resident: the Hessenberg reduction one

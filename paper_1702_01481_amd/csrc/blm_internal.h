@@ -157,7 +157,8 @@ struct EigJob {
   int32_t mode;
   int32_t n_want;       // directions wanted (EIG_BLOCK); 1 for EIG_STAGE2
   int32_t beta0, nbeta; // beta part of each eigenvector: entries [beta0, beta0 + nbeta)
-  int32_t pad;
+  int32_t mw0, mkw;     // launches with several workgroups per pencil: the pencil's first
+                        // workgroup and its count (set by launch_eig_split)
   double* S;            // [d][d] overlap in, Cholesky factor out
   double* A;            // [d][d] shifted Hamiltonian in, destroyed
   double* Hq;           // [d][d] Hessenberg copy
@@ -231,7 +232,9 @@ void launch_eig(const EigJob* d_jobs, int n_jobs, hipStream_t st);
 // the same with each pencil's Hessenberg reduction spread over several
 // workgroups (cooperative launch; d_bar: 2 n_jobs counters); returns false
 // if it had to fall back to one workgroup per pencil
-bool launch_eig_split(const EigJob* d_jobs, int n_jobs, int d_max, int n_cus, int max_kw, unsigned* d_bar,
-                      unsigned spin_limit, hipStream_t st);
+// h_jobs: the host copy of the n_jobs pencils, uploaded to d_jobs by this
+// call (it fills their workgroup ranges first)
+bool launch_eig_split(EigJob* h_jobs, EigJob* d_jobs, int n_jobs, int d_max, int n_cus, int max_kw,
+                      unsigned* d_bar, unsigned spin_limit, hipStream_t st);
 
 }  // namespace blm
