@@ -1,13 +1,13 @@
 """The 16,384-parameter workload (16 blocks of 1,024, three shifts, one
 previous direction) and the 30,000-parameter workload (40 uneven blocks of
-107 to 2,104 parameters, no previous direction) at their full parameter
+116 to 1,849 parameters, no previous direction) at their full parameter
 counts and block structure, on their first 131,072 samples (their full
 sizes, 0.5 and 1.9 TB of FP64 samples, do not fit in one GPU's HBM).
 
 For each: the library's FP64 step against the oracle's own whole step on the
 same sample bytes (tests/whole_step.py: every block's S_b and H_b, Eq. 3 on
 the Eq. 10 basis; the kept spans of every block, Eq. 5 and Eq. 6, the
-2,105-dimensional pencil's included; the stage-two matrices, Eq. 7; energy
+1,850-dimensional pencil's included; the stage-two matrices, Eq. 7; energy
 and update, Eq. 7 and Eq. 8), at the FP64 tolerances.  The 16-block
 workload runs the two-step protocol: both sides' first steps (no history)
 are compared, and the oracle's first update is the previous direction of
