@@ -129,6 +129,12 @@ struct blm_ctx {
   bool offsets_even = false;
   DirBlock *d_theta_blk = nullptr, *d_dir2_blk = nullptr;
   const double **d_theta_ptr = nullptr, **d_dir2_ptr = nullptr;
+  // the same directions as window rows for 16-byte loads (WinCopy), refreshed
+  // by the step's Theta setup and by each block solve
+  double *theta_win = nullptr, *dir2_win = nullptr;
+  const double **d_theta_wptr = nullptr, **d_dir2_wptr = nullptr;
+  WinCopy *d_theta_wcopy = nullptr, *d_dir2_wcopy = nullptr;
+  int theta_maxw = 0, dir2_maxw = 0;
   int32_t* d_auxlist = nullptr;    // per block: [1 + N_O (N_B - 1)]
   int auxlist_stride = 0;
   // eigen workspace: block problems [NS][NB], stage two [NS]
@@ -478,6 +484,23 @@ void plan(blm_ctx* c, Plan& P) {
   add((void**)&c->d_theta_ptr, sizeof(double*) * (size_t)std::max(NO * NB, 1));
   add((void**)&c->d_dir2_blk, sizeof(DirBlock) * (size_t)NB);
   add((void**)&c->d_dir2_ptr, sizeof(double*) * (size_t)c->n2max);
+  {
+    // window rows: N_O per block for Theta, up to n2max for the kept directions
+    int64_t theta_win = 0;
+    int maxw = 2;
+    for (int k = 0; k < NB; ++k) {
+      const int w = window_width(c->off[k], (int)(c->off[k + 1] - c->off[k]));
+      theta_win += (int64_t)NO * w;
+      maxw = std::max(maxw, w);
+    }
+    c->theta_maxw = c->dir2_maxw = maxw;
+    add((void**)&c->theta_win, 8 * (size_t)std::max<int64_t>(theta_win, 2));
+    add((void**)&c->d_theta_wptr, sizeof(double*) * (size_t)std::max(NO * NB, 1));
+    add((void**)&c->d_theta_wcopy, sizeof(WinCopy) * (size_t)std::max(NO * NB, 1));
+    add((void**)&c->dir2_win, 8 * (size_t)c->n2max * maxw);
+    add((void**)&c->d_dir2_wptr, sizeof(double*) * (size_t)c->n2max);
+    add((void**)&c->d_dir2_wcopy, sizeof(WinCopy) * (size_t)c->n2max);
+  }
   add((void**)&c->d_auxlist, 4 * (size_t)NB * c->auxlist_stride);
   add((void**)&c->d_eig1, sizeof(EigJob) * (size_t)NS * NB);
   add((void**)&c->d_eig2, sizeof(EigJob) * (size_t)NS);
@@ -693,8 +716,8 @@ blm_status check_chunks(blm_ctx* c, const blm_chunk* ch, int n, int64_t* total) 
 // tiles and row bases count on from *tiles and 0; *vec is cleared when a
 // chunk cannot take 16-byte loads.
 void add_pchunks(const blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d_blocks, int n_blocks,
-                 const double* const* d_ptr, int n_dirs, double* Xo, double* Yo, int64_t ldo,
-                 std::vector<ProjChunk>& out, int* tiles, bool* vec) {
+                 const double* const* d_ptr, const double* const* d_wptr, int n_dirs, double* Xo, double* Yo,
+                 int64_t ldo, std::vector<ProjChunk>& out, int* tiles, bool* vec) {
   int64_t rb = 0;
   for (int i = 0; i < n; ++i) {
     const int64_t ns = ch[i].n_samples;
@@ -702,6 +725,7 @@ void add_pchunks(const blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
     ProjChunk P{};
     P.blocks = d_blocks;
     P.dir = d_ptr;
+    P.dirw = d_wptr;
     P.Xo = Xo;
     P.Yo = Yo;
     P.ldo = ldo;
@@ -731,7 +755,6 @@ void add_pchunks(const blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d
     rb += ns;
     if ((ch[i].ld & 1) || ((uintptr_t)ch[i].O & 15) || ((uintptr_t)ch[i].e & 15)) *vec = false;
   }
-  if (!c->offsets_even) *vec = false;
 }
 
 int store_kind(const blm_ctx* c) { return c->fp8 ? STORE_FP8 : c->pieces ? STORE_BF16 : STORE_F64; }
@@ -739,12 +762,12 @@ int store_kind(const blm_ctx* c) { return c->fp8 ? STORE_FP8 : c->pieces ? STORE
 // One projection launch over all chunks of a call; returns via c->h_pchunks.
 // max_nd: the most directions of any block
 blm_status run_dirproj(blm_ctx* c, const blm_chunk* ch, int n, const DirBlock* d_blocks,
-                       int n_blocks, const double* const* d_ptr, int n_dirs, int max_nd, double* Xo,
-                       double* Yo, int64_t ldo) {
+                       int n_blocks, const double* const* d_ptr, const double* const* d_wptr, int n_dirs,
+                       int max_nd, double* Xo, double* Yo, int64_t ldo) {
   c->h_pchunks.clear();
   int tiles = 0;
   bool vec = true;
-  add_pchunks(c, ch, n, d_blocks, n_blocks, d_ptr, n_dirs, Xo, Yo, ldo, c->h_pchunks, &tiles, &vec);
+  add_pchunks(c, ch, n, d_blocks, n_blocks, d_ptr, d_wptr, n_dirs, Xo, Yo, ldo, c->h_pchunks, &tiles, &vec);
   if (c->h_pchunks.empty() || c->dry) return BLM_OK;
   if (!c->cap)
     HIPCHK(c, hipMemcpyAsync(c->d_pchunks, c->h_pchunks.data(), sizeof(ProjChunk) * c->h_pchunks.size(),
@@ -809,7 +832,8 @@ blm_status run_gram(blm_ctx* c, GramJob* d_jobs, int n_jobs, int cap, double* s_
 // table (host side, c->h_slices), with the aux columns packed to the
 // build's storage per chunk.
 blm_status build_slices(blm_ctx* c, const blm_chunk* ch, int n) {
-  blm_status s = run_dirproj(c, ch, n, c->d_theta_blk, c->NO > 0 ? c->NB : 0, c->d_theta_ptr, c->NO * c->NB,
+  blm_status s = run_dirproj(c, ch, n, c->d_theta_blk, c->NO > 0 ? c->NB : 0, c->d_theta_ptr, c->d_theta_wptr,
+                             c->NO * c->NB,
                              c->NO, c->Xa, c->Ya, c->NAP);
   if (s != BLM_OK) return s;
   c->h_slices.clear();
@@ -1260,15 +1284,27 @@ blm_status blm_create(const blm_config* cfg, void* stream, blm_ctx** out) {
     // theta direction table (fixed): block k, rows j of D
     std::vector<DirBlock> tb(c->NB);
     std::vector<const double*> tp((size_t)std::max(c->NO * c->NB, 1), nullptr);
+    std::vector<const double*> tpw(tp.size(), nullptr);
+    std::vector<WinCopy> tcw(tp.size());
+    int64_t wbase = 0;
     for (int k = 0; k < c->NB; ++k) {
       tb[k].col0 = c->off[k];
       tb[k].m = (int)(c->off[k + 1] - c->off[k]);
       tb[k].d0 = k * c->NO;
       tb[k].nd = c->NO;
-      for (int j = 0; j < c->NO; ++j) tp[k * c->NO + j] = c->D + (size_t)j * c->NV + c->off[k];
+      const int w = window_width(tb[k].col0, tb[k].m);
+      for (int j = 0; j < c->NO; ++j) {
+        tp[k * c->NO + j] = c->D + (size_t)j * c->NV + c->off[k];
+        double* dst = c->theta_win + wbase;
+        tpw[k * c->NO + j] = dst;
+        tcw[k * c->NO + j] = WinCopy{tp[k * c->NO + j], dst, tb[k].m, (int)(tb[k].col0 & 1), w, 0};
+        wbase += w;
+      }
     }
     (void)hipMemcpy(c->d_theta_blk, tb.data(), sizeof(DirBlock) * c->NB, hipMemcpyHostToDevice);
     (void)hipMemcpy(c->d_theta_ptr, tp.data(), sizeof(double*) * tp.size(), hipMemcpyHostToDevice);
+    (void)hipMemcpy(c->d_theta_wptr, tpw.data(), sizeof(double*) * tpw.size(), hipMemcpyHostToDevice);
+    (void)hipMemcpy(c->d_theta_wcopy, tcw.data(), sizeof(WinCopy) * tcw.size(), hipMemcpyHostToDevice);
   }
   *out = c;
   return BLM_OK;
@@ -1299,6 +1335,8 @@ blm_status blm_begin_step(blm_ctx* c, const double* d_old) {
     } else {
       HIPCHK(c, hipMemsetAsync(c->D, 0, 8 * (size_t)c->NO * c->NV, c->st));
     }
+    launch_window_copy(c->d_theta_wcopy, c->NO * c->NB, c->theta_maxw, c->st);
+    HIPCHK(c, hipGetLastError());
   }
   // per-block aux lists: [0] then Theta_(k,j) for k != b, k-major
   c->auxlist.assign(c->NB, {});
@@ -1698,6 +1736,29 @@ blm_status solve_end(blm_ctx* c, double* h_evals, int32_t* h_kept) {
   HIPCHK(c, hipMemcpyAsync(c->d_dir2_blk, db.data(), sizeof(DirBlock) * NB, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->d_dir2_ptr, dp.data(), sizeof(double*) * std::max<size_t>(dp.size(), 1),
                            hipMemcpyHostToDevice, c->st));
+  {
+    // the kept directions as window rows
+    std::vector<const double*> dpw(dp.size());
+    std::vector<WinCopy> wc(dp.size());
+    int64_t wbase = 0;
+    for (int k = 0; k < NB; ++k) {
+      const int w = window_width(db[k].col0, db[k].m);
+      for (int t = db[k].d0; t < db[k].d0 + db[k].nd; ++t) {
+        double* dst = c->dir2_win + wbase;
+        dpw[t] = dst;
+        wc[t] = WinCopy{dp[t], dst, db[k].m, (int)(db[k].col0 & 1), w, 0};
+        wbase += w;
+      }
+    }
+    if (!dp.empty()) {
+      HIPCHK(c, hipMemcpyAsync(c->d_dir2_wptr, dpw.data(), sizeof(double*) * dpw.size(), hipMemcpyHostToDevice,
+                               c->st));
+      HIPCHK(c, hipMemcpyAsync(c->d_dir2_wcopy, wc.data(), sizeof(WinCopy) * wc.size(), hipMemcpyHostToDevice,
+                               c->st));
+      launch_window_copy(c->d_dir2_wcopy, (int)wc.size(), c->dir2_maxw, c->st);
+      HIPCHK(c, hipGetLastError());
+    }
+  }
   HIPCHK(c, hipMemcpyAsync(c->d_idx2, flat.data(), 4 * flat.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->d_jobs2, jobs.data(), sizeof(GramJob) * jobs.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemsetAsync(c->G2S, 0, 8 * (size_t)n2 * n2, c->st));
@@ -1765,7 +1826,8 @@ blm_status blm_project(blm_ctx* c, const blm_chunk* ch, int32_t n) {
   if (s != BLM_OK) return s;
   const int64_t ldo = c->ld2;
   mark(c, 5, false);
-  s = run_dirproj(c, ch, n, c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->n2 - 1, c->nd2max, c->Yp, c->Zp, ldo);
+  s = run_dirproj(c, ch, n, c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->d_dir2_wptr, c->n2 - 1, c->nd2max, c->Yp,
+                  c->Zp, ldo);
   if (s != BLM_OK) return s;
   proj_slices(c, ch, n);
   mark(c, 5, true);
@@ -2260,7 +2322,8 @@ blm_status blm_batch_project(blm_batch* b, const blm_chunk* const* chunks, const
   bool vec = true;
   for (int i = 0; i < n; ++i) {
     blm_ctx* c = b->ctx[i];
-    add_pchunks(c, chunks[i], n_chunks[i], c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->n2 - 1, c->Yp, c->Zp, c->ld2,
+    add_pchunks(c, chunks[i], n_chunks[i], c->d_dir2_blk, c->NB, c->d_dir2_ptr, c->d_dir2_wptr, c->n2 - 1, c->Yp,
+                c->Zp, c->ld2,
                 b->h_pchunks, &tiles, &vec);
     max_nd = std::max(max_nd, c->nd2max);
   }

@@ -119,6 +119,10 @@ struct DirBlock {
 struct ProjChunk {
   const DirBlock* blocks;
   const double* const* dir;   // the directions, indexed by DirBlock::d0 + t
+  // the same directions as window rows (16-byte loads): each row starts at
+  // the even column at or before its block's first one, with a zero there
+  // for a block at an odd column, and is padded with zeros to an even width
+  const double* const* dirw;
   double* Xo;                 // [rows][ldo]: column 0 is 1, then O . dir
   double* Yo;                 // [rows][ldo]: column 0 is E_L, then e . dir
   int64_t ldo;
@@ -141,6 +145,17 @@ struct ProjChunk {
   const uint16_t* Ot;   // second residuals (FP8 storage with two), else nullptr
   const uint16_t* et;
 };
+// one direction row copied into its window row: dst[r] = src[r - sh] for
+// sh <= r < sh + m, zero elsewhere in [0, mwp)
+struct WinCopy {
+  const double* src;
+  double* dst;
+  int32_t m, sh, mwp, pad;
+};
+void launch_window_copy(const WinCopy* d_tab, int n, int max_mwp, hipStream_t st);
+// window width of a block of m columns starting at column col0
+inline int window_width(int64_t col0, int m) { return (int)(((col0 & 1) + m + 1) & ~1); }
+
 // sample storage of a projection launch
 enum StoreKind : int32_t { STORE_F64 = 0, STORE_BF16 = 1, STORE_FP8 = 2 };
 constexpr int PROJ_ROWS = 64;

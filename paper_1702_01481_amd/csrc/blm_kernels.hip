@@ -886,71 +886,98 @@ __global__ __launch_bounds__(256) void dirproj_small_kernel(const ProjChunk* __r
 // p0 + 8 g + j on both operand sides (the contraction runs over the same
 // permutation of the parameters on both sides), so each lane reads 8
 // consecutive parameters of its sample row, 64 contiguous bytes.  Loads are
-// unconditional (rows clamped to the chunk, columns to the block; values
-// past the block edge meet zeroed direction entries) and the next stage is
-// loaded before the current one is multiplied.
+// unconditional (rows clamped to the chunk, columns to the block) and the
+// next stage is loaded before the current one is multiplied.
+//
+// VEC (even leading dimension, aligned arrays): every load is 16 bytes, in
+// window coordinates: a block's window starts at the even column at or
+// before its first one (sh = 1 for a block at an odd column) and is sh + m
+// columns wide.  The directions come as window rows (zero at the column
+// before an odd block, zero padding to an even width).  A sample row's last
+// pair may reach one column past the block: the next block's first column,
+// or the row's padding when N_V is odd (the leading dimension is even), so
+// inside the [n][ld] array; sample values outside the window are zeroed in
+// registers (the padding may hold anything).
 struct Pj64Regs {
   double o[8], e[8], x0[8], x1[8];
 };
 
-template <bool VEC>
-__device__ __forceinline__ void pj64_row8(const BLM_GLOBAL double* p, int c0, int m, double* v) {
-  if constexpr (VEC) {
+// 8 values of a row from aligned column pairs starting at c0 (pairs past
+// the last one, lp, repeat it)
+__device__ __forceinline__ void pj64_row8_vec(const BLM_GLOBAL double* p, int c0, int lp, double* v) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = min(c0 + 2 * q, m - 2);
-      const double2 t = *reinterpret_cast<const BLM_GLOBAL double2*>(p + c);
-      v[2 * q] = t.x;
-      v[2 * q + 1] = t.y;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = p[min(c0 + q, m - 1)];
+  for (int q = 0; q < 4; ++q) {
+    const int c = min(c0 + 2 * q, 2 * lp);
+    const double2 t = *reinterpret_cast<const BLM_GLOBAL double2*>(p + c);
+    v[2 * q] = t.x;
+    v[2 * q + 1] = t.y;
   }
 }
 
+// 8 entries c0 .. c0 + 7 of a row, clamped to [0, m)
+__device__ __forceinline__ void pj64_row8_scalar(const BLM_GLOBAL double* p, int c0, int m, double* v) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = p[min(c0 + q, m - 1)];
+}
+
+// mw: the window width (sh + m with VEC, m without)
 template <bool VEC>
 __device__ __forceinline__ void pj64_load(const BLM_GLOBAL double* rO, const BLM_GLOBAL double* rE,
                                           const BLM_GLOBAL double* d0, const BLM_GLOBAL double* d1,
-                                          bool two, int c0, int m, Pj64Regs& R) {
-  pj64_row8<VEC>(rO, c0, m, R.o);
-  pj64_row8<VEC>(rE, c0, m, R.e);
-  pj64_row8<VEC>(d0, c0, m, R.x0);
-  if (two) pj64_row8<VEC>(d1, c0, m, R.x1);
+                                          bool two, int c0, int mw, Pj64Regs& R) {
+  if constexpr (VEC) {
+    const int lp = (mw - 1) >> 1;      // the last column pair holding a column of the block
+    pj64_row8_vec(rO, c0, lp, R.o);
+    pj64_row8_vec(rE, c0, lp, R.e);
+    pj64_row8_vec(d0, c0, lp, R.x0);   // window rows: padded to an even width
+    if (two) pj64_row8_vec(d1, c0, lp, R.x1);
+  } else {
+    pj64_row8_scalar(rO, c0, mw, R.o);
+    pj64_row8_scalar(rE, c0, mw, R.e);
+    pj64_row8_scalar(d0, c0, mw, R.x0);
+    if (two) pj64_row8_scalar(d1, c0, mw, R.x1);
+  }
 }
 
-template <bool VEC, bool TWO>
-__device__ __forceinline__ void pj64_mul(const Pj64Regs& R, bool ok0, bool ok1, int p, int m, d4& aO0,
-                                         d4& aE0, d4& aO1, d4& aE1) {
+// p: the window column of R's first value; the block holds window columns
+// sh .. mw - 1.  MASK: sample values outside them are zeroed (a window with
+// a column before the block or a pad column after it; otherwise every value
+// loaded is the block's own, and those past mw meet zero directions)
+template <bool MASK, bool TWO>
+__device__ __forceinline__ void pj64_mul(const Pj64Regs& R, bool ok0, bool ok1, int p, int mw, int sh,
+                                         d4& aO0, d4& aE0, d4& aO1, d4& aE1) {
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const bool inb = p + j < m;
+    const bool inb = p + j < mw;
+    const bool inw = inb && p + j >= sh;
+    const double o = (MASK && !inw) ? 0.0 : R.o[j];
+    const double e = (MASK && !inw) ? 0.0 : R.e[j];
     const double b0 = (ok0 && inb) ? R.x0[j] : 0.0;
-    aO0 = mfma_f64(R.o[j], b0, aO0);
-    aE0 = mfma_f64(R.e[j], b0, aE0);
+    aO0 = mfma_f64(o, b0, aO0);
+    aE0 = mfma_f64(e, b0, aE0);
     if constexpr (TWO) {
       const double b1 = (ok1 && inb) ? R.x1[j] : 0.0;
-      aO1 = mfma_f64(R.o[j], b1, aO1);
-      aE1 = mfma_f64(R.e[j], b1, aE1);
+      aO1 = mfma_f64(o, b1, aO1);
+      aE1 = mfma_f64(e, b1, aE1);
     }
   }
 }
 
 // All stages of one block for one direction group; two register stages
-// alternate (stage t+1 is loaded while stage t is multiplied).  A block
+// alternate (stage t+1 is loaded while stage t is multiplied).  A window
 // whose width is not a multiple of 64 multiplies one all-zero stage more.
-template <bool VEC, bool TWO>
+template <bool VEC, bool MASK, bool TWO>
 __device__ __forceinline__ void pj64_block(const BLM_GLOBAL double* rO, const BLM_GLOBAL double* rE,
                                            const BLM_GLOBAL double* d0, const BLM_GLOBAL double* d1,
-                                           bool ok0, bool ok1, int m, int g, d4& aO0, d4& aE0,
+                                           bool ok0, bool ok1, int mw, int sh, int g, d4& aO0, d4& aE0,
                                            d4& aO1, d4& aE1) {
   Pj64Regs Ra, Rb;
-  pj64_load<VEC>(rO, rE, d0, d1, TWO, 8 * g, m, Ra);
-  for (int p0 = 0; p0 < m; p0 += 2 * PJ_P) {
-    pj64_load<VEC>(rO, rE, d0, d1, TWO, p0 + PJ_P + 8 * g, m, Rb);
-    pj64_mul<VEC, TWO>(Ra, ok0, ok1, p0 + 8 * g, m, aO0, aE0, aO1, aE1);
-    pj64_load<VEC>(rO, rE, d0, d1, TWO, p0 + 2 * PJ_P + 8 * g, m, Ra);
-    pj64_mul<VEC, TWO>(Rb, ok0, ok1, p0 + PJ_P + 8 * g, m, aO0, aE0, aO1, aE1);
+  pj64_load<VEC>(rO, rE, d0, d1, TWO, 8 * g, mw, Ra);
+  for (int p0 = 0; p0 < mw; p0 += 2 * PJ_P) {
+    pj64_load<VEC>(rO, rE, d0, d1, TWO, p0 + PJ_P + 8 * g, mw, Rb);
+    pj64_mul<MASK, TWO>(Ra, ok0, ok1, p0 + 8 * g, mw, sh, aO0, aE0, aO1, aE1);
+    pj64_load<VEC>(rO, rE, d0, d1, TWO, p0 + 2 * PJ_P + 8 * g, mw, Ra);
+    pj64_mul<MASK, TWO>(Rb, ok0, ok1, p0 + PJ_P + 8 * g, mw, sh, aO0, aE0, aO1, aE1);
   }
 }
 
@@ -989,19 +1016,26 @@ __global__ __launch_bounds__(256) void dirproj64_kernel(const ProjChunk* __restr
   const BLM_GLOBAL double* rowE = as_global((const double*)C.e) + sl * C.ld;
   for (int bi = 0; bi < n_blocks; ++bi) {
     const DirBlock B = blocks[bi];
-    const BLM_GLOBAL double* rO = rowO + B.col0;
-    const BLM_GLOBAL double* rE = rowE + B.col0;
+    const int sh = VEC ? (int)(B.col0 & 1) : 0;    // window from the even column at or before the block
+    const int mw = B.m + sh;
+    const BLM_GLOBAL double* rO = rowO + B.col0 - sh;
+    const BLM_GLOBAL double* rE = rowE + B.col0 - sh;
+    const double* const* dtab = VEC ? C.dirw : dir_ptr;
     for (int dg = 0; dg < B.nd; dg += 32) {
       const bool two = (B.nd - dg) > 16;
       const int t0 = dg + i16, t1 = dg + 16 + i16;
       const bool ok0 = t0 < B.nd, ok1 = two && t1 < B.nd;
-      const BLM_GLOBAL double* d0 = as_global(dir_ptr[B.d0 + min(t0, B.nd - 1)]);
-      const BLM_GLOBAL double* d1 = as_global(dir_ptr[B.d0 + min(t1, B.nd - 1)]);
+      const BLM_GLOBAL double* d0 = as_global(dtab[B.d0 + min(t0, B.nd - 1)]);
+      const BLM_GLOBAL double* d1 = as_global(dtab[B.d0 + min(t1, B.nd - 1)]);
       d4 aO0 = {0, 0, 0, 0}, aO1 = {0, 0, 0, 0}, aE0 = {0, 0, 0, 0}, aE1 = {0, 0, 0, 0};
-      if (two)
-        pj64_block<VEC, true>(rO, rE, d0, d1, ok0, ok1, B.m, g, aO0, aE0, aO1, aE1);
-      else
-        pj64_block<VEC, false>(rO, rE, d0, d1, ok0, ok1, B.m, g, aO0, aE0, aO1, aE1);
+      const bool mask = VEC && (sh != 0 || (mw & 1) != 0);
+      if (mask) {
+        if (two) pj64_block<VEC, VEC, true>(rO, rE, d0, d1, ok0, ok1, mw, sh, g, aO0, aE0, aO1, aE1);
+        else pj64_block<VEC, VEC, false>(rO, rE, d0, d1, ok0, ok1, mw, sh, g, aO0, aE0, aO1, aE1);
+      } else {
+        if (two) pj64_block<VEC, false, true>(rO, rE, d0, d1, ok0, ok1, mw, sh, g, aO0, aE0, aO1, aE1);
+        else pj64_block<VEC, false, false>(rO, rE, d0, d1, ok0, ok1, mw, sh, g, aO0, aE0, aO1, aE1);
+      }
       // lane holds D[4 rr + g][i16]: sample sw + 4 rr + g, direction dg + i16 (+16)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
@@ -1018,6 +1052,19 @@ __global__ __launch_bounds__(256) void dirproj64_kernel(const ProjChunk* __restr
       }
     }
   }
+}
+
+__global__ __launch_bounds__(256) void window_copy_kernel(const WinCopy* __restrict__ tab, int n) {
+  const WinCopy W = tab[blockIdx.y];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < W.mwp; r += gridDim.x * blockDim.x) {
+    const int x = r - W.sh;
+    as_global(W.dst)[r] = (x >= 0 && x < W.m) ? as_global(W.src)[x] : 0.0;
+  }
+}
+
+void launch_window_copy(const WinCopy* d_tab, int n, int max_mwp, hipStream_t st) {
+  if (n <= 0 || max_mwp <= 0) return;
+  hipLaunchKernelGGL(window_copy_kernel, dim3((max_mwp + 255) / 256, n), dim3(256), 0, st, d_tab, n);
 }
 
 void launch_dirproj(const ProjChunk* d_chunks, int n_chunks, int n_tiles, bool vec, int store, int max_nd,
