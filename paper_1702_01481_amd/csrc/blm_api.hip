@@ -65,7 +65,7 @@ struct blm_ctx {
   int n_cus = 0;                   // compute units of the device (0: unknown)
   unsigned* d_hbar = nullptr;      // block solves: barrier counter and flag per pencil
   unsigned spin_limit = 1u << 22;  // polls of a workgroup barrier before it gives up
-  int hess_wg = 16;                // most workgroups per pencil in the distributed Cholesky and Hessenberg
+  int hess_wg = 32;                // most workgroups per pencil in the distributed Cholesky and Hessenberg
   std::string err;
   int state = ST_CREATED;
 
@@ -2084,7 +2084,7 @@ struct blm_batch {
   hipStream_t st = nullptr;
   int n_cus = 0;
   unsigned spin_limit = 1u << 22;
-  int hess_wg = 16;
+  int hess_wg = 32;
   EigJob* d_eig1 = nullptr;   // every context's block pencils
   EigJob* d_eig2 = nullptr;   // every context's stage-two pencils
   unsigned* d_hbar = nullptr; // barrier counter and flag per block pencil

@@ -29,7 +29,7 @@ namespace blm {
 namespace {
 
 constexpr int NT = EIG_THREADS;
-constexpr int HKW_MAX = 16;           // workgroups per pencil in the distributed Cholesky and Hessenberg steps
+constexpr int HKW_MAX = 32;           // workgroups per pencil in the distributed Cholesky and Hessenberg steps
 // smallest pencil it takes (smaller ones stay on one workgroup); its
 // workspace, 2 d + 2 kw d doubles, fits in the 2 d^2 of W
 constexpr int HESS_MULTI_MIN = 256;
@@ -1959,14 +1959,17 @@ __global__ __launch_bounds__(NT) void hess_multi_kernel(const EigJob* __restrict
     // all loads of a column are issued before the sums
     double bp = 0.0;
     for (int j = k + 1 + tid; j < d; j += NT) {
-      double qp[HKW_MAX];
-#pragma unroll
-      for (int w = 0; w < HKW_MAX; ++w) qp[w] = (w < kw) ? Qc[(size_t)w * d + j] : 0.0;
       bp += cv[j] * Pc[j];
+      // the partials in order, 8 loads issued before their sums
       double q = 0.0;
+      for (int w0 = 0; w0 < kw; w0 += 8) {
+        double qp[8];
 #pragma unroll
-      for (int w = 0; w < HKW_MAX; ++w)
-        if (w < kw) q += qp[w];
+        for (int w = 0; w < 8; ++w) qp[w] = (w0 + w < kw) ? Qc[(size_t)(w0 + w) * d + j] : 0.0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w)
+          if (w0 + w < kw) q += qp[w];
+      }
       cq[j] = q;
     }
     const double beta = hs_block_sum(hs, bp);
@@ -2337,8 +2340,8 @@ __global__ void fill_u32_kernel(unsigned* p, int n) {
 // Workgroups per pencil for the distributed Cholesky and Hessenberg steps:
 // every pencil one, then the remaining CUs one at a time to the pencil whose
 // estimated time is longest, d^3 / kw (its row passes) + 5e4 d (its
-// barriers, one per step, in the same units), up to max_kw (HKW_MAX for
-// pencils of 1,024 or more, 8 for smaller ones, where a barrier among more
+// barriers, one per step, in the same units), up to max_kw (32 for pencils
+// of 1,536 or more, 16 from 1,024, 8 below, where a barrier among more
 // workgroups costs more than their shorter bands save).  Returns the
 // launch's workgroup count, 0 when there are too few CUs for two per pencil.
 static int plan_split(EigJob* jobs, int n_jobs, int n_cus, int max_kw) {
@@ -2348,7 +2351,7 @@ static int plan_split(EigJob* jobs, int n_jobs, int n_cus, int max_kw) {
     const double d = jobs[j].d;
     return d * d * d / k + 5e4 * d;
   };
-  auto cap = [&](int j) { return min(max_kw, jobs[j].d >= 1024 ? HKW_MAX : 8); };
+  auto cap = [&](int j) { return min(max_kw, jobs[j].d >= 1536 ? 32 : jobs[j].d >= 1024 ? 16 : 8); };
   for (int left = n_cus - n_jobs; left > 0; --left) {
     int best = -1;
     double tb = 0.0;
