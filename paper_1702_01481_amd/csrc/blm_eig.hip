@@ -739,13 +739,16 @@ __device__ __forceinline__ void chase_apply(const Shared& sh, int g, double (&x)
 // l + t0 - 4 g; consecutive bulges' segments overlap, so the segment rolls
 // through registers: 4 new entries loaded, 4 finished ones stored per bulge.
 // Only positions inside the window [wlo, whi] can change; loads are clamped
-// there and stores limited to it.
+// there and stores limited to it.  A is the matrix for a column right of the
+// window (rows are positions) and its transposed copy for a row above it
+// (columns are positions); either way position q of the item is A[q][item],
+// and neighbouring lanes (neighbouring items) touch neighbouring addresses.
 template <class Real>
 __device__ void chase_far(const Shared& sh, Real* A, int ld, int wlo, int whi, int t0, int l, int m,
                           bool right, int item) {
   auto ptr = [&](int pos) -> Real* {
     const int q = min(max(pos, wlo), whi);
-    return right ? A + (size_t)q * ld + item : A + (size_t)item * ld + q;
+    return A + (size_t)q * ld + item;
   };
   double x[CT + 2];
   int B = l + t0;
@@ -769,13 +772,23 @@ __device__ void chase_far(const Shared& sh, Real* A, int ld, int wlo, int whi, i
   }
 }
 
+// The rows above the window live in a transposed copy during a sweep, so
+// that their far updates (one row per lane) read and write consecutive
+// addresses across a wave.  Entry (r, c) moves to T[c][r] when column c is
+// in a batch's window and row r above it: a column holds rows l .. tl - 1 in
+// T, tl being the window's top row of the last batch that held the column
+// (recorded in tlf[c]).  Nothing else reads those entries during the sweep
+// (windows and right items take rows at or below the window's top), and at
+// its end they go back to A.
 template <class Real>
-__device__ void chase_windowed(Shared& sh, Real* A, int ld, int l, int h, int m) {
+__device__ void chase_windowed(Shared& sh, Real* A, int ld, int l, int h, int m, Real* T,
+                               BLM_GLOBAL int32_t* tlf) {
   const int tid = threadIdx.x;
   // group grp of G threads carries bulge grp
   const int mp = m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16;
   const int G = NT / mp, grp = tid / G, lt = tid % G;
   const int ticks = (h - l) + 4 * (m - 1);
+  int wlo_prev = l, whi_prev = l - 1;
   for (int t0 = 0; t0 < ticks; t0 += CT) {
     const int t1 = min(t0 + CT, ticks);
     // the batch's reflectors sit at K in [Kmin, Kmax]; they reach rows and
@@ -864,14 +877,51 @@ __device__ void chase_windowed(Shared& sh, Real* A, int ld, int l, int h, int m)
       const int i = e / nw, j = e % nw;
       A[(size_t)(wlo + i) * ld + wlo + j] = sh.cw[i][j];
     }
+    // into T: rows wlo_prev .. wlo - 1 of the columns the last window also
+    // held, rows l .. wlo - 1 of the entering ones (one row per thread)
+    const int cold = min(whi, whi_prev);
+    const int nold = max(0, cold - wlo + 1), nnew = whi - max(wlo, whi_prev + 1) + 1;
+    const int cnew = max(wlo, whi_prev + 1);
+    for (int e = tid; e < nold * (wlo - wlo_prev); e += NT) {
+      const int c = wlo + e / (wlo - wlo_prev), r = wlo_prev + e % (wlo - wlo_prev);
+      T[(size_t)c * ld + r] = A[(size_t)r * ld + c];
+    }
+    for (int r = l + tid; r < wlo; r += NT)
+      for (int c = cnew; c < cnew + nnew; ++c) T[(size_t)c * ld + r] = A[(size_t)r * ld + c];
+    for (int c = wlo + tid; c <= whi; c += NT) tlf[c] = wlo;
+    wlo_prev = wlo;
+    whi_prev = whi;
+    __syncthreads();
     const int nright = h - whi, ntop = wlo - l;
     for (int it = tid; it < nright + ntop; it += NT) {
       if (it < nright)
         chase_far(sh, A, ld, wlo, whi, t0, l, m, true, whi + 1 + it);
       else
-        chase_far(sh, A, ld, wlo, whi, t0, l, m, false, l + (it - nright));
+        chase_far(sh, T, ld, wlo, whi, t0, l, m, false, l + (it - nright));
     }
     __syncthreads();
+  }
+  // T back to A, through LDS in 64 x 64 tiles (reads of T and writes of A
+  // both along consecutive addresses); tlf is nondecreasing in the column
+  double (*tb)[65] = reinterpret_cast<double (*)[65]>(&sh.cw[0][0]);
+  static_assert(64 * 65 <= CWMAX * CWLD, "transpose tile");
+  for (int c0 = l; c0 <= h; c0 += 64) {
+    const int c1 = min(c0 + 63, h);
+    const int rmax = tlf[c1];                       // rows l .. rmax - 1 hold T entries in this column group
+    for (int r0 = l; r0 < rmax; r0 += 64) {
+      for (int e = tid; e < 64 * 64; e += NT) {
+        const int i = e >> 6, j = e & 63;           // column c0 + i, row r0 + j
+        const int c = c0 + i, r = r0 + j;
+        if (c <= c1 && r < rmax) tb[i][j] = T[(size_t)c * ld + r];
+      }
+      __syncthreads();
+      for (int e = tid; e < 64 * 64; e += NT) {
+        const int j = e >> 6, i = e & 63;           // row r0 + j, column c0 + i
+        const int c = c0 + i, r = r0 + j;
+        if (c <= c1 && r < tlf[c]) A[(size_t)r * ld + c] = tb[i][j];
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -880,7 +930,7 @@ constexpr int AED_NIBBLE = 14;  // percent of the window deflated to skip a swee
 constexpr int CU = 4;           // chase: elements per thread whose loads go out together
 
 template <bool MULTI, class Real>
-__device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* iters) {
+__device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* iters, Real* Tw = nullptr) {
   const int tid = threadIdx.x;
   if (MULTI && tid == 0)
     for (int i = 0; i < 4; ++i) sh.qst[i] = 0;
@@ -1105,7 +1155,7 @@ __device__ int hqr(Shared& sh, Real* A, int ld, int d, Real* wr, Real* wi, int* 
       sh.qst[3] += 1;
     }
     if constexpr (MULTI) {
-      chase_windowed(sh, A, ld, l, h, m);
+      chase_windowed(sh, A, ld, l, h, m, Tw, reinterpret_cast<BLM_GLOBAL int32_t*>(Tw + (size_t)ld * d));
       if (tid == 0) sh.qst[1] += wall_clock64() - t_chase;
       continue;
     }
@@ -2234,7 +2284,7 @@ __global__ __launch_bounds__(NT) void eig_kernel(const EigJob* __restrict__ jobs
   for (size_t i = tid; i < (size_t)d * d; i += NT) part += fabs(J.Hq[i]);
   const double hnorm = block_sum(sh, part);
   int iters = 0;
-  st = hqr<true>(sh, J.A, d, d, J.wr, J.wi, &iters);
+  st = hqr<true>(sh, J.A, d, d, J.wr, J.wi, &iters, J.W);   // W: the chase's transposed rows
   __syncthreads();
   phase_mark(J, clk, 3);
   if (tid == 0) {

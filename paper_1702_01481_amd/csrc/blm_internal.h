@@ -178,7 +178,8 @@ struct EigJob {
   double* A;            // [d][d] shifted Hamiltonian in, destroyed
   double* Hq;           // [d][d] Hessenberg copy
   double* V;            // [d][d] Householder vectors (row k: reflector k)
-  double* W;            // max(2 d^2, 16 d): complex LU, congruence and Hessenberg scratch
+  double* W;            // max(2 d^2, 16 d): complex LU, congruence and Hessenberg scratch, and
+                        // the QR chase's transposed rows above its window (d^2 + d / 2)
   double* vec;          // [n_sel][2][d] complex eigenvectors
   double* wr;           // [d]
   double* wi;           // [d]
