@@ -1669,9 +1669,13 @@ __device__ void back_transform_wave(const gdouble* V, const gdouble* tau, const 
 // of lower_solve_rows.
 constexpr int CSW = 64;   // columns per slice: one lane each
 
+constexpr int CRCH = 128;  // trailing rows per LDS chunk of L
+constexpr int CRW = CRCH / NW;   // of them per wave
+
 struct CongShared {
   double xs[CB][CSW];     // the slice's rows of the current diagonal block
   double ld[CB][CB];      // diagonal block of L
+  double lc[CRCH][CB + 1];  // L's entries left of the diagonal block for a chunk of trailing rows
 };
 
 // X[:, c0:c1] <- L^-1 X[:, c0:c1] for a row-major n x n X, c1 - c0 <= CSW
@@ -1699,31 +1703,36 @@ __device__ void lower_solve_slice(CongShared& cs, const gdouble* Lm, gdouble* X,
       }
     }
     __syncthreads();
-    // trailing rows, two per wave at a time; lanes over the slice's columns
-    for (int iv = k0 + kb + wv; iv < n; iv += 2 * NW) {
-      const int i = __builtin_amdgcn_readfirstlane(iv);
-      const int i2 = i + NW;
-      const bool has2 = i2 < n;
-      const int ib = has2 ? i2 : i;
-      double l1[CB], l2[CB];
+    // trailing rows in chunks of CRCH: the chunk's L entries (columns of the
+    // diagonal block, zero past kb) staged in LDS, then CRW rows per wave
+    // with their loads issued together; lanes over the slice's columns
+    const int jc = min(lane, w - 1);
+    for (int r0 = k0 + kb; r0 < n; r0 += CRCH) {
+      const int nr = min(CRCH, n - r0);
+      for (int t = tid; t < nr * CB; t += NT) {
+        const int r = t / CB, m = t % CB;
+        cs.lc[r][m] = (m < kb) ? Lm[(size_t)(r0 + r) * n + k0 + m] : 0.0;
+      }
+      __syncthreads();
+      double a[CRW];
 #pragma unroll
-      for (int m = 0; m < CB; ++m) {
-        l1[m] = (m < kb) ? Lm[(size_t)i * n + k0 + m] : 0.0;
-        l2[m] = (m < kb) ? Lm[(size_t)ib * n + k0 + m] : 0.0;
+      for (int j = 0; j < CRW; ++j) {
+        const int i = min(r0 + wv + NW * j, n - 1);
+        a[j] = X[(size_t)i * n + c0 + jc];
       }
-      const int jc = min(lane, w - 1);
-      double a1 = X[(size_t)i * n + c0 + jc], a2 = X[(size_t)ib * n + c0 + jc];
+#pragma unroll 1
+      for (int m = 0; m < CB; ++m) {
+        const double x = cs.xs[m][lane];
 #pragma unroll
-      for (int m = 0; m < CB; ++m) {
-        a1 -= l1[m] * cs.xs[m][lane];
-        a2 -= l2[m] * cs.xs[m][lane];
+        for (int j = 0; j < CRW; ++j) a[j] -= cs.lc[wv + NW * j][m] * x;
       }
-      if (lane < w) {
-        X[(size_t)i * n + c0 + lane] = a1;
-        if (has2) X[(size_t)i2 * n + c0 + lane] = a2;
+#pragma unroll
+      for (int j = 0; j < CRW; ++j) {
+        const int i = r0 + wv + NW * j;
+        if (i < n && lane < w) X[(size_t)i * n + c0 + lane] = a[j];
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
